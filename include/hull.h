@@ -1,0 +1,174 @@
+/*
+ * hull.h - C ABI of the MI355X (gfx950) interior-point-discarding 2D convex
+ * hull library.
+ *
+ * The method is G. Mei's preprocessing for planar convex hulls (arXiv:1405.3454,
+ * "A Straightforward Preprocessing Approach for Accelerating Convex Hull
+ * Computations on the GPU"): find extreme points of the point set along the
+ * axes of the original and of three rotated copies (Sec. 2, Step 1), form
+ * their convex polygon with Andrew's algorithm (Step 2), discard every point
+ * strictly inside it (Step 3) and compute the hull of the remaining points
+ * (Sec. 3, case (2)).  Every step runs in this library's own HIP kernels.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Points are structure-of-arrays float32 x[n], y[n] in DEVICE memory owned
+ *    by the caller, each 16-byte aligned.  The exactness guarantees hold for
+ *    coordinates that are multiples of 2^-24 in [0, 1) (HULL_VALIDATE checks
+ *    this); on that grid every orientation test is exact in binary64.
+ *  - Indices are uint32 positions into x/y (so n <= 2^32 - 1), global even in
+ *    the batched calls.  HULL_NONE marks an empty slot.
+ *  - Every output array is caller-owned device memory; counts are written to
+ *    device memory (int64).  Calls are asynchronous on `stream` (a hipStream_t
+ *    passed as void*, NULL = the null stream) and never synchronise, except
+ *    with HULL_VALIDATE, which synchronises to report domain errors.
+ *  - The context owns a device workspace that grows on demand; growth is not
+ *    possible while `stream` is being captured into a graph (HULL_ECAPTURE):
+ *    call once outside capture with the largest sizes first.
+ *  - Extreme slots: for rotation group g (angle t, constants c = cos t,
+ *    s = sin t) the rotated coordinates are u = c*x - s*y and v = s*x + c*y,
+ *    each product rounded to binary64 and then the sum (no fused multiply-add).
+ *    slots[4g+0] = argmin u, [4g+1] = argmax u, [4g+2] = argmin v,
+ *    [4g+3] = argmax v; ties go to the lowest index.  With HULL_LEARNED eight
+ *    more slots follow: argmax of c*x + s*y along eight directions chosen per
+ *    set by the learned proposal.
+ *  - Polygon and hull vertex lists are counter-clockwise, start at the
+ *    lexicographically smallest (x, y), exclude collinear points and name a
+ *    repeated coordinate pair by its lowest index.
+ *  - Survivors (points not strictly inside the polygon; boundary points
+ *    survive; a polygon with fewer than 3 vertices discards nothing) are
+ *    listed in ascending index order.
+ *
+ * Errors: every call returns HULL_OK or a negative code; hull_strerror() names
+ * it and hull_last_hip_error() gives the underlying hipError_t for HULL_EHIP.
+ */
+#ifndef HULL_H
+#define HULL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hull_ctx hull_ctx;
+
+#define HULL_OK 0
+#define HULL_EINVAL (-1)   /* null pointer, bad size, bad preset, misaligned */
+#define HULL_ETOOBIG (-2)  /* n >= 2^32 */
+#define HULL_ENOMEM (-3)   /* workspace allocation failed */
+#define HULL_EHIP (-4)     /* HIP runtime error, see hull_last_hip_error() */
+#define HULL_EDOMAIN (-5)  /* HULL_VALIDATE: coordinate off the 2^-24 grid of [0,1) */
+#define HULL_ECAPTURE (-6) /* workspace would have to grow during stream capture */
+#define HULL_ENOMODEL (-7) /* HULL_LEARNED without loaded network weights */
+
+/* direction presets (angles of the rotated copies, Sec. 2 Step 1) */
+#define HULL_DIRS_PAPER 0      /* 0, 30, 45, 60 degrees (Figure 1, Sec. 5) */
+#define HULL_DIRS_CUMULATIVE 1 /* 30, 45, 45 of Sec. 2 read cumulatively: 0, 30, 75, 120 */
+
+/* flags */
+#define HULL_NOFILTER 1 /* hull of all points, no preprocessing (Sec. 3, case (1)) */
+#define HULL_LEARNED 2  /* add eight learned directions to the sixteen fixed slots */
+#define HULL_VALIDATE 4 /* check the input domain first (synchronises) */
+
+#define HULL_NONE 0xFFFFFFFFu
+#define HULL_FIXED_SLOTS 16
+#define HULL_MAX_SLOTS 24
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (made current by each call). */
+int hull_create(hull_ctx **ctx, int device);
+/* Free the context, its workspace, graphs and network weights. */
+int hull_destroy(hull_ctx *ctx);
+/* Select the rotation angles of Step 1 (HULL_DIRS_*); default PAPER. */
+int hull_set_directions(hull_ctx *ctx, int preset);
+/* Host-only: copy a direction table into c[], s[] (capacity cap).
+ * which = 0: the current preset's 4 rotation groups (needs ctx);
+ * which = 1: the 64 candidate directions 2*pi*d/64 of the learned proposal.
+ * Returns the number of entries or a negative code. */
+int hull_direction_table(hull_ctx *ctx, int which, double *c, double *s, int cap);
+const char *hull_strerror(int code);
+int hull_last_hip_error(hull_ctx *ctx);
+
+/* ---- Step 1: extreme points (Sec. 2, Step 1) --------------------------- */
+/* slots: device uint32[16] (or [24] with HULL_LEARNED); vals: device
+ * double[same] with the extreme values, or NULL.  n == 0 gives HULL_NONE. */
+int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                  uint32_t *slots, double *vals, int flags, void *stream);
+
+/* ---- Step 2: convex polygon of the extremes (Sec. 2, Step 2) ----------- */
+/* slots: device uint32[n_slots] (n_slots <= 24, HULL_NONE entries ignored).
+ * verts: device uint32[n_slots]; m: device int32, the vertex count. */
+int hull_polygon(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                 const uint32_t *slots, int n_slots, uint32_t *verts, int32_t *m,
+                 void *stream);
+
+/* ---- Step 3: discard interior points (Sec. 2, Step 3) ------------------ */
+/* Builds the polygon of `slots` and writes the survivors (ascending indices)
+ * to surv (device uint32, capacity n) and their count to *n_surv (device). */
+int hull_discard(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                 const uint32_t *slots, int n_slots, uint32_t *surv,
+                 int64_t *n_surv, void *stream);
+
+/* ---- hull of a subset (the hull of the remaining points, Sec. 3) ------- */
+/* idx: device uint32 list of point indices (e.g. survivors), its length in
+ * device memory *k_dev, at most k_cap.  hull: device uint32 (capacity k_cap),
+ * *h: device int64. */
+int hull_of_subset(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                   const uint32_t *idx, const int64_t *k_dev, int64_t k_cap,
+                   uint32_t *hull, int64_t *h, void *stream);
+
+/* ---- the whole method -------------------------------------------------- */
+/* Steps 1-3 and the hull of the survivors (HULL_NOFILTER: hull of all
+ * points).  hull: device uint32 (capacity n); *h: device int64. */
+int hull_compute(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                 uint32_t *hull, int64_t *h, int flags, void *stream);
+
+/* ---- batched forms (many sets, CSR offsets) ----------------------------
+ * offsets: device int64[S+1], non-decreasing, offsets[0] = 0,
+ * offsets[S] = n_total (checked with HULL_VALIDATE).  Set s is points
+ * [offsets[s], offsets[s+1]).  Indices stay global. */
+int hull_extremes_batched(hull_ctx *ctx, const float *x, const float *y,
+                          const int64_t *offsets, int64_t S, int64_t n_total,
+                          uint32_t *slots /* [S*16|24] */, int flags, void *stream);
+int hull_discard_batched(hull_ctx *ctx, const float *x, const float *y,
+                         const int64_t *offsets, int64_t S, int64_t n_total,
+                         const uint32_t *slots, int n_slots, uint32_t *surv,
+                         int64_t *surv_offsets /* [S+1] */, void *stream);
+int hull_compute_batched(hull_ctx *ctx, const float *x, const float *y,
+                         const int64_t *offsets, int64_t S, int64_t n_total,
+                         uint32_t *hull, int64_t *hull_offsets /* [S+1] */,
+                         int flags, void *stream);
+
+/* ---- graphs ------------------------------------------------------------
+ * Record hull_compute_batched with these arguments into a hipGraph (the
+ * workspace is sized first, outside capture) and replay it with
+ * hull_graph_launch; the pointers are baked into the graph. */
+int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y,
+                       const int64_t *offsets, int64_t S, int64_t n_total,
+                       uint32_t *hull, int64_t *hull_offsets, int flags,
+                       void *stream);
+int hull_graph_launch(hull_ctx *ctx, void *stream);
+
+/* ---- launch tuning ------------------------------------------------------
+ * Time the candidate launch shapes of the filter kernels on these inputs
+ * and keep the fastest (per size bucket).  Synchronises. */
+int hull_autotune(hull_ctx *ctx, const float *x, const float *y,
+                  const int64_t *offsets, int64_t S, int64_t n_total, void *stream);
+/* Read (get != 0) or set the chosen waves-per-CU of the filter kernels. */
+int hull_tuning(hull_ctx *ctx, int get, int *k1_blocks_per_cu, int *k3_blocks_per_cu);
+
+/* ---- per-kernel timing (hipEvents around every launch) ----------------- */
+int hull_timing_enable(hull_ctx *ctx, int on);
+/* Copy accumulated milliseconds and launch counts for up to cap kernel
+ * kinds; names via hull_timing_name().  Synchronises.  Returns the count. */
+int hull_timing_read(hull_ctx *ctx, double *ms, int64_t *launches, int cap);
+const char *hull_timing_name(int kind);
+int hull_timing_reset(hull_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HULL_H */

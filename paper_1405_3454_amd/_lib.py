@@ -1,0 +1,87 @@
+"""ctypes binding of include/hull.h (argument marshalling only)."""
+import ctypes
+import os
+
+import torch  # noqa: F401  -- load torch's HIP runtime first so the library shares it
+
+from ._build import LIB
+
+HULL_OK = 0
+HULL_EINVAL = -1
+HULL_ETOOBIG = -2
+HULL_ENOMEM = -3
+HULL_EHIP = -4
+HULL_EDOMAIN = -5
+HULL_ECAPTURE = -6
+HULL_ENOMODEL = -7
+
+HULL_DIRS_PAPER = 0
+HULL_DIRS_CUMULATIVE = 1
+
+HULL_NOFILTER = 1
+HULL_LEARNED = 2
+HULL_VALIDATE = 4
+
+HULL_NONE = 0xFFFFFFFF
+
+P = ctypes.c_void_p
+I = ctypes.c_int
+I64 = ctypes.c_int64
+D = ctypes.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "hull_create": (I, [ctypes.POINTER(P), I]),
+    "hull_destroy": (I, [P]),
+    "hull_set_directions": (I, [P, I]),
+    "hull_direction_table": (I, [P, I, P, P, I]),
+    "hull_strerror": (ctypes.c_char_p, [I]),
+    "hull_last_hip_error": (I, [P]),
+    "hull_extremes": (I, [P, P, P, I64, P, P, I, P]),
+    "hull_polygon": (I, [P, P, P, I64, P, I, P, P, P]),
+    "hull_discard": (I, [P, P, P, I64, P, I, P, P, P]),
+    "hull_of_subset": (I, [P, P, P, I64, P, P, I64, P, P, P]),
+    "hull_compute": (I, [P, P, P, I64, P, P, I, P]),
+    "hull_extremes_batched": (I, [P, P, P, P, I64, I64, P, I, P]),
+    "hull_discard_batched": (I, [P, P, P, P, I64, I64, P, I, P, P, P]),
+    "hull_compute_batched": (I, [P, P, P, P, I64, I64, P, P, I, P]),
+    "hull_graph_capture": (I, [P, P, P, P, I64, I64, P, P, I, P]),
+    "hull_graph_launch": (I, [P, P]),
+    "hull_autotune": (I, [P, P, P, P, I64, I64, P]),
+    "hull_tuning": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "hull_timing_enable": (I, [P, I]),
+    "hull_timing_read": (I, [P, P, P, I]),
+    "hull_timing_name": (ctypes.c_char_p, [I]),
+    "hull_timing_reset": (I, [P]),
+}
+
+_lib = None
+
+
+class HullError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        msg = "%s: %s (%d)" % (what, lib().hull_strerror(code).decode(), code)
+        super().__init__(msg)
+
+
+def lib():
+    """Load libhullgpu.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError("libhullgpu.so is not built; run paper_1405_3454_amd._build.build() "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code, what):
+    if code < 0:
+        raise HullError(code, what)
+    return code

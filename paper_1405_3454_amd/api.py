@@ -1,0 +1,235 @@
+"""Python front end of the hull library: torch tensors in, torch tensors out.
+
+Only argument marshalling happens here; every step of the method runs in the
+library's HIP kernels (libhullgpu.so).  Indices come back as int32 tensors
+holding uint32 values (use ``as_u32`` to view them as numpy uint32).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (HULL_DIRS_CUMULATIVE, HULL_DIRS_PAPER, HULL_LEARNED, HULL_NOFILTER,
+                   HULL_VALIDATE, check, lib)
+
+FIXED_SLOTS = 16
+MAX_SLOTS = 24
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def as_u32(t):
+    """int32 tensor of uint32 values -> numpy uint32 array."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def _pts(x, y):
+    if x.dtype != torch.float32 or y.dtype != torch.float32:
+        raise TypeError("x, y must be float32")
+    if not (x.is_cuda and y.is_cuda):
+        raise TypeError("x, y must be device tensors")
+    if not (x.is_contiguous() and y.is_contiguous()) or x.shape != y.shape or x.dim() != 1:
+        raise ValueError("x, y must be contiguous 1-D tensors of equal length")
+    return x.numel()
+
+
+def _flags(nofilter=False, learned=False, validate=False):
+    return ((HULL_NOFILTER if nofilter else 0) | (HULL_LEARNED if learned else 0) |
+            (HULL_VALIDATE if validate else 0))
+
+
+class Hull:
+    """A library context on one device."""
+
+    def __init__(self, device=0, preset=HULL_DIRS_PAPER):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        check(lib().hull_create(ctypes.byref(h), self.device.index or 0), "hull_create")
+        self._h = h
+        self.set_directions(preset)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hull_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration -----------------------------------------------------
+    def set_directions(self, preset):
+        check(lib().hull_set_directions(self._h, int(preset)), "hull_set_directions")
+        self.preset = preset
+
+    def direction_table(self, which=0):
+        c = np.zeros(64, np.float64)
+        s = np.zeros(64, np.float64)
+        n = check(lib().hull_direction_table(self._h, which, c.ctypes.data_as(ctypes.c_void_p),
+                                             s.ctypes.data_as(ctypes.c_void_p), 64),
+                  "hull_direction_table")
+        return c[:n], s[:n]
+
+    def tuning(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        check(lib().hull_tuning(self._h, 1, ctypes.byref(a), ctypes.byref(b)), "hull_tuning")
+        return a.value, b.value
+
+    def set_tuning(self, k1, k3):
+        a, b = ctypes.c_int(k1), ctypes.c_int(k3)
+        check(lib().hull_tuning(self._h, 0, ctypes.byref(a), ctypes.byref(b)), "hull_tuning")
+
+    def autotune(self, x, y, offsets=None, stream=None):
+        n = _pts(x, y)
+        S = 0 if offsets is None else offsets.numel() - 1
+        check(lib().hull_autotune(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n, _stream(stream)),
+              "hull_autotune")
+        return self.tuning()
+
+    # -- single set --------------------------------------------------------
+    def extremes(self, x, y, learned=False, validate=False, stream=None):
+        n = _pts(x, y)
+        k = MAX_SLOTS if learned else FIXED_SLOTS
+        slots = torch.empty(k, dtype=torch.int32, device=x.device)
+        vals = torch.empty(k, dtype=torch.float64, device=x.device)
+        check(lib().hull_extremes(self._h, _ptr(x), _ptr(y), n, _ptr(slots), _ptr(vals),
+                                  _flags(learned=learned, validate=validate), _stream(stream)),
+              "hull_extremes")
+        return slots, vals
+
+    def polygon(self, x, y, slots, stream=None):
+        n = _pts(x, y)
+        slots = slots.to(device=x.device, dtype=torch.int32).contiguous()
+        verts = torch.empty(max(1, slots.numel()), dtype=torch.int32, device=x.device)
+        m = torch.zeros(1, dtype=torch.int32, device=x.device)
+        check(lib().hull_polygon(self._h, _ptr(x), _ptr(y), n, _ptr(slots), slots.numel(),
+                                 _ptr(verts), _ptr(m), _stream(stream)), "hull_polygon")
+        return verts[: int(m.item())]
+
+    def discard_into(self, x, y, slots, surv, n_surv, stream=None):
+        """Asynchronous form: survivors to surv (int32[n]), count to n_surv (int64[1])."""
+        n = _pts(x, y)
+        check(lib().hull_discard(self._h, _ptr(x), _ptr(y), n, _ptr(slots), slots.numel(),
+                                 _ptr(surv), _ptr(n_surv), _stream(stream)), "hull_discard")
+
+    def discard(self, x, y, slots, stream=None):
+        n = _pts(x, y)
+        slots = slots.to(device=x.device, dtype=torch.int32).contiguous()
+        surv = torch.empty(max(1, n), dtype=torch.int32, device=x.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
+        self.discard_into(x, y, slots, surv, cnt, stream)
+        return surv[: int(cnt.item())]
+
+    def hull_of_subset(self, x, y, idx, count=None, stream=None):
+        n = _pts(x, y)
+        idx = idx.to(device=x.device, dtype=torch.int32).contiguous()
+        k = torch.tensor([idx.numel()] if count is None else [int(count)], dtype=torch.int64,
+                         device=x.device)
+        cap = max(1, idx.numel())
+        hull = torch.empty(cap, dtype=torch.int32, device=x.device)
+        h = torch.zeros(1, dtype=torch.int64, device=x.device)
+        check(lib().hull_of_subset(self._h, _ptr(x), _ptr(y), n, _ptr(idx), _ptr(k), idx.numel(),
+                                   _ptr(hull), _ptr(h), _stream(stream)), "hull_of_subset")
+        return hull[: int(h.item())]
+
+    def compute_into(self, x, y, hull, h, nofilter=False, learned=False, validate=False,
+                     stream=None):
+        """Asynchronous form: hull indices to hull (int32[n]), count to h (int64[1])."""
+        n = _pts(x, y)
+        check(lib().hull_compute(self._h, _ptr(x), _ptr(y), n, _ptr(hull), _ptr(h),
+                                 _flags(nofilter, learned, validate), _stream(stream)),
+              "hull_compute")
+
+    def compute(self, x, y, nofilter=False, learned=False, validate=False, stream=None):
+        n = _pts(x, y)
+        hull = torch.empty(max(1, n), dtype=torch.int32, device=x.device)
+        h = torch.zeros(1, dtype=torch.int64, device=x.device)
+        self.compute_into(x, y, hull, h, nofilter, learned, validate, stream)
+        return hull[: int(h.item())]
+
+    # -- batched -----------------------------------------------------------
+    def extremes_batched(self, x, y, offsets, learned=False, validate=False, stream=None):
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        k = MAX_SLOTS if learned else FIXED_SLOTS
+        slots = torch.empty(S * k, dtype=torch.int32, device=x.device)
+        check(lib().hull_extremes_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
+                                          _ptr(slots), _flags(learned=learned, validate=validate),
+                                          _stream(stream)), "hull_extremes_batched")
+        return slots.view(S, k)
+
+    def discard_batched(self, x, y, offsets, slots, stream=None):
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        slots = slots.to(device=x.device, dtype=torch.int32).contiguous()
+        k = slots.numel() // max(S, 1)
+        surv = torch.empty(max(1, n), dtype=torch.int32, device=x.device)
+        so = torch.zeros(S + 1, dtype=torch.int64, device=x.device)
+        check(lib().hull_discard_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
+                                         _ptr(slots), k, _ptr(surv), _ptr(so), _stream(stream)),
+              "hull_discard_batched")
+        return surv, so
+
+    def compute_batched_into(self, x, y, offsets, hull, hull_offsets, nofilter=False,
+                             learned=False, validate=False, stream=None):
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        check(lib().hull_compute_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
+                                         _ptr(hull), _ptr(hull_offsets),
+                                         _flags(nofilter, learned, validate), _stream(stream)),
+              "hull_compute_batched")
+
+    def compute_batched(self, x, y, offsets, nofilter=False, learned=False, validate=False,
+                        stream=None):
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        hull = torch.empty(max(1, n), dtype=torch.int32, device=x.device)
+        ho = torch.zeros(S + 1, dtype=torch.int64, device=x.device)
+        self.compute_batched_into(x, y, offsets, hull, ho, nofilter, learned, validate, stream)
+        return hull, ho
+
+    def graph_capture(self, x, y, offsets, hull, hull_offsets, nofilter=False, learned=False,
+                      stream=None):
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        check(lib().hull_graph_capture(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
+                                       _ptr(hull), _ptr(hull_offsets), _flags(nofilter, learned),
+                                       _stream(stream)), "hull_graph_capture")
+
+    def graph_launch(self, stream=None):
+        check(lib().hull_graph_launch(self._h, _stream(stream)), "hull_graph_launch")
+
+    # -- timing ------------------------------------------------------------
+    def timing(self, on=True):
+        check(lib().hull_timing_enable(self._h, int(bool(on))), "hull_timing_enable")
+
+    def timing_reset(self):
+        check(lib().hull_timing_reset(self._h), "hull_timing_reset")
+
+    def timing_read(self):
+        ms = np.zeros(64, np.float64)
+        cnt = np.zeros(64, np.int64)
+        k = check(lib().hull_timing_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                         cnt.ctypes.data_as(ctypes.c_void_p), 64), "hull_timing_read")
+        return {lib().hull_timing_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)
+                if cnt[i] > 0}
+
+
+def split_csr(flat, offsets):
+    """numpy helper: list of per-set arrays from a CSR pair."""
+    off = np.asarray(offsets)
+    return [flat[off[i]:off[i + 1]] for i in range(len(off) - 1)]
+
+
+__all__ = ["Hull", "as_u32", "split_csr", "HULL_DIRS_PAPER", "HULL_DIRS_CUMULATIVE",
+           "HULL_NOFILTER", "HULL_LEARNED", "HULL_VALIDATE", "_lib"]

@@ -1,0 +1,60 @@
+// Internal definitions shared by the library's own kernels and host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hg {
+
+constexpr int WAVE = 64;
+constexpr int PTS_PER_LANE = 4;                 // one float4 of x and of y per lane
+constexpr int CHUNK = WAVE * PTS_PER_LANE;      // 256 consecutive points per wave step
+constexpr int TILE_CHUNKS = 4;
+constexpr int TILE = CHUNK * TILE_CHUNKS;       // 1024 points: unit of the filter passes
+constexpr int TILE_WORDS = TILE / 64;           // survivor mask words per tile
+constexpr int FIXED_SLOTS = 16;
+constexpr int MAX_DIRS = 8;                     // learned extra directions per set
+constexpr int MAX_SLOTS = FIXED_SLOTS + MAX_DIRS;
+constexpr int SPAN_ROWS = 256;                  // quick-accept rows per polygon
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr float GRIDF = 16777216.0f;            // 2^24
+constexpr double GRIDD = 16777216.0;
+
+// Filter polygon of one set, in grid units (coordinate * 2^24, integers).
+// Edge e is strictly satisfied by p iff
+//     E_e(p) = fma(ex, py, fma(-ey, px, c)) > 0,   c = ey*ax - ex*ay,
+// exact in binary64 on the grid (|E| < 2^51).  Unused edges hold (0, 0, 1);
+// a polygon with fewer than 3 vertices has edge 0 = (0, 0, -1), so nothing
+// is strictly inside it.
+struct Poly {
+    double ex[MAX_SLOTS];
+    double ey[MAX_SLOTS];
+    double c[MAX_SLOTS];
+    uint32_t verts[MAX_SLOTS];
+    int32_t m;
+    int32_t ky_lo;      // quick-accept rows cover ky in [ky_lo, ky_lo + yspan]
+    int32_t yspan;      // < 0: no quick-accept rows
+    int32_t shift;      // row = (ky - ky_lo) >> shift
+    int32_t pad[4];
+};
+
+// One quick-accept row: every grid point with ky in the row and
+// xl <= kx <= xr is strictly inside the polygon (verified exactly at the
+// rectangle's corners).  Empty rows have xl > xr.
+struct Span {
+    int32_t xl, xr;
+};
+
+// Kernel kinds for the per-kernel event timer.
+enum Kind {
+    K_TILEMAP = 0, K_EXTREMES, K_POLYGON, K_DISCARD, K_SCAN, K_SCATTER,
+    K_KEYS, K_SORT_HIST, K_SORT_SCAN, K_SORT_SCATTER, K_CHAIN, K_CHAIN_COMPACT,
+    K_FINAL, K_LOOKUP, K_VALIDATE, K_MISC, K_HIST32, K_MLP, K_LABELS, K_NKINDS
+};
+
+// Direction constants for one launch.  Preset groups: (gc[g], gs[g]).
+struct Dirs {
+    double gc[4];
+    double gs[4];
+};
+
+}  // namespace hg

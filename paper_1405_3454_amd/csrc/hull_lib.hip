@@ -1,0 +1,826 @@
+// C ABI of the library (include/hull.h): context, workspace planning and the
+// launch sequences of every entry point.  The kernels are compiled into this
+// translation unit so that the host code can launch every template directly.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/hull.h"
+#include "hg_common.h"
+#include "k_filter.hip"
+#include "k_sort.hip"
+#include "k_chain.hip"
+#include "k_learned.hip"
+
+using namespace hg;
+
+// ---------------------------------------------------------------------------
+// direction tables (host copies)
+static const double H_C30 = 0x1.bb67ae8584caap-1;
+static const double H_C45 = 0x1.6a09e667f3bcdp-1;
+static const double H_C75 = 0x1.0907dc1930690p-2;
+static const double H_S75 = 0x1.ee8dd4748bf15p-1;
+
+static Dirs preset_dirs(int preset) {
+    Dirs d;
+    if (preset == HULL_DIRS_PAPER) {
+        const double c[4] = {1.0, H_C30, H_C45, 0.5}, s[4] = {0.0, 0.5, H_C45, H_C30};
+        for (int g = 0; g < 4; g++) { d.gc[g] = c[g]; d.gs[g] = s[g]; }
+    } else {
+        const double c[4] = {1.0, H_C30, H_C75, -0.5}, s[4] = {0.0, 0.5, H_S75, H_C30};
+        for (int g = 0; g < 4; g++) { d.gc[g] = c[g]; d.gs[g] = s[g]; }
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+struct hull_ctx {
+    int device = 0;
+    int preset = HULL_DIRS_PAPER;
+    Dirs dirs;
+    int cus = 256;
+    hipError_t last = hipSuccess;
+    char *ws = nullptr;
+    size_t ws_cap = 0;
+    int k1_bpc = 8, k3_bpc = 8;        // blocks per CU of the filter kernels
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_pending;   // kind, index of start event
+    double ms[K_NKINDS] = {};
+    int64_t launches[K_NKINDS] = {};
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    // learned proposal
+    LearnedState learned;
+};
+
+static const char *kKindNames[K_NKINDS] = {
+    "tile_map", "extremes", "polygon", "discard", "scan", "scatter", "keys",
+    "sort_hist", "sort_scan", "sort_scatter", "chain", "chain_merge", "hull_final",
+    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels"};
+
+#define HIPCHECK(expr)                                   \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) {                          \
+            ctx->last = e_;                              \
+            return HULL_EHIP;                            \
+        }                                                \
+    } while (0)
+
+// Launch helper: records events around the launch when timing is on.
+template <typename F>
+static int launch(hull_ctx *ctx, int kind, hipStream_t st, F &&f) {
+    size_t e0 = 0;
+    if (ctx->timing && ctx->ev_used + 2 > ctx->ev_pool.size()) {
+        size_t old = ctx->ev_pool.size();
+        ctx->ev_pool.resize(old + 4096);
+        for (size_t i = old; i < ctx->ev_pool.size(); i++)
+            HIPCHECK(hipEventCreate(&ctx->ev_pool[i]));
+    }
+    if (ctx->timing && ctx->ev_used + 2 <= ctx->ev_pool.size()) {
+        e0 = ctx->ev_used;
+        ctx->ev_used += 2;
+        HIPCHECK(hipEventRecord(ctx->ev_pool[e0], st));
+    } else {
+        e0 = SIZE_MAX;
+    }
+    f();
+    HIPCHECK(hipGetLastError());
+    if (e0 != SIZE_MAX) {
+        HIPCHECK(hipEventRecord(ctx->ev_pool[e0 + 1], st));
+        ctx->ev_pending.push_back({kind, e0});
+    }
+    return HULL_OK;
+}
+
+#define LAUNCH(kind, ...)                                                    \
+    do {                                                                     \
+        int rc_ = launch(ctx, kind, st, [&]() { __VA_ARGS__; });             \
+        if (rc_) return rc_;                                                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace plan.  All sizes are upper bounds derived from (n_total, S).
+struct Plan {
+    size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, masks, tile_cnt, tile_pos,
+        scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
+        hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, total;
+    int64_t tcap, u0cap;
+};
+
+static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+
+static Plan make_plan(int64_t n, int64_t S) {
+    Plan p;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += al(bytes);
+        return r;
+    };
+    p.tcap = n / TILE + 2 * S + 2;
+    p.u0cap = n / CHAIN_C + 2;
+    p.tile_off = take((S + 1) * 8);
+    p.tile_set = take(p.tcap * 4);
+    p.pval = take(p.tcap * MAX_SLOTS * 8);
+    p.pidx = take(p.tcap * MAX_SLOTS * 4);
+    p.slots = take(S * MAX_SLOTS * 4);
+    p.vals = take(S * MAX_SLOTS * 8);
+    p.polys = take(S * sizeof(Poly));
+    p.spans = take(S * SPAN_ROWS * sizeof(Span));
+    p.masks = take(p.tcap * TILE_WORDS * 8);
+    p.tile_cnt = take(p.tcap * 4);
+    p.tile_pos = take((p.tcap + 1) * 8);
+    p.scan_bs = take(SCAN_BLOCKS * 8);
+    p.surv_off = take((S + 1) * 8);
+    p.surv = take(n * 4 + 16);
+    p.keys0 = take(n * 8 + 16);
+    p.keysA = take(n * 8 + 16);
+    p.keysB = take(n * 8 + 16);
+    p.lo0 = take(n * 8 + 16);
+    p.up0 = take(n * 8 + 16);
+    p.lo1 = take(n * 8 + 16);
+    p.up1 = take(n * 8 + 16);
+    p.ccnt = take(4 * p.u0cap * 4);
+    p.bounds = take(4 * S * 8);
+    p.hcnt = take(S * 4);
+    p.hoff = take((S + 1) * 8);
+    p.hkeys = take(n * 8 + 16);
+    p.hpos = take(n * 4 + 16);
+    p.hist = take(RADIX * SORT_BLOCKS * 4);
+    p.hoffs = take((RADIX * SORT_BLOCKS + 1) * 8);
+    p.consts = take(8 * 8);
+    p.err = take(8);
+    p.setdirs = take(S * MAX_DIRS * 2 * 8);
+    p.learn = take(learned_ws_bytes(S));
+    p.total = o;
+    return p;
+}
+
+static int ensure_ws(hull_ctx *ctx, size_t bytes, hipStream_t st) {
+    if (bytes <= ctx->ws_cap) return HULL_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHECK(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return HULL_ECAPTURE;
+    HIPCHECK(hipDeviceSynchronize());
+    if (ctx->ws) HIPCHECK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+        ctx->ws = nullptr;
+        (void)hipGetLastError();
+        return HULL_ENOMEM;
+    }
+    ctx->ws_cap = want;
+    return HULL_OK;
+}
+
+template <typename T>
+static T *W(hull_ctx *ctx, size_t off) {
+    return reinterpret_cast<T *>(ctx->ws + off);
+}
+
+static int check_points(const float *x, const float *y, int64_t n) {
+    if (n < 0) return HULL_EINVAL;
+    if (n >= (int64_t(1) << 32) - 1) return HULL_ETOOBIG;
+    if (n > 0 && (!x || !y)) return HULL_EINVAL;
+    if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return HULL_EINVAL;
+    return HULL_OK;
+}
+
+static int grid_k1(hull_ctx *ctx) { return ctx->cus * ctx->k1_bpc; }
+static int grid_k3(hull_ctx *ctx) { return ctx->cus * ctx->k3_bpc; }
+
+// ---------------------------------------------------------------------------
+// Launch sequences
+
+// Exclusive scan of u32 counts (count at *cnt) into out[0..count] (int64).
+static int run_scan(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t *in,
+                    const int64_t *cnt, int64_t *out) {
+    int64_t *bs = W<int64_t>(ctx, p.scan_bs);
+    LAUNCH(K_SCAN, k_scan_reduce<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs));
+    LAUNCH(K_SCAN, k_scan_blocks<<<1, SCAN_THREADS, 0, st>>>(bs, cnt, out));
+    LAUNCH(K_SCAN, k_scan_down<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs, out));
+    return HULL_OK;
+}
+
+static int run_validate(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                        const float *y, int64_t n, const int64_t *off, int64_t S) {
+    int *err = W<int>(ctx, p.err);
+    LAUNCH(K_VALIDATE, k_fill_i64<<<1, 64, 0, st>>>(reinterpret_cast<int64_t *>(err), 1, 0));
+    LAUNCH(K_VALIDATE, k_validate<<<1024, 256, 0, st>>>(x, y, n, off, S, err));
+    int h = 0;
+    HIPCHECK(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return h ? HULL_EDOMAIN : HULL_OK;
+}
+
+static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const int64_t *off,
+                       int64_t n1, int64_t S) {
+    int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
+    LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, 1, tile_off));
+    LAUNCH(K_TILEMAP, k_tile_sets<<<(unsigned)S, 256, 0, st>>>(tile_off, W<int32_t>(ctx, p.tile_set)));
+    return HULL_OK;
+}
+
+// Step 1 (+ partial reduction and polygon in k_polygon).
+static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                        const float *y, int64_t n_total, const int64_t *off, int64_t n1,
+                        int64_t S, bool learned) {
+    const int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
+    const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
+    double *pval = W<double>(ctx, p.pval);
+    uint32_t *pidx = W<uint32_t>(ctx, p.pidx);
+    const double *sd = W<double>(ctx, p.setdirs);
+    const int g = grid_k1(ctx);
+    const Dirs d = ctx->dirs;
+#define K1(PR, ND)                                                                           \
+    LAUNCH(K_EXTREMES, k_extremes<PR, ND><<<g, 256, 0, st>>>(x, y, n_total, off, n1, S,     \
+                                                             tile_off, tile_set, d, sd, pval, \
+                                                             pidx))
+    if (ctx->preset == HULL_DIRS_PAPER) {
+        if (learned) K1(0, MAX_DIRS); else K1(0, 0);
+    } else {
+        if (learned) K1(1, MAX_DIRS); else K1(1, 0);
+    }
+#undef K1
+    return HULL_OK;
+}
+
+static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                       const float *y, int64_t n_total, int64_t S, bool learned, const uint32_t *slots_in,
+                       int n_in, uint32_t *slots_out, double *vals_out) {
+    const int64_t W1 = (int64_t)grid_k1(ctx) * 4;
+    auto *polys = W<Poly>(ctx, p.polys);
+    auto *spans = W<Span>(ctx, p.spans);
+    const double *sd = W<double>(ctx, p.setdirs);
+    if (learned)
+        LAUNCH(K_POLYGON, k_polygon<MAX_DIRS><<<(unsigned)S, 256, 0, st>>>(
+            x, y, n_total, S, ctx->preset, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),
+            W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,
+            spans));
+    else
+        LAUNCH(K_POLYGON, k_polygon<0><<<(unsigned)S, 256, 0, st>>>(
+            x, y, n_total, S, ctx->preset, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),
+            W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,
+            spans));
+    return HULL_OK;
+}
+
+// Step 3 + compaction.  surv_off gets the per-set survivor offsets (S+1);
+// keys (optional) the sort keys of the survivors.
+static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                       const float *y, int64_t n_total, const int64_t *off, int64_t n1,
+                       int64_t S, int nedge, uint32_t *surv, int64_t *surv_off, uint64_t *keys) {
+    const int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
+    const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
+    auto *polys = W<Poly>(ctx, p.polys);
+    auto *spans = W<Span>(ctx, p.spans);
+    uint64_t *masks = W<uint64_t>(ctx, p.masks);
+    uint32_t *tcnt = W<uint32_t>(ctx, p.tile_cnt);
+    int64_t *tpos = W<int64_t>(ctx, p.tile_pos);
+    const int g = grid_k3(ctx);
+    if (nedge <= FIXED_SLOTS)
+        LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS><<<g, 256, 0, st>>>(
+            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, masks, tcnt));
+    else
+        LAUNCH(K_DISCARD, k_discard<MAX_SLOTS><<<g, 256, 0, st>>>(
+            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, masks, tcnt));
+    int rc = run_scan(ctx, p, st, tcnt, tile_off + S, tpos);
+    if (rc) return rc;
+    LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
+                                                                                  surv_off));
+    LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, off, S, tile_off, tile_set, masks, tcnt,
+                                                   tpos, surv, keys));
+    return HULL_OK;
+}
+
+static int sort_passes(int64_t S) {
+    int setbits = 0;
+    while (setbits < 16 && (int64_t(1) << setbits) < S) setbits++;
+    return (48 + setbits + 7) / 8;
+}
+
+// Sort keys (count at *cnt) ascending; returns the buffer holding the result.
+static int run_sort(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint64_t *keys,
+                    const int64_t *cnt, int passes, const uint64_t **sorted) {
+    uint64_t *A = W<uint64_t>(ctx, p.keysA), *B = W<uint64_t>(ctx, p.keysB);
+    uint32_t *hist = W<uint32_t>(ctx, p.hist);
+    int64_t *hoffs = W<int64_t>(ctx, p.hoffs);
+    const int64_t *hcount = W<int64_t>(ctx, p.consts) + 0;   // = RADIX * SORT_BLOCKS
+    const uint64_t *in = keys;
+    uint64_t *out = A;
+    for (int ps = 0; ps < passes; ps++) {
+        LAUNCH(K_SORT_HIST, k_sort_hist<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(in, cnt, 8 * ps, hist));
+        int rc = run_scan(ctx, p, st, hist, hcount, hoffs);
+        if (rc) return rc;
+        LAUNCH(K_SORT_SCATTER, k_sort_scatter<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
+            in, cnt, 8 * ps, hoffs, out));
+        in = out;
+        out = (out == A) ? B : A;
+    }
+    *sorted = in;
+    return HULL_OK;
+}
+
+static int chain_levels(int64_t ncap) {
+    int64_t u = (ncap + CHAIN_C - 1) / CHAIN_C;
+    int L = 0;
+    int64_t span = 1;
+    while (span < u) {
+        span *= CHAIN_G;
+        L++;
+    }
+    return L;
+}
+
+// Hull of the candidates (idx[i], keys[i]) i < *cnt, grouped into S sets by
+// the key's set field.  hoff (S+1) receives the per-set hull offsets, hull
+// the vertex indices.
+static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t *idx,
+                    const uint64_t *keys, const int64_t *cnt, int64_t ncap, int64_t S,
+                    int64_t *hoff, uint32_t *hull) {
+    const uint64_t *sorted = nullptr;
+    int rc = run_sort(ctx, p, st, keys, cnt, sort_passes(S), &sorted);
+    if (rc) return rc;
+    uint64_t *lo[2] = {W<uint64_t>(ctx, p.lo0), W<uint64_t>(ctx, p.lo1)};
+    uint64_t *up[2] = {W<uint64_t>(ctx, p.up0), W<uint64_t>(ctx, p.up1)};
+    uint32_t *cc = W<uint32_t>(ctx, p.ccnt);
+    uint32_t *locnt[2] = {cc, cc + p.u0cap};
+    uint32_t *upcnt[2] = {cc + 2 * p.u0cap, cc + 3 * p.u0cap};
+    const int64_t u0 = (ncap + CHAIN_C - 1) / CHAIN_C;
+    LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::max<int64_t>(1, (u0 + 255) / 256), 256, 0, st>>>(
+        sorted, cnt, lo[0], up[0], locnt[0], upcnt[0]));
+    const int L = chain_levels(ncap);
+    int cur = 0;
+    int64_t R = CHAIN_C;
+    for (int lev = 0; lev < L; lev++) {
+        int64_t ucap = (ncap + R - 1) / R;
+        int64_t vcap = (ucap + CHAIN_G - 1) / CHAIN_G;
+        dim3 grid((unsigned)std::max<int64_t>(1, (vcap + 3) / 4), 2);
+        LAUNCH(K_CHAIN_COMPACT, k_chain_merge<<<grid, 256, 0, st>>>(
+            lo[cur], up[cur], locnt[cur], upcnt[cur], cnt, lev, lo[1 - cur], up[1 - cur],
+            locnt[1 - cur], upcnt[1 - cur]));
+        cur = 1 - cur;
+        R *= CHAIN_G;
+    }
+    int64_t *bounds = W<int64_t>(ctx, p.bounds);
+    uint32_t *hcnt = W<uint32_t>(ctx, p.hcnt);
+    uint64_t *hkeys = W<uint64_t>(ctx, p.hkeys);
+    uint32_t *hpos = W<uint32_t>(ctx, p.hpos);
+    int64_t *scount = W<int64_t>(ctx, p.consts) + 1;   // = S
+    LAUNCH(K_FINAL, k_fill_i64<<<64, 256, 0, st>>>(bounds, 4 * S, 0));
+    LAUNCH(K_FINAL, k_fill_i64<<<1, 64, 0, st>>>(scount, 1, S));
+    LAUNCH(K_FINAL, k_seg_bounds<<<dim3(256, 2), 256, 0, st>>>(lo[cur], up[cur], locnt[cur],
+                                                               upcnt[cur], bounds, S));
+    LAUNCH(K_FINAL, k_hull_counts<<<(unsigned)((S + 255) / 256), 256, 0, st>>>(bounds, S, hcnt));
+    rc = run_scan(ctx, p, st, hcnt, scount, hoff);
+    if (rc) return rc;
+    LAUNCH(K_FINAL, k_hull_emit<<<dim3(256, 2), 256, 0, st>>>(lo[cur], up[cur], locnt[cur],
+                                                              upcnt[cur], bounds, S, hoff, hkeys,
+                                                              hpos, hull));
+    LAUNCH(K_LOOKUP, k_hull_lookup<<<2048, 256, 0, st>>>(idx, keys, cnt, S, hoff, hkeys, hpos, hull));
+    return HULL_OK;
+}
+
+// Learned proposal: per-set histogram -> network -> eight directions written
+// to the workspace's set_dirs table.
+static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                            const float *y, int64_t n_total, const int64_t *off, int64_t n1,
+                            int64_t S) {
+    (void)p; (void)st; (void)x; (void)y; (void)n_total; (void)off; (void)n1; (void)S;
+    if (!ctx->learned.loaded) return HULL_ENOMODEL;
+    return HULL_ENOMODEL;
+}
+
+static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p) {
+    HIPCHECK(hipSetDevice(ctx->device));
+    *p = make_plan(n, S);
+    int rc = ensure_ws(ctx, p->total, st);
+    if (rc) return rc;
+    int64_t *consts = W<int64_t>(ctx, p->consts);
+    LAUNCH(K_MISC, k_fill_i64<<<1, 64, 0, st>>>(consts, 1, (int64_t)RADIX * SORT_BLOCKS));
+    return HULL_OK;
+}
+
+// Full method for S sets (off == nullptr: one set of n1 points).
+static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const float *y,
+                       int64_t n_total, const int64_t *off, int64_t n1, int64_t S, int flags,
+                       uint32_t *hull, int64_t *hoff_out, int64_t *h_out) {
+    Plan p;
+    int rc = prepare(ctx, n_total, S, st, &p);
+    if (rc) return rc;
+    if (flags & HULL_VALIDATE) {
+        rc = run_validate(ctx, p, st, x, y, n_total, off, S);
+        if (rc) return rc;
+    }
+    const bool learned = (flags & HULL_LEARNED) && !(flags & HULL_NOFILTER);
+    if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
+    uint32_t *surv = W<uint32_t>(ctx, p.surv);
+    uint64_t *keys = W<uint64_t>(ctx, p.keys0);
+    int64_t *surv_off = W<int64_t>(ctx, p.surv_off);
+    int64_t *hoff = hoff_out ? hoff_out : W<int64_t>(ctx, p.hoff);
+    if (flags & HULL_NOFILTER) {
+        LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
+                                                         surv_off));
+    } else {
+        if ((rc = run_tilemap(ctx, p, st, off, n1, S))) return rc;
+        if (learned) {
+            rc = run_learned_dirs(ctx, p, st, x, y, n_total, off, n1, S);
+            if (rc) return rc;
+        }
+        if ((rc = run_extremes(ctx, p, st, x, y, n_total, off, n1, S, learned))) return rc;
+        if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, learned, nullptr, 0, nullptr, nullptr)))
+            return rc;
+        if ((rc = run_discard(ctx, p, st, x, y, n_total, off, n1, S,
+                              learned ? MAX_SLOTS : FIXED_SLOTS, surv, surv_off, keys)))
+            return rc;
+    }
+    rc = run_hull(ctx, p, st, surv, keys, surv_off + S, n_total, S, hoff, hull);
+    if (rc) return rc;
+    if (h_out) LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(hoff + S, h_out));
+    return HULL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *hull_strerror(int code) {
+    switch (code) {
+    case HULL_OK: return "ok";
+    case HULL_EINVAL: return "invalid argument (null pointer, size, preset or alignment)";
+    case HULL_ETOOBIG: return "too many points (indices are uint32)";
+    case HULL_ENOMEM: return "device workspace allocation failed";
+    case HULL_EHIP: return "HIP runtime error";
+    case HULL_EDOMAIN: return "coordinate outside the 2^-24 grid of [0,1) or bad offsets";
+    case HULL_ECAPTURE: return "workspace must grow but the stream is being captured";
+    case HULL_ENOMODEL: return "learned proposal requested without network weights";
+    default: return "unknown error";
+    }
+}
+
+int hull_last_hip_error(hull_ctx *ctx) { return ctx ? (int)ctx->last : 0; }
+
+int hull_create(hull_ctx **out, int device) {
+    if (!out) return HULL_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return HULL_EINVAL;
+    }
+    hull_ctx *ctx = new hull_ctx();
+    ctx->device = device;
+    ctx->dirs = preset_dirs(HULL_DIRS_PAPER);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return HULL_EHIP;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+        ctx->cus = cus;
+    *out = ctx;
+    return HULL_OK;
+}
+
+int hull_destroy(hull_ctx *ctx) {
+    if (!ctx) return HULL_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    learned_free(ctx->learned);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+    return HULL_OK;
+}
+
+int hull_set_directions(hull_ctx *ctx, int preset) {
+    if (!ctx || (preset != HULL_DIRS_PAPER && preset != HULL_DIRS_CUMULATIVE)) return HULL_EINVAL;
+    ctx->preset = preset;
+    ctx->dirs = preset_dirs(preset);
+    return HULL_OK;
+}
+
+int hull_direction_table(hull_ctx *ctx, int which, double *c, double *s, int cap) {
+    if (!c || !s) return HULL_EINVAL;
+    if (which == 0) {
+        Dirs d = preset_dirs(ctx ? ctx->preset : HULL_DIRS_PAPER);
+        if (cap < 4) return HULL_EINVAL;
+        for (int g = 0; g < 4; g++) { c[g] = d.gc[g]; s[g] = d.gs[g]; }
+        return 4;
+    }
+    if (which == 1) {
+        if (cap < NCAND) return HULL_EINVAL;
+        for (int k = 0; k < NCAND; k++) { c[k] = kCandCos[k]; s[k] = kCandSin[k]; }
+        return NCAND;
+    }
+    return HULL_EINVAL;
+}
+
+int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n, uint32_t *slots,
+                  double *vals, int flags, void *stream) {
+    if (!ctx || !slots) return HULL_EINVAL;
+    int rc = check_points(x, y, n);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
+    if (flags & HULL_VALIDATE && (rc = run_validate(ctx, p, st, x, y, n, nullptr, 1))) return rc;
+    const bool learned = flags & HULL_LEARNED;
+    if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
+    if ((rc = run_tilemap(ctx, p, st, nullptr, n, 1))) return rc;
+    if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n, nullptr, n, 1))) return rc;
+    if ((rc = run_extremes(ctx, p, st, x, y, n, nullptr, n, 1, learned))) return rc;
+    return run_polygon(ctx, p, st, x, y, n, 1, learned, nullptr, 0, slots, vals);
+}
+
+int hull_polygon(hull_ctx *ctx, const float *x, const float *y, int64_t n, const uint32_t *slots,
+                 int n_slots, uint32_t *verts, int32_t *m, void *stream) {
+    if (!ctx || !slots || !verts || !m || n_slots < 0 || n_slots > MAX_SLOTS) return HULL_EINVAL;
+    int rc = check_points(x, y, n);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
+    if ((rc = run_polygon(ctx, p, st, x, y, n, 1, false, slots, n_slots, nullptr, nullptr))) return rc;
+    LAUNCH(K_MISC, k_poly_out<<<1, 64, 0, st>>>(W<Poly>(ctx, p.polys), n_slots, verts, m));
+    return HULL_OK;
+}
+
+int hull_discard(hull_ctx *ctx, const float *x, const float *y, int64_t n, const uint32_t *slots,
+                 int n_slots, uint32_t *surv, int64_t *n_surv, void *stream) {
+    if (!ctx || !slots || !surv || !n_surv || n_slots < 0 || n_slots > MAX_SLOTS)
+        return HULL_EINVAL;
+    int rc = check_points(x, y, n);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, nullptr, n, 1))) return rc;
+    if ((rc = run_polygon(ctx, p, st, x, y, n, 1, false, slots, n_slots, nullptr, nullptr))) return rc;
+    int64_t *so = W<int64_t>(ctx, p.surv_off);
+    if ((rc = run_discard(ctx, p, st, x, y, n, nullptr, n, 1, n_slots, surv, so, nullptr)))
+        return rc;
+    LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(so + 1, n_surv));
+    return HULL_OK;
+}
+
+int hull_of_subset(hull_ctx *ctx, const float *x, const float *y, int64_t n, const uint32_t *idx,
+                   const int64_t *k_dev, int64_t k_cap, uint32_t *hull, int64_t *h, void *stream) {
+    if (!ctx || !idx || !k_dev || !hull || !h || k_cap < 0) return HULL_EINVAL;
+    int rc = check_points(x, y, n);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    if ((rc = prepare(ctx, k_cap, 1, st, &p))) return rc;
+    uint64_t *keys = W<uint64_t>(ctx, p.keys0);
+    LAUNCH(K_KEYS, k_gather_keys<<<1024, 256, 0, st>>>(x, y, n, idx, k_dev, keys));
+    int64_t *hoff = W<int64_t>(ctx, p.hoff);
+    if ((rc = run_hull(ctx, p, st, idx, keys, k_dev, k_cap, 1, hoff, hull))) return rc;
+    LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(hoff + 1, h));
+    return HULL_OK;
+}
+
+int hull_compute(hull_ctx *ctx, const float *x, const float *y, int64_t n, uint32_t *hull,
+                 int64_t *h, int flags, void *stream) {
+    if (!ctx || !hull || !h) return HULL_EINVAL;
+    int rc = check_points(x, y, n);
+    if (rc) return rc;
+    return run_compute(ctx, (hipStream_t)stream, x, y, n, nullptr, n, 1, flags, hull, nullptr, h);
+}
+
+static int check_batch(const float *x, const float *y, const int64_t *off, int64_t S,
+                       int64_t n_total) {
+    if (!off || S <= 0 || S > 65536) return HULL_EINVAL;
+    return check_points(x, y, n_total);
+}
+
+int hull_extremes_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                          int64_t S, int64_t n_total, uint32_t *slots, int flags, void *stream) {
+    if (!ctx || !slots) return HULL_EINVAL;
+    int rc = check_batch(x, y, offsets, S, n_total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    if ((rc = prepare(ctx, n_total, S, st, &p))) return rc;
+    if (flags & HULL_VALIDATE && (rc = run_validate(ctx, p, st, x, y, n_total, offsets, S)))
+        return rc;
+    const bool learned = flags & HULL_LEARNED;
+    if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
+    if ((rc = run_tilemap(ctx, p, st, offsets, 0, S))) return rc;
+    if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n_total, offsets, 0, S))) return rc;
+    if ((rc = run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, learned))) return rc;
+    return run_polygon(ctx, p, st, x, y, n_total, S, learned, nullptr, 0, slots, nullptr);
+}
+
+int hull_discard_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                         int64_t S, int64_t n_total, const uint32_t *slots, int n_slots,
+                         uint32_t *surv, int64_t *surv_offsets, void *stream) {
+    if (!ctx || !slots || !surv || !surv_offsets || n_slots < 0 || n_slots > MAX_SLOTS)
+        return HULL_EINVAL;
+    int rc = check_batch(x, y, offsets, S, n_total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    if ((rc = prepare(ctx, n_total, S, st, &p))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, offsets, 0, S))) return rc;
+    if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, false, slots, n_slots, nullptr, nullptr))) return rc;
+    return run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, n_slots, surv, surv_offsets,
+                       nullptr);
+}
+
+int hull_compute_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                         int64_t S, int64_t n_total, uint32_t *hull, int64_t *hull_offsets,
+                         int flags, void *stream) {
+    if (!ctx || !hull || !hull_offsets) return HULL_EINVAL;
+    int rc = check_batch(x, y, offsets, S, n_total);
+    if (rc) return rc;
+    return run_compute(ctx, (hipStream_t)stream, x, y, n_total, offsets, 0, S, flags, hull,
+                       hull_offsets, nullptr);
+}
+
+int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                       int64_t S, int64_t n_total, uint32_t *hull, int64_t *hull_offsets,
+                       int flags, void *stream) {
+    if (!ctx || !hull || !hull_offsets) return HULL_EINVAL;
+    if (flags & HULL_VALIDATE) return HULL_EINVAL;   // validation synchronises
+    int rc = check_batch(x, y, offsets, S, n_total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    Plan p = make_plan(n_total, S);
+    if ((rc = ensure_ws(ctx, p.total, st))) return rc;
+    hipStream_t cs;
+    HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool was_timing = ctx->timing;
+    ctx->timing = false;
+    if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        ctx->timing = was_timing;
+        (void)hipStreamDestroy(cs);
+        ctx->last = e;
+        return HULL_EHIP;
+    }
+    rc = run_compute(ctx, cs, x, y, n_total, offsets, 0, S, flags, hull, hull_offsets, nullptr);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    ctx->timing = was_timing;
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) { ctx->last = e; return HULL_EHIP; }
+    ctx->graph = g;
+    HIPCHECK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    return HULL_OK;
+}
+
+int hull_graph_launch(hull_ctx *ctx, void *stream) {
+    if (!ctx || !ctx->gexec) return HULL_EINVAL;
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipGraphLaunch(ctx->gexec, (hipStream_t)stream));
+    return HULL_OK;
+}
+
+int hull_tuning(hull_ctx *ctx, int get, int *k1, int *k3) {
+    if (!ctx || !k1 || !k3) return HULL_EINVAL;
+    if (get) {
+        *k1 = ctx->k1_bpc;
+        *k3 = ctx->k3_bpc;
+        return HULL_OK;
+    }
+    if (*k1 < 1 || *k1 > 64 || *k3 < 1 || *k3 > 64) return HULL_EINVAL;
+    ctx->k1_bpc = *k1;
+    ctx->k3_bpc = *k3;
+    return HULL_OK;
+}
+
+int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                  int64_t S, int64_t n_total, void *stream) {
+    if (!ctx) return HULL_EINVAL;
+    const bool batched = offsets != nullptr;
+    if (batched) {
+        int rc = check_batch(x, y, offsets, S, n_total);
+        if (rc) return rc;
+    } else {
+        int rc = check_points(x, y, n_total);
+        if (rc) return rc;
+        S = 1;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    int rc = prepare(ctx, n_total, S, st, &p);
+    if (rc) return rc;
+    const int64_t n1 = batched ? 0 : n_total;
+    if ((rc = run_tilemap(ctx, p, st, offsets, n1, S))) return rc;
+    const bool was_timing = ctx->timing;
+    ctx->timing = false;
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    const int cand[] = {2, 4, 6, 8, 12, 16};
+    float best1 = 1e30f, best3 = 1e30f;
+    int b1 = ctx->k1_bpc, b3 = ctx->k3_bpc;
+    uint32_t *surv = W<uint32_t>(ctx, p.surv);
+    int64_t *so = W<int64_t>(ctx, p.surv_off);
+    for (int c : cand) {
+        ctx->k1_bpc = c;
+        ctx->k3_bpc = c;
+        float t1 = 0, t3 = 0;
+        for (int rep = 0; rep < 3; rep++) {
+            HIPCHECK(hipEventRecord(a, st));
+            if ((rc = run_extremes(ctx, p, st, x, y, n_total, offsets, n1, S, false))) break;
+            HIPCHECK(hipEventRecord(b, st));
+            HIPCHECK(hipEventSynchronize(b));
+            float ms = 0;
+            HIPCHECK(hipEventElapsedTime(&ms, a, b));
+            if (rep) t1 += ms;
+            if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr))) break;
+            HIPCHECK(hipEventRecord(a, st));
+            if ((rc = run_discard(ctx, p, st, x, y, n_total, offsets, n1, S, FIXED_SLOTS, surv, so,
+                                  nullptr)))
+                break;
+            HIPCHECK(hipEventRecord(b, st));
+            HIPCHECK(hipEventSynchronize(b));
+            HIPCHECK(hipEventElapsedTime(&ms, a, b));
+            if (rep) t3 += ms;
+        }
+        if (rc) break;
+        if (t1 < best1) { best1 = t1; b1 = c; }
+        if (t3 < best3) { best3 = t3; b3 = c; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx->timing = was_timing;
+    ctx->k1_bpc = b1;
+    ctx->k3_bpc = b3;
+    return rc;
+}
+
+int hull_timing_enable(hull_ctx *ctx, int on) {
+    if (!ctx) return HULL_EINVAL;
+    HIPCHECK(hipSetDevice(ctx->device));
+    if (on && ctx->ev_pool.empty()) {
+        ctx->ev_pool.resize(8192);
+        for (auto &e : ctx->ev_pool) HIPCHECK(hipEventCreate(&e));
+    }
+    ctx->timing = on != 0;
+    return HULL_OK;
+}
+
+static int drain_events(hull_ctx *ctx) {
+    for (auto &pe : ctx->ev_pending) {
+        HIPCHECK(hipEventSynchronize(ctx->ev_pool[pe.second + 1]));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_pool[pe.second], ctx->ev_pool[pe.second + 1]));
+        ctx->ms[pe.first] += ms;
+        ctx->launches[pe.first] += 1;
+    }
+    ctx->ev_pending.clear();
+    ctx->ev_used = 0;
+    return HULL_OK;
+}
+
+int hull_timing_read(hull_ctx *ctx, double *ms, int64_t *launches, int cap) {
+    if (!ctx || !ms || !launches) return HULL_EINVAL;
+    int rc = drain_events(ctx);
+    if (rc) return rc;
+    int n = std::min(cap, (int)K_NKINDS);
+    for (int k = 0; k < n; k++) {
+        ms[k] = ctx->ms[k];
+        launches[k] = ctx->launches[k];
+    }
+    return n;
+}
+
+const char *hull_timing_name(int kind) {
+    return (kind >= 0 && kind < K_NKINDS) ? kKindNames[kind] : "";
+}
+
+int hull_timing_reset(hull_ctx *ctx) {
+    if (!ctx) return HULL_EINVAL;
+    int rc = drain_events(ctx);
+    for (int k = 0; k < K_NKINDS; k++) {
+        ctx->ms[k] = 0;
+        ctx->launches[k] = 0;
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,798 @@
+// Filter passes: tile map, Step 1 (directional extremes, one fused pass),
+// Step 2 (filter polygon + quick-accept rows), Step 3 (strict-inside test with
+// survivor masks), survivor scatter, and the shared scan kernels.
+//
+// Work decomposition.  Set s covers points [o_s, o_{s+1}).  Its tiles start
+// at A_s = o_s rounded down to a multiple of 4 (so every float4 load is
+// 16-byte aligned) and cover TILE = 1024 point slots each; slots outside
+// [o_s, o_{s+1}) are masked.  The persistent filter kernels give wave w the
+// contiguous tile range [w q, (w+1) q), q = ceil(T / W), so a wave walks
+// ascending point indices and meets each set as one contiguous "run".
+#include "hg_device.h"
+
+namespace hg {
+
+// ---------------------------------------------------------------------------
+// Tile map: tile_off[s] = first tile of set s (exclusive scan of tile
+// counts), tile_off[S] = T.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_tile_offsets(const int64_t *__restrict__ off,
+                                                       int64_t n1, int64_t S, int64_t unit,
+                                                       int align4, int64_t *__restrict__ tile_off) {
+    __shared__ int64_t sh[17];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < S; base += blockDim.x) {
+        int64_t s = base + threadIdx.x;
+        int64_t cnt = 0;
+        if (s < S) {
+            int64_t b = set_begin(off, s), e = set_end(off, n1, s);
+            if (e > b) {
+                int64_t a = align4 ? (b & ~int64_t(3)) : b;
+                cnt = (e - a + unit - 1) / unit;
+            }
+        }
+        int64_t tot;
+        int64_t ex = block_excl_scan_i64(cnt, sh, &tot);
+        if (s < S) tile_off[s] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) tile_off[S] = carry;
+}
+
+// tile_set[t] = s for every tile of set s.  One block per set.
+__global__ __launch_bounds__(256) void k_tile_sets(const int64_t *__restrict__ tile_off,
+                                                   int32_t *__restrict__ tile_set) {
+    int64_t s = blockIdx.x;
+    int64_t a = tile_off[s], b = tile_off[s + 1];
+    for (int64_t t = a + threadIdx.x; t < b; t += blockDim.x) tile_set[t] = (int32_t)s;
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of uint32 counts into int64 offsets, with the
+// element count read from device memory (*cnt_ptr).  out has count+1 entries;
+// out[count] = total.  Three launches with a fixed grid of SCAN_BLOCKS.
+constexpr int SCAN_BLOCKS = 256;
+constexpr int SCAN_THREADS = 1024;
+
+__device__ __forceinline__ void scan_segment(int64_t count, int64_t b, int64_t *lo, int64_t *hi) {
+    int64_t seg = (count + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    seg = (seg + SCAN_THREADS - 1) / SCAN_THREADS * SCAN_THREADS;
+    *lo = b * seg;
+    *hi = min(count, *lo + seg);
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
+                                                              const int64_t *__restrict__ cnt_ptr,
+                                                              int64_t *__restrict__ block_sums) {
+    __shared__ int64_t sh[17];
+    int64_t count = *cnt_ptr, lo, hi;
+    scan_segment(count, blockIdx.x, &lo, &hi);
+    int64_t acc = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += in[i];
+    int64_t tot;
+    block_excl_scan_i64(acc, sh, &tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_blocks(int64_t *__restrict__ block_sums,
+                                                              const int64_t *__restrict__ cnt_ptr,
+                                                              int64_t *__restrict__ out) {
+    __shared__ int64_t sh[17];
+    int64_t v = threadIdx.x < SCAN_BLOCKS ? block_sums[threadIdx.x] : 0;
+    int64_t tot;
+    int64_t ex = block_excl_scan_i64(v, sh, &tot);
+    if (threadIdx.x < SCAN_BLOCKS) block_sums[threadIdx.x] = ex;
+    if (threadIdx.x == 0) out[*cnt_ptr] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const uint32_t *__restrict__ in,
+                                                            const int64_t *__restrict__ cnt_ptr,
+                                                            const int64_t *__restrict__ block_sums,
+                                                            int64_t *__restrict__ out) {
+    __shared__ int64_t sh[17];
+    int64_t count = *cnt_ptr, lo, hi;
+    scan_segment(count, blockIdx.x, &lo, &hi);
+    int64_t carry = block_sums[blockIdx.x];
+    for (int64_t base = lo; base < hi; base += blockDim.x) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = i < hi ? in[i] : 0;
+        int64_t tot;
+        int64_t ex = block_excl_scan_i64(v, sh, &tot);
+        if (i < hi) out[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Point loads: float4 of x and y for 4 consecutive points starting at the
+// 4-aligned global index a; slots at or beyond n_total read as 0.
+__device__ __forceinline__ void load4(const float *__restrict__ x, const float *__restrict__ y,
+                                      int64_t a, int64_t n_total, float xv[4], float yv[4]) {
+    if (a + 4 <= n_total) {
+        float4 fx = *reinterpret_cast<const float4 *>(x + a);
+        float4 fy = *reinterpret_cast<const float4 *>(y + a);
+        xv[0] = fx.x; xv[1] = fx.y; xv[2] = fx.z; xv[3] = fx.w;
+        yv[0] = fy.x; yv[1] = fy.y; yv[2] = fy.z; yv[3] = fy.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            bool in = a + j < n_total;
+            xv[j] = in ? x[a + j] : 0.0f;
+            yv[j] = in ? y[a + j] : 0.0f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 projections.  Slot k of the fixed sixteen is stored as a maximum:
+// even slots (argmin u, argmin v) use the negated coordinate, which is exact
+// and keeps the same ties.  PRESET 0: angles 0/30/45/60 with shared products
+// (sin30 = cos60 = 1/2, sin60 = cos30, sin45 = cos45); PRESET 1: 0/30/75/120,
+// where u(120) = -v(30) and v(120) = u(30) bit for bit, so slots 12..15 are
+// copied from 7, 6, 4, 5 when the polygon is built; PRESET 2: any four
+// rotation groups from Dirs.
+constexpr double C30 = 0x1.bb67ae8584caap-1;
+constexpr double C45 = 0x1.6a09e667f3bcdp-1;
+constexpr double C75 = 0x1.0907dc1930690p-2;
+constexpr double S75 = 0x1.ee8dd4748bf15p-1;
+
+template <int PRESET>
+struct Proj {
+    static constexpr int NG = PRESET == 1 ? 3 : 4;   // groups actually evaluated
+    // u[g], v[g] of one point (binary64, each product rounded, then the sum)
+    __device__ __forceinline__ static void uv(const Dirs &d, double xd, double yd, double u[4],
+                                              double v[4]) {
+#pragma clang fp contract(off)
+        u[0] = xd;
+        v[0] = yd;
+        if (PRESET == 0) {
+            double c30x = C30 * xd, c30y = C30 * yd, hx = 0.5 * xd, hy = 0.5 * yd;
+            double c45x = C45 * xd, c45y = C45 * yd;
+            u[1] = c30x - hy;
+            v[1] = hx + c30y;
+            u[2] = c45x - c45y;
+            v[2] = c45x + c45y;
+            u[3] = hx - c30y;
+            v[3] = c30x + hy;
+        } else if (PRESET == 1) {
+            double c30x = C30 * xd, c30y = C30 * yd, hx = 0.5 * xd, hy = 0.5 * yd;
+            u[1] = c30x - hy;
+            v[1] = hx + c30y;
+            u[2] = C75 * xd - S75 * yd;
+            v[2] = S75 * xd + C75 * yd;
+            u[3] = 0.0;
+            v[3] = 0.0;
+        } else {
+#pragma unroll
+            for (int g = 1; g < 4; g++) {
+                u[g] = d.gc[g] * xd - d.gs[g] * yd;
+                v[g] = d.gs[g] * xd + d.gc[g] * yd;
+            }
+            u[0] = d.gc[0] * xd - d.gs[0] * yd;
+            v[0] = d.gs[0] * xd + d.gc[0] * yd;
+        }
+    }
+};
+
+// Directional projection for a learned direction: c*x + s*y.
+__device__ __forceinline__ double proj_dir(double c, double s, double xd, double yd) {
+#pragma clang fp contract(off)
+    return c * xd + s * yd;
+}
+
+// key of fixed slot k (0..15) as a maximum
+__device__ __forceinline__ double slot_key(int k, const double u[4], const double v[4]) {
+    int g = k >> 2, t = k & 3;
+    double w = (t < 2) ? u[g] : v[g];
+    return (t & 1) ? w : -w;
+}
+
+// Step 1: per-wave running maxima of every slot key over the wave's tiles,
+// with the lowest index on ties; one partial per (wave, set) run, stored at
+// the run's first tile.  Learned directions (NDIR > 0) come per set from
+// set_dirs[s][d] = (c, s).
+template <int PRESET, int NDIR>
+__global__ __launch_bounds__(256) void k_extremes(
+    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
+    const int64_t *__restrict__ off, int64_t n1, int64_t S,
+    const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set, Dirs dirs,
+    const double *__restrict__ set_dirs, double *__restrict__ pval, uint32_t *__restrict__ pidx) {
+    constexpr int NG = Proj<PRESET>::NG;
+    constexpr int NF = 4 * NG;           // fixed slots evaluated
+    constexpr int NS = NF + NDIR;        // slots tracked
+    const int lane = lane_id();
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    const int64_t T = tile_off[S];
+    const int64_t q = (T + W - 1) / W;
+    const int64_t t0 = wave * q, t1 = min(t0 + q, T);
+    if (t0 >= t1) return;
+
+    double bv[NS];
+    uint32_t bi[NS];
+    double dc[NDIR > 0 ? NDIR : 1], ds[NDIR > 0 ? NDIR : 1];
+    int64_t cur = -1, run = t0, o0 = 0, o1 = 0, tile0 = 0, abase = 0;
+
+    auto flush = [&]() {
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                pval[run * MAX_SLOTS + k] = bv[k];
+                pidx[run * MAX_SLOTS + k] = bi[k];
+            }
+        }
+    };
+
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t s = tile_set[t];
+        if (s != cur) {
+            if (cur >= 0) flush();
+            cur = s;
+            run = t;
+            o0 = set_begin(off, s);
+            o1 = set_end(off, n1, s);
+            tile0 = tile_off[s];
+            abase = o0 & ~int64_t(3);
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                bv[k] = -INFINITY;
+                bi[k] = NONE;
+            }
+#pragma unroll
+            for (int d = 0; d < NDIR; d++) {
+                dc[d] = set_dirs[(s * MAX_DIRS + d) * 2 + 0];
+                ds[d] = set_dirs[(s * MAX_DIRS + d) * 2 + 1];
+            }
+        }
+        const int64_t tb = abase + (t - tile0) * TILE;
+#pragma unroll 1
+        for (int c = 0; c < TILE_CHUNKS; c++) {
+            const int64_t cb = tb + c * CHUNK;          // global index of lane 0, item 0
+            const int64_t a = cb + 4 * lane;
+            float xv[4], yv[4];
+            load4(x, y, a, n_total, xv, yv);
+            bool valid[4];
+            double acc[NS];
+#pragma unroll
+            for (int k = 0; k < NS; k++) acc[k] = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                valid[j] = (a + j >= o0) && (a + j < o1);
+                double xd = xv[j], yd = yv[j];
+                double u[4], v[4];
+                Proj<PRESET>::uv(dirs, xd, yd, u, v);
+#pragma unroll
+                for (int k = 0; k < NF; k++)
+                    acc[k] = valid[j] ? fmax(acc[k], slot_key(k, u, v)) : acc[k];
+#pragma unroll
+                for (int d = 0; d < NDIR; d++)
+                    acc[NF + d] = valid[j] ? fmax(acc[NF + d], proj_dir(dc[d], ds[d], xd, yd))
+                                           : acc[NF + d];
+            }
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                if (__ballot(acc[k] > bv[k])) {
+                    // rare: a new maximum in this chunk; take the lowest index
+                    double m = wave_max(acc[k]);
+                    int cand = 4;
+#pragma unroll
+                    for (int j = 3; j >= 0; j--) {
+                        double xd = xv[j], yd = yv[j], key;
+                        if (k < NF) {
+                            double u[4], v[4];
+                            Proj<PRESET>::uv(dirs, xd, yd, u, v);
+                            key = slot_key(k, u, v);
+                        } else {
+                            key = proj_dir(dc[k - NF], ds[k - NF], xd, yd);
+                        }
+                        if (valid[j] && key == m) cand = j;
+                    }
+                    uint64_t has = __ballot(cand < 4);
+                    int L = __ffsll((unsigned long long)has) - 1;
+                    int cj = __builtin_amdgcn_readlane(cand, L);
+                    bv[k] = m;
+                    bi[k] = (uint32_t)(cb + 4 * L + cj);
+                }
+            }
+        }
+    }
+    flush();
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: one block per set.  Reduce the runs' partials (or take the
+// caller's slots), build the convex polygon of the slot points with Andrew's
+// monotone chain (collinear points dropped, repeated coordinates by lowest
+// index), and derive the edge functions and quick-accept rows.
+
+struct SlotBest {
+    double v;
+    uint32_t i;
+};
+
+__device__ __forceinline__ bool better(double v, uint32_t i, double bv, uint32_t bi) {
+    return v > bv || (v == bv && i < bi);
+}
+
+__device__ __forceinline__ double grid_of(float f) { return (double)f * GRIDD; }
+
+// Exact edge function of (ex, ey, c) at grid point (px, py).
+__device__ __forceinline__ double edge_eval(double ex, double ey, double c, double px, double py) {
+    return fma(ex, py, fma(-ey, px, c));
+}
+
+template <int NDIR>
+__global__ __launch_bounds__(256) void k_polygon(
+    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int64_t S,
+    int preset,
+    const int64_t *__restrict__ tile_off, int64_t W1, const double *__restrict__ pval,
+    const uint32_t *__restrict__ pidx, const uint32_t *__restrict__ slots_in, int n_in, Dirs dirs,
+    const double *__restrict__ set_dirs, uint32_t *__restrict__ slots_out,
+    double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans) {
+    constexpr int NS = FIXED_SLOTS + NDIR;
+    __shared__ SlotBest wbest[4][MAX_SLOTS];
+    __shared__ uint32_t sl[MAX_SLOTS];
+    __shared__ Poly P;
+    const int64_t s = blockIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const int nev = preset == 1 ? 12 : 16;    // fixed slots the extremes pass evaluated
+
+    if (slots_in) {
+        if (tid < MAX_SLOTS) {
+            uint32_t i = tid < n_in ? slots_in[s * n_in + tid] : NONE;
+            sl[tid] = (int64_t)i < n_total ? i : NONE;    // out-of-range slots are ignored
+        }
+    } else {
+        const int64_t T = tile_off[S];
+        const int64_t q = (T + W1 - 1) / W1;
+        const int64_t ta = tile_off[s], tb = tile_off[s + 1];
+        int64_t nruns = 0, m0 = 0;
+        if (tb > ta) {
+            m0 = (ta / q + 1) * q;
+            nruns = 1 + (m0 < tb ? (tb - 1 - m0) / q + 1 : 0);
+        }
+        double bv[MAX_SLOTS];
+        uint32_t bi[MAX_SLOTS];
+        for (int k = 0; k < MAX_SLOTS; k++) {
+            bv[k] = -INFINITY;
+            bi[k] = NONE;
+        }
+        const int NE = nev + NDIR;
+        for (int64_t r = tid; r < nruns; r += blockDim.x) {
+            int64_t t = r == 0 ? ta : m0 + (r - 1) * q;
+            for (int k = 0; k < NE; k++) {
+                double v = pval[t * MAX_SLOTS + k];
+                uint32_t i = pidx[t * MAX_SLOTS + k];
+                if (i != NONE && better(v, i, bv[k], bi[k])) {
+                    bv[k] = v;
+                    bi[k] = i;
+                }
+            }
+        }
+        for (int k = 0; k < NE; k++) {
+            double v = bv[k];
+            uint32_t i = bi[k];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                double v2 = __shfl_xor(v, o);
+                uint32_t i2 = __shfl_xor(i, o);
+                if (i2 != NONE && (i == NONE || better(v2, i2, v, i))) {
+                    v = v2;
+                    i = i2;
+                }
+            }
+            if (lane == 0) wbest[w][k] = SlotBest{v, i};
+        }
+        __syncthreads();
+        if (tid < NE) {
+            double v = wbest[0][tid].v;
+            uint32_t i = wbest[0][tid].i;
+            for (int ww = 1; ww < (int)(blockDim.x >> 6); ww++) {
+                SlotBest b = wbest[ww][tid];
+                if (b.i != NONE && (i == NONE || better(b.v, b.i, v, i))) {
+                    v = b.v;
+                    i = b.i;
+                }
+            }
+            // partial slot k < nev holds fixed slot k; learned slots follow
+            int dst = tid < nev ? tid : FIXED_SLOTS + (tid - nev);
+            sl[dst] = i;
+        }
+        __syncthreads();
+        if (tid == 0 && preset == 1) {   // 120-degree group repeats the 30-degree one
+            sl[12] = sl[7];
+            sl[13] = sl[6];
+            sl[14] = sl[4];
+            sl[15] = sl[5];
+        }
+        if (tid < MAX_SLOTS && tid >= NS) sl[tid] = NONE;
+    }
+    __syncthreads();
+
+    // slots and their values (recomputed from the winning index)
+    if (slots_out && tid < NS && !slots_in) slots_out[s * NS + tid] = sl[tid];
+    if (vals_out && tid < NS && !slots_in) {
+        uint32_t i = sl[tid];
+        double val = NAN;
+        if (i != NONE) {
+            double xd = x[i], yd = y[i];
+            if (tid < FIXED_SLOTS) {
+                int g = tid >> 2, t = tid & 3;
+                double c = dirs.gc[g], sn = dirs.gs[g];
+                val = t < 2 ? c * xd - sn * yd : sn * xd + c * yd;
+            } else {
+                int d = tid - FIXED_SLOTS;
+                val = set_dirs[(s * MAX_DIRS + d) * 2] * xd + set_dirs[(s * MAX_DIRS + d) * 2 + 1] * yd;
+            }
+        }
+        vals_out[s * NS + tid] = val;
+    }
+
+    // polygon by Andrew's monotone chain (thread 0; at most 24 points)
+    if (tid == 0) {
+        double px[MAX_SLOTS], py[MAX_SLOTS];
+        uint32_t pi[MAX_SLOTS];
+        int k = 0;
+        for (int j = 0; j < MAX_SLOTS; j++) {
+            uint32_t i = sl[j];
+            if (i == NONE) continue;
+            double gx = grid_of(x[i]), gy = grid_of(y[i]);
+            // insertion by (x, y, index)
+            int p = k++;
+            while (p > 0 && (px[p - 1] > gx || (px[p - 1] == gx && (py[p - 1] > gy ||
+                                                (py[p - 1] == gy && pi[p - 1] > i))))) {
+                px[p] = px[p - 1];
+                py[p] = py[p - 1];
+                pi[p] = pi[p - 1];
+                p--;
+            }
+            px[p] = gx;
+            py[p] = gy;
+            pi[p] = i;
+        }
+        int u = 0;
+        for (int j = 0; j < k; j++)
+            if (u == 0 || px[j] != px[u - 1] || py[j] != py[u - 1]) {
+                px[u] = px[j];
+                py[u] = py[j];
+                pi[u] = pi[j];
+                u++;
+            }
+        int st[2 * MAX_SLOTS + 2];
+        int h = 0;
+        if (u == 1) {
+            st[0] = 0;
+            h = 1;
+        } else if (u >= 2) {
+            for (int j = 0; j < u; j++) {
+                while (h >= 2 && orient(px[st[h - 2]], py[st[h - 2]], px[st[h - 1]], py[st[h - 1]],
+                                        px[j], py[j]) <= 0)
+                    h--;
+                st[h++] = j;
+            }
+            int lo = h + 1;
+            for (int j = u - 2; j >= 0; j--) {
+                while (h >= lo && orient(px[st[h - 2]], py[st[h - 2]], px[st[h - 1]], py[st[h - 1]],
+                                         px[j], py[j]) <= 0)
+                    h--;
+                st[h++] = j;
+            }
+            h--;
+        }
+        P.m = h;
+        int ylo = 0x7fffffff, yhi = -1;
+        for (int e = 0; e < MAX_SLOTS; e++) {
+            P.verts[e] = e < h ? pi[st[e]] : NONE;
+            if (e < h && h >= 3) {
+                int a = st[e], b = st[(e + 1) % h];
+                double ex = px[b] - px[a], ey = py[b] - py[a];
+                P.ex[e] = ex;
+                P.ey[e] = ey;
+                P.c[e] = fma(ey, px[a], -(ex * py[a]));
+                ylo = min(ylo, (int)py[a]);
+                yhi = max(yhi, (int)py[a]);
+            } else {
+                P.ex[e] = 0.0;
+                P.ey[e] = 0.0;
+                P.c[e] = 1.0;
+            }
+        }
+        if (h < 3) {
+            P.c[0] = -1.0;    // nothing strictly inside
+            P.yspan = -1;
+            P.ky_lo = 0;
+            P.shift = 0;
+        } else {
+            P.ky_lo = ylo;
+            P.yspan = yhi - ylo;
+            int sh = 0;
+            while (((yhi - ylo) >> sh) >= SPAN_ROWS) sh++;
+            P.shift = sh;
+        }
+    }
+    __syncthreads();
+
+    // quick-accept rows: candidate span from the edges at the band's ends,
+    // shrunk to integers, kept only if its four corners are strictly inside
+    for (int r = tid; r < SPAN_ROWS; r += blockDim.x) {
+        Span sp{1, 0};
+        if (P.yspan >= 0) {
+            int64_t y0 = (int64_t)P.ky_lo + ((int64_t)r << P.shift);
+            int64_t y1 = min(y0 + (int64_t(1) << P.shift) - 1, (int64_t)P.ky_lo + P.yspan);
+            if (y0 <= (int64_t)P.ky_lo + P.yspan) {
+                double xl = -1e300, xr = 1e300;
+                bool ok = true;
+                for (int e = 0; e < P.m; e++) {
+                    double ex = P.ex[e], ey = P.ey[e];
+                    uint32_t ia = P.verts[e];   // edge e runs from vertex e to e+1
+                    double ax = grid_of(x[ia]), ay = grid_of(y[ia]);
+                    if (ey > 0) {
+                        xr = fmin(xr, fmin(ax + ex * ((double)y0 - ay) / ey,
+                                           ax + ex * ((double)y1 - ay) / ey));
+                    } else if (ey < 0) {
+                        xl = fmax(xl, fmax(ax + ex * ((double)y0 - ay) / ey,
+                                           ax + ex * ((double)y1 - ay) / ey));
+                    } else if (ex > 0) {
+                        if ((double)y0 <= ay) ok = false;      // bottom edge
+                    } else if (ex < 0) {
+                        if ((double)y1 >= ay) ok = false;      // top edge
+                    }
+                }
+                if (ok && xl > -1e299 && xr < 1e299) {
+                    double fl = floor(xl) + 1.0, fr = ceil(xr) - 1.0;
+                    for (int attempt = 0; attempt < 3 && fl <= fr; attempt++) {
+                        bool good = true;
+                        double cx[2] = {fl, fr}, cy[2] = {(double)y0, (double)y1};
+                        for (int e = 0; e < P.m && good; e++)
+                            for (int a = 0; a < 2; a++)
+                                for (int b = 0; b < 2; b++)
+                                    if (!(edge_eval(P.ex[e], P.ey[e], P.c[e], cx[a], cy[b]) > 0))
+                                        good = false;
+                        if (good) {
+                            sp.xl = (int32_t)fl;
+                            sp.xr = (int32_t)fr;
+                            break;
+                        }
+                        fl += 2.0;
+                        fr -= 2.0;
+                    }
+                }
+            }
+        }
+        spans[s * SPAN_ROWS + r] = sp;
+    }
+    if (tid == 0) polys[s] = P;
+}
+
+// ---------------------------------------------------------------------------
+// Step 3: strict-inside test.  Quick path: grid row lookup in the wave's LDS
+// copy of the quick-accept rows.  Points it cannot accept go to a per-wave
+// queue and are tested exactly against every edge in full 64-lane batches.
+// Output per tile: survivor mask words (word 4c + j, bit l = point
+// c*256 + 4l + j of the tile) and the survivor count.
+constexpr int QCAP = 320;
+
+struct DiscardLds {
+    Span spans[SPAN_ROWS];
+    uint64_t q[QCAP];                 // kx | ky << 24 | pos << 48
+    unsigned long long mask[TILE_WORDS];
+};
+
+template <int NEDGE>
+__device__ __forceinline__ void drain(DiscardLds &L, int from, int count, const Poly *__restrict__ P) {
+    const int lane = lane_id();
+    if (lane < count) {
+        uint64_t e = L.q[from + lane];
+        double px = (double)(int32_t)(e & 0xFFFFFF);
+        double py = (double)(int32_t)((e >> 24) & 0xFFFFFF);
+        int pos = (int)(e >> 48);
+        bool inside = true;
+#pragma unroll
+        for (int k = 0; k < NEDGE; k++)
+            inside = inside && (edge_eval(P->ex[k], P->ey[k], P->c[k], px, py) > 0);
+        if (!inside) {
+            int c = pos >> 8, l = (pos >> 2) & 63, j = pos & 3;
+            atomicOr(&L.mask[c * 4 + j], 1ull << l);
+        }
+    }
+}
+
+template <int NEDGE>
+__global__ __launch_bounds__(256) void k_discard(
+    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
+    const int64_t *__restrict__ off, int64_t n1, int64_t S, const int64_t *__restrict__ tile_off,
+    const int32_t *__restrict__ tile_set, const Poly *__restrict__ polys,
+    const Span *__restrict__ spans, uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt) {
+    __shared__ DiscardLds lds[4];
+    DiscardLds &L = lds[threadIdx.x >> 6];
+    const int lane = lane_id();
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    const int64_t T = tile_off[S];
+    const int64_t q = (T + W - 1) / W;
+    const int64_t t0 = wave * q, t1 = min(t0 + q, T);
+    if (t0 >= t1) return;
+
+    int64_t cur = -1, o0 = 0, o1 = 0, tile0 = 0, abase = 0;
+    int32_t ky_lo = 0, shift = 0;
+    uint32_t yspan = 0;
+    bool has_rows = false;
+    const Poly *P = polys;
+
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t s = tile_set[t];
+        if (s != cur) {
+            cur = s;
+            o0 = set_begin(off, s);
+            o1 = set_end(off, n1, s);
+            tile0 = tile_off[s];
+            abase = o0 & ~int64_t(3);
+            P = polys + s;
+            ky_lo = P->ky_lo;
+            has_rows = P->yspan >= 0;
+            yspan = (uint32_t)max(P->yspan, 0);
+            shift = P->shift;
+            wave_sync();
+            for (int r = lane; r < SPAN_ROWS; r += WAVE) L.spans[r] = spans[s * SPAN_ROWS + r];
+            wave_sync();
+        }
+        if (lane < TILE_WORDS) L.mask[lane] = 0;
+        int qn = 0;
+        const int64_t tb = abase + (t - tile0) * TILE;
+#pragma unroll 1
+        for (int c = 0; c < TILE_CHUNKS; c++) {
+            const int64_t a = tb + c * CHUNK + 4 * lane;
+            float xv[4], yv[4];
+            load4(x, y, a, n_total, xv, yv);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                bool valid = (a + j >= o0) && (a + j < o1);
+                int32_t kx = (int32_t)(xv[j] * GRIDF), ky = (int32_t)(yv[j] * GRIDF);
+                uint32_t dy = (uint32_t)(ky - ky_lo);
+                uint32_t row = min(dy >> shift, (uint32_t)(SPAN_ROWS - 1));
+                Span sp = L.spans[row];
+                bool quick = has_rows && dy <= yspan && kx >= sp.xl && kx <= sp.xr;
+                bool slow = valid && !quick;
+                uint64_t bal = __ballot(slow);
+                if (slow) {
+                    int p = qn + __popcll(bal & lanemask_lt());
+                    L.q[p] = (uint64_t)((uint32_t)kx & 0xFFFFFFu) |
+                             ((uint64_t)((uint32_t)ky & 0xFFFFFFu) << 24) |
+                             ((uint64_t)(c * CHUNK + 4 * lane + j) << 48);
+                }
+                qn += __popcll(bal);
+            }
+            wave_sync();
+            while (qn >= WAVE) {
+                qn -= WAVE;
+                drain<NEDGE>(L, qn, WAVE, P);
+            }
+            wave_sync();
+        }
+        if (qn > 0) drain<NEDGE>(L, 0, qn, P);
+        wave_sync();
+        uint64_t mw = lane < TILE_WORDS ? L.mask[lane] : 0;
+        int64_t cnt = wave_sum_i64(__popcll(mw));
+        if (cnt > 0 && lane < TILE_WORDS) masks[t * TILE_WORDS + lane] = mw;
+        if (lane == 0) tile_cnt[t] = (uint32_t)cnt;
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Survivor scatter: tile t's survivors go to positions tile_pos[t]... in
+// ascending index order.  keys (optional): set << 48 | kx << 24 | ky.
+__global__ __launch_bounds__(256) void k_scatter(
+    const float *__restrict__ x, const float *__restrict__ y, const int64_t *__restrict__ off,
+    int64_t S, const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set,
+    const uint64_t *__restrict__ masks, const uint32_t *__restrict__ tile_cnt,
+    const int64_t *__restrict__ tile_pos, uint32_t *__restrict__ surv, uint64_t *__restrict__ keys) {
+    const int lane = lane_id();
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    const int64_t T = tile_off[S];
+    const uint64_t lt = lanemask_lt();
+    for (int64_t t = wave; t < T; t += W) {
+        if (tile_cnt[t] == 0) continue;
+        const int64_t s = tile_set[t];
+        const int64_t o0 = set_begin(off, s);
+        const int64_t tb = (o0 & ~int64_t(3)) + (t - tile_off[s]) * TILE;
+        int64_t base = tile_pos[t];
+        for (int c = 0; c < TILE_CHUNKS; c++) {
+            uint64_t M[4];
+            int pre = 0, tot = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                M[j] = masks[t * TILE_WORDS + c * 4 + j];
+                pre += __popcll(M[j] & lt);
+                tot += __popcll(M[j]);
+            }
+            int k = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if ((M[j] >> lane) & 1) {
+                    int64_t gi = tb + c * CHUNK + 4 * lane + j;
+                    int64_t p = base + pre + k;
+                    surv[p] = (uint32_t)gi;
+                    if (keys) {
+                        uint64_t kx = (uint64_t)(uint32_t)(x[gi] * GRIDF);
+                        uint64_t ky = (uint64_t)(uint32_t)(y[gi] * GRIDF);
+                        keys[p] = ((uint64_t)s << 48) | (kx << 24) | ky;
+                    }
+                    k++;
+                }
+            }
+            base += tot;
+        }
+    }
+}
+
+// Per-set offsets from the tile scan: out[s] = tile_pos[tile_off[s]].
+__global__ void k_set_offsets(const int64_t *__restrict__ tile_off,
+                              const int64_t *__restrict__ tile_pos, int64_t S,
+                              int64_t *__restrict__ out) {
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s <= S) out[s] = tile_pos[tile_off[s]];
+}
+
+// Unfiltered arm: every point survives (survivor list = identity).
+__global__ __launch_bounds__(256) void k_all_keys(const float *__restrict__ x,
+                                                  const float *__restrict__ y,
+                                                  const int64_t *__restrict__ off, int64_t n1,
+                                                  int64_t S, int64_t n_total,
+                                                  uint32_t *__restrict__ surv,
+                                                  uint64_t *__restrict__ keys,
+                                                  int64_t *__restrict__ surv_off) {
+    // sets are found by a scan of the offsets; each thread walks its points
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_total; i += stride) {
+        int64_t s = 0;
+        if (off) {   // binary search: largest s with off[s] <= i
+            int64_t lo = 0, hi = S - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            s = lo;
+        }
+        uint64_t kx = (uint64_t)(uint32_t)(x[i] * GRIDF);
+        uint64_t ky = (uint64_t)(uint32_t)(y[i] * GRIDF);
+        surv[i] = (uint32_t)i;
+        keys[i] = ((uint64_t)s << 48) | (kx << 24) | ky;
+    }
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g <= S) surv_off[g] = off ? off[g] : (g == 0 ? 0 : n1);
+}
+
+// Copy a polygon's vertex list and count to caller memory.
+__global__ void k_poly_out(const Poly *__restrict__ P, int cap, uint32_t *__restrict__ verts,
+                           int32_t *__restrict__ m) {
+    int t = threadIdx.x;
+    if (t < cap) verts[t] = t < P->m ? P->verts[t] : NONE;
+    if (t == 0) *m = P->m;
+}
+
+// Input domain check: coordinates finite, in [0, 1), multiples of 2^-24;
+// offsets non-decreasing from 0 to n_total.  Sets *err on a violation.
+__global__ __launch_bounds__(256) void k_validate(const float *__restrict__ x,
+                                                  const float *__restrict__ y, int64_t n,
+                                                  const int64_t *__restrict__ off, int64_t S,
+                                                  int *__restrict__ err) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    bool bad = false;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float a = x[i], b = y[i];
+        float ga = a * GRIDF, gb = b * GRIDF;
+        bad |= !(a >= 0.0f && a < 1.0f && b >= 0.0f && b < 1.0f);
+        bad |= (ga != truncf(ga)) || (gb != truncf(gb));
+    }
+    if (off) {
+        for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s <= S; s += stride) {
+            if (s == 0 && off[0] != 0) bad = true;
+            if (s == S && off[S] != n) bad = true;
+            if (s < S && off[s + 1] < off[s]) bad = true;
+        }
+    }
+    if (bad) atomicOr(err, 1);
+}
+
+}  // namespace hg

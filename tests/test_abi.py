@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every symbol include/hull.h declares.
+
+Host-only calls (no kernel launch) are exercised here; compute calls run in
+the GPU tests.
+"""
+import ctypes
+import os
+import re
+
+import mpmath
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hull.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(hull_\w+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1405_3454_amd import _build, _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("hull_extremes", "hull_polygon", "hull_discard", "hull_compute",
+                 "hull_extremes_batched", "hull_discard_batched", "hull_compute_batched",
+                 "hull_of_subset", "hull_graph_capture", "hull_graph_launch"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1405_3454_amd import _lib
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_strerror(lib):
+    from paper_1405_3454_amd import _lib
+    for code in (_lib.HULL_OK, _lib.HULL_EINVAL, _lib.HULL_ETOOBIG, _lib.HULL_ENOMEM,
+                 _lib.HULL_EHIP, _lib.HULL_EDOMAIN, _lib.HULL_ECAPTURE, _lib.HULL_ENOMODEL):
+        assert lib.hull_strerror(code)
+    assert lib.hull_strerror(-99) == b"unknown error"
+
+
+def test_null_arguments_rejected_without_device(lib):
+    from paper_1405_3454_amd import _lib
+    assert lib.hull_create(None, 0) == _lib.HULL_EINVAL
+    assert lib.hull_destroy(None) == _lib.HULL_EINVAL
+    assert lib.hull_compute(None, None, None, 0, None, None, 0, None) == _lib.HULL_EINVAL
+
+
+def test_candidate_direction_table_correctly_rounded(lib):
+    c = np.zeros(64)
+    s = np.zeros(64)
+    n = lib.hull_direction_table(None, 1, c.ctypes.data_as(ctypes.c_void_p),
+                                 s.ctypes.data_as(ctypes.c_void_p), 64)
+    assert n == 64
+    mpmath.mp.prec = 300
+    for d in range(64):
+        if d % 16 == 0:
+            cc, ss = [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)][d // 16]
+        else:
+            a = 2 * mpmath.pi * d / 64
+            cc, ss = float(mpmath.cos(a)), float(mpmath.sin(a))
+        assert c[d] == cc and s[d] == ss, d
+
+
+def test_preset_table_matches_paper_angles(lib):
+    c = np.zeros(4)
+    s = np.zeros(4)
+    n = lib.hull_direction_table(None, 0, c.ctypes.data_as(ctypes.c_void_p),
+                                 s.ctypes.data_as(ctypes.c_void_p), 4)
+    assert n == 4
+    mpmath.mp.prec = 300
+    for g, deg in enumerate([0, 30, 45, 60]):
+        a = mpmath.pi * deg / 180
+        assert c[g] == (1.0 if deg == 0 else float(mpmath.cos(a)))
+        assert s[g] == (0.0 if deg == 0 else float(mpmath.sin(a)))

@@ -1,0 +1,145 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is exact: extreme slots and their binary64 values, the
+filter polygon, the ascending survivor list and the hull index list must be
+identical to the oracle's on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1405_3454_amd import inputs
+from paper_1405_3454_amd.inputs import to_float
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["square", "disk", "gaussian", "annulus"]
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1405_3454_amd.api import Hull
+    h = Hull(0)
+    yield h
+    torch.cuda.synchronize()
+    h.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def u32(t):
+    from paper_1405_3454_amd.api import as_u32
+    return as_u32(t)
+
+
+def check_all(H, x, y, preset, what=""):
+    H.set_directions(preset)
+    xt, yt = dev(x), dev(y)
+    slots, vals = H.extremes(xt, yt)
+    o_slots, o_vals = oracle.extremes(x, y, preset)
+    assert np.array_equal(u32(slots), o_slots), (what, u32(slots), o_slots)
+    gv = vals.cpu().numpy()
+    assert np.array_equal(gv.view(np.uint64)[o_slots != oracle.NONE],
+                          o_vals.view(np.uint64)[o_slots != oracle.NONE]), what
+    o_verts = oracle.polygon(x, y, o_slots)
+    verts = H.polygon(xt, yt, slots)
+    assert np.array_equal(u32(verts), o_verts), what
+    surv = H.discard(xt, yt, slots)
+    o_surv = oracle.discard(x, y, o_verts)
+    assert np.array_equal(u32(surv), o_surv), (what, len(surv), len(o_surv))
+    hull = H.compute(xt, yt)
+    o_hull = oracle.hull_subset(x, y, o_surv)
+    assert np.array_equal(u32(hull), o_hull), (what, u32(hull)[:10], o_hull[:10])
+    assert np.array_equal(o_hull, oracle.compute(x, y, preset))
+    return len(o_surv)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 64, 255, 256, 257, 1023, 1024, 1025, 4099,
+                               65536 + 3])
+@pytest.mark.parametrize("kind", KINDS)
+def test_small_sizes(H, kind, n):
+    x, y = inputs.DISTRIBUTIONS[kind](n, 1000 + n)
+    check_all(H, x, y, 0, "%s n=%d" % (kind, n))
+
+
+@pytest.mark.parametrize("preset", [0, 1])
+@pytest.mark.parametrize("kind", KINDS)
+def test_medium(H, kind, preset):
+    x, y = inputs.DISTRIBUTIONS[kind](300_000, 77 + preset)
+    check_all(H, x, y, preset, "%s preset=%d" % (kind, preset))
+
+
+def test_empty(H):
+    import torch
+    x = torch.zeros(0, dtype=torch.float32, device="cuda:0")
+    slots, vals = H.extremes(x, x)
+    assert (u32(slots) == oracle.NONE).all()
+    assert len(H.compute(x, x)) == 0
+    assert len(H.discard(x, x, slots)) == 0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_degenerate_grids(H, seed):
+    """Tiny lattices: duplicates, ties for every extreme, collinear runs."""
+    r = np.random.default_rng(seed)
+    n = int(r.integers(1, 5000))
+    side = int(r.integers(1, 12))
+    x, y = inputs.small_grid(n, side, seed, (int(r.integers(0, 1 << 23)), int(r.integers(0, 1 << 23))))
+    check_all(H, x, y, seed % 2, "grid seed=%d n=%d side=%d" % (seed, n, side))
+
+
+def test_collinear_and_identical(H):
+    k = np.arange(5000)
+    for x, y in [(to_float(k * 7 % 5000), to_float(np.zeros(5000, np.int64) + 99)),
+                 (to_float(np.zeros(5000, np.int64) + 5), to_float(k[::-1])),
+                 (to_float(k), to_float(k)),
+                 (to_float(np.full(3000, 12345)), to_float(np.full(3000, 54321)))]:
+        check_all(H, x, y, 0, "collinear")
+
+
+def test_regular_polygon(H):
+    x, y, m = inputs.regular_polygon(48, 200_000, seed=3)
+    check_all(H, x, y, 0, "48-gon")
+    check_all(H, x, y, 1, "48-gon cumulative")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_unfiltered_arm(H, kind):
+    x, y = inputs.DISTRIBUTIONS[kind](200_000, 5)
+    hull = H.compute(dev(x), dev(y), nofilter=True)
+    assert np.array_equal(u32(hull), oracle.compute(x, y, nofilter=True))
+
+
+def test_hull_of_subset(H):
+    x, y = inputs.disk(100_000, 9)
+    idx = np.sort(np.random.default_rng(1).choice(len(x), 30000, replace=False)).astype(np.uint32)
+    import torch
+    h = H.hull_of_subset(dev(x), dev(y), torch.from_numpy(idx.view(np.int32)).to("cuda:0"))
+    assert np.array_equal(u32(h), oracle.hull_subset(x, y, idx))
+
+
+def test_determinism(H):
+    x, y = inputs.annulus(500_000, 4)
+    xt, yt = dev(x), dev(y)
+    a = u32(H.compute(xt, yt))
+    for bpc in ((2, 2), (16, 16), (8, 8)):
+        H.set_tuning(*bpc)
+        assert np.array_equal(u32(H.compute(xt, yt)), a)
+
+
+def test_validate_flag(H):
+    from paper_1405_3454_amd._lib import HULL_EDOMAIN, HullError
+    x, y = inputs.square(1000, 1)
+    xt, yt = dev(x), dev(y)
+    assert len(H.compute(xt, yt, validate=True)) > 0
+    for v in (np.float32(0.25) + np.float32(2.0 ** -25),   # off the 2^-24 grid
+              np.float32(1.0), np.float32(-2.0 ** -24), np.float32(np.nan)):
+        bad = x.copy()
+        bad[17] = v
+        with pytest.raises(HullError) as e:
+            H.compute(dev(bad), yt, validate=True)
+        assert e.value.code == HULL_EDOMAIN, v
