@@ -262,16 +262,18 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     auto *polys = W<Poly>(ctx, p.polys);
     auto *spans = W<Span>(ctx, p.spans);
     const double *sd = W<double>(ctx, p.setdirs);
-    if (learned)
-        LAUNCH(K_POLYGON, k_polygon<MAX_DIRS><<<(unsigned)S, 256, 0, st>>>(
-            x, y, n_total, S, ctx->preset, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),
-            W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,
-            spans));
-    else
-        LAUNCH(K_POLYGON, k_polygon<0><<<(unsigned)S, 256, 0, st>>>(
-            x, y, n_total, S, ctx->preset, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),
-            W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,
-            spans));
+#define K2(NEV, ND)                                                                           \
+    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<(unsigned)S, 256, 0, st>>>(                          \
+        x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
+        W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
+        spans))
+    const bool cum = ctx->preset == HULL_DIRS_CUMULATIVE;
+    if (learned) {
+        if (cum) K2(12, MAX_DIRS); else K2(16, MAX_DIRS);
+    } else {
+        if (cum) K2(12, 0); else K2(16, 0);
+    }
+#undef K2
     return HULL_OK;
 }
 

@@ -38,29 +38,51 @@ __device__ __forceinline__ bool drop_mid(uint64_t a, uint64_t b, uint64_t c) {
     return UPPER ? (o >= 0) : (o <= 0);
 }
 
-// Sequential chain over keys[a..b) into st[0..), segmented by set.
+// Sequential chain state: stack st[0..h) in memory with its top four
+// entries mirrored in registers (t1 = st[h-1] ... t4 = st[h-4]), so a pop
+// only issues a load for an entry that is needed two pops later.  seg is
+// where the current set's part of the stack starts.
+struct ChainState {
+    uint64_t t1, t2, t3, t4;
+    int h, seg;
+};
+
 template <bool UPPER>
-__device__ __forceinline__ uint32_t chunk_chain(const uint64_t *__restrict__ keys, int64_t a,
-                                                int64_t b, uint64_t *__restrict__ st) {
-    int h = 0, seg = 0;
-    uint64_t prev = ~uint64_t(0), t1 = 0, t2 = 0;   // top and second of the stack
-    for (int64_t i = a; i < b; i++) {
-        uint64_t k = keys[i];
-        if (k == prev) continue;
-        prev = k;
-        if (h > seg && key_set(t1) != key_set(k)) seg = h;
-        while (h - seg >= 2 && drop_mid<UPPER>(t2, t1, k)) {
-            h--;
-            t1 = t2;
-            if (h - seg >= 2) t2 = st[h - 2];
-        }
-        st[h++] = k;
-        t2 = t1;
-        t1 = k;
+__device__ __forceinline__ void chain_push(ChainState &c, uint64_t k, uint64_t *__restrict__ st) {
+    if (c.h > c.seg && key_set(c.t1) != key_set(k)) c.seg = c.h;
+    while (c.h - c.seg >= 2 && drop_mid<UPPER>(c.t2, c.t1, k)) {
+        c.h--;
+        c.t1 = c.t2;
+        c.t2 = c.t3;
+        c.t3 = c.t4;
+        if (c.h - c.seg >= 4) c.t4 = st[c.h - 4];
     }
-    return (uint32_t)h;
+    st[c.h++] = k;
+    c.t4 = c.t3;
+    c.t3 = c.t2;
+    c.t2 = c.t1;
+    c.t1 = k;
 }
 
+__device__ __forceinline__ void load_keys8(const uint64_t *__restrict__ keys, int64_t base, int64_t b,
+                                           uint64_t kb[8]) {
+    if (base + 8 <= b) {
+        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(keys + base);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            ulonglong2 v = p[q];
+            kb[2 * q] = v.x;
+            kb[2 * q + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; q++) kb[q] = base + q < b ? keys[base + q] : ~uint64_t(0);
+    }
+}
+
+// One thread per chunk: lower and upper chains of keys[a..b) in one walk;
+// keys are read eight at a time, the next eight in flight while the current
+// ones are consumed.
 __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict__ keys,
                                                       const int64_t *__restrict__ cnt_ptr,
                                                       uint64_t *__restrict__ lo,
@@ -76,8 +98,26 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
     }
     if (j >= U) return;
     const int64_t a = j * CHAIN_C, b = min(a + CHAIN_C, cnt);
-    lo_cnt[j] = chunk_chain<false>(keys, a, b, lo + a);
-    up_cnt[j] = chunk_chain<true>(keys, a, b, up + a);
+    ChainState L{0, 0, 0, 0, 0, 0}, Up{0, 0, 0, 0, 0, 0};
+    uint64_t *lst = lo + a, *ust = up + a;
+    uint64_t prev = ~uint64_t(0);
+    uint64_t kb[8], kn[8];
+    load_keys8(keys, a, b, kb);
+    for (int64_t base = a; base < b; base += 8) {
+        if (base + 8 < b) load_keys8(keys, base + 8, b, kn);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            uint64_t k = kb[q];
+            if (base + q >= b || k == prev) continue;
+            prev = k;
+            chain_push<false>(L, k, lst);
+            chain_push<true>(Up, k, ust);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) kb[q] = kn[q];
+    }
+    lo_cnt[j] = (uint32_t)L.h;
+    up_cnt[j] = (uint32_t)Up.h;
 }
 
 // Index of the first element of src[lo..hi) whose set equals set(src[hi-1]).

@@ -199,6 +199,11 @@ __global__ __launch_bounds__(256) void k_extremes(
     constexpr int NG = Proj<PRESET>::NG;
     constexpr int NF = 4 * NG;           // fixed slots evaluated
     constexpr int NS = NF + NDIR;        // slots tracked
+    // running maxima of the wave (LDS: read once per chunk and slot)
+    __shared__ double sbv[4][NS];
+    __shared__ uint32_t sbi[4][NS];
+    double *bv = sbv[threadIdx.x >> 6];
+    uint32_t *bi = sbi[threadIdx.x >> 6];
     const int lane = lane_id();
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
@@ -207,76 +212,80 @@ __global__ __launch_bounds__(256) void k_extremes(
     const int64_t t0 = wave * q, t1 = min(t0 + q, T);
     if (t0 >= t1) return;
 
-    double bv[NS];
-    uint32_t bi[NS];
     double dc[NDIR > 0 ? NDIR : 1], ds[NDIR > 0 ? NDIR : 1];
     int64_t cur = -1, run = t0, o0 = 0, o1 = 0, tile0 = 0, abase = 0;
-
-    auto flush = [&]() {
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < NS; k++) {
-                pval[run * MAX_SLOTS + k] = bv[k];
-                pidx[run * MAX_SLOTS + k] = bi[k];
-            }
-        }
-    };
+    float x0f = 0.0f, y0f = 0.0f;
 
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t s = tile_set[t];
         if (s != cur) {
-            if (cur >= 0) flush();
+            wave_sync();
+            if (cur >= 0 && lane < NS) {
+                pval[run * MAX_SLOTS + lane] = bv[lane];
+                pidx[run * MAX_SLOTS + lane] = bi[lane];
+            }
+            wave_sync();
             cur = s;
             run = t;
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
             tile0 = tile_off[s];
             abase = o0 & ~int64_t(3);
-#pragma unroll
-            for (int k = 0; k < NS; k++) {
-                bv[k] = -INFINITY;
-                bi[k] = NONE;
+            x0f = x[o0];
+            y0f = y[o0];
+            if (lane < NS) {
+                bv[lane] = -INFINITY;
+                bi[lane] = NONE;
             }
 #pragma unroll
             for (int d = 0; d < NDIR; d++) {
                 dc[d] = set_dirs[(s * MAX_DIRS + d) * 2 + 0];
                 ds[d] = set_dirs[(s * MAX_DIRS + d) * 2 + 1];
             }
+            wave_sync();
         }
         const int64_t tb = abase + (t - tile0) * TILE;
-#pragma unroll 1
+        // issue the whole tile's loads first: 8 KB in flight per wave
+        float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
+#pragma unroll
+        for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
+#pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) {
             const int64_t cb = tb + c * CHUNK;          // global index of lane 0, item 0
             const int64_t a = cb + 4 * lane;
-            float xv[4], yv[4];
-            load4(x, y, a, n_total, xv, yv);
-            bool valid[4];
+            // per-lane maxima of every slot key over the lane's four points.
+            // Slots outside the set hold a copy of the set's first point o0:
+            // it never raises a maximum (o0 itself is met in the set's first
+            // chunk, at or before any copy) and is never chosen as the index.
             double acc[NS];
 #pragma unroll
-            for (int k = 0; k < NS; k++) acc[k] = -INFINITY;
-#pragma unroll
             for (int j = 0; j < 4; j++) {
-                valid[j] = (a + j >= o0) && (a + j < o1);
-                double xd = xv[j], yd = yv[j];
+                const bool valid = (a + j >= o0) && (a + j < o1);
+                double xd = valid ? xv[c][j] : x0f, yd = valid ? yv[c][j] : y0f;
                 double u[4], v[4];
                 Proj<PRESET>::uv(dirs, xd, yd, u, v);
 #pragma unroll
                 for (int k = 0; k < NF; k++)
-                    acc[k] = valid[j] ? fmax(acc[k], slot_key(k, u, v)) : acc[k];
+                    acc[k] = j == 0 ? slot_key(k, u, v) : fmax(acc[k], slot_key(k, u, v));
 #pragma unroll
-                for (int d = 0; d < NDIR; d++)
-                    acc[NF + d] = valid[j] ? fmax(acc[NF + d], proj_dir(dc[d], ds[d], xd, yd))
-                                           : acc[NF + d];
+                for (int d = 0; d < NDIR; d++) {
+                    double w = proj_dir(dc[d], ds[d], xd, yd);
+                    acc[NF + d] = j == 0 ? w : fmax(acc[NF + d], w);
+                }
             }
 #pragma unroll
             for (int k = 0; k < NS; k++) {
                 if (__ballot(acc[k] > bv[k])) {
-                    // rare: a new maximum in this chunk; take the lowest index
+                    // rare: a new maximum in this chunk; take the lowest
+                    // index.  The points are read again (cache hits).
                     double m = wave_max(acc[k]);
+                    float rx[4], ry[4];
+                    load4(x, y, a, n_total, rx, ry);
                     int cand = 4;
 #pragma unroll
                     for (int j = 3; j >= 0; j--) {
-                        double xd = xv[j], yd = yv[j], key;
+                        const bool valid = (a + j >= o0) && (a + j < o1);
+                        double xd = rx[j], yd = ry[j], key;
                         if (k < NF) {
                             double u[4], v[4];
                             Proj<PRESET>::uv(dirs, xd, yd, u, v);
@@ -284,18 +293,26 @@ __global__ __launch_bounds__(256) void k_extremes(
                         } else {
                             key = proj_dir(dc[k - NF], ds[k - NF], xd, yd);
                         }
-                        if (valid[j] && key == m) cand = j;
+                        if (valid && key == m) cand = j;
                     }
                     uint64_t has = __ballot(cand < 4);
                     int L = __ffsll((unsigned long long)has) - 1;
                     int cj = __builtin_amdgcn_readlane(cand, L);
-                    bv[k] = m;
-                    bi[k] = (uint32_t)(cb + 4 * L + cj);
+                    wave_sync();
+                    if (lane == 0) {
+                        bv[k] = m;
+                        bi[k] = (uint32_t)(cb + 4 * L + cj);
+                    }
+                    wave_sync();
                 }
             }
         }
     }
-    flush();
+    wave_sync();
+    if (lane < NS) {
+        pval[run * MAX_SLOTS + lane] = bv[lane];
+        pidx[run * MAX_SLOTS + lane] = bi[lane];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -320,21 +337,28 @@ __device__ __forceinline__ double edge_eval(double ex, double ey, double c, doub
     return fma(ex, py, fma(-ey, px, c));
 }
 
-template <int NDIR>
+template <int NEV, int NDIR>
 __global__ __launch_bounds__(256) void k_polygon(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int64_t S,
-    int preset,
     const int64_t *__restrict__ tile_off, int64_t W1, const double *__restrict__ pval,
     const uint32_t *__restrict__ pidx, const uint32_t *__restrict__ slots_in, int n_in, Dirs dirs,
     const double *__restrict__ set_dirs, uint32_t *__restrict__ slots_out,
     double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans) {
+    // NEV: fixed slots the extremes pass evaluated (12 when the 120-degree
+    // group is a copy of the 30-degree one, else 16); NDIR learned slots.
     constexpr int NS = FIXED_SLOTS + NDIR;
+    constexpr int NE = NEV + NDIR;
     __shared__ SlotBest wbest[4][MAX_SLOTS];
     __shared__ uint32_t sl[MAX_SLOTS];
+    __shared__ double gx[MAX_SLOTS], gy[MAX_SLOTS];   // slot points (grid units)
+    __shared__ double sx[MAX_SLOTS], sy[MAX_SLOTS];   // sorted by (x, y, index, slot)
+    __shared__ uint32_t si[MAX_SLOTS];
+    __shared__ int st[2 * MAX_SLOTS + 2];
+    __shared__ double vx[MAX_SLOTS], vy[MAX_SLOTS];   // polygon vertices
+    __shared__ int nvalid;
     __shared__ Poly P;
     const int64_t s = blockIdx.x;
     const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    const int nev = preset == 1 ? 12 : 16;    // fixed slots the extremes pass evaluated
 
     if (slots_in) {
         if (tid < MAX_SLOTS) {
@@ -350,15 +374,16 @@ __global__ __launch_bounds__(256) void k_polygon(
             m0 = (ta / q + 1) * q;
             nruns = 1 + (m0 < tb ? (tb - 1 - m0) / q + 1 : 0);
         }
-        double bv[MAX_SLOTS];
-        uint32_t bi[MAX_SLOTS];
-        for (int k = 0; k < MAX_SLOTS; k++) {
+        double bv[NE];
+        uint32_t bi[NE];
+#pragma unroll
+        for (int k = 0; k < NE; k++) {
             bv[k] = -INFINITY;
             bi[k] = NONE;
         }
-        const int NE = nev + NDIR;
         for (int64_t r = tid; r < nruns; r += blockDim.x) {
             int64_t t = r == 0 ? ta : m0 + (r - 1) * q;
+#pragma unroll
             for (int k = 0; k < NE; k++) {
                 double v = pval[t * MAX_SLOTS + k];
                 uint32_t i = pidx[t * MAX_SLOTS + k];
@@ -368,6 +393,7 @@ __global__ __launch_bounds__(256) void k_polygon(
                 }
             }
         }
+#pragma unroll
         for (int k = 0; k < NE; k++) {
             double v = bv[k];
             uint32_t i = bi[k];
@@ -393,18 +419,18 @@ __global__ __launch_bounds__(256) void k_polygon(
                     i = b.i;
                 }
             }
-            // partial slot k < nev holds fixed slot k; learned slots follow
-            int dst = tid < nev ? tid : FIXED_SLOTS + (tid - nev);
+            // partial slot k < NEV holds fixed slot k; learned slots follow
+            int dst = tid < NEV ? tid : FIXED_SLOTS + (tid - NEV);
             sl[dst] = i;
         }
+        if (NDIR == 0 && tid >= FIXED_SLOTS && tid < MAX_SLOTS) sl[tid] = NONE;
         __syncthreads();
-        if (tid == 0 && preset == 1) {   // 120-degree group repeats the 30-degree one
+        if (NEV == 12 && tid == 0) {   // 120-degree group repeats the 30-degree one
             sl[12] = sl[7];
             sl[13] = sl[6];
             sl[14] = sl[4];
             sl[15] = sl[5];
         }
-        if (tid < MAX_SLOTS && tid >= NS) sl[tid] = NONE;
     }
     __syncthreads();
 
@@ -421,58 +447,68 @@ __global__ __launch_bounds__(256) void k_polygon(
                 val = t < 2 ? c * xd - sn * yd : sn * xd + c * yd;
             } else {
                 int d = tid - FIXED_SLOTS;
-                val = set_dirs[(s * MAX_DIRS + d) * 2] * xd + set_dirs[(s * MAX_DIRS + d) * 2 + 1] * yd;
+                val = proj_dir(set_dirs[(s * MAX_DIRS + d) * 2], set_dirs[(s * MAX_DIRS + d) * 2 + 1],
+                               xd, yd);
             }
         }
         vals_out[s * NS + tid] = val;
     }
 
-    // polygon by Andrew's monotone chain (thread 0; at most 24 points)
-    if (tid == 0) {
-        double px[MAX_SLOTS], py[MAX_SLOTS];
-        uint32_t pi[MAX_SLOTS];
-        int k = 0;
+    // sort the slot points by (x, y, index, slot) with a rank per thread
+    if (tid < MAX_SLOTS) {
+        uint32_t i = sl[tid];
+        gx[tid] = i != NONE ? grid_of(x[i]) : 0.0;
+        gy[tid] = i != NONE ? grid_of(y[i]) : 0.0;
+    }
+    if (w == 0) {
+        uint64_t vm = __ballot(tid < MAX_SLOTS && sl[tid < MAX_SLOTS ? tid : 0] != NONE);
+        if (tid == 0) nvalid = __popcll(vm);
+    }
+    __syncthreads();
+    if (tid < MAX_SLOTS && sl[tid] != NONE) {
+        double ax = gx[tid], ay = gy[tid];
+        uint32_t ai = sl[tid];
+        int rank = 0;
         for (int j = 0; j < MAX_SLOTS; j++) {
-            uint32_t i = sl[j];
-            if (i == NONE) continue;
-            double gx = grid_of(x[i]), gy = grid_of(y[i]);
-            // insertion by (x, y, index)
-            int p = k++;
-            while (p > 0 && (px[p - 1] > gx || (px[p - 1] == gx && (py[p - 1] > gy ||
-                                                (py[p - 1] == gy && pi[p - 1] > i))))) {
-                px[p] = px[p - 1];
-                py[p] = py[p - 1];
-                pi[p] = pi[p - 1];
-                p--;
-            }
-            px[p] = gx;
-            py[p] = gy;
-            pi[p] = i;
+            uint32_t bj = sl[j];
+            if (bj == NONE || j == tid) continue;
+            double bx = gx[j], by = gy[j];
+            bool less = bx < ax || (bx == ax && (by < ay || (by == ay && (bj < ai ||
+                                                     (bj == ai && j < tid)))));
+            rank += less;
         }
+        sx[rank] = ax;
+        sy[rank] = ay;
+        si[rank] = ai;
+    }
+    __syncthreads();
+
+    // Andrew's monotone chain on the sorted slot points (thread 0, LDS)
+    if (tid == 0) {
+        const int k = nvalid;
         int u = 0;
         for (int j = 0; j < k; j++)
-            if (u == 0 || px[j] != px[u - 1] || py[j] != py[u - 1]) {
-                px[u] = px[j];
-                py[u] = py[j];
-                pi[u] = pi[j];
+            if (u == 0 || sx[j] != sx[u - 1] || sy[j] != sy[u - 1]) {
+                sx[u] = sx[j];
+                sy[u] = sy[j];
+                si[u] = si[j];
                 u++;
             }
-        int st[2 * MAX_SLOTS + 2];
         int h = 0;
         if (u == 1) {
             st[0] = 0;
             h = 1;
         } else if (u >= 2) {
             for (int j = 0; j < u; j++) {
-                while (h >= 2 && orient(px[st[h - 2]], py[st[h - 2]], px[st[h - 1]], py[st[h - 1]],
-                                        px[j], py[j]) <= 0)
+                while (h >= 2 && orient(sx[st[h - 2]], sy[st[h - 2]], sx[st[h - 1]], sy[st[h - 1]],
+                                        sx[j], sy[j]) <= 0)
                     h--;
                 st[h++] = j;
             }
             int lo = h + 1;
             for (int j = u - 2; j >= 0; j--) {
-                while (h >= lo && orient(px[st[h - 2]], py[st[h - 2]], px[st[h - 1]], py[st[h - 1]],
-                                         px[j], py[j]) <= 0)
+                while (h >= lo && orient(sx[st[h - 2]], sy[st[h - 2]], sx[st[h - 1]], sy[st[h - 1]],
+                                         sx[j], sy[j]) <= 0)
                     h--;
                 st[h++] = j;
             }
@@ -481,15 +517,19 @@ __global__ __launch_bounds__(256) void k_polygon(
         P.m = h;
         int ylo = 0x7fffffff, yhi = -1;
         for (int e = 0; e < MAX_SLOTS; e++) {
-            P.verts[e] = e < h ? pi[st[e]] : NONE;
+            P.verts[e] = e < h ? si[st[e]] : NONE;
+            if (e < h) {
+                vx[e] = sx[st[e]];
+                vy[e] = sy[st[e]];
+            }
             if (e < h && h >= 3) {
                 int a = st[e], b = st[(e + 1) % h];
-                double ex = px[b] - px[a], ey = py[b] - py[a];
+                double ex = sx[b] - sx[a], ey = sy[b] - sy[a];
                 P.ex[e] = ex;
                 P.ey[e] = ey;
-                P.c[e] = fma(ey, px[a], -(ex * py[a]));
-                ylo = min(ylo, (int)py[a]);
-                yhi = max(yhi, (int)py[a]);
+                P.c[e] = fma(ey, sx[a], -(ex * sy[a]));
+                ylo = min(ylo, (int)sy[a]);
+                yhi = max(yhi, (int)sy[a]);
             } else {
                 P.ex[e] = 0.0;
                 P.ey[e] = 0.0;
@@ -523,8 +563,7 @@ __global__ __launch_bounds__(256) void k_polygon(
                 bool ok = true;
                 for (int e = 0; e < P.m; e++) {
                     double ex = P.ex[e], ey = P.ey[e];
-                    uint32_t ia = P.verts[e];   // edge e runs from vertex e to e+1
-                    double ax = grid_of(x[ia]), ay = grid_of(y[ia]);
+                    double ax = vx[e], ay = vy[e];     // edge e runs from vertex e to e+1
                     if (ey > 0) {
                         xr = fmin(xr, fmin(ax + ex * ((double)y0 - ay) / ey,
                                            ax + ex * ((double)y1 - ay) / ey));
@@ -638,15 +677,16 @@ __global__ __launch_bounds__(256) void k_discard(
         if (lane < TILE_WORDS) L.mask[lane] = 0;
         int qn = 0;
         const int64_t tb = abase + (t - tile0) * TILE;
-#pragma unroll 1
+        float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
+#pragma unroll
+        for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
+#pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) {
             const int64_t a = tb + c * CHUNK + 4 * lane;
-            float xv[4], yv[4];
-            load4(x, y, a, n_total, xv, yv);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 bool valid = (a + j >= o0) && (a + j < o1);
-                int32_t kx = (int32_t)(xv[j] * GRIDF), ky = (int32_t)(yv[j] * GRIDF);
+                int32_t kx = (int32_t)(xv[c][j] * GRIDF), ky = (int32_t)(yv[c][j] * GRIDF);
                 uint32_t dy = (uint32_t)(ky - ky_lo);
                 uint32_t row = min(dy >> shift, (uint32_t)(SPAN_ROWS - 1));
                 Span sp = L.spans[row];
