@@ -160,6 +160,49 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y,
 /* Read (get != 0) or set the chosen waves-per-CU of the filter kernels. */
 int hull_tuning(hull_ctx *ctx, int get, int *k1_blocks_per_cu, int *k3_blocks_per_cu);
 
+/* ---- learned direction proposal ----------------------------------------
+ * This project's extension, not part of the paper's method.  A 32 x 32
+ * occupancy histogram of each set (hull_histogram_batched) feeds an MLP
+ * 1024 -> 512 -> 512 -> 64 (ReLU; bf16 weights and activations, fp32
+ * accumulation on MFMA) that scores the 64 directions 2*pi*d/64; the eight
+ * best become extra extreme slots.  Extra extremes only enlarge the filter
+ * polygon inside the hull, so every hull stays exact whatever the weights.
+ *
+ * Parameters: one float32 array of hull_mlp_param_count() values in the
+ * order W1[512][1024], b1[512], W2[512][512], b2[512], W3[64][512], b3[64]
+ * (W[out][in]); host memory in the set/get calls. */
+int64_t hull_mlp_param_count(void);
+int hull_mlp_set_params(hull_ctx *ctx, const float *params_host, int64_t count);
+int hull_mlp_get_params(hull_ctx *ctx, float *params_host, int64_t count);
+/* hist: device bf16 bits [S][1024]; hist_f32: device float [S][1024] or NULL.
+ * offsets NULL means one set of n_total points (S must be 1).  The sample
+ * is every ceil(n/16384)-th point; bins span the sample's bounding box;
+ * value = count * 1024 / sample size. */
+int hull_histogram_batched(hull_ctx *ctx, const float *x, const float *y,
+                           const int64_t *offsets, int64_t S, int64_t n_total,
+                           uint16_t *hist, float *hist_f32, void *stream);
+/* scores: device float [B][64]. */
+int hull_mlp_forward(hull_ctx *ctx, const uint16_t *hist, int64_t B, float *scores,
+                     void *stream);
+/* Gradient of sum(dscores * scores) w.r.t. every parameter (device float
+ * [param_count]); dscores is rounded to bf16 first. */
+int hull_mlp_backward(hull_ctx *ctx, const uint16_t *hist, const float *dscores, int64_t B,
+                      float *grads, void *stream);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on the mean squared error between
+ * the scores and gain / max(gain) per set; *loss (device float) gets the loss
+ * before the step. gain: device float [B][64]. */
+int hull_mlp_train_step(hull_ctx *ctx, const uint16_t *hist, const float *gain, int64_t B,
+                        float lr, float *loss, void *stream);
+/* The eight chosen directions per set (device int32 [S][8]) for scores
+ * [S][64]: highest first, lower index on ties. */
+int hull_top_directions(hull_ctx *ctx, const float *scores, int64_t S, int32_t *dirs,
+                        void *stream);
+/* Training labels (device float [S][64]): for direction d, the fraction of the
+ * set's points that the plain filter keeps but the polygon of the sixteen
+ * fixed extremes plus the extreme along d discards. */
+int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                        int64_t S, int64_t n_total, float *gain, void *stream);
+
 /* ---- per-kernel timing (hipEvents around every launch) ----------------- */
 int hull_timing_enable(hull_ctx *ctx, int on);
 /* Copy accumulated milliseconds and launch counts for up to cap kernel

@@ -49,6 +49,15 @@ SIGNATURES = {
     "hull_graph_launch": (I, [P, P]),
     "hull_autotune": (I, [P, P, P, P, I64, I64, P]),
     "hull_tuning": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "hull_mlp_param_count": (I64, []),
+    "hull_mlp_set_params": (I, [P, P, I64]),
+    "hull_mlp_get_params": (I, [P, P, I64]),
+    "hull_histogram_batched": (I, [P, P, P, P, I64, I64, P, P, P]),
+    "hull_mlp_forward": (I, [P, P, I64, P, P]),
+    "hull_mlp_backward": (I, [P, P, P, I64, P, P]),
+    "hull_mlp_train_step": (I, [P, P, P, I64, ctypes.c_float, P, P]),
+    "hull_top_directions": (I, [P, P, I64, P, P]),
+    "hull_labels_batched": (I, [P, P, P, P, I64, I64, P, P]),
     "hull_timing_enable": (I, [P, I]),
     "hull_timing_read": (I, [P, P, P, I]),
     "hull_timing_name": (ctypes.c_char_p, [I]),

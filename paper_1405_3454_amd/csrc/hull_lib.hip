@@ -45,6 +45,7 @@ struct hull_ctx {
     hipError_t last = hipSuccess;
     char *ws = nullptr;
     size_t ws_cap = 0;
+    std::vector<char *> retired;        // old workspaces a graph may still use
     int k1_bpc = 8, k3_bpc = 8;        // blocks per CU of the filter kernels
     // timing
     bool timing = false;
@@ -111,7 +112,7 @@ static int launch(hull_ctx *ctx, int kind, hipStream_t st, F &&f) {
 struct Plan {
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
-        hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, total;
+        hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, total;
     int64_t tcap, u0cap;
 };
 
@@ -160,6 +161,7 @@ static Plan make_plan(int64_t n, int64_t S) {
     p.err = take(8);
     p.setdirs = take(S * MAX_DIRS * 2 * 8);
     p.learn = take(learned_ws_bytes(S));
+    p.cand = take(S * NCAND * 4);
     p.total = o;
     return p;
 }
@@ -170,7 +172,10 @@ static int ensure_ws(hull_ctx *ctx, size_t bytes, hipStream_t st) {
     HIPCHECK(hipStreamIsCapturing(st, &cs));
     if (cs != hipStreamCaptureStatusNone) return HULL_ECAPTURE;
     HIPCHECK(hipDeviceSynchronize());
-    if (ctx->ws) HIPCHECK(hipFree(ctx->ws));
+    // a captured graph holds pointers into the old workspace: keep it alive
+    // until the graph is replaced or the context destroyed
+    if (ctx->ws && ctx->gexec) ctx->retired.push_back(ctx->ws);
+    else if (ctx->ws) HIPCHECK(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_cap = 0;
     size_t want = bytes + bytes / 8;
@@ -359,7 +364,7 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     uint32_t *locnt[2] = {cc, cc + p.u0cap};
     uint32_t *upcnt[2] = {cc + 2 * p.u0cap, cc + 3 * p.u0cap};
     const int64_t u0 = (ncap + CHAIN_C - 1) / CHAIN_C;
-    LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::max<int64_t>(1, (u0 + 255) / 256), 256, 0, st>>>(
+    LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::max<int64_t>(1, (u0 + 3) / 4), 256, 0, st>>>(
         sorted, cnt, lo[0], up[0], locnt[0], upcnt[0]));
     const int L = chain_levels(ncap);
     int cur = 0;
@@ -394,14 +399,10 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
 }
 
 // Learned proposal: per-set histogram -> network -> eight directions written
-// to the workspace's set_dirs table.
+// to the workspace's set_dirs table (defined with the network code below).
 static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                             const float *y, int64_t n_total, const int64_t *off, int64_t n1,
-                            int64_t S) {
-    (void)p; (void)st; (void)x; (void)y; (void)n_total; (void)off; (void)n1; (void)S;
-    if (!ctx->learned.loaded) return HULL_ENOMODEL;
-    return HULL_ENOMODEL;
-}
+                            int64_t S);
 
 static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p) {
     HIPCHECK(hipSetDevice(ctx->device));
@@ -504,6 +505,7 @@ int hull_destroy(hull_ctx *ctx) {
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     learned_free(ctx->learned);
+    for (char *r : ctx->retired) (void)hipFree(r);
     if (ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
     return HULL_OK;
@@ -669,8 +671,14 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int6
     HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     const bool was_timing = ctx->timing;
     ctx->timing = false;
-    if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->gexec) {
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
     if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    for (char *r : ctx->retired) (void)hipFree(r);
+    ctx->retired.clear();
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         ctx->timing = was_timing;
@@ -823,6 +831,247 @@ int hull_timing_reset(hull_ctx *ctx) {
         ctx->launches[k] = 0;
     }
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned proposal: network buffers, forward, backward, training step,
+// labels.  Weight matrices in bf16, activations in bf16, accumulation and
+// the master copy of the parameters in float32.
+
+static int learned_ensure(hull_ctx *ctx, int64_t B, hipStream_t st) {
+    LearnedState &L = ctx->learned;
+    const int64_t Bp = std::max<int64_t>(64, (B + 63) / 64 * 64);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!L.params || Bp > L.bcap) {
+        HIPCHECK(hipStreamIsCapturing(st, &cs));
+        if (cs != hipStreamCaptureStatusNone) return HULL_ECAPTURE;
+        HIPCHECK(hipDeviceSynchronize());
+    }
+    if (!L.params) {
+        HIPCHECK(hipMalloc(&L.params, P_TOTAL * sizeof(float)));
+        HIPCHECK(hipMalloc(&L.grads, P_TOTAL * sizeof(float)));
+        HIPCHECK(hipMalloc(&L.m1, P_TOTAL * sizeof(float)));
+        HIPCHECK(hipMalloc(&L.m2, P_TOTAL * sizeof(float)));
+        HIPCHECK(hipMalloc(&L.wb, Q_TOTAL * sizeof(bf16_t)));
+    }
+    if (Bp > L.bcap) {
+        void *old[] = {L.X, L.H1, L.H2, L.dS, L.dZ2, L.dZ1, L.scores, L.part};
+        for (void *q : old)
+            if (q) HIPCHECK(hipFree(q));
+        HIPCHECK(hipMalloc(&L.X, Bp * HBINS * sizeof(bf16_t)));
+        HIPCHECK(hipMalloc(&L.H1, Bp * L1 * sizeof(bf16_t)));
+        HIPCHECK(hipMalloc(&L.H2, Bp * L2 * sizeof(bf16_t)));
+        HIPCHECK(hipMalloc(&L.dS, Bp * NOUT * sizeof(bf16_t)));
+        HIPCHECK(hipMalloc(&L.dZ2, Bp * L2 * sizeof(bf16_t)));
+        HIPCHECK(hipMalloc(&L.dZ1, Bp * L1 * sizeof(bf16_t)));
+        HIPCHECK(hipMalloc(&L.scores, Bp * NOUT * sizeof(float)));
+        HIPCHECK(hipMalloc(&L.part, Bp * sizeof(float)));
+        L.bcap = Bp;
+    }
+    return HULL_OK;
+}
+
+template <int MODE>
+static int gemm(hull_ctx *ctx, hipStream_t st, const bf16_t *A, int64_t sam, int64_t sak,
+                const bf16_t *B, int64_t sbk, int64_t sbn, int M, int N, int K, const float *bias,
+                const bf16_t *mask, bf16_t *Cb, float *Cf, int ldc) {
+    if (M % GBM || N % GBN || K % GBK) return HULL_EINVAL;
+    dim3 grid(N / GBN, M / GBM);
+    LAUNCH(K_MLP, k_gemm<MODE><<<grid, 256, 0, st>>>(A, sam, sak, B, sbk, sbn, M, N, K, bias, mask,
+                                                     Cb, Cf, ldc));
+    return HULL_OK;
+}
+
+#define RC(expr)                 \
+    do {                         \
+        int rc_ = (expr);        \
+        if (rc_) return rc_;     \
+    } while (0)
+
+// scores (float32 [Bp][64]) of histogram rows hist[B][1024] into L.scores
+static int mlp_forward(hull_ctx *ctx, hipStream_t st, const bf16_t *hist, int64_t B) {
+    LearnedState &L = ctx->learned;
+    RC(learned_ensure(ctx, B, st));
+    const int Bp = (int)std::max<int64_t>(64, (B + 63) / 64 * 64);
+    LAUNCH(K_MLP, k_pad_rows<<<256, 256, 0, st>>>(hist, B, Bp, HBINS, L.X));
+    RC(gemm<G_RELU_BF16>(ctx, st, L.X, HBINS, 1, L.wb + Q_W1, 1, HBINS, Bp, L1, HBINS,
+                         L.params + P_B1, nullptr, L.H1, nullptr, L1));
+    RC(gemm<G_RELU_BF16>(ctx, st, L.H1, L1, 1, L.wb + Q_W2, 1, L1, Bp, L2, L1, L.params + P_B2,
+                         nullptr, L.H2, nullptr, L2));
+    RC(gemm<G_BIAS_F32>(ctx, st, L.H2, L2, 1, L.wb + Q_W3, 1, L2, Bp, NOUT, L2, L.params + P_B3,
+                        nullptr, nullptr, L.scores, NOUT));
+    return HULL_OK;
+}
+
+// gradients of every parameter into L.grads, from L.dS (bf16 [Bp][64]) and
+// the activations of the last forward pass
+static int mlp_backward(hull_ctx *ctx, hipStream_t st, int64_t B) {
+    LearnedState &L = ctx->learned;
+    const int Bp = (int)std::max<int64_t>(64, (B + 63) / 64 * 64);
+    RC(gemm<G_F32>(ctx, st, L.dS, 1, NOUT, L.H2, L2, 1, NOUT, L2, Bp, nullptr, nullptr, nullptr,
+                   L.grads + P_W3, L2));
+    LAUNCH(K_MLP, k_colsum<<<1, 64, 0, st>>>(L.dS, Bp, NOUT, L.grads + P_B3));
+    RC(gemm<G_MASK_BF16>(ctx, st, L.dS, NOUT, 1, L.wb + Q_W3, L2, 1, Bp, L2, NOUT, nullptr, L.H2,
+                         L.dZ2, nullptr, L2));
+    RC(gemm<G_F32>(ctx, st, L.dZ2, 1, L2, L.H1, L1, 1, L2, L1, Bp, nullptr, nullptr, nullptr,
+                   L.grads + P_W2, L1));
+    LAUNCH(K_MLP, k_colsum<<<(L2 + 255) / 256, 256, 0, st>>>(L.dZ2, Bp, L2, L.grads + P_B2));
+    RC(gemm<G_MASK_BF16>(ctx, st, L.dZ2, L2, 1, L.wb + Q_W2, L1, 1, Bp, L1, L2, nullptr, L.H1,
+                         L.dZ1, nullptr, L1));
+    RC(gemm<G_F32>(ctx, st, L.dZ1, 1, L1, L.X, HBINS, 1, L1, HBINS, Bp, nullptr, nullptr, nullptr,
+                   L.grads + P_W1, HBINS));
+    LAUNCH(K_MLP, k_colsum<<<(L1 + 255) / 256, 256, 0, st>>>(L.dZ1, Bp, L1, L.grads + P_B1));
+    return HULL_OK;
+}
+
+static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                            const float *y, int64_t n_total, const int64_t *off, int64_t n1,
+                            int64_t S) {
+    (void)n_total;
+    if (!ctx->learned.loaded) return HULL_ENOMODEL;
+    bf16_t *hist = W<bf16_t>(ctx, p.learn);
+    LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, 256, 0, st>>>(x, y, off, n1, S, hist, nullptr));
+    RC(mlp_forward(ctx, st, hist, S));
+    LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(ctx->learned.scores, S, nullptr,
+                                                                 W<double>(ctx, p.setdirs)));
+    return HULL_OK;
+}
+
+static int init_cand_table() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        err = hipMemcpyToSymbol(HIP_SYMBOL(dCandCos), kCandCos, sizeof(kCandCos));
+        if (err == hipSuccess) err = hipMemcpyToSymbol(HIP_SYMBOL(dCandSin), kCandSin, sizeof(kCandSin));
+    });
+    return err == hipSuccess ? HULL_OK : HULL_EHIP;
+}
+
+extern "C" {
+
+int64_t hull_mlp_param_count(void) { return P_TOTAL; }
+
+int hull_mlp_set_params(hull_ctx *ctx, const float *params, int64_t count) {
+    if (!ctx || !params || count != P_TOTAL) return HULL_EINVAL;
+    HIPCHECK(hipSetDevice(ctx->device));
+    RC(init_cand_table());
+    hipStream_t st = nullptr;
+    RC(learned_ensure(ctx, 64, st));
+    LearnedState &L = ctx->learned;
+    HIPCHECK(hipMemcpy(L.params, params, P_TOTAL * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemset(L.m1, 0, P_TOTAL * sizeof(float)));
+    HIPCHECK(hipMemset(L.m2, 0, P_TOTAL * sizeof(float)));
+    LAUNCH(K_MLP, k_to_bf16<<<1024, 256, 0, st>>>(L.params + P_W1, (int64_t)L1 * HBINS, L.wb + Q_W1));
+    LAUNCH(K_MLP, k_to_bf16<<<1024, 256, 0, st>>>(L.params + P_W2, (int64_t)L2 * L1, L.wb + Q_W2));
+    LAUNCH(K_MLP, k_to_bf16<<<256, 256, 0, st>>>(L.params + P_W3, (int64_t)NOUT * L2, L.wb + Q_W3));
+    HIPCHECK(hipDeviceSynchronize());
+    L.step = 0;
+    L.loaded = true;
+    return HULL_OK;
+}
+
+int hull_mlp_get_params(hull_ctx *ctx, float *params, int64_t count) {
+    if (!ctx || !params || count != P_TOTAL || !ctx->learned.loaded) return HULL_EINVAL;
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(hipMemcpy(params, ctx->learned.params, P_TOTAL * sizeof(float), hipMemcpyDeviceToHost));
+    return HULL_OK;
+}
+
+int hull_histogram_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                           int64_t S, int64_t n_total, uint16_t *hist, float *hist_f32,
+                           void *stream) {
+    if (!ctx || !hist || S <= 0) return HULL_EINVAL;
+    int rc = check_points(x, y, n_total);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    const int64_t n1 = offsets ? 0 : n_total;
+    if (!offsets && S != 1) return HULL_EINVAL;
+    LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, n1, S, hist, hist_f32));
+    return HULL_OK;
+}
+
+int hull_mlp_forward(hull_ctx *ctx, const uint16_t *hist, int64_t B, float *scores, void *stream) {
+    if (!ctx || !hist || !scores || B <= 0) return HULL_EINVAL;
+    if (!ctx->learned.loaded) return HULL_ENOMODEL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    RC(mlp_forward(ctx, st, hist, B));
+    HIPCHECK(hipMemcpyAsync(scores, ctx->learned.scores, B * NOUT * sizeof(float),
+                            hipMemcpyDeviceToDevice, st));
+    return HULL_OK;
+}
+
+int hull_mlp_backward(hull_ctx *ctx, const uint16_t *hist, const float *dscores, int64_t B,
+                      float *grads, void *stream) {
+    if (!ctx || !hist || !dscores || !grads || B <= 0) return HULL_EINVAL;
+    if (!ctx->learned.loaded) return HULL_ENOMODEL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    RC(mlp_forward(ctx, st, hist, B));
+    LearnedState &L = ctx->learned;
+    const int Bp = (int)std::max<int64_t>(64, (B + 63) / 64 * 64);
+    LAUNCH(K_MLP, k_pad_f32_bf16<<<256, 256, 0, st>>>(dscores, B, Bp, NOUT, L.dS));
+    RC(mlp_backward(ctx, st, B));
+    HIPCHECK(hipMemcpyAsync(grads, L.grads, P_TOTAL * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return HULL_OK;
+}
+
+int hull_mlp_train_step(hull_ctx *ctx, const uint16_t *hist, const float *gain, int64_t B, float lr,
+                        float *loss, void *stream) {
+    if (!ctx || !hist || !gain || !loss || B <= 0 || !(lr > 0)) return HULL_EINVAL;
+    if (!ctx->learned.loaded) return HULL_ENOMODEL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    RC(mlp_forward(ctx, st, hist, B));
+    LearnedState &L = ctx->learned;
+    const int Bp = (int)std::max<int64_t>(64, (B + 63) / 64 * 64);
+    LAUNCH(K_MLP, k_loss<<<(unsigned)Bp, 64, 0, st>>>(L.scores, gain, B, Bp, L.dS, L.part));
+    LAUNCH(K_MLP, k_loss_sum<<<1, 64, 0, st>>>(L.part, B, loss));
+    RC(mlp_backward(ctx, st, B));
+    L.step++;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - std::pow(b1, (float)L.step), c2 = 1.0f - std::pow(b2, (float)L.step);
+    LAUNCH(K_MLP, k_adam<<<1024, 256, 0, st>>>(L.params, L.grads, L.m1, L.m2, P_TOTAL, lr, b1, b2,
+                                               eps, c1, c2, L.wb));
+    return HULL_OK;
+}
+
+int hull_top_directions(hull_ctx *ctx, const float *scores, int64_t S, int32_t *dirs, void *stream) {
+    if (!ctx || !scores || !dirs || S <= 0) return HULL_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    RC(init_cand_table());
+    Plan p;
+    RC(prepare(ctx, 0, S, st, &p));
+    LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(scores, S, dirs,
+                                                                 W<double>(ctx, p.setdirs)));
+    return HULL_OK;
+}
+
+int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
+                        int64_t S, int64_t n_total, float *gain, void *stream) {
+    if (!ctx || !gain) return HULL_EINVAL;
+    int rc = check_batch(x, y, offsets, S, n_total);
+    if (rc) return rc;
+    RC(init_cand_table());
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    RC(prepare(ctx, n_total, S, st, &p));
+    RC(run_tilemap(ctx, p, st, offsets, 0, S));
+    RC(run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, false));
+    RC(run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr));
+    uint32_t *surv = W<uint32_t>(ctx, p.surv);
+    int64_t *so = W<int64_t>(ctx, p.surv_off);
+    RC(run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, FIXED_SLOTS, surv, so, nullptr));
+    uint32_t *cand = W<uint32_t>(ctx, p.cand);
+    LAUNCH(K_LABELS, k_cand_extremes<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, cand));
+    LAUNCH(K_LABELS, k_labels<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, W<Poly>(ctx, p.polys),
+                                                          cand, surv, so, gain));
+    return HULL_OK;
 }
 
 }  // extern "C"

@@ -4,7 +4,7 @@
 // Keys are set << 48 | kx << 24 | ky, sorted ascending, so each set is a
 // contiguous run ordered by (x, y).  Every chain below is segmented by the
 // set field: it never joins points of different sets.
-//  1. k_chain_chunks: one thread per CHAIN_C consecutive keys computes the
+//  1. k_chain_chunks: one wave per CHAIN_C consecutive keys computes the
 //     lower and the upper chain of its chunk (duplicates dropped; a point is
 //     popped while it does not make a strict turn, so collinear points go).
 //  2. k_chain_merge: one wave per group of CHAIN_G neighbouring chains joins
@@ -38,91 +38,173 @@ __device__ __forceinline__ bool drop_mid(uint64_t a, uint64_t b, uint64_t c) {
     return UPPER ? (o >= 0) : (o <= 0);
 }
 
-// Sequential chain state: stack st[0..h) in memory with its top four
-// entries mirrored in registers (t1 = st[h-1] ... t4 = st[h-4]), so a pop
-// only issues a load for an entry that is needed two pops later.  seg is
-// where the current set's part of the stack starts.
-struct ChainState {
-    uint64_t t1, t2, t3, t4;
-    int h, seg;
+// ---------------------------------------------------------------------------
+// Level 0: one wave per CHAIN_C consecutive sorted keys (four per lane).
+// Along x-sorted points of one set, a vertex of the lower chain on its
+// falling part has a smaller y than every earlier point, and on its rising
+// part a smaller y than every later point (the first and last points count
+// as such).  Mirrored with maxima for the upper chain.  So only strict
+// prefix/suffix minima and maxima of y can be chain vertices; two wave-wide
+// scans find them (about ln CHAIN_C of each kind for points in general
+// position).  Lanes 0 and 1 then run the lower and upper chain over those
+// candidates in LDS.  A chunk that spans two sets keeps every point.
+constexpr uint32_t YMIN_ID = 0x7fffffffu;   // identity of min over y < 2^24
+constexpr int32_t YMAX_ID = -1;
+
+struct Chain0Lds {
+    uint64_t cand[CHAIN_C];
+    uint64_t stk[2][CHAIN_C];
 };
 
-template <bool UPPER>
-__device__ __forceinline__ void chain_push(ChainState &c, uint64_t k, uint64_t *__restrict__ st) {
-    if (c.h > c.seg && key_set(c.t1) != key_set(k)) c.seg = c.h;
-    while (c.h - c.seg >= 2 && drop_mid<UPPER>(c.t2, c.t1, k)) {
-        c.h--;
-        c.t1 = c.t2;
-        c.t2 = c.t3;
-        c.t3 = c.t4;
-        if (c.h - c.seg >= 4) c.t4 = st[c.h - 4];
+__device__ __forceinline__ uint32_t scan_min_up(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (l >= o) v = min(v, t);
     }
-    st[c.h++] = k;
-    c.t4 = c.t3;
-    c.t3 = c.t2;
-    c.t2 = c.t1;
-    c.t1 = k;
+    return v;
+}
+__device__ __forceinline__ int32_t scan_max_up(int32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int32_t t = __shfl_up(v, o);
+        if (l >= o) v = max(v, t);
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t scan_min_down(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_down(v, o);
+        if (l + o < WAVE) v = min(v, t);
+    }
+    return v;
+}
+__device__ __forceinline__ int32_t scan_max_down(int32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int32_t t = __shfl_down(v, o);
+        if (l + o < WAVE) v = max(v, t);
+    }
+    return v;
 }
 
-__device__ __forceinline__ void load_keys8(const uint64_t *__restrict__ keys, int64_t base, int64_t b,
-                                           uint64_t kb[8]) {
-    if (base + 8 <= b) {
-        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(keys + base);
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            ulonglong2 v = p[q];
-            kb[2 * q] = v.x;
-            kb[2 * q + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 8; q++) kb[q] = base + q < b ? keys[base + q] : ~uint64_t(0);
-    }
-}
-
-// One thread per chunk: lower and upper chains of keys[a..b) in one walk;
-// keys are read eight at a time, the next eight in flight while the current
-// ones are consumed.
 __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict__ keys,
                                                       const int64_t *__restrict__ cnt_ptr,
                                                       uint64_t *__restrict__ lo,
                                                       uint64_t *__restrict__ up,
                                                       uint32_t *__restrict__ lo_cnt,
                                                       uint32_t *__restrict__ up_cnt) {
+    __shared__ Chain0Lds lds[4];
+    Chain0Lds &L = lds[threadIdx.x >> 6];
+    const int lane = lane_id();
     const int64_t cnt = *cnt_ptr;
     const int64_t U = (cnt + CHAIN_C - 1) / CHAIN_C;
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (U == 0 && j == 0) {   // no candidates: the chains are empty
+    const int64_t j = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (U == 0 && j == 0 && lane == 0) {   // no candidates: the chains are empty
         lo_cnt[0] = 0;
         up_cnt[0] = 0;
     }
     if (j >= U) return;
-    const int64_t a = j * CHAIN_C, b = min(a + CHAIN_C, cnt);
-    ChainState L{0, 0, 0, 0, 0, 0}, Up{0, 0, 0, 0, 0, 0};
-    uint64_t *lst = lo + a, *ust = up + a;
-    uint64_t prev = ~uint64_t(0);
-    uint64_t kb[8], kn[8];
-    load_keys8(keys, a, b, kb);
-    for (int64_t base = a; base < b; base += 8) {
-        if (base + 8 < b) load_keys8(keys, base + 8, b, kn);
+    const int64_t a = j * CHAIN_C, e = min(a + CHAIN_C, cnt);
+    uint64_t k[4];
+    bool valid[4];
+    const int64_t p = a + 4 * lane;
+    if (p + 4 <= e) {
+        const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(keys + p);
+        ulonglong2 v0 = q[0], v1 = q[1];
+        k[0] = v0.x; k[1] = v0.y; k[2] = v1.x; k[3] = v1.y;
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            uint64_t k = kb[q];
-            if (base + q >= b || k == prev) continue;
-            prev = k;
-            chain_push<false>(L, k, lst);
-            chain_push<true>(Up, k, ust);
+        for (int i = 0; i < 4; i++) valid[i] = true;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            valid[i] = p + i < e;
+            k[i] = valid[i] ? keys[p + i] : 0;
         }
-#pragma unroll
-        for (int q = 0; q < 8; q++) kb[q] = kn[q];
     }
-    lo_cnt[j] = (uint32_t)L.h;
-    up_cnt[j] = (uint32_t)Up.h;
+    const bool multi = key_set(keys[a]) != key_set(keys[e - 1]);
+    uint32_t ymin[4];
+    int32_t ymax[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        uint32_t yy = (uint32_t)(k[i] & 0xFFFFFF);
+        ymin[i] = valid[i] ? yy : YMIN_ID;
+        ymax[i] = valid[i] ? (int32_t)yy : YMAX_ID;
+    }
+    const uint32_t lmin = min(min(ymin[0], ymin[1]), min(ymin[2], ymin[3]));
+    const int32_t lmax = max(max(ymax[0], ymax[1]), max(ymax[2], ymax[3]));
+    uint32_t pmin = __shfl_up(scan_min_up(lmin), 1);
+    int32_t pmax = __shfl_up(scan_max_up(lmax), 1);
+    uint32_t smin = __shfl_down(scan_min_down(lmin), 1);
+    int32_t smax = __shfl_down(scan_max_down(lmax), 1);
+    if (lane == 0) { pmin = YMIN_ID; pmax = YMAX_ID; }
+    if (lane == WAVE - 1) { smin = YMIN_ID; smax = YMAX_ID; }
+    bool cand[4];
+    {
+        uint32_t rmin = pmin;
+        int32_t rmax = pmax;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {            // strict prefix records
+            cand[i] = valid[i] && (multi || ymin[i] < rmin || ymax[i] > rmax);
+            rmin = min(rmin, ymin[i]);
+            rmax = max(rmax, ymax[i]);
+        }
+        rmin = smin;
+        rmax = smax;
+#pragma unroll
+        for (int i = 3; i >= 0; i--) {           // strict suffix records
+            cand[i] = cand[i] || (valid[i] && (ymin[i] < rmin || ymax[i] > rmax));
+            rmin = min(rmin, ymin[i]);
+            rmax = max(rmax, ymax[i]);
+        }
+    }
+    // compact the candidates in key order: (lane, item)
+    const uint64_t lt = lanemask_lt();
+    int pos = 0, nc = 0;
+    uint64_t B[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        B[i] = __ballot(cand[i]);
+        pos += __popcll(B[i] & lt);
+        nc += __popcll(B[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        if (cand[i]) L.cand[pos++] = k[i];
+    wave_sync();
+    int h = 0;
+    if (lane < 2) {   // lane 0: lower chain, lane 1: upper chain
+        const double sg = lane == 0 ? 1.0 : -1.0;
+        uint64_t *st = L.stk[lane];
+        int seg = 0;
+        uint64_t prev = ~uint64_t(0);
+        for (int i = 0; i < nc; i++) {
+            uint64_t kk = L.cand[i];
+            if (kk == prev) continue;
+            prev = kk;
+            if (h > seg && key_set(st[h - 1]) != key_set(kk)) seg = h;
+            while (h - seg >= 2 && sg * korient(st[h - 2], st[h - 1], kk) <= 0) h--;
+            st[h++] = kk;
+        }
+    }
+    wave_sync();
+    const int hl = __builtin_amdgcn_readlane(h, 0), hu = __builtin_amdgcn_readlane(h, 1);
+    for (int i = lane; i < hl; i += WAVE) lo[a + i] = L.stk[0][i];
+    for (int i = lane; i < hu; i += WAVE) up[a + i] = L.stk[1][i];
+    if (lane == 0) {
+        lo_cnt[j] = (uint32_t)hl;
+        up_cnt[j] = (uint32_t)hu;
+    }
 }
 
 // Index of the first element of src[lo..hi) whose set equals set(src[hi-1]).
-__device__ __forceinline__ int64_t last_seg_start(const uint64_t *__restrict__ src, int64_t lo,
-                                                  int64_t hi) {
+template <typename P>
+__device__ __forceinline__ int64_t last_seg_start(P src, int64_t lo, int64_t hi) {
     uint32_t s = key_set(src[hi - 1]);
     while (lo < hi - 1) {
         int64_t mid = (lo + hi - 1) >> 1;
@@ -131,57 +213,106 @@ __device__ __forceinline__ int64_t last_seg_start(const uint64_t *__restrict__ s
     return lo;
 }
 
-// One wave per group of CHAIN_G chains of level `lev` (unit span R keys).
-// blockIdx.y: 0 = lower chains, 1 = upper chains.
+// Walk the junction of the chain built so far (o[0..len), its last set
+// segment starting at tailseg) with the next chain c[0..m) to their common
+// tangent.  Returns the new length of o and sets *bstart to the first
+// element of c to append.
+template <bool UPPER, typename PO, typename PC>
+__device__ __forceinline__ int64_t bridge(PO o, int64_t len, int64_t tailseg, PC c, int64_t m,
+                                          int64_t *bstart) {
+    int64_t b = 0;
+    if (len > 0) {
+        uint64_t last = o[len - 1];
+        if (c[0] == last) b = 1;
+        if (b < m && key_set(last) == key_set(c[b])) {
+            int64_t a = len - 1;
+            bool changed = true;
+            while (changed) {
+                changed = false;
+                while (a > tailseg && drop_mid<UPPER>(o[a - 1], o[a], c[b])) {
+                    a--;
+                    changed = true;
+                }
+                while (b + 1 < m && key_set(c[b + 1]) == key_set(c[b]) &&
+                       drop_mid<UPPER>(o[a], c[b], c[b + 1])) {
+                    b++;
+                    changed = true;
+                }
+            }
+            len = a + 1;
+        }
+    }
+    *bstart = b;
+    return len;
+}
+
+// Merge of CHAIN_G neighbouring chains by one wave.  Small groups are staged
+// in LDS (walks at LDS latency); larger ones walk in global memory.
+constexpr int MERGE_CAP = 1024;
+
 template <bool UPPER>
 __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__restrict__ cin,
                             int64_t U, int64_t R, int64_t v, uint64_t *__restrict__ out,
-                            uint32_t *__restrict__ cout) {
+                            uint32_t *__restrict__ cout, uint64_t *__restrict__ buf) {
     const int lane = lane_id();
     const int64_t base = v * R * CHAIN_G;
     uint64_t *o = out + base;
+    // chain sizes of the group and their offsets
+    const int64_t u0 = v * CHAIN_G;
+    int64_t mine = (lane < CHAIN_G && u0 + lane < U) ? (int64_t)cin[u0 + lane] : 0;
+    int64_t incl = wave_incl_scan_i64(mine);
+    const int64_t M = __shfl(incl, WAVE - 1);
     int64_t len = 0, tailseg = 0;
-    for (int g = 0; g < CHAIN_G; g++) {
-        const int64_t u = v * CHAIN_G + g;
-        if (u >= U) break;
-        const uint64_t *src = in + u * R;
-        const int64_t m = cin[u];
-        if (m == 0) continue;
-        int64_t b = 0;
-        if (len > 0) {
-            uint64_t last = o[len - 1];
-            if (src[0] == last) b = 1;
-            if (b < m && key_set(last) == key_set(src[b])) {
-                int64_t a = len - 1;
-                bool changed = true;
-                while (changed) {
-                    changed = false;
-                    while (a > tailseg && drop_mid<UPPER>(o[a - 1], o[a], src[b])) {
-                        a--;
-                        changed = true;
-                    }
-                    while (b + 1 < m && key_set(src[b + 1]) == key_set(src[b]) &&
-                           drop_mid<UPPER>(o[a], src[b], src[b + 1])) {
-                        b++;
-                        changed = true;
-                    }
+    if (M <= MERGE_CAP) {
+        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+            const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
+            const uint64_t *src = in + (u0 + g) * R;
+            for (int64_t i = lane; i < m; i += WAVE) buf[og + i] = src[i];
+        }
+        wave_sync();
+        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+            const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
+            if (m == 0) continue;
+            const uint64_t *c = buf + og;
+            int64_t b;
+            len = bridge<UPPER>(buf, len, tailseg, c, m, &b);
+            if (b < m) {
+                int64_t ls = last_seg_start(c, b, m);
+                int64_t newtail;
+                if (ls > b) newtail = len + (ls - b);
+                else newtail = (len > 0 && key_set(buf[len - 1]) == key_set(c[b])) ? tailseg : len;
+                // move c[b..m) down to buf[len..): len <= og + b, copy forward
+                for (int64_t i0 = 0; i0 < m - b; i0 += WAVE) {
+                    int64_t i = i0 + lane;
+                    uint64_t val = i < m - b ? c[b + i] : 0;
+                    wave_sync();
+                    if (i < m - b) buf[len + i] = val;
+                    wave_sync();
                 }
-                len = a + 1;
+                len += m - b;
+                tailseg = newtail;
             }
         }
-        if (b < m) {
-            // the appended part's last set segment decides where the tail starts
-            int64_t ls = last_seg_start(src, b, m);
-            int64_t newtail;
-            if (ls > b) newtail = len + (ls - b);
-            else newtail = (len > 0 && key_set(o[len - 1]) == key_set(src[b])) ? tailseg : len;
-            // all lanes must have read o[] before it is overwritten
-            wave_sync();
-            for (int64_t i = b + lane; i < m; i += WAVE) o[len + (i - b)] = src[i];
-            wave_sync();
-            __threadfence_block();
-            len += m - b;
-            tailseg = newtail;
+        for (int64_t i = lane; i < len; i += WAVE) o[i] = buf[i];
+    } else {
+        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+            const int64_t m = __shfl(mine, g);
+            if (m == 0) continue;
+            const uint64_t *src = in + (u0 + g) * R;
+            int64_t b;
+            len = bridge<UPPER>(o, len, tailseg, src, m, &b);
+            if (b < m) {
+                int64_t ls = last_seg_start(src, b, m);
+                int64_t newtail;
+                if (ls > b) newtail = len + (ls - b);
+                else newtail = (len > 0 && key_set(o[len - 1]) == key_set(src[b])) ? tailseg : len;
+                wave_sync();
+                for (int64_t i = b + lane; i < m; i += WAVE) o[len + (i - b)] = src[i];
+                __threadfence_block();
+                wave_sync();
+                len += m - b;
+                tailseg = newtail;
+            }
         }
     }
     if (lane == 0) cout[v] = (uint32_t)len;
@@ -196,6 +327,7 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
                                                      uint64_t *__restrict__ up_out,
                                                      uint32_t *__restrict__ lo_cout,
                                                      uint32_t *__restrict__ up_cout) {
+    __shared__ uint64_t mbuf[4][MERGE_CAP];
     const int64_t cnt = *cnt_ptr;
     int64_t R = CHAIN_C;
     for (int l = 0; l < lev; l++) R *= CHAIN_G;
@@ -205,8 +337,9 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     if (V == 0 && v == 0 && threadIdx.x == 0)   // no candidates: empty top chain
         (blockIdx.y == 0 ? lo_cout : up_cout)[0] = 0;
     if (v >= V) return;
-    if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lo_out, lo_cout);
-    else merge_group<true>(up_in, up_cin, U, R, v, up_out, up_cout);
+    uint64_t *buf = mbuf[threadIdx.x >> 6];
+    if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lo_out, lo_cout, buf);
+    else merge_group<true>(up_in, up_cin, U, R, v, up_out, up_cout, buf);
 }
 
 // Fill helpers (kernels, so that graph capture records no memset node).

@@ -223,3 +223,43 @@ def batch(sizes, seed, kinds=("square", "disk", "gaussian", "annulus")):
         y[off[i]:off[i + 1]] = sy
         names.append(k)
     return x, y, off, names
+
+
+def mixture_batch_torch(S, n, seed, device="cuda:0", oversample=1.3):
+    """S anisotropic Gaussian-mixture sets of n points each, drawn on the
+    device with torch (same recipe as mixture(): K ~ U{1..8}, Dirichlet(1)
+    weights, means U[0.25, 0.75]^2, major sigma U[0.02, 0.12], axis ratio
+    log-uniform [1, 50], rotation U[0, pi)).  Points outside [0, 1)^2 are
+    replaced by later draws of the same set; in the rare set that runs out of
+    draws the last points are clamped into the square.  Returns float32
+    x, y of length S*n (set s = [s*n, (s+1)*n)) on the device."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    K = torch.randint(1, 9, (S,), generator=g, device=device)
+    comp_ok = torch.arange(8, device=device)[None, :] < K[:, None]
+    e = -torch.log(torch.rand((S, 8), generator=g, device=device, dtype=f64).clamp_min(1e-300))
+    w = torch.where(comp_ok, e, torch.zeros_like(e))
+    w = w / w.sum(1, keepdim=True)
+    mu = 0.25 + 0.5 * torch.rand((S, 8, 2), generator=g, device=device, dtype=f64)
+    smaj = 0.02 + 0.10 * torch.rand((S, 8), generator=g, device=device, dtype=f64)
+    ratio = torch.exp(torch.rand((S, 8), generator=g, device=device, dtype=f64) * np.log(50.0))
+    rot = np.pi * torch.rand((S, 8), generator=g, device=device, dtype=f64)
+    m = int(n * oversample) + 16
+    comp = torch.multinomial(w.float(), m, replacement=True, generator=g)          # [S, m]
+    a = torch.randn((S, m), generator=g, device=device, dtype=f64) * torch.gather(smaj, 1, comp)
+    b = torch.randn((S, m), generator=g, device=device, dtype=f64) * \
+        torch.gather(smaj / ratio, 1, comp)
+    c, s_ = torch.cos(torch.gather(rot, 1, comp)), torch.sin(torch.gather(rot, 1, comp))
+    px = torch.gather(mu[:, :, 0], 1, comp) + c * a - s_ * b
+    py = torch.gather(mu[:, :, 1], 1, comp) + s_ * a + c * b
+    ok = (px >= 0) & (px < 1) & (py >= 0) & (py < 1)
+    order = torch.argsort((~ok).to(torch.int8), dim=1, stable=True)[:, :n]
+    px = torch.gather(px, 1, order).clamp(0.0, 1.0 - 1.0 / GRID)
+    py = torch.gather(py, 1, order).clamp(0.0, 1.0 - 1.0 / GRID)
+    kx = torch.floor(px * GRID).clamp(0, GRID - 1)
+    ky = torch.floor(py * GRID).clamp(0, GRID - 1)
+    scale = 1.0 / GRID
+    return ((kx * scale).to(torch.float32).reshape(-1).contiguous(),
+            (ky * scale).to(torch.float32).reshape(-1).contiguous())

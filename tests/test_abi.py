@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "hull.h")
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(hull_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|const char \*)\s*(hull_\w+)\s*\(", txt, re.M)))
 
 
 @pytest.fixture(scope="module")

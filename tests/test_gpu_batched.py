@@ -1,0 +1,154 @@
+"""Batched forms (many sets, CSR offsets) against the per-set CPU oracle.
+
+Each set's batched result must equal the oracle's result for that set alone
+(global indices = set-local indices + the set's offset): extreme slots,
+survivors and hull, exactly.  Graph replays and launch shapes must not change
+any bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1405_3454_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1405_3454_amd.api import Hull
+    h = Hull(0)
+    yield h
+    torch.cuda.synchronize()
+    h.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def u32(t):
+    from paper_1405_3454_amd.api import as_u32
+    return as_u32(t)
+
+
+def make_batch(sizes, seed, kinds=("square", "disk", "gaussian", "annulus")):
+    return inputs.batch(sizes, seed, kinds)
+
+
+def oracle_sets(x, y, off, preset):
+    res = []
+    for s in range(len(off) - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        xs, ys = x[a:b], y[a:b]
+        slots, _ = oracle.extremes(xs, ys, preset)
+        verts = oracle.polygon(xs, ys, slots)
+        surv = oracle.discard(xs, ys, verts)
+        hull = oracle.hull_subset(xs, ys, surv)
+        g = lambda v: np.where(v == oracle.NONE, oracle.NONE, v.astype(np.int64) + a).astype(np.uint32)
+        res.append((g(slots), surv.astype(np.int64) + a, hull.astype(np.int64) + a))
+    return res
+
+
+def check_batch(H, x, y, off, preset=0, what=""):
+    H.set_directions(preset)
+    xt, yt, ot = dev(x), dev(y), dev(off.astype(np.int64))
+    want = oracle_sets(x, y, off, preset)
+    S = len(off) - 1
+    slots = u32(H.extremes_batched(xt, yt, ot)).reshape(S, 16)
+    for s in range(S):
+        assert np.array_equal(slots[s], want[s][0]), (what, s, slots[s], want[s][0])
+    surv, so = H.discard_batched(xt, yt, ot, dev(slots.view(np.int32)))
+    so = so.cpu().numpy()
+    sv = u32(surv)
+    for s in range(S):
+        assert np.array_equal(sv[so[s]:so[s + 1]], want[s][1]), (what, "surv", s)
+    hull, ho = H.compute_batched(xt, yt, ot)
+    ho = ho.cpu().numpy()
+    hv = u32(hull)
+    for s in range(S):
+        assert np.array_equal(hv[ho[s]:ho[s + 1]], want[s][2]), (what, "hull", s,
+                                                               hv[ho[s]:ho[s + 1]][:8], want[s][2][:8])
+    return hv, ho
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ragged_small_sets(H, seed):
+    r = np.random.default_rng(seed)
+    sizes = list(r.integers(0, 3000, size=37)) + [0, 1, 2, 3, 4, 5, 1023, 1024, 1025, 0]
+    r.shuffle(sizes)
+    x, y, off, _ = make_batch(sizes, 50 + seed)
+    check_batch(H, x, y, off, seed % 2, "ragged seed=%d" % seed)
+
+
+def test_single_set_equals_plain(H):
+    x, y = inputs.annulus(200_000, 3)
+    off = np.array([0, len(x)], np.int64)
+    hv, ho = check_batch(H, x, y, off, 0, "single")
+    assert np.array_equal(hv[:ho[1]], u32(H.compute(dev(x), dev(y))))
+
+
+def test_log_uniform_batch(H):
+    sizes = inputs.batch_sizes(256, 9, lo=1_000, hi=100_000)
+    x, y, off, _ = make_batch(sizes, 10)
+    check_batch(H, x, y, off, 0, "log-uniform")
+
+
+def test_degenerate_sets_in_batch(H):
+    parts = []
+    for s in range(20):
+        n = 1 + 37 * s
+        parts.append(inputs.small_grid(n, 1 + s % 5, s, (1000 * s, 77)))
+    parts.append(inputs.regular_polygon(48, 500, seed=1)[:2])
+    x = np.concatenate([p[0] for p in parts])
+    y = np.concatenate([p[1] for p in parts])
+    off = np.concatenate([[0], np.cumsum([len(p[0]) for p in parts])]).astype(np.int64)
+    check_batch(H, x, y, off, 1, "degenerate")
+
+
+def test_unfiltered_batched(H):
+    sizes = [0, 5, 1000, 20000, 3]
+    x, y, off, _ = make_batch(sizes, 4)
+    hull, ho = H.compute_batched(dev(x), dev(y), dev(off), nofilter=True)
+    ho = ho.cpu().numpy()
+    hv = u32(hull)
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        want = oracle.hull_subset(x[a:b], y[a:b]).astype(np.int64) + a
+        assert np.array_equal(hv[ho[s]:ho[s + 1]], want)
+
+
+def test_graph_replay_matches_eager(H):
+    import torch
+    sizes = inputs.batch_sizes(64, 21, lo=1_000, hi=50_000)
+    x, y, off, _ = make_batch(sizes, 22)
+    xt, yt, ot = dev(x), dev(y), dev(off)
+    eager, eho = H.compute_batched(xt, yt, ot)
+    eager = u32(eager)[: int(eho[-1].item())]
+    hull = torch.full((len(x),), -7, dtype=torch.int32, device="cuda:0")
+    ho = torch.zeros(len(sizes) + 1, dtype=torch.int64, device="cuda:0")
+    H.graph_capture(xt, yt, ot, hull, ho)
+    for rep in range(4):
+        hull.fill_(-7)
+        ho.zero_()
+        torch.cuda.synchronize()
+        H.graph_launch()
+        torch.cuda.synchronize()
+        got = u32(hull)[: int(ho[-1].item())]
+        assert np.array_equal(got, eager), rep
+        # eager work between replays
+        H.compute(xt[:1000], yt[:1000])
+
+
+def test_autotune_keeps_results(H):
+    sizes = inputs.batch_sizes(32, 5, lo=1_000, hi=200_000)
+    x, y, off, _ = make_batch(sizes, 6)
+    xt, yt, ot = dev(x), dev(y), dev(off)
+    a, ao = H.compute_batched(xt, yt, ot)
+    a = u32(a)[: int(ao[-1].item())].copy()
+    H.autotune(xt, yt, ot)
+    b, bo = H.compute_batched(xt, yt, ot)
+    assert np.array_equal(u32(b)[: int(bo[-1].item())], a)
+    assert np.array_equal(ao.cpu().numpy(), bo.cpu().numpy())

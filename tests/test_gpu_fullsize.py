@@ -1,0 +1,51 @@
+"""Parity at the benchmark's full size: 2^27 points per set, in the launch
+configuration bench.py times (default tuning), for each distribution.
+
+The oracle runs the whole method on the same arrays (about 10-30 s per set on
+one core); extreme slots and values, the survivor list and the hull must be
+identical.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1405_3454_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 27
+SEEDS = {"square": 101, "disk": 102, "gaussian": 103, "annulus": 104}   # bench.py's inputs
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1405_3454_amd.api import Hull
+    h = Hull(0)
+    yield h
+    torch.cuda.synchronize()
+    h.close()
+
+
+@pytest.mark.parametrize("kind", ["square", "disk", "gaussian", "annulus"])
+def test_full_size(H, kind):
+    import torch
+    from paper_1405_3454_amd.api import as_u32
+    x, y = inputs.DISTRIBUTIONS[kind](N, SEEDS[kind])
+    xt = torch.from_numpy(x).to("cuda:0")
+    yt = torch.from_numpy(y).to("cuda:0")
+    H.set_directions(0)
+    slots, vals = H.extremes(xt, yt)
+    surv = H.discard(xt, yt, slots)
+    hull = H.compute(xt, yt)
+    g_slots, g_vals, g_surv, g_hull = as_u32(slots), vals.cpu().numpy(), as_u32(surv), as_u32(hull)
+    del xt, yt
+    o_slots, o_vals = oracle.extremes(x, y)
+    assert np.array_equal(g_slots, o_slots)
+    assert np.array_equal(g_vals.view(np.uint64), o_vals.view(np.uint64))
+    o_verts = oracle.polygon(x, y, o_slots)
+    o_surv = oracle.discard(x, y, o_verts)
+    assert len(g_surv) == len(o_surv)
+    assert np.array_equal(g_surv, o_surv)
+    o_hull = oracle.hull_subset(x, y, o_surv)
+    assert np.array_equal(g_hull, o_hull)
