@@ -209,6 +209,70 @@ class Hull:
     def graph_launch(self, stream=None):
         check(lib().hull_graph_launch(self._h, _stream(stream)), "hull_graph_launch")
 
+    # -- learned direction proposal ----------------------------------------
+    def mlp_param_count(self):
+        return int(lib().hull_mlp_param_count())
+
+    def mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        check(lib().hull_mlp_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size),
+              "hull_mlp_set_params")
+
+    def mlp_get_params(self):
+        p = np.zeros(self.mlp_param_count(), np.float32)
+        check(lib().hull_mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size),
+              "hull_mlp_get_params")
+        return p
+
+    def histogram_batched(self, x, y, offsets=None, stream=None):
+        """(bf16 bits as int16 [S][1024], float32 [S][1024])"""
+        n = _pts(x, y)
+        S = 1 if offsets is None else offsets.numel() - 1
+        hb = torch.empty((S, 1024), dtype=torch.int16, device=x.device)
+        hf = torch.empty((S, 1024), dtype=torch.float32, device=x.device)
+        check(lib().hull_histogram_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n, _ptr(hb),
+                                           _ptr(hf), _stream(stream)), "hull_histogram_batched")
+        return hb, hf
+
+    def mlp_forward(self, hist, stream=None):
+        B = hist.shape[0]
+        sc = torch.empty((B, 64), dtype=torch.float32, device=hist.device)
+        check(lib().hull_mlp_forward(self._h, _ptr(hist), B, _ptr(sc), _stream(stream)),
+              "hull_mlp_forward")
+        return sc
+
+    def mlp_backward(self, hist, dscores, stream=None):
+        B = hist.shape[0]
+        dscores = dscores.to(device=hist.device, dtype=torch.float32).contiguous()
+        g = torch.empty(self.mlp_param_count(), dtype=torch.float32, device=hist.device)
+        check(lib().hull_mlp_backward(self._h, _ptr(hist), _ptr(dscores), B, _ptr(g),
+                                      _stream(stream)), "hull_mlp_backward")
+        return g
+
+    def mlp_train_step(self, hist, gain, lr, stream=None):
+        B = hist.shape[0]
+        gain = gain.to(device=hist.device, dtype=torch.float32).contiguous()
+        loss = torch.zeros(1, dtype=torch.float32, device=hist.device)
+        check(lib().hull_mlp_train_step(self._h, _ptr(hist), _ptr(gain), B, ctypes.c_float(lr),
+                                        _ptr(loss), _stream(stream)), "hull_mlp_train_step")
+        return loss
+
+    def top_directions(self, scores, stream=None):
+        S = scores.shape[0]
+        scores = scores.to(dtype=torch.float32).contiguous()
+        d = torch.empty((S, 8), dtype=torch.int32, device=scores.device)
+        check(lib().hull_top_directions(self._h, _ptr(scores), S, _ptr(d), _stream(stream)),
+              "hull_top_directions")
+        return d
+
+    def labels_batched(self, x, y, offsets, stream=None):
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        g = torch.empty((S, 64), dtype=torch.float32, device=x.device)
+        check(lib().hull_labels_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n, _ptr(g),
+                                        _stream(stream)), "hull_labels_batched")
+        return g
+
     # -- timing ------------------------------------------------------------
     def timing(self, on=True):
         check(lib().hull_timing_enable(self._h, int(bool(on))), "hull_timing_enable")

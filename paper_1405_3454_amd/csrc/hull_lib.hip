@@ -46,7 +46,9 @@ struct hull_ctx {
     char *ws = nullptr;
     size_t ws_cap = 0;
     std::vector<char *> retired;        // old workspaces a graph may still use
-    int k1_bpc = 8, k3_bpc = 8;        // blocks per CU of the filter kernels
+    // blocks per CU of the persistent filter kernels: what stays resident
+    // (extremes: ~140 VGPRs -> 3 waves per SIMD; discard: ~112 -> 4)
+    int k1_bpc = 3, k3_bpc = 4;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -201,7 +203,10 @@ static int check_points(const float *x, const float *y, int64_t n) {
     return HULL_OK;
 }
 
-static int grid_k1(hull_ctx *ctx) { return ctx->cus * ctx->k1_bpc; }
+// the learned variant of the extremes pass holds ~190 VGPRs: 2 waves per SIMD
+static int grid_k1(hull_ctx *ctx, bool learned = false) {
+    return ctx->cus * (learned ? std::min(ctx->k1_bpc, 2) : ctx->k1_bpc);
+}
 static int grid_k3(hull_ctx *ctx) { return ctx->cus * ctx->k3_bpc; }
 
 // ---------------------------------------------------------------------------
@@ -245,7 +250,7 @@ static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
     double *pval = W<double>(ctx, p.pval);
     uint32_t *pidx = W<uint32_t>(ctx, p.pidx);
     const double *sd = W<double>(ctx, p.setdirs);
-    const int g = grid_k1(ctx);
+    const int g = grid_k1(ctx, learned);
     const Dirs d = ctx->dirs;
 #define K1(PR, ND)                                                                           \
     LAUNCH(K_EXTREMES, k_extremes<PR, ND><<<g, 256, 0, st>>>(x, y, n_total, off, n1, S,     \
@@ -263,7 +268,7 @@ static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
 static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const float *y, int64_t n_total, int64_t S, bool learned, const uint32_t *slots_in,
                        int n_in, uint32_t *slots_out, double *vals_out) {
-    const int64_t W1 = (int64_t)grid_k1(ctx) * 4;
+    const int64_t W1 = (int64_t)grid_k1(ctx, learned) * 4;
     auto *polys = W<Poly>(ctx, p.polys);
     auto *spans = W<Span>(ctx, p.spans);
     const double *sd = W<double>(ctx, p.setdirs);
@@ -744,7 +749,7 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     hipEvent_t a, b;
     HIPCHECK(hipEventCreate(&a));
     HIPCHECK(hipEventCreate(&b));
-    const int cand[] = {2, 4, 6, 8, 12, 16};
+    const int cand[] = {1, 2, 3, 4, 6, 8};
     float best1 = 1e30f, best3 = 1e30f;
     int b1 = ctx->k1_bpc, b3 = ctx->k3_bpc;
     uint32_t *surv = W<uint32_t>(ctx, p.surv);

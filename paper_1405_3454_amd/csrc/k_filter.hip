@@ -8,6 +8,8 @@
 // [o_s, o_{s+1}) are masked.  The persistent filter kernels give wave w the
 // contiguous tile range [w q, (w+1) q), q = ceil(T / W), so a wave walks
 // ascending point indices and meets each set as one contiguous "run".
+#include <type_traits>
+
 #include "hg_device.h"
 
 namespace hg {
@@ -179,17 +181,26 @@ __device__ __forceinline__ double proj_dir(double c, double s, double xd, double
     return c * xd + s * yd;
 }
 
-// key of fixed slot k (0..15) as a maximum
-__device__ __forceinline__ double slot_key(int k, const double u[4], const double v[4]) {
-    int g = k >> 2, t = k & 3;
-    double w = (t < 2) ? u[g] : v[g];
-    return (t & 1) ? w : -w;
+// Rotated coordinate behind fixed slot k (0..15): slots 4g, 4g+1 are the
+// min and max of u, slots 4g+2, 4g+3 the min and max of v of group g.
+__device__ __forceinline__ double slot_val(int k, const double u[4], const double v[4]) {
+    const int g = k >> 2;
+    return (k & 2) ? v[g] : u[g];
+}
+// Fixed slots with even index are minima; all others (learned ones too) maxima.
+__device__ __forceinline__ constexpr bool slot_is_min(int k, int nfixed) {
+    return k < nfixed && (k & 1) == 0;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
 }
 
-// Step 1: per-wave running maxima of every slot key over the wave's tiles,
-// with the lowest index on ties; one partial per (wave, set) run, stored at
-// the run's first tile.  Learned directions (NDIR > 0) come per set from
-// set_dirs[s][d] = (c, s).
+// Step 1: per-wave running minima/maxima of every slot over the wave's
+// tiles, with the lowest index on ties; one partial per (wave, set) run,
+// stored at the run's first tile.  Learned directions (NDIR > 0) come per set
+// from set_dirs[s][d] = (c, s).
 template <int PRESET, int NDIR>
 __global__ __launch_bounds__(256) void k_extremes(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(256) void k_extremes(
     constexpr int NG = Proj<PRESET>::NG;
     constexpr int NF = 4 * NG;           // fixed slots evaluated
     constexpr int NS = NF + NDIR;        // slots tracked
-    // running maxima of the wave (LDS: read once per chunk and slot)
+    // running extremes of the wave (LDS: read once per chunk and slot)
     __shared__ double sbv[4][NS];
     __shared__ uint32_t sbi[4][NS];
     double *bv = sbv[threadIdx.x >> 6];
@@ -216,9 +227,72 @@ __global__ __launch_bounds__(256) void k_extremes(
     int64_t cur = -1, run = t0, o0 = 0, o1 = 0, tile0 = 0, abase = 0;
     float x0f = 0.0f, y0f = 0.0f;
 
+    // One chunk of 256 points (4 per lane).  FULL: every slot lies in the
+    // set; otherwise slots outside it hold a copy of the set's first point
+    // o0, which never moves an extreme (o0 itself is met in the set's first
+    // chunk, at or before any copy) and is never chosen as the index.
+    auto chunk = [&](auto full_tag, const float *xv, const float *yv, int64_t cb) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        const int64_t a = cb + 4 * lane;
+        double acc[NS];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const bool valid = FULL || ((a + j >= o0) && (a + j < o1));
+            double xd = valid ? xv[j] : x0f, yd = valid ? yv[j] : y0f;
+            double u[4], v[4];
+            Proj<PRESET>::uv(dirs, xd, yd, u, v);
+#pragma unroll
+            for (int k = 0; k < NF; k++) {
+                double w = slot_val(k, u, v);
+                acc[k] = j == 0 ? w : (slot_is_min(k, NF) ? fmin(acc[k], w) : fmax(acc[k], w));
+            }
+#pragma unroll
+            for (int d = 0; d < NDIR; d++) {
+                double w = proj_dir(dc[d], ds[d], xd, yd);
+                acc[NF + d] = j == 0 ? w : fmax(acc[NF + d], w);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NS; k++) {
+            const bool mn = slot_is_min(k, NF);
+            if (__ballot(mn ? acc[k] < bv[k] : acc[k] > bv[k])) {
+                // rare: a new extreme in this chunk; take the lowest index.
+                // The points are read again (cache hits).
+                double m = mn ? wave_min(acc[k]) : wave_max(acc[k]);
+                float rx[4], ry[4];
+                load4(x, y, a, n_total, rx, ry);
+                int cand = 4;
+#pragma unroll
+                for (int j = 3; j >= 0; j--) {
+                    const bool valid = (a + j >= o0) && (a + j < o1);
+                    double xd = rx[j], yd = ry[j], key;
+                    if (k < NF) {
+                        double u[4], v[4];
+                        Proj<PRESET>::uv(dirs, xd, yd, u, v);
+                        key = slot_val(k, u, v);
+                    } else {
+                        key = proj_dir(dc[k - NF], ds[k - NF], xd, yd);
+                    }
+                    if (valid && key == m) cand = j;
+                }
+                uint64_t has = __ballot(cand < 4);
+                int L = __ffsll((unsigned long long)has) - 1;
+                int cj = __builtin_amdgcn_readlane(cand, L);
+                wave_sync();
+                if (lane == 0) {
+                    bv[k] = m;
+                    bi[k] = (uint32_t)(cb + 4 * L + cj);
+                }
+                wave_sync();
+            }
+        }
+    };
+
+    int64_t cur_end = -1;   // first tile after the current set
     for (int64_t t = t0; t < t1; ++t) {
-        const int64_t s = tile_set[t];
-        if (s != cur) {
+        if (t >= cur_end) {     // a new set starts (looked up once per set)
+            const int64_t s = tile_set[t];
+            cur_end = tile_off[s + 1];
             wave_sync();
             if (cur >= 0 && lane < NS) {
                 pval[run * MAX_SLOTS + lane] = bv[lane];
@@ -234,7 +308,7 @@ __global__ __launch_bounds__(256) void k_extremes(
             x0f = x[o0];
             y0f = y[o0];
             if (lane < NS) {
-                bv[lane] = -INFINITY;
+                bv[lane] = slot_is_min(lane, NF) ? INFINITY : -INFINITY;
                 bi[lane] = NONE;
             }
 #pragma unroll
@@ -249,63 +323,14 @@ __global__ __launch_bounds__(256) void k_extremes(
         float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
 #pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
+        if (tb >= o0 && tb + TILE <= o1) {
 #pragma unroll
-        for (int c = 0; c < TILE_CHUNKS; c++) {
-            const int64_t cb = tb + c * CHUNK;          // global index of lane 0, item 0
-            const int64_t a = cb + 4 * lane;
-            // per-lane maxima of every slot key over the lane's four points.
-            // Slots outside the set hold a copy of the set's first point o0:
-            // it never raises a maximum (o0 itself is met in the set's first
-            // chunk, at or before any copy) and is never chosen as the index.
-            double acc[NS];
+            for (int c = 0; c < TILE_CHUNKS; c++)
+                chunk(std::integral_constant<bool, true>(), xv[c], yv[c], tb + c * CHUNK);
+        } else {
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const bool valid = (a + j >= o0) && (a + j < o1);
-                double xd = valid ? xv[c][j] : x0f, yd = valid ? yv[c][j] : y0f;
-                double u[4], v[4];
-                Proj<PRESET>::uv(dirs, xd, yd, u, v);
-#pragma unroll
-                for (int k = 0; k < NF; k++)
-                    acc[k] = j == 0 ? slot_key(k, u, v) : fmax(acc[k], slot_key(k, u, v));
-#pragma unroll
-                for (int d = 0; d < NDIR; d++) {
-                    double w = proj_dir(dc[d], ds[d], xd, yd);
-                    acc[NF + d] = j == 0 ? w : fmax(acc[NF + d], w);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < NS; k++) {
-                if (__ballot(acc[k] > bv[k])) {
-                    // rare: a new maximum in this chunk; take the lowest
-                    // index.  The points are read again (cache hits).
-                    double m = wave_max(acc[k]);
-                    float rx[4], ry[4];
-                    load4(x, y, a, n_total, rx, ry);
-                    int cand = 4;
-#pragma unroll
-                    for (int j = 3; j >= 0; j--) {
-                        const bool valid = (a + j >= o0) && (a + j < o1);
-                        double xd = rx[j], yd = ry[j], key;
-                        if (k < NF) {
-                            double u[4], v[4];
-                            Proj<PRESET>::uv(dirs, xd, yd, u, v);
-                            key = slot_key(k, u, v);
-                        } else {
-                            key = proj_dir(dc[k - NF], ds[k - NF], xd, yd);
-                        }
-                        if (valid && key == m) cand = j;
-                    }
-                    uint64_t has = __ballot(cand < 4);
-                    int L = __ffsll((unsigned long long)has) - 1;
-                    int cj = __builtin_amdgcn_readlane(cand, L);
-                    wave_sync();
-                    if (lane == 0) {
-                        bv[k] = m;
-                        bi[k] = (uint32_t)(cb + 4 * L + cj);
-                    }
-                    wave_sync();
-                }
-            }
+            for (int c = 0; c < TILE_CHUNKS; c++)
+                chunk(std::integral_constant<bool, false>(), xv[c], yv[c], tb + c * CHUNK);
         }
     }
     wave_sync();
@@ -326,8 +351,9 @@ struct SlotBest {
     uint32_t i;
 };
 
-__device__ __forceinline__ bool better(double v, uint32_t i, double bv, uint32_t bi) {
-    return v > bv || (v == bv && i < bi);
+// (v, i) beats (bv, bi) for a minimum (mn) or maximum slot; lower index on ties
+__device__ __forceinline__ bool better(bool mn, double v, uint32_t i, double bv, uint32_t bi) {
+    return (mn ? v < bv : v > bv) || (v == bv && i < bi);
 }
 
 __device__ __forceinline__ double grid_of(float f) { return (double)f * GRIDD; }
@@ -378,18 +404,33 @@ __global__ __launch_bounds__(256) void k_polygon(
         uint32_t bi[NE];
 #pragma unroll
         for (int k = 0; k < NE; k++) {
-            bv[k] = -INFINITY;
+            bv[k] = slot_is_min(k, NEV) ? INFINITY : -INFINITY;
             bi[k] = NONE;
         }
-        for (int64_t r = tid; r < nruns; r += blockDim.x) {
-            int64_t t = r == 0 ? ta : m0 + (r - 1) * q;
+        // two runs per iteration so that both runs' loads are in flight together
+        for (int64_t r = tid; r < nruns; r += 2 * blockDim.x) {
+            const int64_t r2 = r + blockDim.x;
+            const int64_t t = r == 0 ? ta : m0 + (r - 1) * q;
+            const int64_t t2 = r2 < nruns ? m0 + (r2 - 1) * q : t;
+            double v1[NE], v2[NE];
+            uint32_t i1[NE], i2[NE];
 #pragma unroll
             for (int k = 0; k < NE; k++) {
-                double v = pval[t * MAX_SLOTS + k];
-                uint32_t i = pidx[t * MAX_SLOTS + k];
-                if (i != NONE && better(v, i, bv[k], bi[k])) {
-                    bv[k] = v;
-                    bi[k] = i;
+                v1[k] = pval[t * MAX_SLOTS + k];
+                i1[k] = pidx[t * MAX_SLOTS + k];
+                v2[k] = pval[t2 * MAX_SLOTS + k];
+                i2[k] = pidx[t2 * MAX_SLOTS + k];
+            }
+#pragma unroll
+            for (int k = 0; k < NE; k++) {
+                const bool mn = slot_is_min(k, NEV);
+                if (i1[k] != NONE && better(mn, v1[k], i1[k], bv[k], bi[k])) {
+                    bv[k] = v1[k];
+                    bi[k] = i1[k];
+                }
+                if (i2[k] != NONE && better(mn, v2[k], i2[k], bv[k], bi[k])) {
+                    bv[k] = v2[k];
+                    bi[k] = i2[k];
                 }
             }
         }
@@ -401,7 +442,7 @@ __global__ __launch_bounds__(256) void k_polygon(
             for (int o = 32; o >= 1; o >>= 1) {
                 double v2 = __shfl_xor(v, o);
                 uint32_t i2 = __shfl_xor(i, o);
-                if (i2 != NONE && (i == NONE || better(v2, i2, v, i))) {
+                if (i2 != NONE && (i == NONE || better(slot_is_min(k, NEV), v2, i2, v, i))) {
                     v = v2;
                     i = i2;
                 }
@@ -410,11 +451,12 @@ __global__ __launch_bounds__(256) void k_polygon(
         }
         __syncthreads();
         if (tid < NE) {
+            const bool mn = slot_is_min(tid, NEV);
             double v = wbest[0][tid].v;
             uint32_t i = wbest[0][tid].i;
             for (int ww = 1; ww < (int)(blockDim.x >> 6); ww++) {
                 SlotBest b = wbest[ww][tid];
-                if (b.i != NONE && (i == NONE || better(b.v, b.i, v, i))) {
+                if (b.i != NONE && (i == NONE || better(mn, b.v, b.i, v, i))) {
                     v = b.v;
                     i = b.i;
                 }
@@ -657,9 +699,11 @@ __global__ __launch_bounds__(256) void k_discard(
     bool has_rows = false;
     const Poly *P = polys;
 
+    int64_t cur_end = -1;   // first tile after the current set
     for (int64_t t = t0; t < t1; ++t) {
-        const int64_t s = tile_set[t];
-        if (s != cur) {
+        if (t >= cur_end) {     // a new set starts (looked up once per set)
+            const int64_t s = tile_set[t];
+            cur_end = tile_off[s + 1];
             cur = s;
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
@@ -680,12 +724,14 @@ __global__ __launch_bounds__(256) void k_discard(
         float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
 #pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
-#pragma unroll
-        for (int c = 0; c < TILE_CHUNKS; c++) {
+        // one chunk: quick test per point, the others queued for the exact
+        // test (FULL: every slot of the tile lies in the set)
+        auto chunk = [&](auto full_tag, int c) {
+            constexpr bool FULL = decltype(full_tag)::value;
             const int64_t a = tb + c * CHUNK + 4 * lane;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                bool valid = (a + j >= o0) && (a + j < o1);
+                const bool valid = FULL || ((a + j >= o0) && (a + j < o1));
                 int32_t kx = (int32_t)(xv[c][j] * GRIDF), ky = (int32_t)(yv[c][j] * GRIDF);
                 uint32_t dy = (uint32_t)(ky - ky_lo);
                 uint32_t row = min(dy >> shift, (uint32_t)(SPAN_ROWS - 1));
@@ -707,6 +753,13 @@ __global__ __launch_bounds__(256) void k_discard(
                 drain<NEDGE>(L, qn, WAVE, P);
             }
             wave_sync();
+        };
+        if (tb >= o0 && tb + TILE <= o1) {
+#pragma unroll
+            for (int c = 0; c < TILE_CHUNKS; c++) chunk(std::integral_constant<bool, true>(), c);
+        } else {
+#pragma unroll
+            for (int c = 0; c < TILE_CHUNKS; c++) chunk(std::integral_constant<bool, false>(), c);
         }
         if (qn > 0) drain<NEDGE>(L, 0, qn, P);
         wave_sync();

@@ -1,0 +1,175 @@
+"""The learned direction proposal on the GPU against the CPU references.
+
+Exact: histograms, the top-8 choice on the GPU's own scores, the extra
+extreme slots, labels, survivors and hulls.  Within tolerance (bf16 products,
+fp32 accumulation vs binary64): network scores and gradients.  Monotonicity:
+learned survivors are a subset of the plain ones and the hull never changes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1405_3454_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1405_3454_amd.api import Hull
+    h = Hull(0)
+    yield h
+    torch.cuda.synchronize()
+    h.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def u32(t):
+    from paper_1405_3454_amd.api import as_u32
+    return as_u32(t)
+
+
+def mixed_batch(sizes, seed):
+    return inputs.batch(sizes, seed, kinds=("mixture", "ellipse", "disk", "square"))
+
+
+def bf16_bits(a):
+    r = np.asarray(mlp.bf16(np.asarray(a, np.float64)), np.float32)
+    return (r.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def test_histogram_parity(H):
+    sizes = [1, 2, 5, 100, 16384, 16385, 40000, 70001]
+    x, y, off, _ = mixed_batch(sizes, 3)
+    hb, hf = H.histogram_batched(dev(x), dev(y), dev(off))
+    hf = hf.cpu().numpy()
+    hb = hb.cpu().numpy().view(np.uint16)
+    for s in range(len(sizes)):
+        want = oracle.histogram(x[off[s]:off[s + 1]], y[off[s]:off[s + 1]])
+        assert np.array_equal(hf[s], want), s
+        assert np.array_equal(hb[s], bf16_bits(want)), s
+
+
+def _hist_batch(H, B, seed):
+    sizes = list(np.random.default_rng(seed).integers(2000, 30000, size=B))
+    x, y, off, _ = mixed_batch(sizes, seed)
+    hb, hf = H.histogram_batched(dev(x), dev(y), dev(off))
+    return hb, hf.cpu().numpy()
+
+
+def test_forward_backward_against_binary64(H):
+    import torch
+    p = mlp.he_init(11)
+    p[mlp.N_PARAMS - 64:] = np.linspace(-0.1, 0.1, 64, dtype=np.float32)   # non-zero b3
+    H.mlp_set_params(p)
+    hb, hf = _hist_batch(H, 100, 5)
+    scores = H.mlp_forward(hb).cpu().numpy()
+    want, cache = mlp.forward(p, hf, emulate=True)
+    err = np.abs(scores - want).max() / np.abs(want).max()
+    assert err < 1e-2, err
+    dS = np.random.default_rng(6).standard_normal((100, 64)).astype(np.float32)
+    g = H.mlp_backward(hb, torch.from_numpy(dS).to("cuda:0")).cpu().numpy().astype(np.float64)
+    gw = mlp.backward(cache, dS, emulate=True)
+    for part, (a, b) in zip(("W1", "b1", "W2", "b2", "W3", "b3"), zip(mlp.split(g), mlp.split(gw))):
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel < 2e-2, (part, rel)
+
+
+def test_top_directions_exact(H):
+    import torch
+    r = np.random.default_rng(9)
+    sc = r.standard_normal((37, 64)).astype(np.float32)
+    sc[3, :] = 0.0                     # all ties
+    sc[4, [1, 2, 60]] = 5.0            # partial ties
+    sc[5, 10] = np.nan
+    sc[6, :] = -0.0
+    got = H.top_directions(torch.from_numpy(sc).to("cuda:0")).cpu().numpy()
+    assert np.array_equal(got, mlp.top_directions(sc))
+
+
+def test_learned_extremes_survivors_and_hull(H):
+    p = mlp.he_init(21)
+    H.mlp_set_params(p)
+    sizes = [3000, 1, 70000, 12345, 500]
+    x, y, off, _ = mixed_batch(sizes, 8)
+    xt, yt, ot = dev(x), dev(y), dev(off)
+    hb, _ = H.histogram_batched(xt, yt, ot)
+    dirs = H.top_directions(H.mlp_forward(hb)).cpu().numpy()
+    cd, sd = oracle.direction_table()
+    slots = u32(H.extremes_batched(xt, yt, ot, learned=True))
+    plain = u32(H.extremes_batched(xt, yt, ot))
+    assert np.array_equal(slots[:, :16], plain)
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        es, _ = oracle.extremes_dirs(x[a:b], y[a:b], cd[dirs[s]], sd[dirs[s]])
+        assert np.array_equal(slots[s, 16:].astype(np.int64), es.astype(np.int64) + a), s
+    sv_l, so_l = H.discard_batched(xt, yt, ot, dev(slots.view(np.int32)))
+    sv_p, so_p = H.discard_batched(xt, yt, ot, dev(plain.view(np.int32)))
+    so_l, so_p = so_l.cpu().numpy(), so_p.cpu().numpy()
+    sv_l, sv_p = u32(sv_l), u32(sv_p)
+    hl, hlo = H.compute_batched(xt, yt, ot, learned=True)
+    hp, hpo = H.compute_batched(xt, yt, ot)
+    hl, hp, hlo, hpo = u32(hl), u32(hp), hlo.cpu().numpy(), hpo.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        L = sv_l[so_l[s]:so_l[s + 1]]
+        Pn = sv_p[so_p[s]:so_p[s + 1]]
+        assert set(L) <= set(Pn)
+        verts = oracle.polygon(x[a:b], y[a:b], slots[s] - a)
+        want = oracle.discard(x[a:b], y[a:b], verts).astype(np.int64) + a
+        assert np.array_equal(L.astype(np.int64), want), s
+        hw = oracle.hull_subset(x[a:b], y[a:b]).astype(np.int64) + a
+        assert np.array_equal(hl[hlo[s]:hlo[s + 1]].astype(np.int64), hw)
+        assert np.array_equal(hp[hpo[s]:hpo[s + 1]].astype(np.int64), hw)
+
+
+def test_labels_parity(H):
+    sizes = [2000, 7000, 1, 4, 30000]
+    x, y, off, _ = mixed_batch(sizes, 12)
+    g = H.labels_batched(dev(x), dev(y), dev(off)).cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        want = oracle.labels(x[a:b], y[a:b]).astype(np.float32)
+        assert np.array_equal(g[s], want), (s, g[s][:8], want[:8])
+
+
+def test_train_step_matches_binary64_adam(H):
+    """One training step on the GPU moves the parameters like the binary64
+    loss gradient + Adam step (within the bf16 tolerance)."""
+    import torch
+    p = mlp.he_init(31)
+    H.mlp_set_params(p)
+    hb, hf = _hist_batch(H, 64, 14)
+    gain = np.abs(np.random.default_rng(2).standard_normal((64, 64))).astype(np.float32) * 0.01
+    loss = H.mlp_train_step(hb, torch.from_numpy(gain).to("cuda:0"), 1e-3).item()
+    S, cache = mlp.forward(p, hf, emulate=True)
+    L, dS = mlp.loss_and_grad(S, gain)
+    assert loss == pytest.approx(L, rel=2e-2)
+    g = mlp.backward(cache, dS, emulate=True)
+    p2, _, _ = mlp.adam(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    got = H.mlp_get_params().astype(np.float64)
+    moved = np.abs(p2 - p) > 5e-4      # parameters whose first step is clearly +-lr
+    assert moved.mean() > 0.05
+    assert np.mean(np.sign(got - p)[moved] == np.sign(p2 - p)[moved]) > 0.95
+
+
+def test_training_gains_over_plain(H):
+    """A short training run on the GPU: the trained proposal discards more
+    than the plain 16-extreme filter and more than the untrained network."""
+    from paper_1405_3454_amd import train
+    x, y, off = train.batch_tensors(256, 1 << 15, 424242, H.device)
+    H.mlp_set_params(train.init_params(5))
+    untrained = train.evaluate(H, x, y, off)
+    params, losses = train.train(H, sets=96 * 64, batch=64, points=1 << 15, lr=1e-3, seed=5)
+    trained = train.evaluate(H, x, y, off)
+    print("untrained", untrained, "trained", trained, "loss", losses[0], losses[-1])
+    assert trained["plain"] == untrained["plain"]
+    assert trained["learned"] >= trained["plain"]
+    assert trained["learned"] - trained["plain"] > untrained["learned"] - untrained["plain"]
+    assert losses[-1] < losses[0]
