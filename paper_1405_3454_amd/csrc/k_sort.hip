@@ -40,48 +40,85 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__re
     hist[threadIdx.x * SORT_BLOCKS + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one pass.  Per tile of SORT_TILE keys (round r, wave w, lane l
+// holds key r*256 + w*64 + l): stable ranks from wave ballots and per
+// (round, wave, digit) counts; the tile is reordered by digit in LDS and then
+// written out run by run, so consecutive lanes write consecutive addresses.
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint64_t *__restrict__ in,
                                                                const int64_t *__restrict__ cnt_ptr,
                                                                int shift,
                                                                const int64_t *__restrict__ hoff,
                                                                uint64_t *__restrict__ out) {
     constexpr int NW = SORT_THREADS / WAVE;
-    __shared__ int64_t run[RADIX];
-    __shared__ uint32_t wcnt[NW][RADIX];
+    __shared__ int64_t run[RADIX];                       // next output position per digit
+    __shared__ __attribute__((aligned(16))) uint16_t wcnt[SORT_ROUNDS][NW][RADIX];
+    __shared__ uint32_t dstart[RADIX + 1], dtot[RADIX];
+    __shared__ int64_t scan_sh[17];
+    __shared__ uint64_t buf[SORT_TILE];
     const int tid = threadIdx.x, w = tid >> 6;
     run[tid] = hoff[tid * SORT_BLOCKS + blockIdx.x];
-    for (int ww = 0; ww < NW; ww++) wcnt[ww][tid] = 0;
-    __syncthreads();
     int64_t lo, hi;
     sort_range(*cnt_ptr, blockIdx.x, &lo, &hi);
     const uint64_t lt = lanemask_lt();
-    for (int64_t base = lo; base < hi; base += SORT_THREADS) {
-        const int64_t i = base + tid;
-        const bool valid = i < hi;
-        uint64_t k = valid ? in[i] : 0;
-        uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
-        uint64_t peers = __ballot(valid);
+    for (int64_t base = lo; base < hi; base += SORT_TILE) {
+        const int ntile = (int)min((int64_t)SORT_TILE, hi - base);
+        {   // clear the per-(round, wave, digit) counts: 16 KB, 64 B per thread
+            uint4 *z = reinterpret_cast<uint4 *>(&wcnt[0][0][0]);
+            for (int i = tid; i < (int)(sizeof(wcnt) / sizeof(uint4)); i += SORT_THREADS)
+                z[i] = make_uint4(0, 0, 0, 0);
+        }
+        uint64_t k[SORT_ROUNDS];
+        uint32_t d[SORT_ROUNDS];
+        int rank[SORT_ROUNDS], cnt[SORT_ROUNDS];
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
-            bool bit = (d >> b) & 1;
-            uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+        for (int r = 0; r < SORT_ROUNDS; r++) {
+            const int i = r * SORT_THREADS + tid;
+            const bool valid = i < ntile;
+            k[r] = valid ? in[base + i] : 0;
+            d[r] = (uint32_t)(k[r] >> shift) & (RADIX - 1);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                bool bit = (d[r] >> b) & 1;
+                uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            rank[r] = valid ? __popcll(peers & lt) : -1;
+            cnt[r] = __popcll(peers);
         }
-        int rank = __popcll(peers & lt);
-        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        if (valid) {
-            int64_t p = run[d] + rank;
-            for (int ww = 0; ww < w; ww++) p += wcnt[ww][d];
-            out[p] = k;
+#pragma unroll
+        for (int r = 0; r < SORT_ROUNDS; r++)
+            if (rank[r] == 0) wcnt[r][w][d[r]] = (uint16_t)cnt[r];
+        __syncthreads();
+        {   // digit tid: exclusive prefix over (round, wave) in key order
+            uint32_t acc = 0;
+            for (int r = 0; r < SORT_ROUNDS; r++)
+                for (int ww = 0; ww < NW; ww++) {
+                    uint32_t c = wcnt[r][ww][tid];
+                    wcnt[r][ww][tid] = (uint16_t)acc;
+                    acc += c;
+                }
+            dtot[tid] = acc;
         }
         __syncthreads();
-        uint32_t t = 0;
-        for (int ww = 0; ww < NW; ww++) {
-            t += wcnt[ww][tid];
-            wcnt[ww][tid] = 0;
+        {
+            int64_t tot;
+            int64_t ex = block_excl_scan_i64(dtot[tid], scan_sh, &tot);
+            dstart[tid] = (uint32_t)ex;
         }
-        run[tid] += t;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SORT_ROUNDS; r++)
+            if (rank[r] >= 0) buf[dstart[d[r]] + wcnt[r][w][d[r]] + rank[r]] = k[r];
+        __syncthreads();
+        for (int i = tid; i < ntile; i += SORT_THREADS) {
+            uint64_t kk = buf[i];
+            uint32_t dd = (uint32_t)(kk >> shift) & (RADIX - 1);
+            out[run[dd] + (i - (int)dstart[dd])] = kk;
+        }
+        __syncthreads();
+        run[tid] += dtot[tid];
         __syncthreads();
     }
 }
