@@ -110,8 +110,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const uint32_t *__re
 __device__ __forceinline__ void load4(const float *__restrict__ x, const float *__restrict__ y,
                                       int64_t a, int64_t n_total, float xv[4], float yv[4]) {
     if (a + 4 <= n_total) {
-        float4 fx = *reinterpret_cast<const float4 *>(x + a);
-        float4 fy = *reinterpret_cast<const float4 *>(y + a);
+        // streaming reads: marked non-temporal so they do not displace
+        // reusable lines from the caches
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 fx = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(x + a));
+        const f4 fy = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(y + a));
         xv[0] = fx.x; xv[1] = fx.y; xv[2] = fx.z; xv[3] = fx.w;
         yv[0] = fy.x; yv[1] = fy.y; yv[2] = fy.z; yv[3] = fy.w;
     } else {
@@ -125,14 +128,21 @@ __device__ __forceinline__ void load4(const float *__restrict__ x, const float *
 }
 
 // ---------------------------------------------------------------------------
-// Step 1 projections.  Slot k of the fixed sixteen is stored as a maximum:
-// even slots (argmin u, argmin v) use the negated coordinate, which is exact
-// and keeps the same ties.  PRESET 0: angles 0/30/45/60 with shared products
-// (sin30 = cos60 = 1/2, sin60 = cos30, sin45 = cos45); PRESET 1: 0/30/75/120,
-// where u(120) = -v(30) and v(120) = u(30) bit for bit, so slots 12..15 are
-// copied from 7, 6, 4, 5 when the polygon is built; PRESET 2: any four
-// rotation groups from Dirs.
+// Step 1 keys.  Fixed slot 4g+0 / 4g+1 is the argmin / argmax of
+// u_g = cos_g x - sin_g y and 4g+2 / 4g+3 that of v_g = sin_g x + cos_g y,
+// each product rounded to binary64 and then the sum (no contraction).
+//
+// PRESET 0 (0/30/45/60 degrees) and PRESET 1 (0/30/75/120) compare 2 u_g and
+// 2 v_g for the 30- and 60-degree groups: there sin30 = cos60 = 1/2 and
+// sin60 = cos30, so 2 u_30 = fl(fl(2 cos30 x) - y) and so on, which is
+// exactly twice the rounded u_30 (scaling by 2 commutes with rounding here)
+// and orders the points identically with two fewer products.  Only the
+// comparisons see these keys; the reported values are recomputed from the
+// winning points.  Under PRESET 1 u_120 = -v_30 and v_120 = u_30 bit for bit,
+// so slots 12..15 are copies of 7, 6, 4, 5 made when the polygon is built.
+// PRESET 2 evaluates the four groups of Dirs as written.
 constexpr double C30 = 0x1.bb67ae8584caap-1;
+constexpr double C30X2 = 0x1.bb67ae8584caap+0;   // 2 cos30, exact
 constexpr double C45 = 0x1.6a09e667f3bcdp-1;
 constexpr double C75 = 0x1.0907dc1930690p-2;
 constexpr double S75 = 0x1.ee8dd4748bf15p-1;
@@ -140,37 +150,35 @@ constexpr double S75 = 0x1.ee8dd4748bf15p-1;
 template <int PRESET>
 struct Proj {
     static constexpr int NG = PRESET == 1 ? 3 : 4;   // groups actually evaluated
-    // u[g], v[g] of one point (binary64, each product rounded, then the sum)
     __device__ __forceinline__ static void uv(const Dirs &d, double xd, double yd, double u[4],
                                               double v[4]) {
 #pragma clang fp contract(off)
-        u[0] = xd;
-        v[0] = yd;
         if (PRESET == 0) {
-            double c30x = C30 * xd, c30y = C30 * yd, hx = 0.5 * xd, hy = 0.5 * yd;
-            double c45x = C45 * xd, c45y = C45 * yd;
-            u[1] = c30x - hy;
-            v[1] = hx + c30y;
-            u[2] = c45x - c45y;
-            v[2] = c45x + c45y;
-            u[3] = hx - c30y;
-            v[3] = c30x + hy;
+            const double p = C30X2 * xd, q = C30X2 * yd, r = C45 * xd, t = C45 * yd;
+            u[0] = xd;
+            v[0] = yd;
+            u[1] = p - yd;       // 2 u_30
+            v[1] = xd + q;       // 2 v_30
+            u[2] = r - t;
+            v[2] = r + t;
+            u[3] = xd - q;       // 2 u_60
+            v[3] = p + yd;       // 2 v_60
         } else if (PRESET == 1) {
-            double c30x = C30 * xd, c30y = C30 * yd, hx = 0.5 * xd, hy = 0.5 * yd;
-            u[1] = c30x - hy;
-            v[1] = hx + c30y;
+            const double p = C30X2 * xd, q = C30X2 * yd;
+            u[0] = xd;
+            v[0] = yd;
+            u[1] = p - yd;
+            v[1] = xd + q;
             u[2] = C75 * xd - S75 * yd;
             v[2] = S75 * xd + C75 * yd;
             u[3] = 0.0;
             v[3] = 0.0;
         } else {
 #pragma unroll
-            for (int g = 1; g < 4; g++) {
+            for (int g = 0; g < 4; g++) {
                 u[g] = d.gc[g] * xd - d.gs[g] * yd;
                 v[g] = d.gs[g] * xd + d.gc[g] * yd;
             }
-            u[0] = d.gc[0] * xd - d.gs[0] * yd;
-            v[0] = d.gs[0] * xd + d.gc[0] * yd;
         }
     }
 };
@@ -181,40 +189,90 @@ __device__ __forceinline__ double proj_dir(double c, double s, double xd, double
     return c * xd + s * yd;
 }
 
-// Rotated coordinate behind fixed slot k (0..15): slots 4g, 4g+1 are the
-// min and max of u, slots 4g+2, 4g+3 the min and max of v of group g.
-__device__ __forceinline__ double slot_val(int k, const double u[4], const double v[4]) {
-    const int g = k >> 2;
-    return (k & 2) ? v[g] : u[g];
-}
 // Fixed slots with even index are minima; all others (learned ones too) maxima.
 __device__ __forceinline__ constexpr bool slot_is_min(int k, int nfixed) {
     return k < nfixed && (k & 1) == 0;
 }
-__device__ __forceinline__ double wave_min(double v) {
+
+// Key of tracked slot k (fixed slots first, then the learned directions).
+template <int PRESET, int NDIR>
+__device__ __forceinline__ void slot_keys(const Dirs &d, const double *dc, const double *ds,
+                                          double xd, double yd, double *key) {
+    constexpr int NF = 4 * Proj<PRESET>::NG;
+    double u[4], v[4];
+    Proj<PRESET>::uv(d, xd, yd, u, v);
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
+    for (int k = 0; k < NF; k++) key[k] = (k & 2) ? v[k >> 2] : u[k >> 2];
+#pragma unroll
+    for (int e = 0; e < NDIR; e++) key[NF + e] = proj_dir(dc[e], ds[e], xd, yd);
 }
 
-// Step 1: per-wave running minima/maxima of every slot over the wave's
-// tiles, with the lowest index on ties; one partial per (wave, set) run,
-// stored at the run's first tile.  Learned directions (NDIR > 0) come per set
-// from set_dirs[s][d] = (c, s).
+// Cross-lane moves within rows of 16 lanes (DPP) and whole-wave extremes.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = dpp_u32<CTRL>((uint32_t)b), hi = dpp_u32<CTRL>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <bool MN>
+__device__ __forceinline__ double pick(double a, double b) { return MN ? fmin(a, b) : fmax(a, b); }
+
+// Minimum (MN) or maximum of v over the 64 lanes, in every lane.  Steps:
+// swap neighbours, swap pairs, mirror half rows, mirror rows (each lane then
+// holds its row's extreme), then combine the four rows.
+template <bool MN>
+__device__ __forceinline__ double wave_extreme(double v) {
+    v = pick<MN>(v, dpp_f64<0xB1>(v));
+    v = pick<MN>(v, dpp_f64<0x4E>(v));
+    v = pick<MN>(v, dpp_f64<0x141>(v));
+    v = pick<MN>(v, dpp_f64<0x140>(v));
+    return pick<MN>(pick<MN>(readlane_f64(v, 0), readlane_f64(v, 16)),
+                    pick<MN>(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    v = min(v, dpp_u32<0xB1>(v));
+    v = min(v, dpp_u32<0x4E>(v));
+    v = min(v, dpp_u32<0x141>(v));
+    v = min(v, dpp_u32<0x140>(v));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, e));
+}
+
+// Step 1: directional extremes of every slot over the wave's tiles, with the
+// lowest index on ties; one partial per (wave, set) run, stored at the run's
+// first tile.  Learned directions (NDIR > 0) come per set from
+// set_dirs[s][d] = (c, s).
+//
+// Per lane and slot the kernel keeps the best key seen so far (lb) and the
+// tile of the run in which the lane first reached it (rt); a tile costs one
+// min/max per point and slot plus one compare per slot.  At the end of a run
+// the wave takes the extreme m of lb and, for the lanes holding m, reloads
+// their 16 points of tile rt to find the lowest index whose key is m.  In
+// tiles that straddle a set boundary, positions outside the set hold a copy of
+// the set's first point o0: a copy never beats a genuine extreme, and if the
+// run's extreme is only met by copies, the run reports (key(o0), o0), a
+// genuine pair of the set.
 template <int PRESET, int NDIR>
 __global__ __launch_bounds__(256) void k_extremes(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
     const int64_t *__restrict__ off, int64_t n1, int64_t S,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set, Dirs dirs,
     const double *__restrict__ set_dirs, double *__restrict__ pval, uint32_t *__restrict__ pidx) {
-    constexpr int NG = Proj<PRESET>::NG;
-    constexpr int NF = 4 * NG;           // fixed slots evaluated
-    constexpr int NS = NF + NDIR;        // slots tracked
-    // running extremes of the wave (LDS: read once per chunk and slot)
-    __shared__ double sbv[4][NS];
-    __shared__ uint32_t sbi[4][NS];
-    double *bv = sbv[threadIdx.x >> 6];
-    uint32_t *bi = sbi[threadIdx.x >> 6];
+    constexpr int NF = 4 * Proj<PRESET>::NG;   // fixed slots evaluated
+    constexpr int NS = NF + NDIR;               // slots tracked
     const int lane = lane_id();
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
@@ -224,82 +282,63 @@ __global__ __launch_bounds__(256) void k_extremes(
     if (t0 >= t1) return;
 
     double dc[NDIR > 0 ? NDIR : 1], ds[NDIR > 0 ? NDIR : 1];
-    int64_t cur = -1, run = t0, o0 = 0, o1 = 0, tile0 = 0, abase = 0;
+    double lb[NS];
+    uint32_t rt[NS];
+    int64_t run = t0, o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1;
     float x0f = 0.0f, y0f = 0.0f;
 
-    // One chunk of 256 points (4 per lane).  FULL: every slot lies in the
-    // set; otherwise slots outside it hold a copy of the set's first point
-    // o0, which never moves an extreme (o0 itself is met in the set's first
-    // chunk, at or before any copy) and is never chosen as the index.
-    auto chunk = [&](auto full_tag, const float *xv, const float *yv, int64_t cb) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        const int64_t a = cb + 4 * lane;
-        double acc[NS];
+    auto reset = [&]() {
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const bool valid = FULL || ((a + j >= o0) && (a + j < o1));
-            double xd = valid ? xv[j] : x0f, yd = valid ? yv[j] : y0f;
-            double u[4], v[4];
-            Proj<PRESET>::uv(dirs, xd, yd, u, v);
-#pragma unroll
-            for (int k = 0; k < NF; k++) {
-                double w = slot_val(k, u, v);
-                acc[k] = j == 0 ? w : (slot_is_min(k, NF) ? fmin(acc[k], w) : fmax(acc[k], w));
-            }
-#pragma unroll
-            for (int d = 0; d < NDIR; d++) {
-                double w = proj_dir(dc[d], ds[d], xd, yd);
-                acc[NF + d] = j == 0 ? w : fmax(acc[NF + d], w);
-            }
+        for (int k = 0; k < NS; k++) {
+            lb[k] = slot_is_min(k, NF) ? INFINITY : -INFINITY;
+            rt[k] = NONE;
         }
+    };
+    // Resolve the run's extremes and store its partial.
+    auto flush = [&]() {
 #pragma unroll
         for (int k = 0; k < NS; k++) {
             const bool mn = slot_is_min(k, NF);
-            if (__ballot(mn ? acc[k] < bv[k] : acc[k] > bv[k])) {
-                // rare: a new extreme in this chunk; take the lowest index.
-                // The points are read again (cache hits).
-                double m = mn ? wave_min(acc[k]) : wave_max(acc[k]);
-                float rx[4], ry[4];
-                load4(x, y, a, n_total, rx, ry);
-                int cand = 4;
+            const double m = mn ? wave_extreme<true>(lb[k]) : wave_extreme<false>(lb[k]);
+            uint64_t cand = __ballot(rt[k] != NONE && lb[k] == m);
+            uint32_t found = NONE;
+            // lane l examines point (chunk l/16, element l%4) of candidate (l/4)%4
+            const int cq = (lane >> 2) & 3;
+            while (cand) {     // up to four candidate lanes per round
+                int cl[4];
 #pragma unroll
-                for (int j = 3; j >= 0; j--) {
-                    const bool valid = (a + j >= o0) && (a + j < o1);
-                    double xd = rx[j], yd = ry[j], key;
-                    if (k < NF) {
-                        double u[4], v[4];
-                        Proj<PRESET>::uv(dirs, xd, yd, u, v);
-                        key = slot_val(k, u, v);
-                    } else {
-                        key = proj_dir(dc[k - NF], ds[k - NF], xd, yd);
+                for (int e = 0; e < 4; e++) {
+                    cl[e] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
+                    if (cand) cand &= cand - 1;
+                }
+                const int L = cq == 0 ? cl[0] : cq == 1 ? cl[1] : cq == 2 ? cl[2] : cl[3];
+                // tile of candidate L (whole wave active for the permute)
+                const uint32_t rl = (uint32_t)__builtin_amdgcn_ds_bpermute((L < 0 ? 0 : L) << 2, (int)rt[k]);
+                uint32_t my = NONE;
+                if (L >= 0) {
+                    const int64_t tb = abase + (run + (int64_t)rl - tile0) * TILE;
+                    const int64_t p = tb + (lane >> 4) * CHUNK + 4 * L + (lane & 3);
+                    if (p >= o0 && p < o1) {
+                        double key[NS];
+                        slot_keys<PRESET, NDIR>(dirs, dc, ds, (double)x[p], (double)y[p], key);
+                        if (key[k] == m) my = (uint32_t)p;
                     }
-                    if (valid && key == m) cand = j;
                 }
-                uint64_t has = __ballot(cand < 4);
-                int L = __ffsll((unsigned long long)has) - 1;
-                int cj = __builtin_amdgcn_readlane(cand, L);
-                wave_sync();
-                if (lane == 0) {
-                    bv[k] = m;
-                    bi[k] = (uint32_t)(cb + 4 * L + cj);
-                }
-                wave_sync();
+                found = min(found, wave_min_u32(my));
+            }
+            if (found == NONE) found = (uint32_t)o0;
+            if (lane == 0) {
+                pval[run * MAX_SLOTS + k] = m;
+                pidx[run * MAX_SLOTS + k] = found;
             }
         }
     };
 
-    int64_t cur_end = -1;   // first tile after the current set
     for (int64_t t = t0; t < t1; ++t) {
         if (t >= cur_end) {     // a new set starts (looked up once per set)
+            if (cur_end >= 0) flush();
             const int64_t s = tile_set[t];
             cur_end = tile_off[s + 1];
-            wave_sync();
-            if (cur >= 0 && lane < NS) {
-                pval[run * MAX_SLOTS + lane] = bv[lane];
-                pidx[run * MAX_SLOTS + lane] = bi[lane];
-            }
-            wave_sync();
-            cur = s;
             run = t;
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
@@ -307,39 +346,56 @@ __global__ __launch_bounds__(256) void k_extremes(
             abase = o0 & ~int64_t(3);
             x0f = x[o0];
             y0f = y[o0];
-            if (lane < NS) {
-                bv[lane] = slot_is_min(lane, NF) ? INFINITY : -INFINITY;
-                bi[lane] = NONE;
-            }
 #pragma unroll
-            for (int d = 0; d < NDIR; d++) {
-                dc[d] = set_dirs[(s * MAX_DIRS + d) * 2 + 0];
-                ds[d] = set_dirs[(s * MAX_DIRS + d) * 2 + 1];
+            for (int e = 0; e < NDIR; e++) {
+                dc[e] = set_dirs[(s * MAX_DIRS + e) * 2 + 0];
+                ds[e] = set_dirs[(s * MAX_DIRS + e) * 2 + 1];
             }
-            wave_sync();
+            reset();
         }
         const int64_t tb = abase + (t - tile0) * TILE;
         // issue the whole tile's loads first: 8 KB in flight per wave
         float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
 #pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
-        if (tb >= o0 && tb + TILE <= o1) {
+        double acc[NS];
+        // FULL: every position of the tile lies in the set
+        auto accumulate = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
-            for (int c = 0; c < TILE_CHUNKS; c++)
-                chunk(std::integral_constant<bool, true>(), xv[c], yv[c], tb + c * CHUNK);
-        } else {
+            for (int c = 0; c < TILE_CHUNKS; c++) {
 #pragma unroll
-            for (int c = 0; c < TILE_CHUNKS; c++)
-                chunk(std::integral_constant<bool, false>(), xv[c], yv[c], tb + c * CHUNK);
+                for (int j = 0; j < 4; j++) {
+                    float xf = xv[c][j], yf = yv[c][j];
+                    if (!FULL) {
+                        const int64_t p = tb + c * CHUNK + 4 * lane + j;
+                        const bool valid = p >= o0 && p < o1;
+                        xf = valid ? xf : x0f;
+                        yf = valid ? yf : y0f;
+                    }
+                    double key[NS];
+                    slot_keys<PRESET, NDIR>(dirs, dc, ds, (double)xf, (double)yf, key);
+#pragma unroll
+                    for (int k = 0; k < NS; k++)
+                        acc[k] = (c == 0 && j == 0) ? key[k]
+                                 : slot_is_min(k, NF) ? fmin(acc[k], key[k]) : fmax(acc[k], key[k]);
+                }
+            }
+        };
+        if (tb >= o0 && tb + TILE <= o1)
+            accumulate(std::integral_constant<bool, true>());
+        else
+            accumulate(std::integral_constant<bool, false>());
+        const uint32_t rel = (uint32_t)(t - run);
+#pragma unroll
+        for (int k = 0; k < NS; k++) {
+            const bool upd = slot_is_min(k, NF) ? acc[k] < lb[k] : acc[k] > lb[k];
+            lb[k] = upd ? acc[k] : lb[k];
+            rt[k] = upd ? rel : rt[k];
         }
     }
-    wave_sync();
-    if (lane < NS) {
-        pval[run * MAX_SLOTS + lane] = bv[lane];
-        pidx[run * MAX_SLOTS + lane] = bi[lane];
-    }
+    flush();
 }
-
 // ---------------------------------------------------------------------------
 // Step 2: one block per set.  Reduce the runs' partials (or take the
 // caller's slots), build the convex polygon of the slot points with Andrew's
