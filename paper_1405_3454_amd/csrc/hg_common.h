@@ -37,12 +37,20 @@ struct Poly {
     int32_t pad[4];
 };
 
-// One quick-accept row: every grid point with ky in the row and
-// xl <= kx <= xr is strictly inside the polygon (verified exactly at the
-// rectangle's corners).  Empty rows have xl > xr.
+// One row of the polygon's y-range (ky in [y0, y1]):
+//  - every grid point of the row with xl <= kx <= xr is strictly inside the
+//    polygon (verified exactly at the rectangle's corners; xl > xr: none);
+//  - every grid point of the row with kx <= ol or kx >= orr is not strictly
+//    inside (the polygon's x-extent over the row, widened by a grid unit).
+// Per row a second word lists the edges whose y-range meets the row (one byte
+// each, ROW_EDGE_NONE = unused, ROW_EDGES_ALL = more than four): for a point
+// of the row, being strictly inside those edges is the same as being
+// strictly inside the polygon.
 struct Span {
-    int32_t xl, xr;
+    int32_t xl, xr, ol, orr;
 };
+constexpr uint32_t ROW_EDGE_NONE = 31;          // index of an always-satisfied edge
+constexpr uint32_t ROW_EDGES_ALL = 0xFFFFFFFFu;
 
 // Kernel kinds for the per-kernel event timer.
 enum Kind {

@@ -112,7 +112,7 @@ static int launch(hull_ctx *ctx, int kind, hipStream_t st, F &&f) {
 // ---------------------------------------------------------------------------
 // Workspace plan.  All sizes are upper bounds derived from (n_total, S).
 struct Plan {
-    size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, masks, tile_cnt, tile_pos,
+    size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, total;
     int64_t tcap, u0cap;
@@ -138,6 +138,7 @@ static Plan make_plan(int64_t n, int64_t S) {
     p.vals = take(S * MAX_SLOTS * 8);
     p.polys = take(S * sizeof(Poly));
     p.spans = take(S * SPAN_ROWS * sizeof(Span));
+    p.redges = take(S * SPAN_ROWS * 4);
     p.masks = take(p.tcap * TILE_WORDS * 8);
     p.tile_cnt = take(p.tcap * 4);
     p.tile_pos = take((p.tcap + 1) * 8);
@@ -276,7 +277,7 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<(unsigned)S, 256, 0, st>>>(                          \
         x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
         W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
-        spans))
+        spans, W<uint32_t>(ctx, p.redges)))
     const bool cum = ctx->preset == HULL_DIRS_CUMULATIVE;
     if (learned) {
         if (cum) K2(12, MAX_DIRS); else K2(16, MAX_DIRS);
@@ -296,16 +297,17 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
     auto *polys = W<Poly>(ctx, p.polys);
     auto *spans = W<Span>(ctx, p.spans);
+    const uint32_t *redges = W<uint32_t>(ctx, p.redges);
     uint64_t *masks = W<uint64_t>(ctx, p.masks);
     uint32_t *tcnt = W<uint32_t>(ctx, p.tile_cnt);
     int64_t *tpos = W<int64_t>(ctx, p.tile_pos);
     const int g = grid_k3(ctx);
     if (nedge <= FIXED_SLOTS)
         LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS><<<g, 256, 0, st>>>(
-            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, masks, tcnt));
+            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
     else
         LAUNCH(K_DISCARD, k_discard<MAX_SLOTS><<<g, 256, 0, st>>>(
-            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, masks, tcnt));
+            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
     int rc = run_scan(ctx, p, st, tcnt, tile_off + S, tpos);
     if (rc) return rc;
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,

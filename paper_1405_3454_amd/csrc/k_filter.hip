@@ -425,7 +425,8 @@ __global__ __launch_bounds__(256) void k_polygon(
     const int64_t *__restrict__ tile_off, int64_t W1, const double *__restrict__ pval,
     const uint32_t *__restrict__ pidx, const uint32_t *__restrict__ slots_in, int n_in, Dirs dirs,
     const double *__restrict__ set_dirs, uint32_t *__restrict__ slots_out,
-    double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans) {
+    double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans,
+    uint32_t *__restrict__ redges) {
     // NEV: fixed slots the extremes pass evaluated (12 when the 120-degree
     // group is a copy of the 30-degree one, else 16); NDIR learned slots.
     constexpr int NS = FIXED_SLOTS + NDIR;
@@ -649,40 +650,77 @@ __global__ __launch_bounds__(256) void k_polygon(
     }
     __syncthreads();
 
-    // quick-accept rows: candidate span from the edges at the band's ends,
-    // shrunk to integers, kept only if its four corners are strictly inside
+    // Rows: quick-accept span from the edges at the row's ends, shrunk to
+    // integers and kept only if its four corners are strictly inside; the
+    // polygon's x-extent over the row (vertices in the row and the edges'
+    // crossings of its two boundary lines); the edges whose y-range meets it.
     for (int r = tid; r < SPAN_ROWS; r += blockDim.x) {
-        Span sp{1, 0};
+        Span sp{1, 0, INT32_MAX, INT32_MIN};
+        uint32_t re = ROW_EDGES_ALL;
         if (P.yspan >= 0) {
             int64_t y0 = (int64_t)P.ky_lo + ((int64_t)r << P.shift);
             int64_t y1 = min(y0 + (int64_t(1) << P.shift) - 1, (int64_t)P.ky_lo + P.yspan);
             if (y0 <= (int64_t)P.ky_lo + P.yspan) {
-                double xl = -1e300, xr = 1e300;
+                const double fy0 = (double)y0, fy1 = (double)y1;
+                double xl = -1e300, xr = 1e300, mnx = 1e300, mxx = -1e300;
                 bool ok = true;
+                int ne = 0;
+                re = 0;
                 for (int e = 0; e < P.m; e++) {
-                    double ex = P.ex[e], ey = P.ey[e];
-                    double ax = vx[e], ay = vy[e];     // edge e runs from vertex e to e+1
+                    const double ex = P.ex[e], ey = P.ey[e];
+                    const double ax = vx[e], ay = vy[e];     // edge e runs from vertex e to e+1
+                    const double by = ay + ey;
                     if (ey > 0) {
-                        xr = fmin(xr, fmin(ax + ex * ((double)y0 - ay) / ey,
-                                           ax + ex * ((double)y1 - ay) / ey));
+                        xr = fmin(xr, fmin(ax + ex * (fy0 - ay) / ey, ax + ex * (fy1 - ay) / ey));
                     } else if (ey < 0) {
-                        xl = fmax(xl, fmax(ax + ex * ((double)y0 - ay) / ey,
-                                           ax + ex * ((double)y1 - ay) / ey));
+                        xl = fmax(xl, fmax(ax + ex * (fy0 - ay) / ey, ax + ex * (fy1 - ay) / ey));
                     } else if (ex > 0) {
-                        if ((double)y0 <= ay) ok = false;      // bottom edge
+                        if (fy0 <= ay) ok = false;      // bottom edge
                     } else if (ex < 0) {
-                        if ((double)y1 >= ay) ok = false;      // top edge
+                        if (fy1 >= ay) ok = false;      // top edge
                     }
+                    if (ay >= fy0 && ay <= fy1) {
+                        mnx = fmin(mnx, ax);
+                        mxx = fmax(mxx, ax);
+                    }
+                    const double elo = fmin(ay, by), ehi = fmax(ay, by);
+                    if (ey != 0) {
+                        for (int b2 = 0; b2 < 2; b2++) {
+                            const double yy = b2 ? fy1 : fy0;
+                            if (elo <= yy && yy <= ehi) {
+                                const double xx = ax + ex * (yy - ay) / ey;
+                                mnx = fmin(mnx, xx);
+                                mxx = fmax(mxx, xx);
+                            }
+                        }
+                    }
+                    if (elo <= fy1 && ehi >= fy0) {
+                        if (ne < 4) re |= (uint32_t)e << (8 * ne);
+                        ne++;
+                    }
+                }
+                if (ne > 4) re = ROW_EDGES_ALL;
+                else
+                    for (int k = ne; k < 4; k++) re |= ROW_EDGE_NONE << (8 * k);
+                // the crossings carry at most a few ulps of rounding; one grid
+                // unit of margin keeps the outer test conservative
+                if (mnx <= mxx) {
+                    sp.ol = (int32_t)floor(mnx) - 1;
+                    sp.orr = (int32_t)ceil(mxx) + 1;
+                } else {
+                    sp.ol = INT32_MIN;      // unreachable: keep every point for the exact test
+                    sp.orr = INT32_MAX;
+                    re = ROW_EDGES_ALL;
                 }
                 if (ok && xl > -1e299 && xr < 1e299) {
                     double fl = floor(xl) + 1.0, fr = ceil(xr) - 1.0;
                     for (int attempt = 0; attempt < 3 && fl <= fr; attempt++) {
                         bool good = true;
-                        double cx[2] = {fl, fr}, cy[2] = {(double)y0, (double)y1};
+                        double cx[2] = {fl, fr}, cy[2] = {fy0, fy1};
                         for (int e = 0; e < P.m && good; e++)
-                            for (int a = 0; a < 2; a++)
-                                for (int b = 0; b < 2; b++)
-                                    if (!(edge_eval(P.ex[e], P.ey[e], P.c[e], cx[a], cy[b]) > 0))
+                            for (int a2 = 0; a2 < 2; a2++)
+                                for (int b2 = 0; b2 < 2; b2++)
+                                    if (!(edge_eval(P.ex[e], P.ey[e], P.c[e], cx[a2], cy[b2]) > 0))
                                         good = false;
                         if (good) {
                             sp.xl = (int32_t)fl;
@@ -696,41 +734,66 @@ __global__ __launch_bounds__(256) void k_polygon(
             }
         }
         spans[s * SPAN_ROWS + r] = sp;
+        redges[s * SPAN_ROWS + r] = re;
     }
     if (tid == 0) polys[s] = P;
 }
 
 // ---------------------------------------------------------------------------
-// Step 3: strict-inside test.  Quick path: grid row lookup in the wave's LDS
-// copy of the quick-accept rows.  Points it cannot accept go to a per-wave
-// queue and are tested exactly against every edge in full 64-lane batches.
-// Output per tile: survivor mask words (word 4c + j, bit l = point
+// Step 3: strict-inside test.  Each point is first classified with its row
+// of the polygon's y-range (wave-private LDS copy): quick accept (strictly
+// inside), quick reject (outside the row's x-extent or the polygon's y-range:
+// a survivor), or undecided.  Undecided points go to a per-wave queue and are
+// tested exactly, in full 64-lane batches, against the edges that meet their
+// row.  Output per tile: survivor mask words (word 4c + j, bit l = point
 // c*256 + 4l + j of the tile) and the survivor count.
 constexpr int QCAP = 320;
+constexpr int EDGE_SLOTS = 32;        // edge arrays in LDS; slots >= m hold (0, 0, 1)
 
 struct DiscardLds {
-    Span spans[SPAN_ROWS];
+    Span rows[SPAN_ROWS];
+    uint32_t redge[SPAN_ROWS];
+    double ex[EDGE_SLOTS], ey[EDGE_SLOTS], c[EDGE_SLOTS];
     uint64_t q[QCAP];                 // kx | ky << 24 | pos << 48
     unsigned long long mask[TILE_WORDS];
 };
 
+__device__ __forceinline__ bool edge_in(const DiscardLds &L, uint32_t e, double px, double py) {
+    return edge_eval(L.ex[e], L.ey[e], L.c[e], px, py) > 0;
+}
+
 template <int NEDGE>
-__device__ __forceinline__ void drain(DiscardLds &L, int from, int count, const Poly *__restrict__ P) {
+__device__ __forceinline__ void drain(DiscardLds &L, int from, int count, int32_t ky_lo, int shift) {
     const int lane = lane_id();
     if (lane < count) {
-        uint64_t e = L.q[from + lane];
-        double px = (double)(int32_t)(e & 0xFFFFFF);
-        double py = (double)(int32_t)((e >> 24) & 0xFFFFFF);
-        int pos = (int)(e >> 48);
-        bool inside = true;
+        const uint64_t e = L.q[from + lane];
+        const int32_t kx = (int32_t)(e & 0xFFFFFF), ky = (int32_t)((e >> 24) & 0xFFFFFF);
+        const double px = (double)kx, py = (double)ky;
+        const int pos = (int)(e >> 48);
+        const uint32_t re = L.redge[(uint32_t)(ky - ky_lo) >> shift];
+        bool inside;
+        if (re != ROW_EDGES_ALL) {
+            inside = edge_in(L, re & 0xFF, px, py) & edge_in(L, (re >> 8) & 0xFF, px, py) &
+                     edge_in(L, (re >> 16) & 0xFF, px, py) & edge_in(L, re >> 24, px, py);
+        } else {
+            inside = true;
 #pragma unroll
-        for (int k = 0; k < NEDGE; k++)
-            inside = inside && (edge_eval(P->ex[k], P->ey[k], P->c[k], px, py) > 0);
+            for (int k = 0; k < NEDGE; k++) inside = inside && edge_in(L, k, px, py);
+        }
         if (!inside) {
-            int c = pos >> 8, l = (pos >> 2) & 63, j = pos & 3;
+            const int c = pos >> 8, l = (pos >> 2) & 63, j = pos & 3;
             atomicOr(&L.mask[c * 4 + j], 1ull << l);
         }
     }
+}
+
+// Sum over lanes 0..15 (other lanes' values are ignored), in every lane.
+__device__ __forceinline__ uint32_t row0_sum_u32(uint32_t v) {
+    v += dpp_u32<0xB1>(v);
+    v += dpp_u32<0x4E>(v);
+    v += dpp_u32<0x141>(v);
+    v += dpp_u32<0x140>(v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
 }
 
 template <int NEDGE>
@@ -738,7 +801,8 @@ __global__ __launch_bounds__(256) void k_discard(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
     const int64_t *__restrict__ off, int64_t n1, int64_t S, const int64_t *__restrict__ tile_off,
     const int32_t *__restrict__ tile_set, const Poly *__restrict__ polys,
-    const Span *__restrict__ spans, uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt) {
+    const Span *__restrict__ spans, const uint32_t *__restrict__ redges,
+    uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt) {
     __shared__ DiscardLds lds[4];
     DiscardLds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
@@ -749,64 +813,82 @@ __global__ __launch_bounds__(256) void k_discard(
     const int64_t t0 = wave * q, t1 = min(t0 + q, T);
     if (t0 >= t1) return;
 
-    int64_t cur = -1, o0 = 0, o1 = 0, tile0 = 0, abase = 0;
+    int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1;
     int32_t ky_lo = 0, shift = 0;
-    uint32_t yspan = 0;
+    uint32_t ylim = 0;          // in the y-range: (ky - ky_lo) <= ylim (unsigned)
     bool has_rows = false;
-    const Poly *P = polys;
 
-    int64_t cur_end = -1;   // first tile after the current set
     for (int64_t t = t0; t < t1; ++t) {
         if (t >= cur_end) {     // a new set starts (looked up once per set)
-            const int64_t s = tile_set[t];
+            const int64_t s = __builtin_amdgcn_readfirstlane(tile_set[t]);
             cur_end = tile_off[s + 1];
-            cur = s;
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
             tile0 = tile_off[s];
             abase = o0 & ~int64_t(3);
-            P = polys + s;
+            const Poly *P = polys + s;
             ky_lo = P->ky_lo;
             has_rows = P->yspan >= 0;
-            yspan = (uint32_t)max(P->yspan, 0);
+            ylim = (uint32_t)max(P->yspan, 0);
             shift = P->shift;
             wave_sync();
-            for (int r = lane; r < SPAN_ROWS; r += WAVE) L.spans[r] = spans[s * SPAN_ROWS + r];
+            for (int r = lane; r < SPAN_ROWS; r += WAVE) {
+                L.rows[r] = spans[s * SPAN_ROWS + r];
+                L.redge[r] = redges[s * SPAN_ROWS + r];
+            }
+            if (lane < EDGE_SLOTS) {
+                const bool used = lane < MAX_SLOTS;
+                L.ex[lane] = used ? P->ex[lane] : 0.0;
+                L.ey[lane] = used ? P->ey[lane] : 0.0;
+                L.c[lane] = used ? P->c[lane] : 1.0;
+            }
             wave_sync();
         }
-        if (lane < TILE_WORDS) L.mask[lane] = 0;
         int qn = 0;
         const int64_t tb = abase + (t - tile0) * TILE;
         float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
 #pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
-        // one chunk: quick test per point, the others queued for the exact
-        // test (FULL: every slot of the tile lies in the set)
+        // one chunk: classify its 4 points per lane, queue the undecided
+        // ones, drain full batches (FULL: every position lies in the set)
         auto chunk = [&](auto full_tag, int c) {
             constexpr bool FULL = decltype(full_tag)::value;
             const int64_t a = tb + c * CHUNK + 4 * lane;
+            int32_t kx[4], ky[4];
+            uint32_t dy[4];
+            Span sp[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                kx[j] = (int32_t)(xv[c][j] * GRIDF);
+                ky[j] = (int32_t)(yv[c][j] * GRIDF);
+                dy[j] = (uint32_t)(ky[j] - ky_lo);
+                sp[j] = L.rows[min(dy[j] >> shift, (uint32_t)(SPAN_ROWS - 1))];
+            }
+            uint64_t sw[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const bool valid = FULL || ((a + j >= o0) && (a + j < o1));
-                int32_t kx = (int32_t)(xv[c][j] * GRIDF), ky = (int32_t)(yv[c][j] * GRIDF);
-                uint32_t dy = (uint32_t)(ky - ky_lo);
-                uint32_t row = min(dy >> shift, (uint32_t)(SPAN_ROWS - 1));
-                Span sp = L.spans[row];
-                bool quick = has_rows && dy <= yspan && kx >= sp.xl && kx <= sp.xr;
-                bool slow = valid && !quick;
-                uint64_t bal = __ballot(slow);
-                if (slow) {
-                    int p = qn + __popcll(bal & lanemask_lt());
-                    L.q[p] = (uint64_t)((uint32_t)kx & 0xFFFFFFu) |
-                             ((uint64_t)((uint32_t)ky & 0xFFFFFFu) << 24) |
-                             ((uint64_t)(c * CHUNK + 4 * lane + j) << 48);
+                const bool in_y = has_rows && dy[j] <= ylim;
+                const bool inside = in_y && kx[j] >= sp[j].xl && kx[j] <= sp[j].xr;
+                const bool outside = !in_y || kx[j] <= sp[j].ol || kx[j] >= sp[j].orr;
+                sw[j] = __ballot(valid && outside);
+                const bool slow = valid && !inside && !outside;
+                const uint64_t bal = __ballot(slow);
+                if (bal) {
+                    if (slow) {
+                        const int p = qn + __popcll(bal & lanemask_lt());
+                        L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
+                                 ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
+                                 ((uint64_t)(c * CHUNK + 4 * lane + j) << 48);
+                    }
+                    qn += __popcll(bal);
                 }
-                qn += __popcll(bal);
             }
+            if (lane < 4) L.mask[c * 4 + lane] = lane == 0 ? sw[0] : lane == 1 ? sw[1] : lane == 2 ? sw[2] : sw[3];
             wave_sync();
             while (qn >= WAVE) {
                 qn -= WAVE;
-                drain<NEDGE>(L, qn, WAVE, P);
+                drain<NEDGE>(L, qn, WAVE, ky_lo, shift);
             }
             wave_sync();
         };
@@ -817,12 +899,12 @@ __global__ __launch_bounds__(256) void k_discard(
 #pragma unroll
             for (int c = 0; c < TILE_CHUNKS; c++) chunk(std::integral_constant<bool, false>(), c);
         }
-        if (qn > 0) drain<NEDGE>(L, 0, qn, P);
+        if (qn > 0) drain<NEDGE>(L, 0, qn, ky_lo, shift);
         wave_sync();
-        uint64_t mw = lane < TILE_WORDS ? L.mask[lane] : 0;
-        int64_t cnt = wave_sum_i64(__popcll(mw));
+        const uint64_t mw = lane < TILE_WORDS ? L.mask[lane] : 0;
+        const uint32_t cnt = row0_sum_u32((uint32_t)__popcll(mw));
         if (cnt > 0 && lane < TILE_WORDS) masks[t * TILE_WORDS + lane] = mw;
-        if (lane == 0) tile_cnt[t] = (uint32_t)cnt;
+        if (lane == 0) tile_cnt[t] = cnt;
         wave_sync();
     }
 }
