@@ -59,6 +59,135 @@ def cpu_baseline(sample_n):
             "seconds": round(t, 3)}
 
 
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _discard_fraction_batched(H, x, y, off):
+    slots = H.extremes_batched(x, y, off)
+    _, so = H.discard_batched(x, y, off, slots)
+    return 1.0 - float(so[-1].item()) / x.numel()
+
+
+def bench_batched(args, dev):
+    """Batched plain method: 4096 sets, sizes log-uniform in [1e3, 1e6], kinds
+    uniform over square/disk/gaussian/annulus.  Per-set calls vs one batched
+    call vs the same batched call replayed from a captured hipGraph."""
+    import torch
+    from paper_1405_3454_amd import inputs
+    from paper_1405_3454_amd.api import Hull
+    S = args.batch_sets
+    sizes = inputs.batch_sizes(S, 2024)
+    t0 = time.time()
+    x, y, off, names = inputs.batch_torch(sizes, 2025, device=dev)
+    torch.cuda.synchronize()
+    n = x.numel()
+    print("[bench] batched: %d sets, %d points, generated in %.1fs" % (S, n, time.time() - t0),
+          file=sys.stderr, flush=True)
+    H = Hull(0)
+    tuning = H.autotune(x, y, off)
+    hull = torch.empty(n, dtype=torch.int32, device=dev)
+    ho = torch.zeros(S + 1, dtype=torch.int64, device=dev)
+    hcnt = torch.zeros(S, dtype=torch.int64, device=dev)
+    offs = off.cpu().numpy()
+
+    def per_set():
+        for s in range(S):
+            a, b = int(offs[s]), int(offs[s + 1])
+            H.compute_into(x[a:b], y[a:b], hull[a:b], hcnt[s:s + 1])
+
+    def batched():
+        H.compute_batched_into(x, y, off, hull, ho)
+
+    t_set = _time(per_set, 2, 1)
+    t_bat = _time(batched, args.steps, 1)
+    H.graph_capture(x, y, off, hull, ho)
+    t_graph = _time(H.graph_launch, args.steps, 1)
+    disc = _discard_fraction_batched(H, x, y, off)
+    H.close()
+    res = {"workload": "%d sets, sizes log-uniform [1e3, 1e6], square/disk/gaussian/annulus" % S,
+           "points": int(n),
+           "per_set_gpts": round(n / t_set / 1e9, 3),
+           "batched_gpts": round(n / t_bat / 1e9, 3),
+           "graph_gpts": round(n / t_graph / 1e9, 3),
+           "ms": {"per_set": round(t_set * 1e3, 3), "batched": round(t_bat * 1e3, 3),
+                  "graph": round(t_graph * 1e3, 3)},
+           "speedup_graph_vs_per_set": round(t_set / t_graph, 2),
+           "discard_fraction": round(disc, 6),
+           "tuning": tuning}
+    del x, y, hull
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_learned(args, dev):
+    """Learned proposal.  Training: mixture sets of 2^16 points, labels,
+    histograms, forward/backward and Adam all on the GPU.  Inference: 1024
+    sets of 2^17 points (thin ellipses and mixtures alternating) plus one
+    thin-ellipse set of 2^27, plain vs learned filter, each replayed from a
+    captured hipGraph (histogram, network and top-8 inside the graph)."""
+    import torch
+    from paper_1405_3454_amd import inputs, train
+    from paper_1405_3454_amd.api import Hull
+    H = Hull(0)
+    t0 = time.perf_counter()
+    params, losses = train.train(H, sets=args.train_sets, batch=512, points=1 << 16, lr=1e-3,
+                                 seed=7)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    H.close()
+    sizes = [1 << 17] * 1024 + [1 << 27]
+    t0 = time.time()
+    x, y, off, names = inputs.batch_torch(
+        sizes, 4242, device=dev, pick=lambda i: "ellipse" if (i % 2 == 0 or i == 1024) else "mixture")
+    torch.cuda.synchronize()
+    n = x.numel()
+    S = len(sizes)
+    print("[bench] learned: trained on %d sets in %.1fs; %d points generated in %.1fs"
+          % (args.train_sets, t_train, n, time.time() - t0), file=sys.stderr, flush=True)
+    out = {}
+    hulls = {}
+    for name, learned in (("plain", False), ("learned", True)):
+        Hc = Hull(0)
+        Hc.mlp_set_params(params)
+        hull = torch.empty(n, dtype=torch.int32, device=dev)
+        ho = torch.zeros(S + 1, dtype=torch.int64, device=dev)
+        Hc.graph_capture(x, y, off, hull, ho, learned=learned)
+        t = _time(Hc.graph_launch, args.steps, 1)
+        slots = Hc.extremes_batched(x, y, off, learned=learned)
+        _, so = Hc.discard_batched(x, y, off, slots)
+        out[name] = (t, 1.0 - float(so[-1].item()) / n)
+        hulls[name] = (ho.cpu(), hull[: int(ho[-1].item())].cpu())
+        Hc.close()
+        del hull
+    same = bool(torch.equal(hulls["plain"][0], hulls["learned"][0]) and
+                torch.equal(hulls["plain"][1], hulls["learned"][1]))
+    del x, y
+    torch.cuda.empty_cache()
+    return {"training": {"sets": args.train_sets, "points_per_set": 1 << 16, "batch": 512,
+                         "seconds": round(t_train, 2),
+                         "sets_per_s": round(args.train_sets / t_train, 1),
+                         "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 5)},
+            "workload": "1024 sets x 2^17 (thin ellipses / mixtures) + 1 thin ellipse x 2^27",
+            "points": int(n),
+            "plain_gpts": round(n / out["plain"][0] / 1e9, 3),
+            "learned_gpts": round(n / out["learned"][0] / 1e9, 3),
+            "ms": {"plain": round(out["plain"][0] * 1e3, 3),
+                   "learned": round(out["learned"][0] * 1e3, 3)},
+            "discard_fraction": {"plain": round(out["plain"][1], 6),
+                                 "learned": round(out["learned"][1], 6)},
+            "speedup_learned_vs_plain": round(out["plain"][0] / out["learned"][0], 3),
+            "hulls_identical": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +198,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 23)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--batch-sets", type=int, default=4096)
+    ap.add_argument("--train-sets", type=int, default=200000)
+    ap.add_argument("--skip-extra", action="store_true",
+                    help="only the four 2^27 sets (no unfiltered, batched or learned lines)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -181,10 +314,29 @@ def main():
         "hull_vertices": hs,
         "per_kernel": per_kernel,
     }
+    if not args.skip_extra:
+        # unfiltered arm: the same hull without the filter (sort + chain of all points)
+        hull_u = torch.empty(n, dtype=torch.int32, device=dev)
+        hu = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def step_u():
+            for k in KINDS:
+                H.compute_into(X[k], Y[k], hull_u, hu, nofilter=True)
+        t_u = _time(step_u, max(2, args.steps // 2), 1)
+        out["unfiltered"] = {"gpts": round(total_pts / t_u / 1e9, 3),
+                             "ms_per_step": round(t_u * 1e3, 3),
+                             "speedup_of_filter": round(t_u / dt, 3)}
+        del hull_u
+        H.close()
+        del X, Y, hull
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(args, dev)
+        out["learned"] = bench_learned(args, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)
-    H.close()
+    if args.skip_extra:
+        H.close()
 
 
 if __name__ == "__main__":

@@ -13,7 +13,10 @@
  * Conventions shared by every call
  * --------------------------------
  *  - Points are structure-of-arrays float32 x[n], y[n] in DEVICE memory owned
- *    by the caller, each 16-byte aligned.  The exactness guarantees hold for
+ *    by the caller, each 4-byte aligned and both at the same address modulo
+ *    16 (for example equal offsets into two 16-byte aligned arrays); reads
+ *    may touch the up to three floats before x[0] and y[0] that share their
+ *    16-byte block, never anything beyond x[n-1].  The exactness guarantees hold for
  *    coordinates that are multiples of 2^-24 in [0, 1) (HULL_VALIDATE checks
  *    this); on that grid every orientation test is exact in binary64.
  *  - Indices are uint32 positions into x/y (so n <= 2^32 - 1), global even in
@@ -194,14 +197,34 @@ int hull_mlp_backward(hull_ctx *ctx, const uint16_t *hist, const float *dscores,
 int hull_mlp_train_step(hull_ctx *ctx, const uint16_t *hist, const float *gain, int64_t B,
                         float lr, float *loss, void *stream);
 /* The eight chosen directions per set (device int32 [S][8]) for scores
- * [S][64]: highest first, lower index on ties. */
+ * [S][64]: highest first, lower index on ties, NaN as -inf; with a direction
+ * gap g (hull_set_direction_gap) each pick also rules out the directions
+ * within g steps of it on the circle of 64. */
 int hull_top_directions(hull_ctx *ctx, const float *scores, int64_t S, int32_t *dirs,
                         void *stream);
+/* Minimum spacing of the learned picks: gap g in [0, 3] (default 2) makes
+ * any two of the eight chosen directions at least g + 1 of the 64 steps
+ * apart, for hull_top_directions and for the HULL_LEARNED paths.
+ * Errors: HULL_EINVAL for g outside [0, 3]. */
+int hull_set_direction_gap(hull_ctx *ctx, int gap);
 /* Training labels (device float [S][64]): for direction d, the fraction of the
  * set's points that the plain filter keeps but the polygon of the sixteen
  * fixed extremes plus the extreme along d discards. */
 int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
                         int64_t S, int64_t n_total, float *gain, void *stream);
+/* Greedy joint training targets (device float [S][64]) and the greedy order
+ * (device int32 [S][rounds], -1 after the sequence ends), 1 <= rounds <= 8.
+ * Starting from the fixed filter's polygon, each round adds the candidate
+ * direction whose extreme point makes the polygon strictly contain the most
+ * of the fixed filter's survivors not yet contained (ties: lowest direction);
+ * a round without gain ends the sequence.  The direction chosen in round r
+ * gets 1 - r / (2 rounds); every other direction d gets 0.5 g_d / max g, g_d
+ * its gain in the first round (0 if all are 0).  Targets peak at 1, so
+ * hull_mlp_train_step's scaling by the per-set maximum leaves them as they
+ * are.  Errors: HULL_EINVAL for rounds outside [1, 8]. */
+int hull_label_targets_batched(hull_ctx *ctx, const float *x, const float *y,
+                               const int64_t *offsets, int64_t S, int64_t n_total, int rounds,
+                               float *target, int32_t *order, void *stream);
 
 /* ---- per-kernel timing (hipEvents around every launch) ----------------- */
 int hull_timing_enable(hull_ctx *ctx, int on);

@@ -69,6 +69,8 @@ def lib():
         L.oracle_histogram.restype = None
         L.oracle_labels.argtypes = [P, P, I64, P, P, I, P, P, I, P]
         L.oracle_labels.restype = I
+        L.oracle_label_targets.argtypes = [P, P, I64, P, P, I, P, P, I, I, P, P]
+        L.oracle_label_targets.restype = I
         _lib = L
     return _lib
 
@@ -213,3 +215,22 @@ def labels(x, y, p=PRESET_PAPER, cs=None, dirs=None):
     if rc:
         raise RuntimeError("oracle_labels failed")
     return gain
+
+
+def label_targets(x, y, rounds=8, p=PRESET_PAPER, cs=None, dirs=None):
+    """Greedy joint training targets (float32 per direction) and the greedy
+    order (int32 per round, -1 after the sequence ends)."""
+    x, y = _pts(x, y)
+    c, s = cs if cs is not None else preset(p)
+    c = np.ascontiguousarray(c, np.float64)
+    s = np.ascontiguousarray(s, np.float64)
+    cd, sd = dirs if dirs is not None else direction_table()
+    cd = np.ascontiguousarray(cd, np.float64)
+    sd = np.ascontiguousarray(sd, np.float64)
+    target = np.zeros(len(cd), np.float32)
+    order = np.full(rounds, -1, np.int32)
+    rc = lib().oracle_label_targets(_p(x), _p(y), len(x), _p(c), _p(s), len(c), _p(cd), _p(sd),
+                                    len(cd), int(rounds), _p(target), _p(order))
+    if rc:
+        raise RuntimeError("oracle_label_targets failed")
+    return target, order

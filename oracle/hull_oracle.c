@@ -307,10 +307,13 @@ int oracle_compute(const float *x, const float *y, int64_t n,
 
 /* 32 x 32 occupancy histogram of a point set, the network's input.
  * Sample: every stride-th point, stride = ceil(n / 16384), starting at 0.
- * Grid coordinates kx = x * 2^24 (integers on the input grid).  Bins span the
- * sample's bounding box: bx = (kx - min kx) * 32 / (max kx - min kx + 1) in
- * integer arithmetic, likewise by.  hist[by * 32 + bx] = count * 1024 / ns
- * (binary64 product and quotient, rounded to float), ns the sample size. */
+ * Grid coordinates kx = x * 2^24 (integers on the input grid).  The bins
+ * span a square window around the sample's bounding box, so the set keeps its
+ * aspect ratio: with box widths wx = max kx - min kx + 1, wy likewise, and
+ * w = max(wx, wy), the window starts at (min kx - (w - wx) / 2,
+ * min ky - (w - wy) / 2) and bx = (kx - start x) * 32 / w in integer
+ * arithmetic, likewise by.  hist[by * 32 + bx] = count * 1024 / ns (binary64
+ * product and quotient, rounded to float), ns the sample size. */
 void oracle_histogram(const float *x, const float *y, int64_t n, float *hist)
 {
     int64_t cnt[1024];
@@ -328,11 +331,13 @@ void oracle_histogram(const float *x, const float *y, int64_t n, float *hist)
         if (ky < y0) y0 = ky;
         if (ky > y1) y1 = ky;
     }
+    int64_t wx = x1 - x0 + 1, wy = y1 - y0 + 1, w = wx > wy ? wx : wy;
+    int64_t sx = x0 - (w - wx) / 2, sy = y0 - (w - wy) / 2;
     for (int64_t j = 0; j < ns; j++) {
         int64_t kx = (int64_t)((double)x[j * stride] * 16777216.0);
         int64_t ky = (int64_t)((double)y[j * stride] * 16777216.0);
-        int64_t bx = (kx - x0) * 32 / (x1 - x0 + 1);
-        int64_t by = (ky - y0) * 32 / (y1 - y0 + 1);
+        int64_t bx = (kx - sx) * 32 / w;
+        int64_t by = (ky - sy) * 32 / w;
         cnt[by * 32 + bx]++;
     }
     for (int b = 0; b < 1024; b++)
@@ -380,6 +385,80 @@ int oracle_labels(const float *x, const float *y, int64_t n,
         }
         gain[d] = (double)inside / (double)n;
     }
+    free(sv);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Greedy joint training targets for the learned proposal (an extension of
+ * this project; the paper has no learned part).  The fixed filter's extreme
+ * points start the set E.  Round r = 0, 1, ... tries every candidate
+ * direction d: g_d(r) = number of the fixed filter's survivors strictly
+ * inside polygon(E + {e_d}) but not strictly inside polygon(E).  The
+ * direction with the largest g_d(r) (lowest d on ties) joins E; a round
+ * whose largest gain is 0 ends the sequence.  Targets: the direction chosen
+ * in round r gets 1 - r / (2R); any other direction d gets 0.5 g_d(0) / max
+ * g(0), or 0 when that maximum is 0.  order[r] is the chosen direction or -1.
+ * ---------------------------------------------------------------------- */
+static int strictly_inside(const float *x, const float *y, const uint32_t *v, int m, uint32_t i)
+{
+    if (m < 3) return 0;
+    double px = (double)x[i], py = (double)y[i];
+    for (int e = 0; e < m; e++) {
+        uint32_t a = v[e], b = v[(e + 1) % m];
+        double ax = x[a], ay = y[a], bx = x[b], by = y[b];
+        if (!((bx - ax) * (py - ay) - (by - ay) * (px - ax) > 0)) return 0;
+    }
+    return 1;
+}
+
+int oracle_label_targets(const float *x, const float *y, int64_t n,
+                         const double *c, const double *s, int G,
+                         const double *cd, const double *sd, int D, int R,
+                         float *target, int32_t *order)
+{
+    if (G < 0 || G > 16 || D < 1 || D > 256 || R < 1 || R > 16) return -1;
+    for (int d = 0; d < D; d++) target[d] = 0.0f;
+    for (int r = 0; r < R; r++) order[r] = -1;
+    if (n <= 0) return 0;
+    uint32_t base[64], ed[256], pts[96], cur[96], trial[96];
+    int64_t *g0 = (int64_t *)calloc((size_t)D, sizeof(int64_t));
+    uint32_t *sv = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (!g0 || !sv) { free(g0); free(sv); return -1; }
+    int m = 0;
+    oracle_extremes(x, y, n, c, s, G, base, NULL);
+    oracle_polygon(x, y, base, 4 * G, cur, &m);
+    int64_t cnt = 0;
+    oracle_discard(x, y, n, cur, m, sv, &cnt);
+    oracle_extremes_dirs(x, y, n, cd, sd, D, ed, NULL);
+    int np = 4 * G;
+    for (int j = 0; j < np; j++) pts[j] = base[j];
+    for (int r = 0; r < R; r++) {
+        int mc = 0;
+        oracle_polygon(x, y, pts, np, cur, &mc);
+        int best = -1;
+        int64_t bestg = 0;
+        for (int d = 0; d < D; d++) {
+            pts[np] = ed[d];
+            int mt = 0;
+            oracle_polygon(x, y, pts, np + 1, trial, &mt);
+            int64_t g = 0;
+            for (int64_t j = 0; j < cnt; j++)
+                if (!strictly_inside(x, y, cur, mc, sv[j]) && strictly_inside(x, y, trial, mt, sv[j])) g++;
+            if (r == 0) g0[d] = g;
+            if (g > bestg) { bestg = g; best = d; }
+        }
+        if (best < 0) break;
+        order[r] = best;
+        pts[np++] = ed[best];
+    }
+    int64_t gmax = 0;
+    for (int d = 0; d < D; d++) if (g0[d] > gmax) gmax = g0[d];
+    for (int d = 0; d < D; d++)
+        target[d] = gmax > 0 ? (float)(0.5 * ((double)g0[d] / (double)gmax)) : 0.0f;
+    for (int r = 0; r < R; r++)
+        if (order[r] >= 0) target[order[r]] = (float)(1.0 - (double)r / (2.0 * R));
+    free(g0);
     free(sv);
     return 0;
 }

@@ -104,9 +104,23 @@ def adam(params, grads, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def top_directions(scores, k=8):
+def top_directions(scores, k=8, gap=0):
     """Indices of the k largest scores per row, largest first, lower index on
-    ties (NaN counts as -inf)."""
+    ties (NaN counts as -inf).  With gap > 0 every pick also rules out the
+    directions within gap steps of it on the circle of len(row)."""
     s = np.where(np.isnan(scores), -np.inf, np.asarray(scores, np.float64))
-    order = np.lexsort((np.broadcast_to(np.arange(s.shape[1]), s.shape), -s), axis=1)
-    return order[:, :k]
+    if gap == 0:
+        order = np.lexsort((np.broadcast_to(np.arange(s.shape[1]), s.shape), -s), axis=1)
+        return order[:, :k]
+    D = s.shape[1]
+    out = np.zeros((s.shape[0], k), np.int64)
+    for r in range(s.shape[0]):
+        avail = np.ones(D, bool)
+        for j in range(k):
+            cand = [d for d in range(D) if avail[d]]
+            best = max(cand, key=lambda d: (s[r, d], -d))
+            out[r, j] = best
+            for d in range(D):
+                if min((d - best) % D, (best - d) % D) <= gap:
+                    avail[d] = False
+    return out

@@ -58,6 +58,8 @@ SIGNATURES = {
     "hull_mlp_train_step": (I, [P, P, P, I64, ctypes.c_float, P, P]),
     "hull_top_directions": (I, [P, P, I64, P, P]),
     "hull_labels_batched": (I, [P, P, P, P, I64, I64, P, P]),
+    "hull_label_targets_batched": (I, [P, P, P, P, I64, I64, I, P, P, P]),
+    "hull_set_direction_gap": (I, [P, I]),
     "hull_timing_enable": (I, [P, I]),
     "hull_timing_read": (I, [P, P, P, I]),
     "hull_timing_name": (ctypes.c_char_p, [I]),

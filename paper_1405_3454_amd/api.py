@@ -257,6 +257,12 @@ class Hull:
                                         _ptr(loss), _stream(stream)), "hull_mlp_train_step")
         return loss
 
+    DEFAULT_DIRECTION_GAP = 2
+
+    def set_direction_gap(self, gap):
+        """Minimum spacing (gap + 1 of 64 steps) between the learned picks."""
+        check(lib().hull_set_direction_gap(self._h, int(gap)), "hull_set_direction_gap")
+
     def top_directions(self, scores, stream=None):
         S = scores.shape[0]
         scores = scores.to(dtype=torch.float32).contiguous()
@@ -272,6 +278,18 @@ class Hull:
         check(lib().hull_labels_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n, _ptr(g),
                                         _stream(stream)), "hull_labels_batched")
         return g
+
+    def label_targets_batched(self, x, y, offsets, rounds=8, stream=None):
+        """Greedy joint targets [S, 64] (float32) and the greedy order
+        [S, rounds] (int32, -1 after the sequence ends)."""
+        n = _pts(x, y)
+        S = offsets.numel() - 1
+        t = torch.empty((S, 64), dtype=torch.float32, device=x.device)
+        o = torch.empty((S, rounds), dtype=torch.int32, device=x.device)
+        check(lib().hull_label_targets_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
+                                               int(rounds), _ptr(t), _ptr(o), _stream(stream)),
+              "hull_label_targets_batched")
+        return t, o
 
     # -- timing ------------------------------------------------------------
     def timing(self, on=True):

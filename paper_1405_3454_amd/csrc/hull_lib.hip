@@ -41,6 +41,7 @@ struct hull_ctx {
     int device = 0;
     int preset = HULL_DIRS_PAPER;
     Dirs dirs;
+    int dir_gap = 2;           // learned picks: minimum spacing - 1 on the circle of 64
     int cus = 256;
     hipError_t last = hipSuccess;
     char *ws = nullptr;
@@ -200,9 +201,14 @@ static int check_points(const float *x, const float *y, int64_t n) {
     if (n < 0) return HULL_EINVAL;
     if (n >= (int64_t(1) << 32) - 1) return HULL_ETOOBIG;
     if (n > 0 && (!x || !y)) return HULL_EINVAL;
-    if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return HULL_EINVAL;
+    if (((uintptr_t)x & 3) || ((uintptr_t)y & 3) || (((uintptr_t)x ^ (uintptr_t)y) & 15))
+        return HULL_EINVAL;
     return HULL_OK;
 }
+
+// Position of x[0] within its 16-byte block, in floats: the filter passes
+// align their tiles to absolute 16-byte boundaries.
+static int phase_of(const float *x) { return (int)(((uintptr_t)x >> 2) & 3); }
 
 // the learned variant of the extremes pass holds ~190 VGPRs: 2 waves per SIMD
 static int grid_k1(hull_ctx *ctx, bool learned = false) {
@@ -234,10 +240,10 @@ static int run_validate(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
     return h ? HULL_EDOMAIN : HULL_OK;
 }
 
-static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const int64_t *off,
-                       int64_t n1, int64_t S) {
+static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                       const int64_t *off, int64_t n1, int64_t S) {
     int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
-    LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, 1, tile_off));
+    LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, phase_of(x), tile_off));
     LAUNCH(K_TILEMAP, k_tile_sets<<<(unsigned)S, 256, 0, st>>>(tile_off, W<int32_t>(ctx, p.tile_set)));
     return HULL_OK;
 }
@@ -254,9 +260,9 @@ static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
     const int g = grid_k1(ctx, learned);
     const Dirs d = ctx->dirs;
 #define K1(PR, ND)                                                                           \
-    LAUNCH(K_EXTREMES, k_extremes<PR, ND><<<g, 256, 0, st>>>(x, y, n_total, off, n1, S,     \
-                                                             tile_off, tile_set, d, sd, pval, \
-                                                             pidx))
+    LAUNCH(K_EXTREMES, k_extremes<PR, ND><<<g, 256, 0, st>>>(x, y, n_total, phase_of(x), off, \
+                                                             n1, S, tile_off, tile_set, d, sd, \
+                                                             pval, pidx))
     if (ctx->preset == HULL_DIRS_PAPER) {
         if (learned) K1(0, MAX_DIRS); else K1(0, 0);
     } else {
@@ -304,15 +310,15 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     const int g = grid_k3(ctx);
     if (nedge <= FIXED_SLOTS)
         LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS><<<g, 256, 0, st>>>(
-            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
+            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
     else
         LAUNCH(K_DISCARD, k_discard<MAX_SLOTS><<<g, 256, 0, st>>>(
-            x, y, n_total, off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
+            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
     int rc = run_scan(ctx, p, st, tcnt, tile_off + S, tpos);
     if (rc) return rc;
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
                                                                                   surv_off));
-    LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, off, S, tile_off, tile_set, masks, tcnt,
+    LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, phase_of(x), off, S, tile_off, tile_set, masks, tcnt,
                                                    tpos, surv, keys));
     return HULL_OK;
 }
@@ -410,6 +416,8 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
 static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                             const float *y, int64_t n_total, const int64_t *off, int64_t n1,
                             int64_t S);
+static int learned_ensure(hull_ctx *ctx, int64_t B, hipStream_t st);
+static int init_cand_table();
 
 static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p) {
     HIPCHECK(hipSetDevice(ctx->device));
@@ -442,7 +450,7 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
         LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
                                                          surv_off));
     } else {
-        if ((rc = run_tilemap(ctx, p, st, off, n1, S))) return rc;
+        if ((rc = run_tilemap(ctx, p, st, x, off, n1, S))) return rc;
         if (learned) {
             rc = run_learned_dirs(ctx, p, st, x, y, n_total, off, n1, S);
             if (rc) return rc;
@@ -552,7 +560,7 @@ int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n, uint
     if (flags & HULL_VALIDATE && (rc = run_validate(ctx, p, st, x, y, n, nullptr, 1))) return rc;
     const bool learned = flags & HULL_LEARNED;
     if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
-    if ((rc = run_tilemap(ctx, p, st, nullptr, n, 1))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, x, nullptr, n, 1))) return rc;
     if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n, nullptr, n, 1))) return rc;
     if ((rc = run_extremes(ctx, p, st, x, y, n, nullptr, n, 1, learned))) return rc;
     return run_polygon(ctx, p, st, x, y, n, 1, learned, nullptr, 0, slots, vals);
@@ -580,7 +588,7 @@ int hull_discard(hull_ctx *ctx, const float *x, const float *y, int64_t n, const
     hipStream_t st = (hipStream_t)stream;
     Plan p;
     if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
-    if ((rc = run_tilemap(ctx, p, st, nullptr, n, 1))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, x, nullptr, n, 1))) return rc;
     if ((rc = run_polygon(ctx, p, st, x, y, n, 1, false, slots, n_slots, nullptr, nullptr))) return rc;
     int64_t *so = W<int64_t>(ctx, p.surv_off);
     if ((rc = run_discard(ctx, p, st, x, y, n, nullptr, n, 1, n_slots, surv, so, nullptr)))
@@ -631,7 +639,7 @@ int hull_extremes_batched(hull_ctx *ctx, const float *x, const float *y, const i
         return rc;
     const bool learned = flags & HULL_LEARNED;
     if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
-    if ((rc = run_tilemap(ctx, p, st, offsets, 0, S))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, x, offsets, 0, S))) return rc;
     if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n_total, offsets, 0, S))) return rc;
     if ((rc = run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, learned))) return rc;
     return run_polygon(ctx, p, st, x, y, n_total, S, learned, nullptr, 0, slots, nullptr);
@@ -647,7 +655,7 @@ int hull_discard_batched(hull_ctx *ctx, const float *x, const float *y, const in
     hipStream_t st = (hipStream_t)stream;
     Plan p;
     if ((rc = prepare(ctx, n_total, S, st, &p))) return rc;
-    if ((rc = run_tilemap(ctx, p, st, offsets, 0, S))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, x, offsets, 0, S))) return rc;
     if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, false, slots, n_slots, nullptr, nullptr))) return rc;
     return run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, n_slots, surv, surv_offsets,
                        nullptr);
@@ -674,6 +682,12 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int6
     HIPCHECK(hipSetDevice(ctx->device));
     Plan p = make_plan(n_total, S);
     if ((rc = ensure_ws(ctx, p.total, st))) return rc;
+    if ((flags & HULL_LEARNED) && !(flags & HULL_NOFILTER)) {
+        // the network's buffers are sized before capture: nothing allocates inside
+        if (!ctx->learned.loaded) return HULL_ENOMODEL;
+        if ((rc = init_cand_table())) return rc;
+        if ((rc = learned_ensure(ctx, S, st))) return rc;
+    }
     hipStream_t cs;
     HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     const bool was_timing = ctx->timing;
@@ -745,7 +759,7 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     int rc = prepare(ctx, n_total, S, st, &p);
     if (rc) return rc;
     const int64_t n1 = batched ? 0 : n_total;
-    if ((rc = run_tilemap(ctx, p, st, offsets, n1, S))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, x, offsets, n1, S))) return rc;
     const bool was_timing = ctx->timing;
     ctx->timing = false;
     hipEvent_t a, b;
@@ -941,7 +955,7 @@ static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const 
     bf16_t *hist = W<bf16_t>(ctx, p.learn);
     LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, 256, 0, st>>>(x, y, off, n1, S, hist, nullptr));
     RC(mlp_forward(ctx, st, hist, S));
-    LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(ctx->learned.scores, S, nullptr,
+    LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(ctx->learned.scores, S, ctx->dir_gap, nullptr,
                                                                  W<double>(ctx, p.setdirs)));
     return HULL_OK;
 }
@@ -1047,6 +1061,12 @@ int hull_mlp_train_step(hull_ctx *ctx, const uint16_t *hist, const float *gain, 
     return HULL_OK;
 }
 
+int hull_set_direction_gap(hull_ctx *ctx, int gap) {
+    if (!ctx || gap < 0 || gap > 3) return HULL_EINVAL;
+    ctx->dir_gap = gap;
+    return HULL_OK;
+}
+
 int hull_top_directions(hull_ctx *ctx, const float *scores, int64_t S, int32_t *dirs, void *stream) {
     if (!ctx || !scores || !dirs || S <= 0) return HULL_EINVAL;
     hipStream_t st = (hipStream_t)stream;
@@ -1054,7 +1074,7 @@ int hull_top_directions(hull_ctx *ctx, const float *scores, int64_t S, int32_t *
     RC(init_cand_table());
     Plan p;
     RC(prepare(ctx, 0, S, st, &p));
-    LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(scores, S, dirs,
+    LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(scores, S, ctx->dir_gap, dirs,
                                                                  W<double>(ctx, p.setdirs)));
     return HULL_OK;
 }
@@ -1068,7 +1088,7 @@ int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int
     hipStream_t st = (hipStream_t)stream;
     Plan p;
     RC(prepare(ctx, n_total, S, st, &p));
-    RC(run_tilemap(ctx, p, st, offsets, 0, S));
+    RC(run_tilemap(ctx, p, st, x, offsets, 0, S));
     RC(run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, false));
     RC(run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr));
     uint32_t *surv = W<uint32_t>(ctx, p.surv);
@@ -1078,6 +1098,29 @@ int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int
     LAUNCH(K_LABELS, k_cand_extremes<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, cand));
     LAUNCH(K_LABELS, k_labels<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, W<Poly>(ctx, p.polys),
                                                           cand, surv, so, gain));
+    return HULL_OK;
+}
+
+int hull_label_targets_batched(hull_ctx *ctx, const float *x, const float *y,
+                               const int64_t *offsets, int64_t S, int64_t n_total, int rounds,
+                               float *target, int32_t *order, void *stream) {
+    if (!ctx || !target || !order || rounds < 1 || rounds > LT_MAXR) return HULL_EINVAL;
+    int rc = check_batch(x, y, offsets, S, n_total);
+    if (rc) return rc;
+    RC(init_cand_table());
+    hipStream_t st = (hipStream_t)stream;
+    Plan p;
+    RC(prepare(ctx, n_total, S, st, &p));
+    RC(run_tilemap(ctx, p, st, x, offsets, 0, S));
+    RC(run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, false));
+    RC(run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr));
+    uint32_t *surv = W<uint32_t>(ctx, p.surv);
+    int64_t *so = W<int64_t>(ctx, p.surv_off);
+    RC(run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, FIXED_SLOTS, surv, so, nullptr));
+    uint32_t *cand = W<uint32_t>(ctx, p.cand);
+    LAUNCH(K_LABELS, k_cand_extremes<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, cand));
+    LAUNCH(K_LABELS, k_label_targets<<<(unsigned)S, 256, 0, st>>>(
+        x, y, offsets, 0, S, W<Poly>(ctx, p.polys), cand, surv, so, rounds, target, order));
     return HULL_OK;
 }
 

@@ -3,8 +3,9 @@
 // survivor masks), survivor scatter, and the shared scan kernels.
 //
 // Work decomposition.  Set s covers points [o_s, o_{s+1}).  Its tiles start
-// at A_s = o_s rounded down to a multiple of 4 (so every float4 load is
-// 16-byte aligned) and cover TILE = 1024 point slots each; slots outside
+// at A_s = o_s rounded down to the nearest position whose address is 16-byte
+// aligned (so every float4 load is aligned) and cover TILE = 1024 point
+// slots each; slots outside
 // [o_s, o_{s+1}) are masked.  The persistent filter kernels give wave w the
 // contiguous tile range [w q, (w+1) q), q = ceil(T / W), so a wave walks
 // ascending point indices and meets each set as one contiguous "run".
@@ -14,12 +15,19 @@
 
 namespace hg {
 
+// First tile position of a set starting at o: o rounded down so that the
+// point's address is 16-byte aligned, given the block position (phase) of
+// x[0].  May be up to 3 below 0; those positions lie in x[0]'s own block.
+__device__ __forceinline__ int64_t tile_base(int64_t o, int phase) {
+    return o - ((o + phase) & 3);
+}
+
 // ---------------------------------------------------------------------------
 // Tile map: tile_off[s] = first tile of set s (exclusive scan of tile
 // counts), tile_off[S] = T.  One block of 1024 threads.
 __global__ __launch_bounds__(1024) void k_tile_offsets(const int64_t *__restrict__ off,
                                                        int64_t n1, int64_t S, int64_t unit,
-                                                       int align4, int64_t *__restrict__ tile_off) {
+                                                       int phase, int64_t *__restrict__ tile_off) {
     __shared__ int64_t sh[17];
     int64_t carry = 0;
     for (int64_t base = 0; base < S; base += blockDim.x) {
@@ -28,7 +36,7 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const int64_t *__restrict
         if (s < S) {
             int64_t b = set_begin(off, s), e = set_end(off, n1, s);
             if (e > b) {
-                int64_t a = align4 ? (b & ~int64_t(3)) : b;
+                int64_t a = phase >= 0 ? tile_base(b, phase) : b;
                 cnt = (e - a + unit - 1) / unit;
             }
         }
@@ -267,7 +275,7 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 // genuine pair of the set.
 template <int PRESET, int NDIR>
 __global__ __launch_bounds__(256) void k_extremes(
-    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
+    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int phase,
     const int64_t *__restrict__ off, int64_t n1, int64_t S,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set, Dirs dirs,
     const double *__restrict__ set_dirs, double *__restrict__ pval, uint32_t *__restrict__ pidx) {
@@ -343,7 +351,7 @@ __global__ __launch_bounds__(256) void k_extremes(
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
             tile0 = tile_off[s];
-            abase = o0 & ~int64_t(3);
+            abase = tile_base(o0, phase);
             x0f = x[o0];
             y0f = y[o0];
 #pragma unroll
@@ -773,8 +781,10 @@ __device__ __forceinline__ void drain(DiscardLds &L, int from, int count, int32_
         const uint32_t re = L.redge[(uint32_t)(ky - ky_lo) >> shift];
         bool inside;
         if (re != ROW_EDGES_ALL) {
-            inside = edge_in(L, re & 0xFF, px, py) & edge_in(L, (re >> 8) & 0xFF, px, py) &
-                     edge_in(L, (re >> 16) & 0xFF, px, py) & edge_in(L, re >> 24, px, py);
+            // all four evaluated (no short circuit): unused entries name an
+            // always-satisfied edge
+            inside = ((int)edge_in(L, re & 0xFF, px, py) & (int)edge_in(L, (re >> 8) & 0xFF, px, py) &
+                      (int)edge_in(L, (re >> 16) & 0xFF, px, py) & (int)edge_in(L, re >> 24, px, py)) != 0;
         } else {
             inside = true;
 #pragma unroll
@@ -798,7 +808,7 @@ __device__ __forceinline__ uint32_t row0_sum_u32(uint32_t v) {
 
 template <int NEDGE>
 __global__ __launch_bounds__(256) void k_discard(
-    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total,
+    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int phase,
     const int64_t *__restrict__ off, int64_t n1, int64_t S, const int64_t *__restrict__ tile_off,
     const int32_t *__restrict__ tile_set, const Poly *__restrict__ polys,
     const Span *__restrict__ spans, const uint32_t *__restrict__ redges,
@@ -825,7 +835,7 @@ __global__ __launch_bounds__(256) void k_discard(
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
             tile0 = tile_off[s];
-            abase = o0 & ~int64_t(3);
+            abase = tile_base(o0, phase);
             const Poly *P = polys + s;
             ky_lo = P->ky_lo;
             has_rows = P->yspan >= 0;
@@ -913,7 +923,8 @@ __global__ __launch_bounds__(256) void k_discard(
 // Survivor scatter: tile t's survivors go to positions tile_pos[t]... in
 // ascending index order.  keys (optional): set << 48 | kx << 24 | ky.
 __global__ __launch_bounds__(256) void k_scatter(
-    const float *__restrict__ x, const float *__restrict__ y, const int64_t *__restrict__ off,
+    const float *__restrict__ x, const float *__restrict__ y, int phase,
+    const int64_t *__restrict__ off,
     int64_t S, const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set,
     const uint64_t *__restrict__ masks, const uint32_t *__restrict__ tile_cnt,
     const int64_t *__restrict__ tile_pos, uint32_t *__restrict__ surv, uint64_t *__restrict__ keys) {
@@ -926,7 +937,7 @@ __global__ __launch_bounds__(256) void k_scatter(
         if (tile_cnt[t] == 0) continue;
         const int64_t s = tile_set[t];
         const int64_t o0 = set_begin(off, s);
-        const int64_t tb = (o0 & ~int64_t(3)) + (t - tile_off[s]) * TILE;
+        const int64_t tb = tile_base(o0, phase) + (t - tile_off[s]) * TILE;
         int64_t base = tile_pos[t];
         for (int c = 0; c < TILE_CHUNKS; c++) {
             uint64_t M[4];

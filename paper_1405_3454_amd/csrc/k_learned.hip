@@ -76,9 +76,12 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32
 
 // ---------------------------------------------------------------------------
 // 32 x 32 occupancy histogram of each set (one block per set).  Sample: every
-// stride-th point of the set, stride = ceil(n / 16384); bins over the
-// sample's bounding box in grid units with integer arithmetic; value =
-// count * 1024 / ns (binary64 product and quotient, then float, then bf16).
+// stride-th point of the set, stride = ceil(n / 16384).  Bins cover a square
+// window of side w = max(width, height) of the sample's bounding box (grid
+// units), centred on the box, so that the set's aspect ratio and the angles
+// of its features are kept: origin (x0 - (w - wx) / 2, y0 - (w - wy) / 2),
+// bin = (k - origin) * 32 / w in integer arithmetic; value = count * 1024 / ns
+// (binary64 product and quotient, then float, then bf16).
 __global__ __launch_bounds__(256) void k_hist32(const float *__restrict__ x,
                                                 const float *__restrict__ y,
                                                 const int64_t *__restrict__ off, int64_t n1,
@@ -117,10 +120,11 @@ __global__ __launch_bounds__(256) void k_hist32(const float *__restrict__ x,
         x0 = min(x0, bb[ww][0]); x1 = max(x1, bb[ww][1]);
         y0 = min(y0, bb[ww][2]); y1 = max(y1, bb[ww][3]);
     }
-    const int64_t wx = (int64_t)x1 - x0 + 1, wy = (int64_t)y1 - y0 + 1;
+    const int64_t wx = (int64_t)x1 - x0 + 1, wy = (int64_t)y1 - y0 + 1, wd = max(wx, wy);
+    const int64_t cx0 = x0 - (wd - wx) / 2, cy0 = y0 - (wd - wy) / 2;
     for (int64_t j = tid; j < ns; j += blockDim.x) {
         int64_t kx = (int32_t)(x[a + j * stride] * GRIDF), ky = (int32_t)(y[a + j * stride] * GRIDF);
-        int64_t bx = (kx - x0) * 32 / wx, by = (ky - y0) * 32 / wy;
+        int64_t bx = (kx - cx0) * 32 / wd, by = (ky - cy0) * 32 / wd;
         atomicAdd(&cnt[by * 32 + bx], 1u);
     }
     __syncthreads();
@@ -303,8 +307,13 @@ __device__ __forceinline__ int32_t score_rank(float v) {
     return (int32_t)(u - 0x80000000u);
 }
 
-__global__ void k_top8(const float *__restrict__ scores, int64_t S, int32_t *__restrict__ dirs,
-                       double *__restrict__ set_dirs) {
+// Eight directions per set (one wave per set): repeatedly the highest score
+// (lowest index on ties, NaN as -inf) among the directions still available;
+// each pick removes itself and, for gap > 0, the directions within gap steps
+// of it on the circle of 64, so that picks are at least gap + 1 steps apart.
+// gap <= 3 always leaves eight picks.
+__global__ void k_top8(const float *__restrict__ scores, int64_t S, int gap,
+                       int32_t *__restrict__ dirs, double *__restrict__ set_dirs) {
     const int64_t s = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int d = lane_id();
     if (s >= S) return;
@@ -323,7 +332,8 @@ __global__ void k_top8(const float *__restrict__ scores, int64_t S, int32_t *__r
             set_dirs[(s * MAX_DIRS + r) * 2 + 0] = dCandCos[bi];
             set_dirs[(s * MAX_DIRS + r) * 2 + 1] = dCandSin[bi];
         }
-        if (d == bi) key = INT32_MIN;
+        const int dist = min((d - bi) & (NOUT - 1), (bi - d) & (NOUT - 1));
+        if (dist <= gap) key = INT32_MIN;
     }
 }
 
@@ -495,6 +505,178 @@ __global__ __launch_bounds__(256) void k_labels(const float *__restrict__ x,
         for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) c += pcnt[ww][tid];
         gain[s * NCAND + tid] = n > 0 ? (float)((double)c / (double)n) : 0.0f;
     }
+}
+
+// Greedy joint training targets (this project's extension).  One block per
+// set.  V starts as the fixed filter's polygon vertices; each of R rounds
+// adds the candidate extreme whose polygon hull(V + {e_d}) newly contains,
+// strictly inside, the most of the fixed filter's survivors (ties: lowest
+// d); a round whose best gain is zero ends the sequence.  Targets: the
+// direction chosen in round r gets 1 - r / (2R); every other direction gets
+// 0.5 g_d / g_max with g_d its round-0 gain (0 if g_max = 0).
+constexpr int LT_MAXR = MAX_DIRS;
+constexpr int LT_V = FIXED_SLOTS + LT_MAXR + 1;       // vertices of hull(V + {e_d})
+
+// Edges of the convex hull of k points sorted by (x, y) without repeats
+// (Andrew's monotone chain, collinear points dropped); returns the vertex
+// count, or 0 when fewer than 3 vertices remain.
+__device__ int hull_edges_sorted(const double *px, const double *py, int k, double *ex, double *ey,
+                                 double *ec) {
+    int st[2 * LT_V + 2];
+    int h = 0;
+    if (k >= 3) {
+        for (int j = 0; j < k; j++) {
+            while (h >= 2 && orient(px[st[h - 2]], py[st[h - 2]], px[st[h - 1]], py[st[h - 1]],
+                                    px[j], py[j]) <= 0)
+                h--;
+            st[h++] = j;
+        }
+        const int lo = h + 1;
+        for (int j = k - 2; j >= 0; j--) {
+            while (h >= lo && orient(px[st[h - 2]], py[st[h - 2]], px[st[h - 1]], py[st[h - 1]],
+                                     px[j], py[j]) <= 0)
+                h--;
+            st[h++] = j;
+        }
+        h--;
+    }
+    if (h < 3) return 0;
+    for (int i = 0; i < h; i++) {
+        const int p0 = st[i], p1 = st[(i + 1) % h];
+        const double ddx = px[p1] - px[p0], ddy = py[p1] - py[p0];
+        ex[i] = ddx;
+        ey[i] = ddy;
+        ec[i] = fma(ddy, px[p0], -(ddx * py[p0]));
+    }
+    return h;
+}
+
+// Insert (gx, gy) into the (x, y)-sorted list of k points unless it is
+// already there; writes k' points to (ox, oy) and returns k'.
+__device__ int merge_point(const double *vx, const double *vy, int k, double gx, double gy,
+                           double *ox, double *oy) {
+    int o = 0;
+    bool ins = true;
+    for (int i = 0; i < k; i++) {
+        if (ins && (gx < vx[i] || (gx == vx[i] && gy <= vy[i]))) {
+            if (!(gx == vx[i] && gy == vy[i])) { ox[o] = gx; oy[o] = gy; o++; }
+            ins = false;
+        }
+        ox[o] = vx[i]; oy[o] = vy[i]; o++;
+    }
+    if (ins) { ox[o] = gx; oy[o] = gy; o++; }
+    return o;
+}
+
+__global__ __launch_bounds__(256) void k_label_targets(
+    const float *__restrict__ x, const float *__restrict__ y, const int64_t *__restrict__ off,
+    int64_t n1, int64_t S, const Poly *__restrict__ polys, const uint32_t *__restrict__ cand,
+    const uint32_t *__restrict__ surv, const int64_t *__restrict__ surv_off, int R,
+    float *__restrict__ target, int32_t *__restrict__ order) {
+    __shared__ double vx[LT_V], vy[LT_V];                  // current vertex set, sorted
+    __shared__ int nv;
+    __shared__ double ex[NCAND][LT_V], ey[NCAND][LT_V], ec[NCAND][LT_V];
+    __shared__ int ne[NCAND];
+    __shared__ double cex[LT_V], cey[LT_V], cec[LT_V];     // hull(V)
+    __shared__ int cm;
+    __shared__ uint32_t pcnt[4][NCAND];
+    __shared__ uint32_t g0[NCAND];
+    __shared__ int chosen[LT_MAXR];
+    __shared__ int stop;
+    const int64_t s = blockIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    const int64_t a = set_begin(off, s), n = set_end(off, n1, s) - a;
+    const Poly &P = polys[s];
+    if (tid == 0) {
+        int k = 0;
+        for (int i = 0; i < P.m; i++) {       // insertion sort by (x, y)
+            const uint32_t id = P.verts[i];
+            const double gx = (double)x[id] * GRIDD, gy = (double)y[id] * GRIDD;
+            int p = k++;
+            while (p > 0 && (vx[p - 1] > gx || (vx[p - 1] == gx && vy[p - 1] > gy))) {
+                vx[p] = vx[p - 1]; vy[p] = vy[p - 1];
+                p--;
+            }
+            vx[p] = gx; vy[p] = gy;
+        }
+        nv = k;
+        stop = n <= 0;
+    }
+    if (tid < LT_MAXR) chosen[tid] = -1;
+    __syncthreads();
+    const int64_t sa = surv_off[s], sb = surv_off[s + 1];
+    for (int r = 0; r < R && !stop; r++) {
+        if (tid < NCAND) {
+            const uint32_t e = cand[s * NCAND + tid];
+            double px[LT_V], py[LT_V];
+            int k = nv;
+            if (e != NONE) {
+                k = merge_point(vx, vy, nv, (double)x[e] * GRIDD, (double)y[e] * GRIDD, px, py);
+            } else {
+                for (int i = 0; i < nv; i++) { px[i] = vx[i]; py[i] = vy[i]; }
+            }
+            ne[tid] = hull_edges_sorted(px, py, k, ex[tid], ey[tid], ec[tid]);
+        } else if (tid == NCAND) {
+            cm = hull_edges_sorted(vx, vy, nv, cex, cey, cec);
+        }
+        __syncthreads();
+        uint32_t cnt[NCAND];
+#pragma unroll
+        for (int d = 0; d < NCAND; d++) cnt[d] = 0;
+        for (int64_t j = sa + tid; j < sb; j += blockDim.x) {
+            const uint32_t id = surv[j];
+            const double qx = (double)x[id] * GRIDD, qy = (double)y[id] * GRIDD;
+            bool in = cm >= 3;
+            for (int i = 0; i < cm && in; i++) in = edge_eval(cex[i], cey[i], cec[i], qx, qy) > 0;
+            if (in) continue;                 // already inside hull(V): no candidate gains it
+#pragma unroll
+            for (int d = 0; d < NCAND; d++) {
+                const int m = ne[d];
+                bool ind = m >= 3;
+                for (int i = 0; i < m && ind; i++) ind = edge_eval(ex[d][i], ey[d][i], ec[d][i], qx, qy) > 0;
+                cnt[d] += ind;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < NCAND; d++) {
+            uint32_t c = cnt[d];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+            if (lane == 0) pcnt[w][d] = c;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int best = -1;
+            uint32_t bc = 0;
+            for (int d = 0; d < NCAND; d++) {
+                uint32_t c = 0;
+                for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) c += pcnt[ww][d];
+                if (r == 0) g0[d] = c;
+                if (c > bc) { bc = c; best = d; }
+            }
+            if (best < 0) {
+                stop = 1;
+            } else {
+                chosen[r] = best;
+                const uint32_t e = cand[s * NCAND + best];
+                double tx[LT_V], ty[LT_V];
+                const int k = merge_point(vx, vy, nv, (double)x[e] * GRIDD, (double)y[e] * GRIDD, tx, ty);
+                for (int i = 0; i < k; i++) { vx[i] = tx[i]; vy[i] = ty[i]; }
+                nv = k;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < NCAND) {
+        uint32_t gmax = 0;
+        bool g0_set = !(n <= 0);
+        for (int d = 0; d < NCAND && g0_set; d++) gmax = max(gmax, g0[d]);
+        float t = (g0_set && gmax > 0) ? (float)(0.5 * ((double)g0[tid] / (double)gmax)) : 0.0f;
+        for (int r = 0; r < R; r++)
+            if (chosen[r] == tid) t = (float)(1.0 - (double)r / (2.0 * R));
+        target[s * NCAND + tid] = t;
+    }
+    if (tid < R) order[s * R + tid] = chosen[tid];
 }
 
 struct LearnedState {

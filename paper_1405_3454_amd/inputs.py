@@ -263,3 +263,111 @@ def mixture_batch_torch(S, n, seed, device="cuda:0", oversample=1.3):
     scale = 1.0 / GRID
     return ((kx * scale).to(torch.float32).reshape(-1).contiguous(),
             (ky * scale).to(torch.float32).reshape(-1).contiguous())
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators (torch), for the large benchmark workloads.  Same
+# recipes as the numpy generators above, different random streams.
+
+def _grid_to_float_t(k):
+    import torch
+    return (k.to(torch.float64) * (1.0 / GRID)).to(torch.float32)
+
+
+def _reject_int_t(n, g, device, accept, factor):
+    import torch
+    kx, ky, got = [], [], 0
+    while got < n:
+        m = int((n - got) * factor) + 4096
+        a = torch.randint(0, GRID, (m,), generator=g, device=device, dtype=torch.int64)
+        b = torch.randint(0, GRID, (m,), generator=g, device=device, dtype=torch.int64)
+        ok = accept(a - HALF, b - HALF)
+        a, b = a[ok][: n - got], b[ok][: n - got]
+        kx.append(a)
+        ky.append(b)
+        got += a.numel()
+    return torch.cat(kx), torch.cat(ky)
+
+
+def _reject_real_t(n, g, device, draw):
+    import torch
+    kx, ky, got = [], [], 0
+    while got < n:
+        m = int((n - got) * 1.2) + 4096
+        px, py = draw(m)
+        ok = (px >= 0) & (px < 1) & (py >= 0) & (py < 1)
+        a = torch.floor(px[ok] * GRID).to(torch.int64)
+        b = torch.floor(py[ok] * GRID).to(torch.int64)
+        ok2 = (a < GRID) & (b < GRID)
+        a, b = a[ok2][: n - got], b[ok2][: n - got]
+        kx.append(a)
+        ky.append(b)
+        got += a.numel()
+    return torch.cat(kx), torch.cat(ky)
+
+
+def set_torch(kind, n, seed, device="cuda:0"):
+    """One set of n points of the given kind ("square", "disk", "gaussian",
+    "annulus", "mixture", "ellipse") drawn on the device; float32 x, y."""
+    import torch
+    if kind == "mixture":
+        return mixture_batch_torch(1, n, seed, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    if n == 0:
+        z = torch.zeros(0, dtype=torch.float32, device=device)
+        return z, z.clone()
+    if kind == "square":
+        kx = torch.randint(0, GRID, (n,), generator=g, device=device, dtype=torch.int64)
+        ky = torch.randint(0, GRID, (n,), generator=g, device=device, dtype=torch.int64)
+    elif kind == "disk":
+        kx, ky = _reject_int_t(n, g, device, lambda dx, dy: dx * dx + dy * dy < (1 << 46), 1.35)
+    elif kind == "annulus":
+        def acc(dx, dy):
+            d2 = dx * dx + dy * dy
+            return (d2 < (1 << 46)) & (d2 >= ANNULUS_R2_MIN)
+        kx, ky = _reject_int_t(n, g, device, acc, 7.0)
+    elif kind == "gaussian":
+        kx, ky = _reject_real_t(n, g, device, lambda m: (
+            0.5 + 0.15 * torch.randn(m, generator=g, device=device, dtype=f64),
+            0.5 + 0.15 * torch.randn(m, generator=g, device=device, dtype=f64)))
+    elif kind == "ellipse":
+        r = _rng(seed)
+        cx, cy = r.uniform(0.45, 0.55, size=2)
+        a = r.uniform(0.2, 0.44)
+        b = a / np.exp(r.uniform(np.log(20.0), np.log(200.0)))
+        th = r.uniform(0.0, np.pi)
+        c, s = np.cos(th), np.sin(th)
+        ux, uy = _reject_int_t(n, g, device, lambda dx, dy: dx * dx + dy * dy < (1 << 46), 1.35)
+        ux = (ux.to(f64) - HALF) / HALF
+        uy = (uy.to(f64) - HALF) / HALF
+        px = cx + c * a * ux - s * b * uy
+        py = cy + s * a * ux + c * b * uy
+        kx = torch.floor(px * GRID).clamp(0, GRID - 1).to(torch.int64)
+        ky = torch.floor(py * GRID).clamp(0, GRID - 1).to(torch.int64)
+    else:
+        raise ValueError(kind)
+    return _grid_to_float_t(kx), _grid_to_float_t(ky)
+
+
+def batch_torch(sizes, seed, kinds=("square", "disk", "gaussian", "annulus"),
+                device="cuda:0", pick=None):
+    """Concatenated sets on the device, one per size; set i's kind is
+    pick(i) if given, else drawn uniformly from kinds.  Returns
+    (x, y, offsets[S+1] int64 on the device, kind names)."""
+    import torch
+    r = _rng(seed)
+    sizes = np.asarray(sizes, np.int64)
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    x = torch.empty(int(off[-1]), dtype=torch.float32, device=device)
+    y = torch.empty(int(off[-1]), dtype=torch.float32, device=device)
+    names = []
+    for i, n in enumerate(sizes):
+        k = pick(i) if pick is not None else kinds[int(r.integers(0, len(kinds)))]
+        sx, sy = set_torch(k, int(n), int(r.integers(0, 2**31)), device)
+        x[off[i]:off[i + 1]] = sx
+        y[off[i]:off[i + 1]] = sy
+        names.append(k)
+    return x, y, torch.from_numpy(off).to(device), names

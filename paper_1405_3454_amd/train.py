@@ -2,11 +2,15 @@
 kernels (labels, histograms, bf16 MFMA forward/backward, Adam).
 
 Training data: sets of anisotropic Gaussian mixtures drawn on the device
-(inputs.mixture_batch_torch).  Labels: for each of the 64 candidate
-directions, the fraction of the set that the 16-extreme filter keeps but the
-filter with that direction's extreme point added discards
-(hull_labels_batched).  Loss: mean squared error between the 64 scores and
-the labels scaled by their per-set maximum.
+(inputs.mixture_batch_torch).  Targets (default "marginal"): for each of the 64 candidate directions, the
+fraction of the set that the 16-extreme filter keeps but the filter with
+that direction's extreme point added discards (hull_labels_batched), scaled
+per set by its maximum.  Alternative "greedy": joint labels
+(hull_label_targets_batched), eight rounds each adding the direction whose
+extreme point discards the most of what is still kept.  The picks at
+inference are spread out by the direction gap (hull_set_direction_gap), so
+the smooth marginal targets serve well.  Loss: mean squared error between
+the 64 scores and the targets.
 
     python -m paper_1405_3454_amd.train --sets 20000 --batch 512 --points 65536 \
         --out paper_1405_3454_amd/weights/proposal.safetensors
@@ -54,8 +58,10 @@ def batch_tensors(S, n, seed, device):
     return x, y, off
 
 
-def train(H, sets, batch, points, lr=1e-3, seed=0, log=None, init=None):
-    """Train for ceil(sets / batch) Adam steps; returns (params, losses)."""
+def train(H, sets, batch, points, lr=1e-3, seed=0, log=None, init=None, targets="marginal"):
+    """Train for ceil(sets / batch) Adam steps; returns (params, losses).
+    targets: "greedy" (joint greedy targets) or "marginal" (per-direction
+    marginal gains, each set scaled by its maximum)."""
     import torch
     dev = H.device
     H.mlp_set_params(init if init is not None else init_params(seed))
@@ -64,7 +70,10 @@ def train(H, sets, batch, points, lr=1e-3, seed=0, log=None, init=None):
     t0 = time.time()
     for k in range(steps):
         x, y, off = batch_tensors(batch, points, 1_000_003 * (seed + 1) + k, dev)
-        gain = H.labels_batched(x, y, off)
+        if targets == "greedy":
+            gain, _ = H.label_targets_batched(x, y, off, rounds=8)
+        else:
+            gain = H.labels_batched(x, y, off)
         hist, _ = H.histogram_batched(x, y, off)
         loss = H.mlp_train_step(hist, gain, lr)
         losses.append(loss)

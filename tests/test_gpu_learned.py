@@ -81,7 +81,8 @@ def test_forward_backward_against_binary64(H):
         assert rel < 2e-2, (part, rel)
 
 
-def test_top_directions_exact(H):
+@pytest.mark.parametrize("gap", [0, 1, 2, 3])
+def test_top_directions_exact(H, gap):
     import torch
     r = np.random.default_rng(9)
     sc = r.standard_normal((37, 64)).astype(np.float32)
@@ -89,8 +90,13 @@ def test_top_directions_exact(H):
     sc[4, [1, 2, 60]] = 5.0            # partial ties
     sc[5, 10] = np.nan
     sc[6, :] = -0.0
-    got = H.top_directions(torch.from_numpy(sc).to("cuda:0")).cpu().numpy()
-    assert np.array_equal(got, mlp.top_directions(sc))
+    sc[7, :] = -np.abs(np.arange(64) - 10)
+    H.set_direction_gap(gap)
+    try:
+        got = H.top_directions(torch.from_numpy(sc).to("cuda:0")).cpu().numpy()
+    finally:
+        H.set_direction_gap(H.DEFAULT_DIRECTION_GAP)
+    assert np.array_equal(got, mlp.top_directions(sc, gap=gap))
 
 
 def test_learned_extremes_survivors_and_hull(H):
@@ -139,6 +145,19 @@ def test_labels_parity(H):
         assert np.array_equal(g[s], want), (s, g[s][:8], want[:8])
 
 
+def test_label_targets_parity(H):
+    """Greedy joint targets and orders: bit-exact against the oracle."""
+    sizes = [2000, 7000, 1, 4, 30000, 0, 12345]
+    x, y, off, _ = mixed_batch(sizes, 13)
+    t, o = H.label_targets_batched(dev(x), dev(y), dev(off), rounds=8)
+    t, o = t.cpu().numpy(), o.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        wt, wo = oracle.label_targets(x[a:b], y[a:b], rounds=8)
+        assert np.array_equal(o[s], wo), (s, o[s], wo)
+        assert np.array_equal(t[s], wt), s
+
+
 def test_train_step_matches_binary64_adam(H):
     """One training step on the GPU moves the parameters like the binary64
     loss gradient + Adam step (within the bf16 tolerance)."""
@@ -166,10 +185,39 @@ def test_training_gains_over_plain(H):
     x, y, off = train.batch_tensors(256, 1 << 15, 424242, H.device)
     H.mlp_set_params(train.init_params(5))
     untrained = train.evaluate(H, x, y, off)
-    params, losses = train.train(H, sets=96 * 64, batch=64, points=1 << 15, lr=1e-3, seed=5)
+    params, losses = train.train(H, sets=256 * 128, batch=128, points=1 << 15, lr=1e-3, seed=5)
     trained = train.evaluate(H, x, y, off)
     print("untrained", untrained, "trained", trained, "loss", losses[0], losses[-1])
     assert trained["plain"] == untrained["plain"]
     assert trained["learned"] >= trained["plain"]
     assert trained["learned"] - trained["plain"] > untrained["learned"] - untrained["plain"]
     assert losses[-1] < losses[0]
+
+
+def test_learned_graph_replay_matches_eager(H):
+    """hipGraph of the learned batched method (histogram, network, top-8,
+    extremes, discard, hull) replayed several times, with eager work in
+    between: every replay equals the eager learned result and the oracle."""
+    import torch
+    H.mlp_set_params(mlp.he_init(41))
+    sizes = [5000, 1, 30000, 777, 12000]
+    x, y, off, _ = mixed_batch(sizes, 17)
+    xt, yt, ot = dev(x), dev(y), dev(off)
+    eager, eho = H.compute_batched(xt, yt, ot, learned=True)
+    eager = u32(eager)[: int(eho[-1].item())].copy()
+    hull = torch.full((len(x),), -7, dtype=torch.int32, device="cuda:0")
+    ho = torch.zeros(len(sizes) + 1, dtype=torch.int64, device="cuda:0")
+    H.graph_capture(xt, yt, ot, hull, ho, learned=True)
+    for rep in range(3):
+        hull.fill_(-7)
+        ho.zero_()
+        torch.cuda.synchronize()
+        H.graph_launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(hull)[: int(ho[-1].item())], eager), rep
+        H.extremes_batched(xt, yt, ot, learned=True)       # eager work between replays
+    eo = eho.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        want = oracle.hull_subset(x[a:b], y[a:b]).astype(np.int64) + a
+        assert np.array_equal(eager[eo[s]:eo[s + 1]].astype(np.int64), want)

@@ -143,3 +143,41 @@ def test_validate_flag(H):
         with pytest.raises(HullError) as e:
             H.compute(dev(bad), yt, validate=True)
         assert e.value.code == HULL_EDOMAIN, v
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+@pytest.mark.parametrize("n", [1, 5, 1023, 5000, 70001])
+def test_unaligned_inputs(H, shift, n):
+    """x, y that start 1-3 floats into a 16-byte block (slices of aligned
+    tensors): the tiles align to absolute 16-byte boundaries; every result
+    equals the oracle on the same points, indices relative to the slice."""
+    H.set_directions(0)
+    x, y = inputs.disk(n + 3, 40 + shift)
+    xt, yt = dev(x)[shift:], dev(y)[shift:]
+    xs, ys = x[shift:][:n], y[shift:][:n]
+    xt, yt = xt[:n], yt[:n]
+    slots, _ = H.extremes(xt, yt)
+    o_slots, _ = oracle.extremes(xs, ys)
+    assert np.array_equal(u32(slots), o_slots)
+    surv = H.discard(xt, yt, slots)
+    o_surv = oracle.discard(xs, ys, oracle.polygon(xs, ys, o_slots))
+    assert np.array_equal(u32(surv), o_surv)
+    assert np.array_equal(u32(H.compute(xt, yt)), oracle.hull_subset(xs, ys, o_surv))
+
+
+def test_unaligned_batched_and_mismatched_phase(H):
+    from paper_1405_3454_amd._lib import HullError
+    H.set_directions(0)
+    sizes = [3000, 1, 17, 4096, 999]
+    x, y, off, _ = inputs.batch(sizes, 44)
+    pad = np.zeros(2, np.float32)
+    xt = dev(np.concatenate([pad, x]))[2:]
+    yt = dev(np.concatenate([pad, y]))[2:]
+    hull, ho = H.compute_batched(xt, yt, dev(off))
+    hull, ho = u32(hull), ho.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        want = oracle.hull_subset(x[a:b], y[a:b]).astype(np.int64) + a
+        assert np.array_equal(hull[ho[s]:ho[s + 1]].astype(np.int64), want)
+    with pytest.raises(HullError):      # x and y at different positions in their blocks
+        H.compute(dev(x)[1:len(x) - 1], dev(y)[2:])

@@ -85,3 +85,15 @@ def test_top_directions_ties_and_nan():
     top = mlp.top_directions(s)[0]
     assert list(top[:4]) == [63, 5, 9, 40]
     assert list(top[4:]) == [0, 1, 2, 3]
+
+
+def test_top_directions_gap_hand_case():
+    """Scores peaking at direction 10 (score -|d - 10|): without a gap the
+    picks walk outwards from the peak; with gap 2 every pick rules out its
+    two neighbours on each side."""
+    sc = -np.abs(np.arange(64) - 10).astype(np.float32)[None, :]
+    assert list(mlp.top_directions(sc)[0]) == [10, 9, 11, 8, 12, 7, 13, 6]
+    assert list(mlp.top_directions(sc, gap=2)[0]) == [10, 7, 13, 4, 16, 1, 19, 22]
+    # wrap-around: the peak at 0 rules out 62, 63, 1, 2
+    sc = -np.minimum(np.arange(64), 64 - np.arange(64)).astype(np.float32)[None, :]
+    assert list(mlp.top_directions(sc, gap=2)[0]) == [0, 3, 61, 6, 58, 9, 55, 12]

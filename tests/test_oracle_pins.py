@@ -297,11 +297,24 @@ def test_histogram_hand_cases():
     assert (h == want).all()
     h = oracle.histogram(to_float([7] * 10), to_float([9] * 10))
     assert h[0] == 1024.0 and h[1:].sum() == 0
-    # stride: n = 16385 -> every 2nd point, 8193 samples
+    # stride: n = 16385 -> every 2nd point, 8193 samples, all at kx = 0 and
+    # ky = 0; the 1 x 1 box becomes a 1 x 1 window
     kx = np.arange(16385) % 2 * 1000
     h = oracle.histogram(to_float(kx), to_float(np.zeros(16385, np.int64)))
     assert h.sum() == pytest.approx(1024.0, rel=1e-6)
     assert h[0] == np.float32(8193 * 1024.0 / 8193) and h[31] == 0.0
+    # aspect ratio kept: a 3200 x 100 box sits in the middle rows of a
+    # 3200 x 3200 window (origin y = -1550): rows 15 and 16 only
+    kx = np.array([0, 3199, 1600, 0, 3199], np.int64)
+    ky = np.array([0, 99, 50, 99, 0], np.int64)
+    h = oracle.histogram(to_float(kx), to_float(ky)).reshape(32, 32)
+    assert h.sum() == pytest.approx(1024.0)
+    rows = set(np.nonzero(h.sum(1))[0])
+    assert rows == {15, 16}
+    assert h[15, 0] > 0 and h[15, 31] > 0 and h[16, 0] > 0 and h[16, 31] > 0 and h[16, 16] > 0
+    # the same box rotated by 90 degrees: columns 15 and 16 only
+    h2 = oracle.histogram(to_float(ky), to_float(kx)).reshape(32, 32)
+    assert np.array_equal(h2, h.T)
 
 
 def test_labels_bruteforce():
@@ -323,3 +336,75 @@ def test_labels_bruteforce():
         vx, vy = [int(kx[v]) for v in v2], [int(ky[v]) for v in v2]
         cnt = sum(_brute.strictly_inside(int(kx[i]), int(ky[i]), vx, vy) for i in surv)
         assert gain[d] == cnt / len(x), d
+
+
+def _greedy_bruteforce(x, y, rounds):
+    """Greedy joint targets by brute force (exact integer geometry)."""
+    c, s = oracle.preset(0)
+    slots = _brute.extremes_numpy(x, y, c, s)
+    kx, ky = to_grid(x), to_grid(y)
+    E = set(int(v) for v in slots)
+    cache = {}
+
+    def poly(pts):
+        key = frozenset(pts)
+        if key not in cache:
+            u = sorted(key)
+            v = [u[j] for j in _brute.hull(x[u], y[u])]
+            cache[key] = ([int(kx[i]) for i in v], [int(ky[i]) for i in v])
+        return cache[key]
+
+    bx, by = poly(E)
+    surv = [i for i in range(len(x)) if not _brute.strictly_inside(int(kx[i]), int(ky[i]), bx, by)]
+    cd, sd = oracle.direction_table()
+    w = np.outer(cd, x.astype(np.float64)) + np.outer(sd, y.astype(np.float64))
+    ext = [int(np.argmax(w[d])) for d in range(64)]
+    order, g0 = [], None
+    for r in range(rounds):
+        cx, cy = poly(E)
+        active = [i for i in surv if not _brute.strictly_inside(int(kx[i]), int(ky[i]), cx, cy)]
+        gains = []
+        for d in range(64):
+            vx, vy = poly(E | {ext[d]})
+            gains.append(sum(_brute.strictly_inside(int(kx[i]), int(ky[i]), vx, vy) for i in active))
+        if r == 0:
+            g0 = gains
+        if max(gains) == 0:
+            break
+        best = gains.index(max(gains))
+        order.append(best)
+        E = E | {ext[best]}
+    gmax = max(g0)
+    target = [np.float32(0.5 * (g / gmax)) if gmax > 0 else np.float32(0) for g in g0]
+    for r, d in enumerate(order):
+        target[d] = np.float32(1.0 - r / (2.0 * rounds))
+    return np.array(target, np.float32), order + [-1] * (rounds - len(order))
+
+
+@pytest.mark.parametrize("kind,seed", [("mixture", 11), ("ellipse", 4)])
+def test_label_targets_bruteforce(kind, seed):
+    """Greedy joint targets: the oracle equals a brute-force greedy run with
+    exact integer geometry, and its first choice is the argmax of the
+    (independently pinned) marginal gains."""
+    x, y = getattr(inputs, kind)(250, seed)
+    t, o = oracle.label_targets(x, y, rounds=8)
+    bt, bo = _greedy_bruteforce(x, y, 8)
+    assert list(o) == bo
+    assert np.array_equal(t, bt)
+    gain = oracle.labels(x, y, 0)
+    if gain.max() > 0:
+        assert o[0] == int(np.argmax(gain))
+    # chosen directions rank first, in round order
+    chosen = [d for d in o if d >= 0]
+    assert list(np.argsort(-t, kind="stable")[:len(chosen)]) == chosen
+
+
+def test_label_targets_degenerate():
+    """No survivors to gain (a triangle's vertices): every target is 0 and the
+    sequence is empty; an empty set gives the same."""
+    x = np.array([0.25, 0.75, 0.5], np.float32)
+    y = np.array([0.25, 0.25, 0.75], np.float32)
+    t, o = oracle.label_targets(x, y, rounds=4)
+    assert not t.any() and list(o) == [-1] * 4
+    t, o = oracle.label_targets(x[:0], y[:0], rounds=4)
+    assert not t.any() and list(o) == [-1] * 4
