@@ -74,6 +74,8 @@ typedef struct hull_ctx hull_ctx;
 #define HULL_NOFILTER 1 /* hull of all points, no preprocessing (Sec. 3, case (1)) */
 #define HULL_LEARNED 2  /* add eight learned directions to the sixteen fixed slots */
 #define HULL_VALIDATE 4 /* check the input domain first (synchronises) */
+#define HULL_NOREFINE 8 /* hull of the survivors by sort + chain alone, without the
+                           QuickHull refinement rounds that shrink them first */
 
 #define HULL_NONE 0xFFFFFFFFu
 #define HULL_FIXED_SLOTS 16

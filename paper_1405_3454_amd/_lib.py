@@ -21,6 +21,7 @@ HULL_DIRS_CUMULATIVE = 1
 HULL_NOFILTER = 1
 HULL_LEARNED = 2
 HULL_VALIDATE = 4
+HULL_NOREFINE = 8
 
 HULL_NONE = 0xFFFFFFFF
 

@@ -11,7 +11,7 @@ import torch
 
 from . import _lib
 from ._lib import (HULL_DIRS_CUMULATIVE, HULL_DIRS_PAPER, HULL_LEARNED, HULL_NOFILTER,
-                   HULL_VALIDATE, check, lib)
+                   HULL_VALIDATE, HULL_NOREFINE, check, lib)
 
 FIXED_SLOTS = 16
 MAX_SLOTS = 24
@@ -41,9 +41,9 @@ def _pts(x, y):
     return x.numel()
 
 
-def _flags(nofilter=False, learned=False, validate=False):
+def _flags(nofilter=False, learned=False, validate=False, refine=True):
     return ((HULL_NOFILTER if nofilter else 0) | (HULL_LEARNED if learned else 0) |
-            (HULL_VALIDATE if validate else 0))
+            (HULL_VALIDATE if validate else 0) | (0 if refine else HULL_NOREFINE))
 
 
 class Hull:
@@ -143,18 +143,19 @@ class Hull:
         return hull[: int(h.item())]
 
     def compute_into(self, x, y, hull, h, nofilter=False, learned=False, validate=False,
-                     stream=None):
+                     stream=None, refine=True):
         """Asynchronous form: hull indices to hull (int32[n]), count to h (int64[1])."""
         n = _pts(x, y)
         check(lib().hull_compute(self._h, _ptr(x), _ptr(y), n, _ptr(hull), _ptr(h),
-                                 _flags(nofilter, learned, validate), _stream(stream)),
+                                 _flags(nofilter, learned, validate, refine), _stream(stream)),
               "hull_compute")
 
-    def compute(self, x, y, nofilter=False, learned=False, validate=False, stream=None):
+    def compute(self, x, y, nofilter=False, learned=False, validate=False, stream=None,
+                refine=True):
         n = _pts(x, y)
         hull = torch.empty(max(1, n), dtype=torch.int32, device=x.device)
         h = torch.zeros(1, dtype=torch.int64, device=x.device)
-        self.compute_into(x, y, hull, h, nofilter, learned, validate, stream)
+        self.compute_into(x, y, hull, h, nofilter, learned, validate, stream, refine)
         return hull[: int(h.item())]
 
     # -- batched -----------------------------------------------------------
@@ -181,29 +182,32 @@ class Hull:
         return surv, so
 
     def compute_batched_into(self, x, y, offsets, hull, hull_offsets, nofilter=False,
-                             learned=False, validate=False, stream=None):
+                             learned=False, validate=False, stream=None, refine=True):
         n = _pts(x, y)
         S = offsets.numel() - 1
         check(lib().hull_compute_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
                                          _ptr(hull), _ptr(hull_offsets),
-                                         _flags(nofilter, learned, validate), _stream(stream)),
+                                         _flags(nofilter, learned, validate, refine),
+                                         _stream(stream)),
               "hull_compute_batched")
 
     def compute_batched(self, x, y, offsets, nofilter=False, learned=False, validate=False,
-                        stream=None):
+                        stream=None, refine=True):
         n = _pts(x, y)
         S = offsets.numel() - 1
         hull = torch.empty(max(1, n), dtype=torch.int32, device=x.device)
         ho = torch.zeros(S + 1, dtype=torch.int64, device=x.device)
-        self.compute_batched_into(x, y, offsets, hull, ho, nofilter, learned, validate, stream)
+        self.compute_batched_into(x, y, offsets, hull, ho, nofilter, learned, validate, stream,
+                                  refine)
         return hull, ho
 
     def graph_capture(self, x, y, offsets, hull, hull_offsets, nofilter=False, learned=False,
-                      stream=None):
+                      stream=None, refine=True):
         n = _pts(x, y)
         S = offsets.numel() - 1
         check(lib().hull_graph_capture(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
-                                       _ptr(hull), _ptr(hull_offsets), _flags(nofilter, learned),
+                                       _ptr(hull), _ptr(hull_offsets),
+                                       _flags(nofilter, learned, refine=refine),
                                        _stream(stream)), "hull_graph_capture")
 
     def graph_launch(self, stream=None):
@@ -314,4 +318,4 @@ def split_csr(flat, offsets):
 
 
 __all__ = ["Hull", "as_u32", "split_csr", "HULL_DIRS_PAPER", "HULL_DIRS_CUMULATIVE",
-           "HULL_NOFILTER", "HULL_LEARNED", "HULL_VALIDATE", "_lib"]
+           "HULL_NOFILTER", "HULL_LEARNED", "HULL_VALIDATE", "HULL_NOREFINE", "_lib"]

@@ -14,6 +14,7 @@
 #include "k_sort.hip"
 #include "k_chain.hip"
 #include "k_learned.hip"
+#include "k_refine.hip"
 
 using namespace hg;
 
@@ -67,7 +68,7 @@ struct hull_ctx {
 static const char *kKindNames[K_NKINDS] = {
     "tile_map", "extremes", "polygon", "discard", "scan", "scatter", "keys",
     "sort_hist", "sort_scan", "sort_scatter", "chain", "chain_merge", "hull_final",
-    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels"};
+    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels", "refine", "refine_compact"};
 
 #define HIPCHECK(expr)                                   \
     do {                                                 \
@@ -115,7 +116,8 @@ static int launch(hull_ctx *ctx, int kind, hipStream_t st, F &&f) {
 struct Plan {
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
-        hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, total;
+        hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
+        rfar1, rchunk, rcpos, total;
     int64_t tcap, u0cap;
 };
 
@@ -166,6 +168,12 @@ static Plan make_plan(int64_t n, int64_t S) {
     p.setdirs = take(S * MAX_DIRS * 2 * 8);
     p.learn = take(learned_ws_bytes(S));
     p.cand = take(S * NCAND * 4);
+    p.rtab0 = take(S * RE_CAP * sizeof(REdge));
+    p.rtab1 = take(S * RE_CAP * sizeof(REdge));
+    p.rfar0 = take(S * RE_CAP * 8);
+    p.rfar1 = take(S * RE_CAP * 8);
+    p.rchunk = take((n / REF_CH + 2) * 4);
+    p.rcpos = take((n / REF_CH + 3) * 8);
     p.total = o;
     return p;
 }
@@ -411,6 +419,50 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     return HULL_OK;
 }
 
+// Refinement rounds on the survivors (surv, keys0, count at surv_off[S]):
+// QuickHull splits of the filter polygon's edges.  The kept survivors end up
+// back in surv/keys0 (an even number of rounds ping-pongs through lo0/lo1/
+// up0/up1, which the hull stage only uses afterwards) with their count at
+// *out_cnt; the per-set offsets are not kept (the hull stage reads the set
+// from each key).
+static_assert(REF_ROUNDS % 2 == 0, "refinement must end in the first buffer set");
+static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                      const float *y, int64_t S, const int64_t *in_cnt, int64_t **out_cnt) {
+    uint32_t *idxs[2] = {W<uint32_t>(ctx, p.surv), W<uint32_t>(ctx, p.lo0)};
+    uint64_t *keys[2] = {W<uint64_t>(ctx, p.keys0), W<uint64_t>(ctx, p.lo1)};
+    uint16_t *eds[2] = {W<uint16_t>(ctx, p.up0), W<uint16_t>(ctx, p.up1)};
+    REdge *tab[2] = {W<REdge>(ctx, p.rtab0), W<REdge>(ctx, p.rtab1)};
+    unsigned long long *far[2] = {W<unsigned long long>(ctx, p.rfar0),
+                                  W<unsigned long long>(ctx, p.rfar1)};
+    uint32_t *ccnt = W<uint32_t>(ctx, p.rchunk);
+    int64_t *cpos = W<int64_t>(ctx, p.rcpos);
+    int64_t *nch = W<int64_t>(ctx, p.consts) + 2;       // chunks of the current round
+    int64_t *cnts[2] = {W<int64_t>(ctx, p.consts) + 3, W<int64_t>(ctx, p.consts) + 4};
+    const Poly *polys = W<Poly>(ctx, p.polys);
+    const unsigned g = (unsigned)(ctx->cus * 8);
+    const int64_t *cur_cnt = in_cnt;
+    LAUNCH(K_REFINE, k_ref_init<<<(unsigned)S, 64, 0, st>>>(x, y, polys, tab[0], far[0]));
+    LAUNCH(K_REFINE, k_ref_pass<true><<<g, REF_THREADS, 0, st>>>(
+        idxs[0], keys[0], cur_cnt, eds[0], polys, nullptr, far[0], nullptr));
+    for (int r = 0; r < REF_ROUNDS; r++) {
+        const int a = r & 1, b = 1 - a;
+        const int er = MAX_SLOTS << r;
+        LAUNCH(K_REFINE, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
+            x, y, S, er, tab[a], far[a], tab[b], far[b]));
+        LAUNCH(K_REFINE, k_ref_pass<false><<<g, REF_THREADS, 0, st>>>(
+            idxs[a], keys[a], cur_cnt, eds[a], polys, tab[b], far[b], ccnt));
+        LAUNCH(K_REFINE_COMPACT, k_ref_nchunks<<<1, 64, 0, st>>>(cur_cnt, nch));
+        int rc = run_scan(ctx, p, st, ccnt, nch, cpos);
+        if (rc) return rc;
+        LAUNCH(K_REFINE_COMPACT, k_ref_compact<<<g, REF_THREADS, 0, st>>>(
+            idxs[a], keys[a], eds[a], cur_cnt, cpos, idxs[b], keys[b], eds[b]));
+        LAUNCH(K_REFINE_COMPACT, k_ref_total<<<1, 64, 0, st>>>(cpos, nch, cnts[b]));
+        cur_cnt = cnts[b];
+    }
+    *out_cnt = cnts[REF_ROUNDS & 1];
+    return HULL_OK;
+}
+
 // Learned proposal: per-set histogram -> network -> eight directions written
 // to the workspace's set_dirs table (defined with the network code below).
 static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
@@ -462,7 +514,13 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
                               learned ? MAX_SLOTS : FIXED_SLOTS, surv, surv_off, keys)))
             return rc;
     }
-    rc = run_hull(ctx, p, st, surv, keys, surv_off + S, n_total, S, hoff, hull);
+    const int64_t *cnt = surv_off + S;
+    if (!(flags & (HULL_NOREFINE | HULL_NOFILTER))) {
+        int64_t *rc_cnt = nullptr;
+        if ((rc = run_refine(ctx, p, st, x, y, S, cnt, &rc_cnt))) return rc;
+        cnt = rc_cnt;
+    }
+    rc = run_hull(ctx, p, st, surv, keys, cnt, n_total, S, hoff, hull);
     if (rc) return rc;
     if (h_out) LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(hoff + S, h_out));
     return HULL_OK;

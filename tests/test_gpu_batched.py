@@ -152,3 +152,18 @@ def test_autotune_keeps_results(H):
     b, bo = H.compute_batched(xt, yt, ot)
     assert np.array_equal(u32(b)[: int(bo[-1].item())], a)
     assert np.array_equal(ao.cpu().numpy(), bo.cpu().numpy())
+
+
+def test_refinement_batched_matches_plain_chain(H):
+    sizes = list(inputs.batch_sizes(48, 31, lo=1, hi=300_000)) + [0, 1, 2]
+    x, y, off, _ = make_batch(sizes, 32)
+    xt, yt, ot = dev(x), dev(y), dev(off)
+    a, ao = H.compute_batched(xt, yt, ot)
+    b, bo = H.compute_batched(xt, yt, ot, refine=False)
+    a, ao, b, bo = u32(a), ao.cpu().numpy(), u32(b), bo.cpu().numpy()
+    assert np.array_equal(ao, bo)
+    assert np.array_equal(a[: ao[-1]], b[: bo[-1]])
+    for s in range(len(sizes)):
+        p, q = off[s], off[s + 1]
+        want = oracle.hull_subset(x[p:q], y[p:q]).astype(np.int64) + p
+        assert np.array_equal(a[ao[s]:ao[s + 1]].astype(np.int64), want), s

@@ -181,3 +181,27 @@ def test_unaligned_batched_and_mismatched_phase(H):
         assert np.array_equal(hull[ho[s]:ho[s + 1]].astype(np.int64), want)
     with pytest.raises(HullError):      # x and y at different positions in their blocks
         H.compute(dev(x)[1:len(x) - 1], dev(y)[2:])
+
+
+@pytest.mark.parametrize("kind", ["disk", "annulus", "gaussian", "square"])
+@pytest.mark.parametrize("n", [3, 100, 4096, 200_001])
+def test_refinement_keeps_the_hull(H, kind, n):
+    """The QuickHull refinement rounds before the sort drop only points
+    strictly inside triangles of set points: the hull equals the oracle's and
+    the one computed without the rounds."""
+    H.set_directions(0)
+    x, y = inputs.DISTRIBUTIONS[kind](n, 70 + n % 97)
+    xt, yt = dev(x), dev(y)
+    want = oracle.compute(x, y, 0)
+    assert np.array_equal(u32(H.compute(xt, yt)), want)
+    assert np.array_equal(u32(H.compute(xt, yt, refine=False)), want)
+
+
+def test_refinement_degenerate_inputs(H):
+    H.set_directions(0)
+    for seed in range(6):
+        x, y = inputs.small_grid(3000, 1 + seed % 4, seed)
+        want = oracle.compute(x, y, 0)
+        assert np.array_equal(u32(H.compute(dev(x), dev(y))), want), seed
+    x, y, m = inputs.regular_polygon(48, 5000, 3)
+    assert np.array_equal(u32(H.compute(dev(x), dev(y))), oracle.compute(x, y, 0))
