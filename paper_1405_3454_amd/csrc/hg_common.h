@@ -32,9 +32,10 @@ struct Poly {
     uint32_t verts[MAX_SLOTS];
     int32_t m;
     int32_t ky_lo;      // quick-accept rows cover ky in [ky_lo, ky_lo + yspan]
-    int32_t yspan;      // < 0: no quick-accept rows
+    int32_t yspan;      // < 0: no quick-accept rows (and nothing strictly inside)
     int32_t shift;      // row = (ky - ky_lo) >> shift
-    int32_t pad[4];
+    int32_t ymin, ymax; // the polygon's y-range (grid units)
+    int32_t pad[2];
 };
 
 // One row of the polygon's y-range (ky in [y0, y1]):

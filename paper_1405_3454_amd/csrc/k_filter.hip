@@ -135,6 +135,16 @@ __device__ __forceinline__ void load4(const float *__restrict__ x, const float *
     }
 }
 
+// The same for positions known to lie in [0, n_total): no guard.
+__device__ __forceinline__ void load4_full(const float *__restrict__ x, const float *__restrict__ y,
+                                           int64_t a, float xv[4], float yv[4]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 fx = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(x + a));
+    const f4 fy = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(y + a));
+    xv[0] = fx.x; xv[1] = fx.y; xv[2] = fx.z; xv[3] = fx.w;
+    yv[0] = fy.x; yv[1] = fy.y; yv[2] = fy.z; yv[3] = fy.w;
+}
+
 // ---------------------------------------------------------------------------
 // Step 1 keys.  Fixed slot 4g+0 / 4g+1 is the argmin / argmax of
 // u_g = cos_g x - sin_g y and 4g+2 / 4g+3 that of v_g = sin_g x + cos_g y,
@@ -648,11 +658,20 @@ __global__ __launch_bounds__(256) void k_polygon(
             P.yspan = -1;
             P.ky_lo = 0;
             P.shift = 0;
+            P.ymin = 1;
+            P.ymax = 0;
         } else {
-            P.ky_lo = ylo;
-            P.yspan = yhi - ylo;
+            // the rows stop a thin sliver (1/1024 of the height) short of
+            // the top and bottom vertices, where the polygon narrows to a
+            // point or an edge and a row could hold no quick-accept span;
+            // points in the slivers take the exact test
+            const int d = (yhi - ylo) >> 10;
+            P.ymin = ylo;
+            P.ymax = yhi;
+            P.ky_lo = ylo + d;
+            P.yspan = (yhi - d) - (ylo + d);
             int sh = 0;
-            while (((yhi - ylo) >> sh) >= SPAN_ROWS) sh++;
+            while ((P.yspan >> sh) >= SPAN_ROWS) sh++;
             P.shift = sh;
         }
     }
@@ -771,14 +790,16 @@ __device__ __forceinline__ bool edge_in(const DiscardLds &L, uint32_t e, double 
 }
 
 template <int NEDGE>
-__device__ __forceinline__ void drain(DiscardLds &L, int from, int count, int32_t ky_lo, int shift) {
+__device__ __forceinline__ void drain(DiscardLds &L, int from, int count, int32_t ky_lo, int shift,
+                                      uint32_t ylim) {
     const int lane = lane_id();
     if (lane < count) {
         const uint64_t e = L.q[from + lane];
         const int32_t kx = (int32_t)(e & 0xFFFFFF), ky = (int32_t)((e >> 24) & 0xFFFFFF);
         const double px = (double)kx, py = (double)ky;
         const int pos = (int)(e >> 48);
-        const uint32_t re = L.redge[(uint32_t)(ky - ky_lo) >> shift];
+        const uint32_t dy = (uint32_t)(ky - ky_lo);   // outside the rows: every edge
+        const uint32_t re = dy <= ylim ? L.redge[dy >> shift] : ROW_EDGES_ALL;
         bool inside;
         if (re != ROW_EDGES_ALL) {
             // all four evaluated (no short circuit): unused entries name an
@@ -824,8 +845,9 @@ __global__ __launch_bounds__(256) void k_discard(
     if (t0 >= t1) return;
 
     int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1;
-    int32_t ky_lo = 0, shift = 0;
-    uint32_t ylim = 0;          // in the y-range: (ky - ky_lo) <= ylim (unsigned)
+    int32_t ky_lo = 0, shift = 0, ymin = 0;
+    uint32_t ylim = 0;          // in the rows: (ky - ky_lo) <= ylim (unsigned)
+    uint32_t yext = 0;          // in the polygon's y-range: (ky - ymin) <= yext
     bool has_rows = false;
 
     for (int64_t t = t0; t < t1; ++t) {
@@ -841,6 +863,14 @@ __global__ __launch_bounds__(256) void k_discard(
             has_rows = P->yspan >= 0;
             ylim = (uint32_t)max(P->yspan, 0);
             shift = P->shift;
+            ymin = P->ymin;
+            yext = (uint32_t)(P->ymax - P->ymin);
+            if (!has_rows) {     // nothing strictly inside: every point is outside
+                ky_lo = INT32_MAX;
+                ylim = 0;
+                ymin = INT32_MAX;
+                yext = 0;
+            }
             wave_sync();
             for (int r = lane; r < SPAN_ROWS; r += WAVE) {
                 L.rows[r] = spans[s * SPAN_ROWS + r];
@@ -856,60 +886,77 @@ __global__ __launch_bounds__(256) void k_discard(
         }
         int qn = 0;
         const int64_t tb = abase + (t - tile0) * TILE;
-        float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
-#pragma unroll
-        for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
-        // one chunk: classify its 4 points per lane, queue the undecided
-        // ones, drain full batches (FULL: every position lies in the set)
-        auto chunk = [&](auto full_tag, int c) {
+        // one tile (FULL: every position lies in the set, so the loads need
+        // no guard): per chunk, classify its 4 points per lane, queue the
+        // undecided ones (one ballot per chunk when there are none), drain
+        // full batches
+        auto tile = [&](auto full_tag) {
             constexpr bool FULL = decltype(full_tag)::value;
-            const int64_t a = tb + c * CHUNK + 4 * lane;
-            int32_t kx[4], ky[4];
-            uint32_t dy[4];
-            Span sp[4];
+            float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                kx[j] = (int32_t)(xv[c][j] * GRIDF);
-                ky[j] = (int32_t)(yv[c][j] * GRIDF);
-                dy[j] = (uint32_t)(ky[j] - ky_lo);
-                sp[j] = L.rows[min(dy[j] >> shift, (uint32_t)(SPAN_ROWS - 1))];
+            for (int c = 0; c < TILE_CHUNKS; c++) {
+                if (FULL) load4_full(x, y, tb + c * CHUNK + 4 * lane, xv[c], yv[c]);
+                else load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
             }
-            uint64_t sw[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const bool valid = FULL || ((a + j >= o0) && (a + j < o1));
-                const bool in_y = has_rows && dy[j] <= ylim;
-                const bool inside = in_y && kx[j] >= sp[j].xl && kx[j] <= sp[j].xr;
-                const bool outside = !in_y || kx[j] <= sp[j].ol || kx[j] >= sp[j].orr;
-                sw[j] = __ballot(valid && outside);
-                const bool slow = valid && !inside && !outside;
-                const uint64_t bal = __ballot(slow);
-                if (bal) {
-                    if (slow) {
-                        const int p = qn + __popcll(bal & lanemask_lt());
-                        L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
-                                 ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
-                                 ((uint64_t)(c * CHUNK + 4 * lane + j) << 48);
-                    }
-                    qn += __popcll(bal);
+            for (int c = 0; c < TILE_CHUNKS; c++) {
+                const int64_t a = tb + c * CHUNK + 4 * lane;
+                int32_t kx[4], ky[4];
+                uint32_t dy[4];
+                Span sp[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    kx[j] = (int32_t)(xv[c][j] * GRIDF);
+                    ky[j] = (int32_t)(yv[c][j] * GRIDF);
+                    dy[j] = (uint32_t)(ky[j] - ky_lo);
+                    sp[j] = L.rows[min(dy[j] >> shift, (uint32_t)(SPAN_ROWS - 1))];
                 }
+                // classification as wave masks (one bit per lane), combined
+                // with scalar logic: outside = not in the polygon's y-range,
+                // or in the rows and outside the row's extent; inside = in
+                // the rows and in the row's quick-accept span
+                uint64_t sw[4], slow[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint64_t m_valid = FULL ? __ballot(true)
+                                                  : __ballot(a + j >= o0) & __ballot(a + j < o1);
+                    const uint64_t m_rows = __ballot(dy[j] <= ylim);
+                    const uint64_t m_ext = __ballot((uint32_t)(ky[j] - ymin) <= yext);
+                    // one comparison per ballot: no short-circuit branches
+                    const uint64_t m_span = __ballot(kx[j] >= sp[j].xl) & __ballot(kx[j] <= sp[j].xr);
+                    const uint64_t m_out = __ballot(kx[j] <= sp[j].ol) | __ballot(kx[j] >= sp[j].orr);
+                    const uint64_t outside = ~m_ext | (m_rows & m_out);
+                    const uint64_t inside = m_rows & m_span;
+                    sw[j] = outside & m_valid;
+                    slow[j] = ~(outside | inside) & m_valid;
+                }
+                if (slow[0] | slow[1] | slow[2] | slow[3]) {   // some undecided point
+                    const uint64_t lt = lanemask_lt();
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if ((slow[j] >> lane) & 1) {
+                            const int p = qn + __popcll(slow[j] & lt);
+                            L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
+                                     ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
+                                     ((uint64_t)(c * CHUNK + 4 * lane + j) << 48);
+                        }
+                        qn += __popcll(slow[j]);
+                    }
+                }
+                if (lane < 4) L.mask[c * 4 + lane] = lane == 0 ? sw[0] : lane == 1 ? sw[1] : lane == 2 ? sw[2] : sw[3];
+                wave_sync();
+                while (qn >= WAVE) {
+                    qn -= WAVE;
+                    drain<NEDGE>(L, qn, WAVE, ky_lo, shift, ylim);
+                }
+                wave_sync();
             }
-            if (lane < 4) L.mask[c * 4 + lane] = lane == 0 ? sw[0] : lane == 1 ? sw[1] : lane == 2 ? sw[2] : sw[3];
-            wave_sync();
-            while (qn >= WAVE) {
-                qn -= WAVE;
-                drain<NEDGE>(L, qn, WAVE, ky_lo, shift);
-            }
-            wave_sync();
         };
-        if (tb >= o0 && tb + TILE <= o1) {
-#pragma unroll
-            for (int c = 0; c < TILE_CHUNKS; c++) chunk(std::integral_constant<bool, true>(), c);
-        } else {
-#pragma unroll
-            for (int c = 0; c < TILE_CHUNKS; c++) chunk(std::integral_constant<bool, false>(), c);
-        }
-        if (qn > 0) drain<NEDGE>(L, 0, qn, ky_lo, shift);
+        if (tb >= o0 && tb + TILE <= o1)
+            tile(std::integral_constant<bool, true>());
+        else
+            tile(std::integral_constant<bool, false>());
+        if (qn > 0) drain<NEDGE>(L, 0, qn, ky_lo, shift, ylim);
         wave_sync();
         const uint64_t mw = lane < TILE_WORDS ? L.mask[lane] : 0;
         const uint32_t cnt = row0_sum_u32((uint32_t)__popcll(mw));
