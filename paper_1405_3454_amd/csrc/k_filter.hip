@@ -372,14 +372,17 @@ __global__ __launch_bounds__(256) void k_extremes(
             reset();
         }
         const int64_t tb = abase + (t - tile0) * TILE;
-        // issue the whole tile's loads first: 8 KB in flight per wave
-        float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
-#pragma unroll
-        for (int c = 0; c < TILE_CHUNKS; c++) load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
         double acc[NS];
-        // FULL: every position of the tile lies in the set
+        // FULL: every position of the tile lies in the set (loads unguarded)
         auto accumulate = [&](auto full_tag) {
             constexpr bool FULL = decltype(full_tag)::value;
+            // issue the whole tile's loads first: 8 KB in flight per wave
+            float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
+#pragma unroll
+            for (int c = 0; c < TILE_CHUNKS; c++) {
+                if (FULL) load4_full(x, y, tb + c * CHUNK + 4 * lane, xv[c], yv[c]);
+                else load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
+            }
 #pragma unroll
             for (int c = 0; c < TILE_CHUNKS; c++) {
 #pragma unroll
