@@ -57,7 +57,7 @@ constexpr uint32_t ROW_EDGES_ALL = 0xFFFFFFFFu;
 enum Kind {
     K_TILEMAP = 0, K_EXTREMES, K_POLYGON, K_DISCARD, K_SCAN, K_SCATTER,
     K_KEYS, K_SORT_HIST, K_SORT_SCAN, K_SORT_SCATTER, K_CHAIN, K_CHAIN_COMPACT,
-    K_FINAL, K_LOOKUP, K_VALIDATE, K_MISC, K_HIST32, K_MLP, K_LABELS, K_REFINE, K_REFINE_COMPACT, K_NKINDS
+    K_FINAL, K_LOOKUP, K_VALIDATE, K_MISC, K_HIST32, K_MLP, K_LABELS, K_REFINE, K_REFINE_COMPACT, K_REFINE_ASSIGN, K_REFINE_SPLIT, K_NKINDS
 };
 
 // Direction constants for one launch.  Preset groups: (gc[g], gs[g]).

@@ -68,7 +68,7 @@ struct hull_ctx {
 static const char *kKindNames[K_NKINDS] = {
     "tile_map", "extremes", "polygon", "discard", "scan", "scatter", "keys",
     "sort_hist", "sort_scan", "sort_scatter", "chain", "chain_merge", "hull_final",
-    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels", "refine", "refine_compact"};
+    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels", "refine_pass", "refine_compact", "refine_assign", "refine_split"};
 
 #define HIPCHECK(expr)                                   \
     do {                                                 \
@@ -326,7 +326,7 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     if (rc) return rc;
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
                                                                                   surv_off));
-    LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, phase_of(x), off, S, tile_off, tile_set, masks, tcnt,
+    LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, n_total, phase_of(x), off, S, tile_off, tile_set, masks, tcnt,
                                                    tpos, surv, keys));
     return HULL_OK;
 }
@@ -441,13 +441,13 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
     const Poly *polys = W<Poly>(ctx, p.polys);
     const unsigned g = (unsigned)(ctx->cus * 8);
     const int64_t *cur_cnt = in_cnt;
-    LAUNCH(K_REFINE, k_ref_init<<<(unsigned)S, 64, 0, st>>>(x, y, polys, tab[0], far[0]));
-    LAUNCH(K_REFINE, k_ref_pass<true><<<g, REF_THREADS, 0, st>>>(
+    LAUNCH(K_REFINE_SPLIT, k_ref_init<<<(unsigned)S, 64, 0, st>>>(x, y, polys, tab[0], far[0]));
+    LAUNCH(K_REFINE_ASSIGN, k_ref_pass<true><<<g, REF_THREADS, 0, st>>>(
         idxs[0], keys[0], cur_cnt, eds[0], polys, nullptr, far[0], nullptr));
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
-        LAUNCH(K_REFINE, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
+        LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
             x, y, S, er, tab[a], far[a], tab[b], far[b]));
         LAUNCH(K_REFINE, k_ref_pass<false><<<g, REF_THREADS, 0, st>>>(
             idxs[a], keys[a], cur_cnt, eds[a], polys, tab[b], far[b], ccnt));

@@ -973,7 +973,7 @@ __global__ __launch_bounds__(256) void k_discard(
 // Survivor scatter: tile t's survivors go to positions tile_pos[t]... in
 // ascending index order.  keys (optional): set << 48 | kx << 24 | ky.
 __global__ __launch_bounds__(256) void k_scatter(
-    const float *__restrict__ x, const float *__restrict__ y, int phase,
+    const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int phase,
     const int64_t *__restrict__ off,
     int64_t S, const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set,
     const uint64_t *__restrict__ masks, const uint32_t *__restrict__ tile_cnt,
@@ -984,30 +984,56 @@ __global__ __launch_bounds__(256) void k_scatter(
     const int64_t T = tile_off[S];
     const uint64_t lt = lanemask_lt();
     for (int64_t t = wave; t < T; t += W) {
-        if (tile_cnt[t] == 0) continue;
+        const uint32_t tc = tile_cnt[t];
+        if (tc == 0) continue;
         const int64_t s = tile_set[t];
         const int64_t o0 = set_begin(off, s);
         const int64_t tb = tile_base(o0, phase) + (t - tile_off[s]) * TILE;
         int64_t base = tile_pos[t];
+        // all loads of the tile are issued together: the 16 mask words, then
+        // either the whole tile as float4 rows (many survivors) or one
+        // gather per survivor
+        const bool dense = keys && tc >= WAVE;
+        uint64_t M[TILE_WORDS];
+#pragma unroll
+        for (int w = 0; w < TILE_WORDS; w++) M[w] = masks[t * TILE_WORDS + w];
+        float xv[TILE_CHUNKS][4], yv[TILE_CHUNKS][4];
+        if (dense) {
+#pragma unroll
+            for (int c = 0; c < TILE_CHUNKS; c++)
+                load4(x, y, tb + c * CHUNK + 4 * lane, n_total, xv[c], yv[c]);
+        } else if (keys) {
+#pragma unroll
+            for (int c = 0; c < TILE_CHUNKS; c++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int64_t gi = tb + c * CHUNK + 4 * lane + j;
+                    xv[c][j] = 0.0f;
+                    yv[c][j] = 0.0f;
+                    if ((M[c * 4 + j] >> lane) & 1) {   // survivors only: in range
+                        xv[c][j] = x[gi];
+                        yv[c][j] = y[gi];
+                    }
+                }
+        }
+#pragma unroll
         for (int c = 0; c < TILE_CHUNKS; c++) {
-            uint64_t M[4];
             int pre = 0, tot = 0;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                M[j] = masks[t * TILE_WORDS + c * 4 + j];
-                pre += __popcll(M[j] & lt);
-                tot += __popcll(M[j]);
+                pre += __popcll(M[c * 4 + j] & lt);
+                tot += __popcll(M[c * 4 + j]);
             }
             int k = 0;
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                if ((M[j] >> lane) & 1) {
-                    int64_t gi = tb + c * CHUNK + 4 * lane + j;
-                    int64_t p = base + pre + k;
+                if ((M[c * 4 + j] >> lane) & 1) {
+                    const int64_t gi = tb + c * CHUNK + 4 * lane + j;
+                    const int64_t p = base + pre + k;
                     surv[p] = (uint32_t)gi;
                     if (keys) {
-                        uint64_t kx = (uint64_t)(uint32_t)(x[gi] * GRIDF);
-                        uint64_t ky = (uint64_t)(uint32_t)(y[gi] * GRIDF);
+                        const uint64_t kx = (uint64_t)(uint32_t)(xv[c][j] * GRIDF);
+                        const uint64_t ky = (uint64_t)(uint32_t)(yv[c][j] * GRIDF);
                         keys[p] = ((uint64_t)s << 48) | (kx << 24) | ky;
                     }
                     k++;
