@@ -252,7 +252,8 @@ static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
                        const int64_t *off, int64_t n1, int64_t S) {
     int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
     LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, phase_of(x), tile_off));
-    LAUNCH(K_TILEMAP, k_tile_sets<<<(unsigned)S, 256, 0, st>>>(tile_off, W<int32_t>(ctx, p.tile_set)));
+    LAUNCH(K_TILEMAP, k_tile_sets<<<(unsigned)std::min<int64_t>(ctx->cus * 4, (p.tcap + 255) / 256), 256,
+                                     0, st>>>(tile_off, S, W<int32_t>(ctx, p.tile_set)));
     return HULL_OK;
 }
 
@@ -385,7 +386,8 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     uint32_t *locnt[2] = {cc, cc + p.u0cap};
     uint32_t *upcnt[2] = {cc + 2 * p.u0cap, cc + 3 * p.u0cap};
     const int64_t u0 = (ncap + CHAIN_C - 1) / CHAIN_C;
-    LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::max<int64_t>(1, (u0 + 3) / 4), 256, 0, st>>>(
+    const int64_t gmax = (int64_t)ctx->cus * 4;       // blocks of 4 waves; kernels loop
+    LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::min(gmax, std::max<int64_t>(1, (u0 + 3) / 4)), 256, 0, st>>>(
         sorted, cnt, lo[0], up[0], locnt[0], upcnt[0]));
     const int L = chain_levels(ncap);
     int cur = 0;
@@ -393,7 +395,7 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     for (int lev = 0; lev < L; lev++) {
         int64_t ucap = (ncap + R - 1) / R;
         int64_t vcap = (ucap + CHAIN_G - 1) / CHAIN_G;
-        dim3 grid((unsigned)std::max<int64_t>(1, (vcap + 3) / 4), 2);
+        dim3 grid((unsigned)std::min(gmax, std::max<int64_t>(1, (vcap + 3) / 4)), 2);
         LAUNCH(K_CHAIN_COMPACT, k_chain_merge<<<grid, 256, 0, st>>>(
             lo[cur], up[cur], locnt[cur], upcnt[cur], cnt, lev, lo[1 - cur], up[1 - cur],
             locnt[1 - cur], upcnt[1 - cur]));
@@ -442,15 +444,16 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
     const unsigned g = (unsigned)(ctx->cus * 8);
     const int64_t *cur_cnt = in_cnt;
     LAUNCH(K_REFINE_SPLIT, k_ref_init<<<(unsigned)S, 64, 0, st>>>(x, y, polys, tab[0], far[0]));
+    const uint32_t *redges = W<uint32_t>(ctx, p.redges);
     LAUNCH(K_REFINE_ASSIGN, k_ref_pass<true><<<g, REF_THREADS, 0, st>>>(
-        idxs[0], keys[0], cur_cnt, eds[0], polys, nullptr, far[0], nullptr));
+        idxs[0], keys[0], cur_cnt, eds[0], polys, redges, nullptr, far[0], nullptr));
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
             x, y, S, er, tab[a], far[a], tab[b], far[b]));
         LAUNCH(K_REFINE, k_ref_pass<false><<<g, REF_THREADS, 0, st>>>(
-            idxs[a], keys[a], cur_cnt, eds[a], polys, tab[b], far[b], ccnt));
+            idxs[a], keys[a], cur_cnt, eds[a], polys, redges, tab[b], far[b], ccnt));
         LAUNCH(K_REFINE_COMPACT, k_ref_nchunks<<<1, 64, 0, st>>>(cur_cnt, nch));
         int rc = run_scan(ctx, p, st, ccnt, nch, cpos);
         if (rc) return rc;

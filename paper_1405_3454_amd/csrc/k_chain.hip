@@ -104,12 +104,14 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
     const int lane = lane_id();
     const int64_t cnt = *cnt_ptr;
     const int64_t U = (cnt + CHAIN_C - 1) / CHAIN_C;
-    const int64_t j = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (U == 0 && j == 0 && lane == 0) {   // no candidates: the chains are empty
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    if (U == 0 && wave == 0 && lane == 0) {   // no candidates: the chains are empty
         lo_cnt[0] = 0;
         up_cnt[0] = 0;
     }
-    if (j >= U) return;
+    // a fixed grid walks the chunks the count actually has
+    for (int64_t j = wave; j < U; j += nw) {
     const int64_t a = j * CHAIN_C, e = min(a + CHAIN_C, cnt);
     uint64_t k[4];
     bool valid[4];
@@ -199,6 +201,8 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
     if (lane == 0) {
         lo_cnt[j] = (uint32_t)hl;
         up_cnt[j] = (uint32_t)hu;
+    }
+    wave_sync();       // the next chunk reuses the wave's LDS
     }
 }
 
@@ -333,13 +337,16 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     for (int l = 0; l < lev; l++) R *= CHAIN_G;
     const int64_t U = (cnt + R - 1) / R;                  // chains at this level
     const int64_t V = (U + CHAIN_G - 1) / CHAIN_G;        // groups
-    const int64_t v = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (V == 0 && v == 0 && threadIdx.x == 0)   // no candidates: empty top chain
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    if (V == 0 && wave == 0 && threadIdx.x == 0)   // no candidates: empty top chain
         (blockIdx.y == 0 ? lo_cout : up_cout)[0] = 0;
-    if (v >= V) return;
     uint64_t *buf = mbuf[threadIdx.x >> 6];
-    if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lo_out, lo_cout, buf);
-    else merge_group<true>(up_in, up_cin, U, R, v, up_out, up_cout, buf);
+    for (int64_t v = wave; v < V; v += nw) {        // groups the count actually has
+        if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lo_out, lo_cout, buf);
+        else merge_group<true>(up_in, up_cin, U, R, v, up_out, up_cout, buf);
+        wave_sync();
+    }
 }
 
 // Fill helpers (kernels, so that graph capture records no memset node).

@@ -48,12 +48,20 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const int64_t *__restrict
     if (threadIdx.x == 0) tile_off[S] = carry;
 }
 
-// tile_set[t] = s for every tile of set s.  One block per set.
-__global__ __launch_bounds__(256) void k_tile_sets(const int64_t *__restrict__ tile_off,
+// tile_set[t] = s for every tile of set s: grid-stride over the tiles, the
+// set found by binary search in tile_off (last s with tile_off[s] <= t).
+__global__ __launch_bounds__(256) void k_tile_sets(const int64_t *__restrict__ tile_off, int64_t S,
                                                    int32_t *__restrict__ tile_set) {
-    int64_t s = blockIdx.x;
-    int64_t a = tile_off[s], b = tile_off[s + 1];
-    for (int64_t t = a + threadIdx.x; t < b; t += blockDim.x) tile_set[t] = (int32_t)s;
+    const int64_t T = tile_off[S];
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < T;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        int64_t lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (tile_off[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        tile_set[t] = (int32_t)lo;
+    }
 }
 
 // ---------------------------------------------------------------------------

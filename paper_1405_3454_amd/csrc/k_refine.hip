@@ -144,11 +144,13 @@ template <bool ASSIGN>
 __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
     const int64_t *__restrict__ cnt_ptr, uint16_t *__restrict__ edge,
-    const Poly *__restrict__ polys, const REdge *__restrict__ tab_nxt,
-    unsigned long long *__restrict__ far, uint32_t *__restrict__ chunk_cnt) {
+    const Poly *__restrict__ polys, const uint32_t *__restrict__ redges,
+    const REdge *__restrict__ tab_nxt, unsigned long long *__restrict__ far,
+    uint32_t *__restrict__ chunk_cnt) {
     __shared__ RefFar L;
-    __shared__ double pex[MAX_SLOTS], pey[MAX_SLOTS], pc[MAX_SLOTS];
-    __shared__ int pm;
+    __shared__ double pex[ROW_EDGE_NONE + 1], pey[ROW_EDGE_NONE + 1], pc[ROW_EDGE_NONE + 1];
+    __shared__ uint32_t lre[SPAN_ROWS];     // the set's row edge lists (Step 3's rows)
+    __shared__ int pm, pky, pyl, psh;
     __shared__ uint32_t wsum[REF_THREADS / WAVE];
     const int64_t cnt = *cnt_ptr;
     const int64_t nch = (cnt + REF_CH - 1) / REF_CH;
@@ -159,12 +161,20 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
         const bool local = s0 == s1;
         if (local) {
             for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
-            if (ASSIGN && tid < MAX_SLOTS) {
+            if (ASSIGN) {
                 const Poly &P = polys[s0];
-                pex[tid] = P.ex[tid];
-                pey[tid] = P.ey[tid];
-                pc[tid] = P.c[tid];
-                if (tid == 0) pm = P.m >= 3 ? P.m : 0;
+                if (tid <= ROW_EDGE_NONE) {    // unused slots: an always-satisfied edge
+                    pex[tid] = tid < MAX_SLOTS ? P.ex[tid] : 0.0;
+                    pey[tid] = tid < MAX_SLOTS ? P.ey[tid] : 0.0;
+                    pc[tid] = tid < MAX_SLOTS ? P.c[tid] : 1.0;
+                }
+                for (int r = tid; r < SPAN_ROWS; r += REF_THREADS) lre[r] = redges[s0 * SPAN_ROWS + r];
+                if (tid == 0) {
+                    pm = P.m >= 3 ? P.m : 0;
+                    pky = P.ky_lo;
+                    pyl = P.yspan;
+                    psh = P.shift;
+                }
             }
         }
         __syncthreads();
@@ -188,9 +198,24 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             double dist = 0.0;
             if (ASSIGN) {
                 if (local) {
-                    for (int e = 0; e < pm; e++) {
-                        const double E = edge_eval(pex[e], pey[e], pc[e], px, py);
-                        if (E < 0) { out = (uint16_t)e; dist = -E; break; }
+                    // a point of a row is strictly outside the polygon iff it is
+                    // strictly outside one of the (at most four) edges meeting
+                    // the row; points outside the rows try every edge
+                    const uint32_t dy = (uint32_t)((int32_t)py - pky);
+                    const uint32_t re = (pm > 0 && pyl >= 0 && dy <= (uint32_t)pyl) ? lre[dy >> psh]
+                                                                                 : ROW_EDGES_ALL;
+                    if (re != ROW_EDGES_ALL) {
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            const int e = (re >> (8 * q)) & 0xFF;
+                            const double E = edge_eval(pex[e], pey[e], pc[e], px, py);
+                            if (E < 0 && out == RE_NONE) { out = (uint16_t)e; dist = -E; }
+                        }
+                    } else {
+                        for (int e = 0; e < pm; e++) {
+                            const double E = edge_eval(pex[e], pey[e], pc[e], px, py);
+                            if (E < 0) { out = (uint16_t)e; dist = -E; break; }
+                        }
                     }
                 } else {
                     const Poly &P = polys[s];
