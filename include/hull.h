@@ -77,6 +77,9 @@ typedef struct hull_ctx hull_ctx;
 #define HULL_NOREFINE 8 /* hull of the survivors by sort + chain alone, without the
                            QuickHull refinement rounds that shrink them first */
 
+#define HULL_NCOUNTS 5  /* entries of hull_candidate_counts: the discard pass, then
+                           each of the four refinement rounds */
+
 #define HULL_NONE 0xFFFFFFFFu
 #define HULL_FIXED_SLOTS 16
 #define HULL_MAX_SLOTS 24
@@ -235,6 +238,17 @@ int hull_timing_enable(hull_ctx *ctx, int on);
 int hull_timing_read(hull_ctx *ctx, double *ms, int64_t *launches, int cap);
 const char *hull_timing_name(int kind);
 int hull_timing_reset(hull_ctx *ctx);
+
+/* ---- candidate counts (diagnostics) ------------------------------------ */
+/* Copy up to cap (at most HULL_NCOUNTS) counts, summed over all sets, of the
+ * context's last hull_compute / hull_compute_batched call (or graph replay):
+ * [0] candidates handed to the hull stage's input, i.e. the discard pass's
+ * survivors (every point with HULL_NOFILTER); [1 + r] candidates left after
+ * QuickHull refinement round r (each round splits every polygon edge at its
+ * farthest survivor), -1 when refinement did not run.  Synchronises the
+ * device.  Returns the number of entries copied; HULL_EINVAL for a null
+ * pointer or cap < 0. */
+int hull_candidate_counts(hull_ctx *ctx, int64_t *counts, int cap);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,7 @@ SIGNATURES = {
     "hull_set_direction_gap": (I, [P, I]),
     "hull_timing_enable": (I, [P, I]),
     "hull_timing_read": (I, [P, P, P, I]),
+    "hull_candidate_counts": (I, [P, P, I]),
     "hull_timing_name": (ctypes.c_char_p, [I]),
     "hull_timing_reset": (I, [P]),
 }

@@ -302,6 +302,14 @@ class Hull:
     def timing_reset(self):
         check(lib().hull_timing_reset(self._h), "hull_timing_reset")
 
+    def candidate_counts(self):
+        """Candidates summed over sets at each stage of the last computation:
+        [discard survivors, after refinement round 1..4] (-1: round not run)."""
+        c = np.full(8, -1, np.int64)
+        k = check(lib().hull_candidate_counts(self._h, c.ctypes.data_as(ctypes.c_void_p), 8),
+                  "hull_candidate_counts")
+        return [int(v) for v in c[:k]]
+
     def timing_read(self):
         ms = np.zeros(64, np.float64)
         cnt = np.zeros(64, np.int64)

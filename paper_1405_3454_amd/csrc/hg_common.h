@@ -53,11 +53,23 @@ struct Span {
 constexpr uint32_t ROW_EDGE_NONE = 31;          // index of an always-satisfied edge
 constexpr uint32_t ROW_EDGES_ALL = 0xFFFFFFFFu;
 
+// QuickHull refinement of the survivors (hull stage): rounds, edge slots per
+// set and round, and the per-survivor edge states besides an edge id.
+constexpr int REF_ROUNDS = 4;
+constexpr int RE_CAP = MAX_SLOTS << REF_ROUNDS;
+constexpr uint16_t RE_NONE = 0xFFFF;              // kept, not assigned to an edge
+constexpr uint16_t RE_DROP = 0xFFFE;              // strictly inside the hull
+
+// Unordered survivor lists of the full method are kept in NSEG segments, each
+// with its own counter (appends spread over NSEG addresses instead of one):
+// segment i holds its entries at [i * segcap, i * segcap + count[i]).
+constexpr int NSEG = 64;
+
 // Kernel kinds for the per-kernel event timer.
 enum Kind {
     K_TILEMAP = 0, K_EXTREMES, K_POLYGON, K_DISCARD, K_SCAN, K_SCATTER,
     K_KEYS, K_SORT_HIST, K_SORT_SCAN, K_SORT_SCATTER, K_CHAIN, K_CHAIN_COMPACT,
-    K_FINAL, K_LOOKUP, K_VALIDATE, K_MISC, K_HIST32, K_MLP, K_LABELS, K_REFINE, K_REFINE_COMPACT, K_REFINE_ASSIGN, K_REFINE_SPLIT, K_NKINDS
+    K_FINAL, K_LOOKUP, K_VALIDATE, K_MISC, K_HIST32, K_MLP, K_LABELS, K_REFINE, K_REFINE_SPLIT, K_NKINDS
 };
 
 // Direction constants for one launch.  Preset groups: (gc[g], gs[g]).

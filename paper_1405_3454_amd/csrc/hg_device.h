@@ -13,6 +13,18 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Farthest-point key of a refinement edge: float(distance) bits << 32 |
+// ~index, so the maximum is (close to) the farthest point, lowest index among
+// equal keys, whatever the order of the updates.
+__device__ __forceinline__ uint64_t far_key(double dist, uint32_t idx) {
+    return ((uint64_t)__float_as_uint((float)dist) << 32) | (uint64_t)(~idx);
+}
+
+// Raise *slot to key unless it already holds at least as much.
+__device__ __forceinline__ void far_update(unsigned long long *slot, uint64_t key) {
+    if (*reinterpret_cast<volatile unsigned long long *>(slot) < key) atomicMax(slot, key);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     return (uint64_t(1) << lane_id()) - 1;
 }

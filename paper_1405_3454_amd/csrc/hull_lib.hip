@@ -47,6 +47,8 @@ struct hull_ctx {
     hipError_t last = hipSuccess;
     char *ws = nullptr;
     size_t ws_cap = 0;
+    int64_t *counts = nullptr;          // candidates per stage of the last computation
+    uint32_t *tickets = nullptr;        // last-block tickets (zero between launches)
     std::vector<char *> retired;        // old workspaces a graph may still use
     // blocks per CU of the persistent filter kernels: what stays resident
     // (extremes: ~140 VGPRs -> 3 waves per SIMD; discard: ~112 -> 4)
@@ -68,7 +70,7 @@ struct hull_ctx {
 static const char *kKindNames[K_NKINDS] = {
     "tile_map", "extremes", "polygon", "discard", "scan", "scatter", "keys",
     "sort_hist", "sort_scan", "sort_scatter", "chain", "chain_merge", "hull_final",
-    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels", "refine_pass", "refine_compact", "refine_assign", "refine_split"};
+    "hull_lookup", "validate", "misc", "histogram32", "mlp", "labels", "refine_pass", "refine_split"};
 
 #define HIPCHECK(expr)                                   \
     do {                                                 \
@@ -117,13 +119,26 @@ struct Plan {
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
-        rfar1, rchunk, rcpos, total;
+        rfar1, segcnt, cidx, ckeys, total;
     int64_t tcap, u0cap;
+    int64_t segcap;     // entries per segment of the full method's survivor lists
 };
 
 static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 
-static Plan make_plan(int64_t n, int64_t S) {
+// Entries per segment that no segmented survivor list can exceed, for W
+// waves of the discard pass: wave w appends the survivors of its q =
+// ceil(T / W) tiles to segment w mod NSEG (at most T / NSEG + 2q tiles per
+// segment), and a refinement round appends chunk c of its input (at most
+// n / REF_CH + NSEG chunks) to segment c mod NSEG.
+static int64_t seg_capacity(int64_t n, int64_t tcap, int64_t W) {
+    const int64_t q = (tcap + W - 1) / W;
+    const int64_t d = (tcap / NSEG + 2 * q + 1) * TILE;
+    const int64_t r = ((n / REF_CH + NSEG) / NSEG + 1) * REF_CH;
+    return std::max(d, r);
+}
+
+static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     Plan p;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -133,6 +148,8 @@ static Plan make_plan(int64_t n, int64_t S) {
     };
     p.tcap = n / TILE + 2 * S + 2;
     p.u0cap = n / CHAIN_C + 2;
+    p.segcap = seg_capacity(n, p.tcap, W);
+    const size_t lcap = (size_t)std::max<int64_t>(n, NSEG * p.segcap);   // list entries
     p.tile_off = take((S + 1) * 8);
     p.tile_set = take(p.tcap * 4);
     p.pval = take(p.tcap * MAX_SLOTS * 8);
@@ -147,14 +164,14 @@ static Plan make_plan(int64_t n, int64_t S) {
     p.tile_pos = take((p.tcap + 1) * 8);
     p.scan_bs = take(SCAN_BLOCKS * 8);
     p.surv_off = take((S + 1) * 8);
-    p.surv = take(n * 4 + 16);
-    p.keys0 = take(n * 8 + 16);
+    p.surv = take(lcap * 4 + 16);
+    p.keys0 = take(lcap * 8 + 16);
     p.keysA = take(n * 8 + 16);
     p.keysB = take(n * 8 + 16);
-    p.lo0 = take(n * 8 + 16);
-    p.up0 = take(n * 8 + 16);
-    p.lo1 = take(n * 8 + 16);
-    p.up1 = take(n * 8 + 16);
+    p.lo0 = take(lcap * 8 + 16);
+    p.up0 = take(lcap * 8 + 16);
+    p.lo1 = take(lcap * 8 + 16);
+    p.up1 = take(lcap * 8 + 16);
     p.ccnt = take(4 * p.u0cap * 4);
     p.bounds = take(4 * S * 8);
     p.hcnt = take(S * 4);
@@ -172,8 +189,9 @@ static Plan make_plan(int64_t n, int64_t S) {
     p.rtab1 = take(S * RE_CAP * sizeof(REdge));
     p.rfar0 = take(S * RE_CAP * 8);
     p.rfar1 = take(S * RE_CAP * 8);
-    p.rchunk = take((n / REF_CH + 2) * 4);
-    p.rcpos = take((n / REF_CH + 3) * 8);
+    p.segcnt = take((REF_ROUNDS + 1) * NSEG * 8);
+    p.cidx = take(n * 4 + 16);
+    p.ckeys = take(n * 8 + 16);
     p.total = o;
     return p;
 }
@@ -231,8 +249,8 @@ static int grid_k3(hull_ctx *ctx) { return ctx->cus * ctx->k3_bpc; }
 static int run_scan(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t *in,
                     const int64_t *cnt, int64_t *out) {
     int64_t *bs = W<int64_t>(ctx, p.scan_bs);
-    LAUNCH(K_SCAN, k_scan_reduce<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs));
-    LAUNCH(K_SCAN, k_scan_blocks<<<1, SCAN_THREADS, 0, st>>>(bs, cnt, out));
+    LAUNCH(K_SCAN, k_scan_reduce<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs, out,
+                                                                       ctx->tickets + 0));
     LAUNCH(K_SCAN, k_scan_down<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs, out));
     return HULL_OK;
 }
@@ -318,17 +336,51 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     int64_t *tpos = W<int64_t>(ctx, p.tile_pos);
     const int g = grid_k3(ctx);
     if (nedge <= FIXED_SLOTS)
-        LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS><<<g, 256, 0, st>>>(
-            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
+        LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS, DISCARD_MASKS><<<g, 256, 0, st>>>(
+            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt,
+            nullptr, nullptr, nullptr, nullptr, 0, nullptr));
     else
-        LAUNCH(K_DISCARD, k_discard<MAX_SLOTS><<<g, 256, 0, st>>>(
-            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt));
+        LAUNCH(K_DISCARD, k_discard<MAX_SLOTS, DISCARD_MASKS><<<g, 256, 0, st>>>(
+            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt,
+            nullptr, nullptr, nullptr, nullptr, 0, nullptr));
     int rc = run_scan(ctx, p, st, tcnt, tile_off + S, tpos);
     if (rc) return rc;
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
                                                                                   surv_off));
     LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, n_total, phase_of(x), off, S, tile_off, tile_set, masks, tcnt,
                                                    tpos, surv, keys));
+    return HULL_OK;
+}
+
+// Step 3 for the full method: survivors appended to the segmented list
+// (surv, keys[, edges]) with segment counts seg_cnt[NSEG] (zero before);
+// with gfar, also the refinement's round-0 edge states and farthest points.
+static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
+                              const float *y, int64_t n_total, const int64_t *off, int64_t n1,
+                              int64_t S, int nedge, uint32_t *surv, uint64_t *keys,
+                              uint16_t *edges, int64_t *seg_cnt, unsigned long long *gfar) {
+    const int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
+    const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
+    auto *polys = W<Poly>(ctx, p.polys);
+    auto *spans = W<Span>(ctx, p.spans);
+    const uint32_t *redges = W<uint32_t>(ctx, p.redges);
+    auto *c = reinterpret_cast<unsigned long long *>(seg_cnt);
+    const int64_t segcap = p.segcap;
+    const int g = grid_k3(ctx);
+    const int ph = phase_of(x);
+#define K3A(NE, MODE)                                                                             \
+    LAUNCH(K_DISCARD, (k_discard<NE, MODE><<<g, 256, 0, st>>>(x, y, n_total, ph, off, n1, S,    \
+                                                               tile_off, tile_set, polys, spans,  \
+                                                               redges, nullptr, nullptr, surv,    \
+                                                               keys, edges, c, segcap, gfar)))
+    if (gfar) {
+        if (nedge <= FIXED_SLOTS) K3A(FIXED_SLOTS, DISCARD_ASSIGN);
+        else K3A(MAX_SLOTS, DISCARD_ASSIGN);
+    } else {
+        if (nedge <= FIXED_SLOTS) K3A(FIXED_SLOTS, DISCARD_APPEND);
+        else K3A(MAX_SLOTS, DISCARD_APPEND);
+    }
+#undef K3A
     return HULL_OK;
 }
 
@@ -344,13 +396,11 @@ static int run_sort(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint64_t
     uint64_t *A = W<uint64_t>(ctx, p.keysA), *B = W<uint64_t>(ctx, p.keysB);
     uint32_t *hist = W<uint32_t>(ctx, p.hist);
     int64_t *hoffs = W<int64_t>(ctx, p.hoffs);
-    const int64_t *hcount = W<int64_t>(ctx, p.consts) + 0;   // = RADIX * SORT_BLOCKS
     const uint64_t *in = keys;
     uint64_t *out = A;
     for (int ps = 0; ps < passes; ps++) {
-        LAUNCH(K_SORT_HIST, k_sort_hist<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(in, cnt, 8 * ps, hist));
-        int rc = run_scan(ctx, p, st, hist, hcount, hoffs);
-        if (rc) return rc;
+        LAUNCH(K_SORT_HIST, k_sort_hist<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
+            in, cnt, 8 * ps, hist, hoffs, ctx->tickets + 1));
         LAUNCH(K_SORT_SCATTER, k_sort_scatter<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
             in, cnt, 8 * ps, hoffs, out));
         in = out;
@@ -421,48 +471,45 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     return HULL_OK;
 }
 
-// Refinement rounds on the survivors (surv, keys0, count at surv_off[S]):
-// QuickHull splits of the filter polygon's edges.  The kept survivors end up
-// back in surv/keys0 (an even number of rounds ping-pongs through lo0/lo1/
-// up0/up1, which the hull stage only uses afterwards) with their count at
-// *out_cnt; the per-set offsets are not kept (the hull stage reads the set
-// from each key).
+// Refinement rounds on the segmented survivor list (surv, keys0, round-0
+// edge states in up0 and farthest points in rfar0 from the discard pass,
+// segment counts at stage 0 of segcnt): QuickHull splits of the filter
+// polygon's edges.  Round r appends to stage r + 1; an even number of rounds
+// ends back in surv/keys0 (ping-pong through lo0/lo1/up1, which the hull stage
+// only uses afterwards).  ctx->counts[r] records the input total of round r.
+static_assert(HULL_NCOUNTS == 1 + REF_ROUNDS, "one count per refinement round");
 static_assert(REF_ROUNDS % 2 == 0, "refinement must end in the first buffer set");
 static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
-                      const float *y, int64_t S, const int64_t *in_cnt, int64_t **out_cnt) {
+                      const float *y, int64_t S) {
     uint32_t *idxs[2] = {W<uint32_t>(ctx, p.surv), W<uint32_t>(ctx, p.lo0)};
     uint64_t *keys[2] = {W<uint64_t>(ctx, p.keys0), W<uint64_t>(ctx, p.lo1)};
     uint16_t *eds[2] = {W<uint16_t>(ctx, p.up0), W<uint16_t>(ctx, p.up1)};
     REdge *tab[2] = {W<REdge>(ctx, p.rtab0), W<REdge>(ctx, p.rtab1)};
     unsigned long long *far[2] = {W<unsigned long long>(ctx, p.rfar0),
                                   W<unsigned long long>(ctx, p.rfar1)};
-    uint32_t *ccnt = W<uint32_t>(ctx, p.rchunk);
-    int64_t *cpos = W<int64_t>(ctx, p.rcpos);
-    int64_t *nch = W<int64_t>(ctx, p.consts) + 2;       // chunks of the current round
-    int64_t *cnts[2] = {W<int64_t>(ctx, p.consts) + 3, W<int64_t>(ctx, p.consts) + 4};
-    const Poly *polys = W<Poly>(ctx, p.polys);
+    int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
     const unsigned g = (unsigned)(ctx->cus * 8);
-    const int64_t *cur_cnt = in_cnt;
-    LAUNCH(K_REFINE_SPLIT, k_ref_init<<<(unsigned)S, 64, 0, st>>>(x, y, polys, tab[0], far[0]));
-    const uint32_t *redges = W<uint32_t>(ctx, p.redges);
-    LAUNCH(K_REFINE_ASSIGN, k_ref_pass<true><<<g, REF_THREADS, 0, st>>>(
-        idxs[0], keys[0], cur_cnt, eds[0], polys, redges, nullptr, far[0], nullptr));
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
+        int64_t *cin = segcnt + r * NSEG, *cout = segcnt + (r + 1) * NSEG;
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
-            x, y, S, er, tab[a], far[a], tab[b], far[b]));
-        LAUNCH(K_REFINE, k_ref_pass<false><<<g, REF_THREADS, 0, st>>>(
-            idxs[a], keys[a], cur_cnt, eds[a], polys, redges, tab[b], far[b], ccnt));
-        LAUNCH(K_REFINE_COMPACT, k_ref_nchunks<<<1, 64, 0, st>>>(cur_cnt, nch));
-        int rc = run_scan(ctx, p, st, ccnt, nch, cpos);
-        if (rc) return rc;
-        LAUNCH(K_REFINE_COMPACT, k_ref_compact<<<g, REF_THREADS, 0, st>>>(
-            idxs[a], keys[a], eds[a], cur_cnt, cpos, idxs[b], keys[b], eds[b]));
-        LAUNCH(K_REFINE_COMPACT, k_ref_total<<<1, 64, 0, st>>>(cpos, nch, cnts[b]));
-        cur_cnt = cnts[b];
+            x, y, S, er, tab[a], far[a], tab[b], far[b], cin, cout, ctx->counts + r));
+        LAUNCH(K_REFINE, k_ref_pass<<<g, REF_THREADS, 0, st>>>(
+            idxs[a], keys[a], eds[a], cin, p.segcap, tab[b], far[b], idxs[b], keys[b], eds[b],
+            reinterpret_cast<unsigned long long *>(cout)));
     }
-    *out_cnt = cnts[REF_ROUNDS & 1];
+    return HULL_OK;
+}
+
+// Segmented list (surv, keys0) at segment counts cnt -> contiguous (cidx,
+// ckeys); the total goes to *total.
+static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, const int64_t *cnt,
+                      int64_t *total) {
+    const unsigned per = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, p.segcap / 1024));
+    LAUNCH(K_SCATTER, k_seg_gather<<<NSEG * per, 256, 0, st>>>(
+        W<uint32_t>(ctx, p.surv), W<uint64_t>(ctx, p.keys0), cnt, p.segcap,
+        W<uint32_t>(ctx, p.cidx), W<uint64_t>(ctx, p.ckeys), total));
     return HULL_OK;
 }
 
@@ -476,12 +523,9 @@ static int init_cand_table();
 
 static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p) {
     HIPCHECK(hipSetDevice(ctx->device));
-    *p = make_plan(n, S);
+    *p = make_plan(n, S, (int64_t)grid_k3(ctx) * 4);
     int rc = ensure_ws(ctx, p->total, st);
-    if (rc) return rc;
-    int64_t *consts = W<int64_t>(ctx, p->consts);
-    LAUNCH(K_MISC, k_fill_i64<<<1, 64, 0, st>>>(consts, 1, (int64_t)RADIX * SORT_BLOCKS));
-    return HULL_OK;
+    return rc;
 }
 
 // Full method for S sets (off == nullptr: one set of n1 points).
@@ -501,9 +545,14 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
     uint64_t *keys = W<uint64_t>(ctx, p.keys0);
     int64_t *surv_off = W<int64_t>(ctx, p.surv_off);
     int64_t *hoff = hoff_out ? hoff_out : W<int64_t>(ctx, p.hoff);
+    const bool refine = !(flags & (HULL_NOREFINE | HULL_NOFILTER));
+    const int64_t *cnt = ctx->counts;
+    int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
+    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(ctx->counts, HULL_NCOUNTS, segcnt));
     if (flags & HULL_NOFILTER) {
         LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
                                                          surv_off));
+        LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(surv_off + S, ctx->counts));
     } else {
         if ((rc = run_tilemap(ctx, p, st, x, off, n1, S))) return rc;
         if (learned) {
@@ -513,15 +562,24 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
         if ((rc = run_extremes(ctx, p, st, x, y, n_total, off, n1, S, learned))) return rc;
         if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, learned, nullptr, 0, nullptr, nullptr)))
             return rc;
-        if ((rc = run_discard(ctx, p, st, x, y, n_total, off, n1, S,
-                              learned ? MAX_SLOTS : FIXED_SLOTS, surv, surv_off, keys)))
+        unsigned long long *far0 = nullptr;
+        uint16_t *edges = nullptr;
+        if (refine) {    // round-0 edge table; the discard pass fills its states
+            far0 = W<unsigned long long>(ctx, p.rfar0);
+            edges = W<uint16_t>(ctx, p.up0);
+            LAUNCH(K_REFINE_SPLIT, k_ref_init<<<(unsigned)S, 64, 0, st>>>(
+                x, y, W<Poly>(ctx, p.polys), W<REdge>(ctx, p.rtab0), far0));
+        }
+        if ((rc = run_discard_append(ctx, p, st, x, y, n_total, off, n1, S,
+                                     learned ? MAX_SLOTS : FIXED_SLOTS, surv, keys, edges,
+                                     segcnt, far0)))
             return rc;
-    }
-    const int64_t *cnt = surv_off + S;
-    if (!(flags & (HULL_NOREFINE | HULL_NOFILTER))) {
-        int64_t *rc_cnt = nullptr;
-        if ((rc = run_refine(ctx, p, st, x, y, S, cnt, &rc_cnt))) return rc;
-        cnt = rc_cnt;
+        const int stage = refine ? REF_ROUNDS : 0;
+        if (refine && (rc = run_refine(ctx, p, st, x, y, S))) return rc;
+        if ((rc = run_gather(ctx, p, st, segcnt + stage * NSEG, ctx->counts + stage))) return rc;
+        surv = W<uint32_t>(ctx, p.cidx);
+        keys = W<uint64_t>(ctx, p.ckeys);
+        cnt = ctx->counts + stage;
     }
     rc = run_hull(ctx, p, st, surv, keys, cnt, n_total, S, hoff, hull);
     if (rc) return rc;
@@ -569,6 +627,17 @@ int hull_create(hull_ctx **out, int device) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
         ctx->cus = cus;
+    if (hipMalloc(&ctx->counts, HULL_NCOUNTS * sizeof(int64_t)) != hipSuccess ||
+        hipMemset(ctx->counts, 0xff, HULL_NCOUNTS * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&ctx->tickets, 8 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(ctx->tickets, 0, 8 * sizeof(uint32_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->counts) (void)hipFree(ctx->counts);
+        if (ctx->tickets) (void)hipFree(ctx->tickets);
+        delete ctx;
+        return HULL_ENOMEM;
+    }
     *out = ctx;
     return HULL_OK;
 }
@@ -583,6 +652,8 @@ int hull_destroy(hull_ctx *ctx) {
     learned_free(ctx->learned);
     for (char *r : ctx->retired) (void)hipFree(r);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->counts) (void)hipFree(ctx->counts);
+    if (ctx->tickets) (void)hipFree(ctx->tickets);
     delete ctx;
     return HULL_OK;
 }
@@ -741,7 +812,7 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int6
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     HIPCHECK(hipSetDevice(ctx->device));
-    Plan p = make_plan(n_total, S);
+    Plan p = make_plan(n_total, S, (int64_t)grid_k3(ctx) * 4);
     if ((rc = ensure_ws(ctx, p.total, st))) return rc;
     if ((flags & HULL_LEARNED) && !(flags & HULL_NOFILTER)) {
         // the network's buffers are sized before capture: nothing allocates inside
@@ -903,6 +974,15 @@ int hull_timing_read(hull_ctx *ctx, double *ms, int64_t *launches, int cap) {
 
 const char *hull_timing_name(int kind) {
     return (kind >= 0 && kind < K_NKINDS) ? kKindNames[kind] : "";
+}
+
+int hull_candidate_counts(hull_ctx *ctx, int64_t *counts, int cap) {
+    if (!ctx || !counts || cap < 0) return HULL_EINVAL;
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipDeviceSynchronize());
+    const int k = std::min(cap, HULL_NCOUNTS);
+    if (k > 0) HIPCHECK(hipMemcpy(counts, ctx->counts, k * sizeof(int64_t), hipMemcpyDeviceToHost));
+    return k;
 }
 
 int hull_timing_reset(hull_ctx *ctx) {

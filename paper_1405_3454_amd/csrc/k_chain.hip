@@ -5,13 +5,14 @@
 // contiguous run ordered by (x, y).  Every chain below is segmented by the
 // set field: it never joins points of different sets.
 //  1. k_chain_chunks: one wave per CHAIN_C consecutive keys computes the
-//     lower and the upper chain of its chunk (duplicates dropped; a point is
-//     popped while it does not make a strict turn, so collinear points go).
+//     lower and the upper chain of its chunk (duplicates dropped; a point
+//     goes while it does not make a strict turn, so collinear points go).
 //  2. k_chain_merge: one wave per group of CHAIN_G neighbouring chains joins
-//     them left to right: at each junction the tail of the chain built so far
-//     and the head of the next one are walked to their common tangent (the
-//     bridge), then the rest of the next chain is appended.  Repeated until
-//     one chain per kind is left.
+//     them: the chains side by side are pruned like a chunk (below), or, for
+//     groups too large for LDS, joined left to right, the tail of the chain
+//     built so far and the head of the next one walked to their common
+//     tangent (the bridge) at each junction.  Repeated until one chain per
+//     kind is left.
 //  3. Per set: the lower chain followed by the upper chain's interior in
 //     reverse gives the counter-clockwise hull from the lexicographic
 //     minimum; each hull key is mapped back to the lowest point index with
@@ -21,7 +22,7 @@
 namespace hg {
 
 constexpr int CHAIN_C = 256;
-constexpr int CHAIN_G = 8;
+constexpr int CHAIN_G = 32;
 
 __device__ __forceinline__ uint32_t key_set(uint64_t k) { return (uint32_t)(k >> 48); }
 __device__ __forceinline__ double key_x(uint64_t k) { return (double)((k >> 24) & 0xFFFFFF); }
@@ -44,16 +45,24 @@ __device__ __forceinline__ bool drop_mid(uint64_t a, uint64_t b, uint64_t c) {
 // falling part has a smaller y than every earlier point, and on its rising
 // part a smaller y than every later point (the first and last points count
 // as such).  Mirrored with maxima for the upper chain.  So only strict
-// prefix/suffix minima and maxima of y can be chain vertices; two wave-wide
-// scans find them (about ln CHAIN_C of each kind for points in general
-// position).  Lanes 0 and 1 then run the lower and upper chain over those
-// candidates in LDS.  A chunk that spans two sets keeps every point.
+// prefix/suffix minima of y can be lower-chain vertices and only strict
+// prefix/suffix maxima upper-chain ones; wave-wide scans find both kinds and
+// each goes to a list of its own.  A chunk that spans two sets keeps every
+// point in both lists.
+//
+// The lists are then pruned in parallel: a point whose neighbours in its list
+// (same set) make it lie on or above (lower chain; below for the upper) the
+// segment joining them is no strict vertex of the chain, and removing such
+// points, all at once, leaves the chain unchanged; a repeated key goes too.
+// A pass that removes nothing leaves an x-monotone list that turns strictly
+// the same way at every point, which is a convex chain: the answer.  When the
+// passes run out first, lanes 0 and 1 finish with the serial monotone chain.
 constexpr uint32_t YMIN_ID = 0x7fffffffu;   // identity of min over y < 2^24
 constexpr int32_t YMAX_ID = -1;
+constexpr int PRUNE_PASSES = 24;
 
 struct Chain0Lds {
-    uint64_t cand[CHAIN_C];
-    uint64_t stk[2][CHAIN_C];
+    uint64_t list[2][2][CHAIN_C];   // [lower, upper][ping-pong]
 };
 
 __device__ __forceinline__ uint32_t scan_min_up(uint32_t v) {
@@ -93,6 +102,58 @@ __device__ __forceinline__ int32_t scan_max_down(int32_t v) {
     return v;
 }
 
+// One pruning pass over src[0..n) into dst; returns the kept count (uniform).
+// dst may be src: a round reads its 64 entries and their neighbours before
+// it writes, and a kept entry never moves up, so no later read is clobbered.
+template <bool UPPER>
+__device__ __forceinline__ int prune_pass(const uint64_t *src, uint64_t *dst, int n,
+                                          uint64_t lt) {
+    const int lane = lane_id();
+    int out = 0;
+    for (int r = 0; r < n; r += WAVE) {
+        const int i = r + lane;
+        bool keep = false;
+        uint64_t me = 0;
+        if (i < n) {
+            me = src[i];
+            keep = true;
+            if (i > 0) {
+                const uint64_t pv = src[i - 1];
+                if (pv == me) {
+                    keep = false;                  // a repeated key
+                } else if (i + 1 < n) {
+                    const uint64_t nx = src[i + 1];
+                    const uint32_t sm = key_set(me);
+                    if (nx != me && key_set(pv) == sm && key_set(nx) == sm &&
+                        drop_mid<UPPER>(pv, me, nx))
+                        keep = false;
+                }
+            }
+        }
+        const uint64_t b = __ballot(keep);
+        if (keep) dst[out + __popcll(b & lt)] = me;
+        out += __popcll(b);
+    }
+    return out;
+}
+
+// Serial monotone chain over st[0..n) in place (the stack never passes the
+// read position); resets at set boundaries.
+template <bool UPPER>
+__device__ int serial_chain(uint64_t *st, int n) {
+    int h = 0, seg = 0;
+    uint64_t prev = ~uint64_t(0);
+    for (int i = 0; i < n; i++) {
+        const uint64_t kk = st[i];
+        if (kk == prev) continue;
+        prev = kk;
+        if (h > seg && key_set(st[h - 1]) != key_set(kk)) seg = h;
+        while (h - seg >= 2 && drop_mid<UPPER>(st[h - 2], st[h - 1], kk)) h--;
+        st[h++] = kk;
+    }
+    return h;
+}
+
 __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict__ keys,
                                                       const int64_t *__restrict__ cnt_ptr,
                                                       uint64_t *__restrict__ lo,
@@ -102,6 +163,7 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
     __shared__ Chain0Lds lds[4];
     Chain0Lds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
     const int64_t cnt = *cnt_ptr;
     const int64_t U = (cnt + CHAIN_C - 1) / CHAIN_C;
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
@@ -146,13 +208,14 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
     int32_t smax = __shfl_down(scan_max_down(lmax), 1);
     if (lane == 0) { pmin = YMIN_ID; pmax = YMAX_ID; }
     if (lane == WAVE - 1) { smin = YMIN_ID; smax = YMAX_ID; }
-    bool cand[4];
+    bool cl[4], cu[4];
     {
         uint32_t rmin = pmin;
         int32_t rmax = pmax;
 #pragma unroll
         for (int i = 0; i < 4; i++) {            // strict prefix records
-            cand[i] = valid[i] && (multi || ymin[i] < rmin || ymax[i] > rmax);
+            cl[i] = valid[i] && (multi || ymin[i] < rmin);
+            cu[i] = valid[i] && (multi || ymax[i] > rmax);
             rmin = min(rmin, ymin[i]);
             rmax = max(rmax, ymax[i]);
         }
@@ -160,47 +223,52 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
         rmax = smax;
 #pragma unroll
         for (int i = 3; i >= 0; i--) {           // strict suffix records
-            cand[i] = cand[i] || (valid[i] && (ymin[i] < rmin || ymax[i] > rmax));
+            cl[i] = cl[i] || (valid[i] && ymin[i] < rmin);
+            cu[i] = cu[i] || (valid[i] && ymax[i] > rmax);
             rmin = min(rmin, ymin[i]);
             rmax = max(rmax, ymax[i]);
         }
     }
-    // compact the candidates in key order: (lane, item)
-    const uint64_t lt = lanemask_lt();
-    int pos = 0, nc = 0;
-    uint64_t B[4];
+    // compact both lists in key order: (lane, item)
+    int pl = 0, pu = 0, nl = 0, nu = 0;
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-        B[i] = __ballot(cand[i]);
-        pos += __popcll(B[i] & lt);
-        nc += __popcll(B[i]);
+        const uint64_t bl = __ballot(cl[i]), bu = __ballot(cu[i]);
+        pl += __popcll(bl & lt);
+        nl += __popcll(bl);
+        pu += __popcll(bu & lt);
+        nu += __popcll(bu);
     }
 #pragma unroll
-    for (int i = 0; i < 4; i++)
-        if (cand[i]) L.cand[pos++] = k[i];
-    wave_sync();
-    int h = 0;
-    if (lane < 2) {   // lane 0: lower chain, lane 1: upper chain
-        const double sg = lane == 0 ? 1.0 : -1.0;
-        uint64_t *st = L.stk[lane];
-        int seg = 0;
-        uint64_t prev = ~uint64_t(0);
-        for (int i = 0; i < nc; i++) {
-            uint64_t kk = L.cand[i];
-            if (kk == prev) continue;
-            prev = kk;
-            if (h > seg && key_set(st[h - 1]) != key_set(kk)) seg = h;
-            while (h - seg >= 2 && sg * korient(st[h - 2], st[h - 1], kk) <= 0) h--;
-            st[h++] = kk;
-        }
+    for (int i = 0; i < 4; i++) {
+        if (cl[i]) L.list[0][0][pl++] = k[i];
+        if (cu[i]) L.list[1][0][pu++] = k[i];
     }
     wave_sync();
-    const int hl = __builtin_amdgcn_readlane(h, 0), hu = __builtin_amdgcn_readlane(h, 1);
-    for (int i = lane; i < hl; i += WAVE) lo[a + i] = L.stk[0][i];
-    for (int i = lane; i < hu; i += WAVE) up[a + i] = L.stk[1][i];
+    int cur = 0, pass = 0;
+    bool moved = true;
+    for (; moved && pass < PRUNE_PASSES; pass++) {
+        const int ml = prune_pass<false>(L.list[0][cur], L.list[0][1 - cur], nl, lt);
+        const int mu = prune_pass<true>(L.list[1][cur], L.list[1][1 - cur], nu, lt);
+        moved = ml != nl || mu != nu;
+        nl = ml;
+        nu = mu;
+        cur = 1 - cur;
+        wave_sync();
+    }
+    if (moved) {      // passes ran out: finish serially (lane 0 lower, lane 1 upper)
+        int h = 0;
+        if (lane == 0) h = serial_chain<false>(L.list[0][cur], nl);
+        if (lane == 1) h = serial_chain<true>(L.list[1][cur], nu);
+        wave_sync();
+        nl = __builtin_amdgcn_readlane(h, 0);
+        nu = __builtin_amdgcn_readlane(h, 1);
+    }
+    for (int i = lane; i < nl; i += WAVE) lo[a + i] = L.list[0][cur][i];
+    for (int i = lane; i < nu; i += WAVE) up[a + i] = L.list[1][cur][i];
     if (lane == 0) {
-        lo_cnt[j] = (uint32_t)hl;
-        up_cnt[j] = (uint32_t)hu;
+        lo_cnt[j] = (uint32_t)nl;
+        up_cnt[j] = (uint32_t)nu;
     }
     wave_sync();       // the next chunk reuses the wave's LDS
     }
@@ -250,9 +318,10 @@ __device__ __forceinline__ int64_t bridge(PO o, int64_t len, int64_t tailseg, PC
     return len;
 }
 
-// Merge of CHAIN_G neighbouring chains by one wave.  Small groups are staged
-// in LDS (walks at LDS latency); larger ones walk in global memory.
-constexpr int MERGE_CAP = 1024;
+// Merge of CHAIN_G neighbouring chains by one wave.  Groups that fit are
+// staged in LDS and pruned in parallel (serial chain only when the passes run
+// out); larger ones walk the junction bridges in global memory.
+constexpr int MERGE_CAP = 4096;           // keys staged per wave (32 KB)
 
 template <bool UPPER>
 __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__restrict__ cin,
@@ -268,35 +337,30 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
     const int64_t M = __shfl(incl, WAVE - 1);
     int64_t len = 0, tailseg = 0;
     if (M <= MERGE_CAP) {
+        // the group's chains side by side form one x-sorted list holding every
+        // vertex of the merged chain: prune it in place like a level-0 chunk
         for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
             const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
             const uint64_t *src = in + (u0 + g) * R;
             for (int64_t i = lane; i < m; i += WAVE) buf[og + i] = src[i];
         }
         wave_sync();
-        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
-            const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
-            if (m == 0) continue;
-            const uint64_t *c = buf + og;
-            int64_t b;
-            len = bridge<UPPER>(buf, len, tailseg, c, m, &b);
-            if (b < m) {
-                int64_t ls = last_seg_start(c, b, m);
-                int64_t newtail;
-                if (ls > b) newtail = len + (ls - b);
-                else newtail = (len > 0 && key_set(buf[len - 1]) == key_set(c[b])) ? tailseg : len;
-                // move c[b..m) down to buf[len..): len <= og + b, copy forward
-                for (int64_t i0 = 0; i0 < m - b; i0 += WAVE) {
-                    int64_t i = i0 + lane;
-                    uint64_t val = i < m - b ? c[b + i] : 0;
-                    wave_sync();
-                    if (i < m - b) buf[len + i] = val;
-                    wave_sync();
-                }
-                len += m - b;
-                tailseg = newtail;
-            }
+        const uint64_t lt = lanemask_lt();
+        int n = (int)M;
+        bool moved = true;
+        for (int pass = 0; moved && pass < PRUNE_PASSES; pass++) {
+            const int m2 = prune_pass<UPPER>(buf, buf, n, lt);
+            moved = m2 != n;
+            n = m2;
+            wave_sync();
         }
+        if (moved) {      // passes ran out: finish serially
+            int h = 0;
+            if (lane == 0) h = serial_chain<UPPER>(buf, n);
+            wave_sync();
+            n = __builtin_amdgcn_readlane(h, 0);
+        }
+        len = n;
         for (int64_t i = lane; i < len; i += WAVE) o[i] = buf[i];
     } else {
         for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
@@ -482,6 +546,13 @@ __global__ __launch_bounds__(256) void k_gather_keys(const float *__restrict__ x
         uint64_t ky = (uint64_t)(uint32_t)(y[j] * GRIDF);
         keys[i] = (kx << 24) | ky;
     }
+}
+
+// Before a computation: the recorded stage counts to -1 (stages that do not
+// run keep it) and the discard pass's segment counts to 0.
+__global__ void k_counts_init(int64_t *__restrict__ c, int n, int64_t *__restrict__ seg0) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = -1;
+    if (blockIdx.x == 0 && (int)threadIdx.x < NSEG) seg0[threadIdx.x] = 0;
 }
 
 __global__ void k_copy_count(const int64_t *__restrict__ src, int64_t *__restrict__ dst) {

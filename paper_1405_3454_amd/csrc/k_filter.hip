@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_tile_sets(const int64_t *__restrict__ t
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of uint32 counts into int64 offsets, with the
 // element count read from device memory (*cnt_ptr).  out has count+1 entries;
-// out[count] = total.  Three launches with a fixed grid of SCAN_BLOCKS.
+// out[count] = total.  Two launches with a fixed grid of SCAN_BLOCKS.
 constexpr int SCAN_BLOCKS = 256;
 constexpr int SCAN_THREADS = 1024;
 
@@ -78,28 +78,47 @@ __device__ __forceinline__ void scan_segment(int64_t count, int64_t b, int64_t *
     *hi = min(count, *lo + seg);
 }
 
+// Blocks whose segment is not empty: 0 .. scan_busy(count) - 1.
+__device__ __forceinline__ int scan_busy(int64_t count) {
+    int64_t seg = (count + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    seg = (seg + SCAN_THREADS - 1) / SCAN_THREADS * SCAN_THREADS;
+    return seg ? (int)((count + seg - 1) / seg) : 0;
+}
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
                                                               const int64_t *__restrict__ cnt_ptr,
-                                                              int64_t *__restrict__ block_sums) {
+                                                              int64_t *__restrict__ block_sums,
+                                                              int64_t *__restrict__ out,
+                                                              uint32_t *__restrict__ ticket) {
     __shared__ int64_t sh[17];
+    __shared__ bool last;
     int64_t count = *cnt_ptr, lo, hi;
+    const int nbusy = scan_busy(count);
+    if ((int)blockIdx.x >= nbusy) {    // empty segment: only the empty scan writes
+        if (nbusy == 0 && blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+        return;
+    }
     scan_segment(count, blockIdx.x, &lo, &hi);
     int64_t acc = 0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += in[i];
     int64_t tot;
     block_excl_scan_i64(acc, sh, &tot);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_blocks(int64_t *__restrict__ block_sums,
-                                                              const int64_t *__restrict__ cnt_ptr,
-                                                              int64_t *__restrict__ out) {
-    __shared__ int64_t sh[17];
-    int64_t v = threadIdx.x < SCAN_BLOCKS ? block_sums[threadIdx.x] : 0;
-    int64_t tot;
+    // the last block to finish (ticket, self-resetting) scans the block sums
+    if (threadIdx.x == 0) {
+        block_sums[blockIdx.x] = tot;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == (uint32_t)nbusy - 1;
+        if (last) __threadfence();
+    }
+    __syncthreads();
+    if (!last) return;
+    int64_t v = (int)threadIdx.x < nbusy ? block_sums[threadIdx.x] : 0;
     int64_t ex = block_excl_scan_i64(v, sh, &tot);
     if (threadIdx.x < SCAN_BLOCKS) block_sums[threadIdx.x] = ex;
-    if (threadIdx.x == 0) out[*cnt_ptr] = tot;
+    if (threadIdx.x == 0) {
+        out[count] = tot;
+        *ticket = 0;
+    }
 }
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const uint32_t *__restrict__ in,
@@ -783,9 +802,20 @@ __global__ __launch_bounds__(256) void k_polygon(
 // inside), quick reject (outside the row's x-extent or the polygon's y-range:
 // a survivor), or undecided.  Undecided points go to a per-wave queue and are
 // tested exactly, in full 64-lane batches, against the edges that meet their
-// row.  Output per tile: survivor mask words (word 4c + j, bit l = point
-// c*256 + 4l + j of the tile) and the survivor count.
+// row.  Output (MODE):
+//  - DISCARD_MASKS: per tile, survivor mask words (word 4c + j, bit l = point
+//    c*256 + 4l + j of the tile) and the survivor count, for the ordered
+//    scatter;
+//  - DISCARD_APPEND: each tile's survivors (index, key) appended at once to
+//    segment (wave mod NSEG) of the survivor list, one atomic per tile
+//    reserving their range (the hull stage does not need index order: it
+//    sorts by key, and maps keys back to the lowest index);
+//  - DISCARD_ASSIGN: as APPEND, and each survivor also gets the first
+//    polygon edge it is strictly outside of (RE_NONE: on the boundary), with
+//    the farthest-point key of every edge raised: the refinement's round-0
+//    state, taken while the points are still in registers.
 constexpr int QCAP = 320;
+constexpr int DISCARD_MASKS = 0, DISCARD_APPEND = 1, DISCARD_ASSIGN = 2;
 constexpr int EDGE_SLOTS = 32;        // edge arrays in LDS; slots >= m hold (0, 0, 1)
 
 struct DiscardLds {
@@ -794,7 +824,21 @@ struct DiscardLds {
     double ex[EDGE_SLOTS], ey[EDGE_SLOTS], c[EDGE_SLOTS];
     uint64_t q[QCAP];                 // kx | ky << 24 | pos << 48
     unsigned long long mask[TILE_WORDS];
+    unsigned long long far[MAX_SLOTS];  // DISCARD_ASSIGN: farthest-point keys of the set's edges
 };
+
+// Raise the global farthest-point keys of set s's edges from the wave's
+// copies, and clear those.
+__device__ __forceinline__ void far_flush(DiscardLds &L, unsigned long long *gfar, int64_t s) {
+    const int lane = lane_id();
+    wave_sync();
+    if (lane < MAX_SLOTS) {
+        const unsigned long long v = L.far[lane];
+        if (v) far_update(&gfar[s * RE_CAP + lane], v);
+        L.far[lane] = 0;
+    }
+    wave_sync();
+}
 
 __device__ __forceinline__ bool edge_in(const DiscardLds &L, uint32_t e, double px, double py) {
     return edge_eval(L.ex[e], L.ey[e], L.c[e], px, py) > 0;
@@ -838,13 +882,15 @@ __device__ __forceinline__ uint32_t row0_sum_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
 }
 
-template <int NEDGE>
-__global__ __launch_bounds__(256) void k_discard(
+template <int NEDGE, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_discard(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int phase,
     const int64_t *__restrict__ off, int64_t n1, int64_t S, const int64_t *__restrict__ tile_off,
     const int32_t *__restrict__ tile_set, const Poly *__restrict__ polys,
     const Span *__restrict__ spans, const uint32_t *__restrict__ redges,
-    uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt) {
+    uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ surv,
+    uint64_t *__restrict__ keys, uint16_t *__restrict__ edges,
+    unsigned long long *__restrict__ seg_cnt, int64_t segcap, unsigned long long *__restrict__ gfar) {
     __shared__ DiscardLds lds[4];
     DiscardLds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
@@ -855,8 +901,8 @@ __global__ __launch_bounds__(256) void k_discard(
     const int64_t t0 = wave * q, t1 = min(t0 + q, T);
     if (t0 >= t1) return;
 
-    int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1;
-    int32_t ky_lo = 0, shift = 0, ymin = 0;
+    int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1, cur_s = -1;
+    int32_t ky_lo = 0, shift = 0, ymin = 0, pm = 0;
     uint32_t ylim = 0;          // in the rows: (ky - ky_lo) <= ylim (unsigned)
     uint32_t yext = 0;          // in the polygon's y-range: (ky - ymin) <= yext
     bool has_rows = false;
@@ -864,6 +910,11 @@ __global__ __launch_bounds__(256) void k_discard(
     for (int64_t t = t0; t < t1; ++t) {
         if (t >= cur_end) {     // a new set starts (looked up once per set)
             const int64_t s = __builtin_amdgcn_readfirstlane(tile_set[t]);
+            if (MODE == DISCARD_ASSIGN) {
+                if (cur_s >= 0) far_flush(L, gfar, cur_s);
+                else if (lane < MAX_SLOTS) L.far[lane] = 0;
+            }
+            cur_s = s;
             cur_end = tile_off[s + 1];
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
@@ -874,6 +925,7 @@ __global__ __launch_bounds__(256) void k_discard(
             has_rows = P->yspan >= 0;
             ylim = (uint32_t)max(P->yspan, 0);
             shift = P->shift;
+            pm = P->m;
             ymin = P->ymin;
             yext = (uint32_t)(P->ymax - P->ymin);
             if (!has_rows) {     // nothing strictly inside: every point is outside
@@ -962,19 +1014,101 @@ __global__ __launch_bounds__(256) void k_discard(
                 }
                 wave_sync();
             }
+            if (qn > 0) drain<NEDGE>(L, 0, qn, ky_lo, shift, ylim);
+            wave_sync();
+            if constexpr (MODE != DISCARD_MASKS) {
+                // append the tile's survivors: positions compacted into the
+                // (now empty) queue, then 64 at a time with their coordinates
+                // loaded again (the tile was just read: cache hits), so the
+                // epilogue holds no point registers across the tile
+                int tc = 0;
+#pragma unroll
+                for (int w = 0; w < TILE_WORDS; w++) tc += __popcll(L.mask[w]);
+                if (tc > 0) {
+                    const int seg = (int)(wave & (NSEG - 1));
+                    unsigned long long b0 = 0;
+                    if (lane == 0) b0 = atomicAdd(&seg_cnt[seg], (unsigned long long)tc);
+                    uint16_t *plist = reinterpret_cast<uint16_t *>(L.q);   // >= TILE slots
+                    const uint64_t lt = lanemask_lt();
+                    int done = 0;
+#pragma unroll
+                    for (int c = 0; c < TILE_CHUNKS; c++) {
+                        uint64_t M[4];
+                        int pre = 0, tot = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            M[j] = L.mask[c * 4 + j];
+                            pre += __popcll(M[j] & lt);
+                            tot += __popcll(M[j]);
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            if ((M[j] >> lane) & 1)
+                                plist[done + pre++] = (uint16_t)(c * CHUNK + 4 * lane + j);
+                        done += tot;
+                    }
+                    wave_sync();
+                    const int64_t base = seg * segcap +
+                        (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(b0 >> 32), 0) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b0, 0));
+                    for (int b = 0; b < tc; b += WAVE) {
+                        const int i = b + lane;
+                        if (i < tc) {
+                            const int64_t gi = tb + plist[i];
+                            const int32_t kx = (int32_t)(x[gi] * GRIDF);
+                            const int32_t ky = (int32_t)(y[gi] * GRIDF);
+                            const int64_t pp = base + i;
+                            surv[pp] = (uint32_t)gi;
+                            keys[pp] = ((uint64_t)cur_s << 48) | ((uint64_t)(uint32_t)kx << 24) |
+                                       (uint64_t)(uint32_t)ky;
+                            if constexpr (MODE == DISCARD_ASSIGN) {
+                                // first edge strictly outside: the row's (at most
+                                // four) edges decide for points of the rows
+                                uint16_t e_out = RE_NONE;
+                                double dist = 0.0;
+                                if (pm >= 3) {
+                                    const double px = (double)kx, py = (double)ky;
+                                    const uint32_t dyv = (uint32_t)(ky - ky_lo);
+                                    const uint32_t re = dyv <= ylim ? L.redge[dyv >> shift] : ROW_EDGES_ALL;
+                                    if (re != ROW_EDGES_ALL) {
+#pragma unroll
+                                        for (int q4 = 0; q4 < 4; q4++) {
+                                            const int e = (re >> (8 * q4)) & 0xFF;
+                                            const double E = edge_eval(L.ex[e], L.ey[e], L.c[e], px, py);
+                                            if (E < 0 && e_out == RE_NONE) { e_out = (uint16_t)e; dist = -E; }
+                                        }
+                                    } else {
+                                        for (int e = 0; e < pm; e++) {
+                                            const double E = edge_eval(L.ex[e], L.ey[e], L.c[e], px, py);
+                                            if (E < 0) { e_out = (uint16_t)e; dist = -E; break; }
+                                        }
+                                    }
+                                }
+                                edges[pp] = e_out;
+                                if (e_out != RE_NONE) {
+                                    const uint64_t fk = far_key(dist, (uint32_t)gi);
+                                    if (L.far[e_out] < fk) atomicMax(&L.far[e_out], (unsigned long long)fk);
+                                }
+                            }
+                        }
+                    }
+                    wave_sync();     // the queue is reused by the next tile
+                }
+            }
         };
         if (tb >= o0 && tb + TILE <= o1)
             tile(std::integral_constant<bool, true>());
         else
             tile(std::integral_constant<bool, false>());
-        if (qn > 0) drain<NEDGE>(L, 0, qn, ky_lo, shift, ylim);
-        wave_sync();
-        const uint64_t mw = lane < TILE_WORDS ? L.mask[lane] : 0;
-        const uint32_t cnt = row0_sum_u32((uint32_t)__popcll(mw));
-        if (cnt > 0 && lane < TILE_WORDS) masks[t * TILE_WORDS + lane] = mw;
-        if (lane == 0) tile_cnt[t] = cnt;
+        if constexpr (MODE == DISCARD_MASKS) {
+            const uint64_t mw = lane < TILE_WORDS ? L.mask[lane] : 0;
+            const uint32_t cnt = row0_sum_u32((uint32_t)__popcll(mw));
+            if (cnt > 0 && lane < TILE_WORDS) masks[t * TILE_WORDS + lane] = mw;
+            if (lane == 0) tile_cnt[t] = cnt;
+        }
         wave_sync();
     }
+    if (MODE == DISCARD_ASSIGN) far_flush(L, gfar, cur_s);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,17 +2,18 @@
 // shrink the survivor list before the sort and the monotone chain.
 //
 // Every survivor of Step 3 lies outside the filter polygon or on its
-// boundary.  Round 0 assigns each survivor to an edge of the polygon that it
-// lies strictly outside of (points on the boundary are kept and never looked
-// at again).  Each round then, for every edge a->b, takes an outside point f
+// boundary.  The discard pass assigns each survivor to an edge of the polygon
+// that it lies strictly outside of (points on the boundary are kept and never
+// looked at again).  Each round then, for every edge a->b, takes an outside point f
 // of (close to) the largest distance from the edge's line, and replaces the
 // edge by a->f and f->b; a point of the edge strictly inside the triangle
 // (a, f, b) is dropped (the triangle's corners are points of the set, so such
 // a point is strictly inside the hull), a point outside a->f or f->b moves to
 // that edge.  Nothing depends on f being the exact farthest point: only the
-// drops change the work, never the hull.  The survivors stay in ascending
-// index order within each set, so the hull's lowest-index representatives of
-// repeated coordinates are the ones the chain finds.
+// drops change the work, never the hull.  Repeated coordinates share every
+// test, so all copies of a point stay or go together, and the hull stage picks
+// the lowest index among them whatever order the kept survivors are in: each
+// round appends them with one atomic allocation per chunk.
 //
 // Distances are exact edge functions in grid units (binary64, |E| < 2^52 on
 // the grid); the farthest point per edge is the maximum of the packed key
@@ -22,13 +23,9 @@
 
 namespace hg {
 
-constexpr int REF_ROUNDS = 4;
-constexpr int RE_CAP = MAX_SLOTS << REF_ROUNDS;   // edge slots per set and round
-constexpr int REF_CH = 2048;                      // survivors per compaction chunk
+constexpr int REF_CH = 2048;                      // survivors per block step
 constexpr int REF_THREADS = 256;
 constexpr int REF_PER_THREAD = REF_CH / REF_THREADS;
-constexpr uint16_t RE_NONE = 0xFFFF;              // kept, not assigned to an edge
-constexpr uint16_t RE_DROP = 0xFFFE;              // strictly inside the hull
 
 struct REdge {
     int32_t ax, ay, bx, by;                       // grid units; ax == INT32_MIN: empty slot
@@ -42,15 +39,6 @@ __device__ __forceinline__ double redge_eval(const REdge &e, double px, double p
     const double ex = (double)e.bx - ax, ey = (double)e.by - ay;
     const double c = fma(ey, ax, -(ex * ay));
     return fma(ex, py, fma(-ey, px, c));
-}
-
-__device__ __forceinline__ uint64_t far_key(double dist, uint32_t idx) {
-    return ((uint64_t)__float_as_uint((float)dist) << 32) | (uint64_t)(~idx);
-}
-
-// Raise *slot to key unless it already holds at least as much.
-__device__ __forceinline__ void far_update(unsigned long long *slot, uint64_t key) {
-    if (*reinterpret_cast<volatile unsigned long long *>(slot) < key) atomicMax(slot, key);
 }
 
 __device__ __forceinline__ void key_point(uint64_t k, int64_t *s, double *px, double *py) {
@@ -82,14 +70,23 @@ __global__ __launch_bounds__(64) void k_ref_init(const float *__restrict__ x,
 
 // Split every edge of round r at its farthest outside point: children 2e
 // (a->f) and 2e+1 (f->b); an edge without outside points keeps itself as
-// child 2e.  Clears the next round's farthest-point keys.
+// child 2e.  Clears the next round's farthest-point keys and the segment
+// counts the round's pass appends to, and records the round's input total.
 __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
                                                    const float *__restrict__ y, int64_t S, int er,
                                                    const REdge *__restrict__ tab,
                                                    const unsigned long long *__restrict__ far,
                                                    REdge *__restrict__ tab_nxt,
-                                                   unsigned long long *__restrict__ far_nxt) {
+                                                   unsigned long long *__restrict__ far_nxt,
+                                                   const int64_t *__restrict__ cnt_in,
+                                                   int64_t *__restrict__ cnt_nxt,
+                                                   int64_t *__restrict__ total_in) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < NSEG) {
+        cnt_nxt[t] = 0;
+        const int64_t v = wave_sum_i64(cnt_in[t]);
+        if (t == 0) *total_in = v;
+    }
     if (t >= S * er) return;
     const int64_t s = t / er;
     const int e = (int)(t % er);
@@ -112,11 +109,6 @@ __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
     far_nxt[s * RE_CAP + 2 * e + 1] = 0;
 }
 
-// Number of compaction chunks for the current survivor count.
-__global__ void k_ref_nchunks(const int64_t *__restrict__ cnt_ptr, int64_t *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = (*cnt_ptr + REF_CH - 1) / REF_CH;
-}
-
 // Farthest-point keys of a chunk: when the whole chunk belongs to one set,
 // the block keeps them in LDS (ds_max_u64) and raises the global slots once
 // per edge at the end; otherwise every point goes to the global slot.
@@ -133,51 +125,60 @@ __device__ __forceinline__ void far_put(bool local, RefFar &L, unsigned long lon
     }
 }
 
-// One pass over the survivors in chunks of REF_CH (thread t holds elements
-// t * REF_PER_THREAD ...).  ASSIGN (round 0): each survivor goes to the first
-// filter-polygon edge it is strictly outside of (RE_NONE: on the boundary).
-// Otherwise: each survivor is classified against the two children of its
-// edge (state written in place: RE_DROP, RE_NONE or the new edge id) and the
-// kept ones are counted per chunk.  Either way the farthest-point key of each
-// (new) edge is raised.
-template <bool ASSIGN>
+// Chunks of REF_CH entries of a segmented list: prefix of the per-segment
+// chunk counts (NSEG + 1 entries, computed by the block's first wave).
+__device__ __forceinline__ void seg_chunks(const int64_t *__restrict__ cnt, int64_t *pre) {
+    if (threadIdx.x < WAVE) {
+        const int64_t nc = (cnt[threadIdx.x] + REF_CH - 1) / REF_CH;
+        const int64_t inc = wave_incl_scan_i64(nc);
+        pre[threadIdx.x] = inc - nc;
+        if (threadIdx.x == WAVE - 1) pre[NSEG] = inc;
+    }
+    __syncthreads();
+}
+
+// Exclusive prefix of the segment counts themselves (NSEG + 1 entries).
+__device__ __forceinline__ void seg_prefix(const int64_t *__restrict__ cnt, int64_t *pre) {
+    if (threadIdx.x < WAVE) {
+        const int64_t v = cnt[threadIdx.x];
+        const int64_t inc = wave_incl_scan_i64(v);
+        pre[threadIdx.x] = inc - v;
+        if (threadIdx.x == WAVE - 1) pre[NSEG] = inc;
+    }
+    __syncthreads();
+}
+
+// Segment of chunk c: the last i with pre[i] <= c (one ballot per wave).
+__device__ __forceinline__ int seg_of(const int64_t *pre, int64_t c) {
+    const uint64_t m = __ballot(pre[lane_id()] <= c);
+    return 63 - __clzll((long long)m);
+}
+
+// One round over the survivors, a chunk of REF_CH entries of one segment per
+// block step (thread t holds entries t * REF_PER_THREAD ...).  Each survivor
+// is classified against the two children of its edge (RE_DROP, RE_NONE or the
+// new edge id); the kept ones are appended to segment (chunk mod NSEG) of the
+// next list, the block's kept count reserving their range with one atomic.
+// The farthest-point key of each new edge is raised.  (Round 0's edge states
+// come from the discard pass.)
 __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
-    const int64_t *__restrict__ cnt_ptr, uint16_t *__restrict__ edge,
-    const Poly *__restrict__ polys, const uint32_t *__restrict__ redges,
+    const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int64_t segcap,
     const REdge *__restrict__ tab_nxt, unsigned long long *__restrict__ far,
-    uint32_t *__restrict__ chunk_cnt) {
+    uint32_t *__restrict__ idx_out, uint64_t *__restrict__ keys_out,
+    uint16_t *__restrict__ edge_out, unsigned long long *__restrict__ cnt_out) {
+    static_assert(NSEG == WAVE, "segment lookups use one lane per segment");
     __shared__ RefFar L;
-    __shared__ double pex[ROW_EDGE_NONE + 1], pey[ROW_EDGE_NONE + 1], pc[ROW_EDGE_NONE + 1];
-    __shared__ uint32_t lre[SPAN_ROWS];     // the set's row edge lists (Step 3's rows)
-    __shared__ int pm, pky, pyl, psh;
-    __shared__ uint32_t wsum[REF_THREADS / WAVE];
-    const int64_t cnt = *cnt_ptr;
-    const int64_t nch = (cnt + REF_CH - 1) / REF_CH;
+    __shared__ int64_t scan_sh[17];
+    __shared__ int64_t pre[NSEG + 1];
+    __shared__ unsigned long long out_base;
     const int tid = threadIdx.x;
+    seg_chunks(cnt_in, pre);
+    const int64_t nch = pre[NSEG];
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int64_t jb = c * REF_CH, je = min(cnt, jb + REF_CH);
-        const int64_t s0 = (int64_t)(keys[jb] >> 48), s1 = (int64_t)(keys[je - 1] >> 48);
-        const bool local = s0 == s1;
-        if (local) {
-            for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
-            if (ASSIGN) {
-                const Poly &P = polys[s0];
-                if (tid <= ROW_EDGE_NONE) {    // unused slots: an always-satisfied edge
-                    pex[tid] = tid < MAX_SLOTS ? P.ex[tid] : 0.0;
-                    pey[tid] = tid < MAX_SLOTS ? P.ey[tid] : 0.0;
-                    pc[tid] = tid < MAX_SLOTS ? P.c[tid] : 1.0;
-                }
-                for (int r = tid; r < SPAN_ROWS; r += REF_THREADS) lre[r] = redges[s0 * SPAN_ROWS + r];
-                if (tid == 0) {
-                    pm = P.m >= 3 ? P.m : 0;
-                    pky = P.ky_lo;
-                    pyl = P.yspan;
-                    psh = P.shift;
-                }
-            }
-        }
-        __syncthreads();
+        const int sg = seg_of(pre, c);
+        const int64_t jb = sg * segcap + (c - pre[sg]) * REF_CH;
+        const int64_t je = min(sg * segcap + cnt_in[sg], jb + REF_CH);
         const int64_t j0 = jb + (int64_t)tid * REF_PER_THREAD;
         uint64_t k[REF_PER_THREAD];
         uint16_t st[REF_PER_THREAD];
@@ -185,9 +186,20 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
         for (int i = 0; i < REF_PER_THREAD; i++) {
             const bool in = j0 + i < je;
             k[i] = in ? keys[j0 + i] : 0;
-            st[i] = in ? (ASSIGN ? (uint16_t)0 : edge[j0 + i]) : RE_DROP;
+            st[i] = in ? edge[j0 + i] : RE_DROP;
         }
-        uint32_t kept = 0;
+        // one set in the whole chunk?  (survivors of different sets can
+        // interleave, so both ends alone do not tell)
+        const int64_t s0 = (int64_t)(keys[jb] >> 48);
+        bool same = true;
+#pragma unroll
+        for (int i = 0; i < REF_PER_THREAD; i++)
+            same = same && (j0 + i >= je || (int64_t)(k[i] >> 48) == s0);
+        const bool local = __syncthreads_and(same) != 0;
+        if (local)
+            for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
+        __syncthreads();
+        int kept = 0;
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
             if (st[i] == RE_DROP) continue;
@@ -196,36 +208,7 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             key_point(k[i], &s, &px, &py);
             uint16_t out = RE_NONE;
             double dist = 0.0;
-            if (ASSIGN) {
-                if (local) {
-                    // a point of a row is strictly outside the polygon iff it is
-                    // strictly outside one of the (at most four) edges meeting
-                    // the row; points outside the rows try every edge
-                    const uint32_t dy = (uint32_t)((int32_t)py - pky);
-                    const uint32_t re = (pm > 0 && pyl >= 0 && dy <= (uint32_t)pyl) ? lre[dy >> psh]
-                                                                                 : ROW_EDGES_ALL;
-                    if (re != ROW_EDGES_ALL) {
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            const int e = (re >> (8 * q)) & 0xFF;
-                            const double E = edge_eval(pex[e], pey[e], pc[e], px, py);
-                            if (E < 0 && out == RE_NONE) { out = (uint16_t)e; dist = -E; }
-                        }
-                    } else {
-                        for (int e = 0; e < pm; e++) {
-                            const double E = edge_eval(pex[e], pey[e], pc[e], px, py);
-                            if (E < 0) { out = (uint16_t)e; dist = -E; break; }
-                        }
-                    }
-                } else {
-                    const Poly &P = polys[s];
-                    const int m = P.m >= 3 ? P.m : 0;
-                    for (int e = 0; e < m; e++) {
-                        const double E = edge_eval(P.ex[e], P.ey[e], P.c[e], px, py);
-                        if (E < 0) { out = (uint16_t)e; dist = -E; break; }
-                    }
-                }
-            } else if (st[i] != RE_NONE) {
+            if (st[i] != RE_NONE) {
                 const REdge c0 = tab_nxt[s * RE_CAP + 2 * st[i]];
                 const REdge c1 = tab_nxt[s * RE_CAP + 2 * st[i] + 1];
                 if (c1.ax == INT32_MIN) {            // edge without a split point
@@ -239,14 +222,22 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
                 }
             }
             if (out != RE_NONE && out != RE_DROP) far_put(local, L, far, s, out, far_key(dist, idx[j0 + i]));
-            if (ASSIGN || st[i] != RE_NONE) edge[j0 + i] = out;
+            st[i] = out;
             kept += out != RE_DROP;
         }
-        if (!ASSIGN) {
-            uint32_t v = kept;
+        const int og = (int)(c & (NSEG - 1));
+        int64_t tot;
+        int64_t pos = block_excl_scan_i64(kept, scan_sh, &tot);
+        if (tid == 0) out_base = tot ? atomicAdd(&cnt_out[og], (unsigned long long)tot) : 0;
+        __syncthreads();
+        pos += og * segcap + (int64_t)out_base;
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-            if (lane_id() == 0) wsum[tid >> 6] = v;
+        for (int i = 0; i < REF_PER_THREAD; i++) {
+            if (st[i] == RE_DROP) continue;
+            idx_out[pos] = idx[j0 + i];
+            keys_out[pos] = k[i];
+            edge_out[pos] = st[i];
+            pos++;
         }
         __syncthreads();
         if (local)
@@ -254,56 +245,30 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
                 const unsigned long long v = L.v[e];
                 if (v) far_update(&far[s0 * RE_CAP + e], v);
             }
-        if (!ASSIGN && tid == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < REF_THREADS / WAVE; w++) t += wsum[w];
-            chunk_cnt[c] = t;
-        }
         __syncthreads();
     }
 }
 
-// Order-preserving compaction of the kept survivors into the next arrays.
-__global__ __launch_bounds__(REF_THREADS) void k_ref_compact(
-    const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
-    const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_ptr,
-    const int64_t *__restrict__ chunk_pos, uint32_t *__restrict__ idx_nxt,
-    uint64_t *__restrict__ keys_nxt, uint16_t *__restrict__ edge_nxt) {
-    __shared__ int64_t sh[REF_THREADS / WAVE + 1];
-    const int64_t cnt = *cnt_ptr;
-    const int64_t nch = (cnt + REF_CH - 1) / REF_CH;
-    const int tid = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int64_t j0 = c * REF_CH + (int64_t)tid * REF_PER_THREAD;
-        uint16_t st[REF_PER_THREAD];
-        uint64_t k[REF_PER_THREAD];
-        uint32_t ix[REF_PER_THREAD];
-        int kept = 0;
-#pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++) {
-            st[i] = (j0 + i < cnt) ? edge[j0 + i] : RE_DROP;
-            const bool keep = st[i] != RE_DROP;
-            k[i] = keep ? keys[j0 + i] : 0;
-            ix[i] = keep ? idx[j0 + i] : 0;
-            kept += keep;
-        }
-        int64_t tot;
-        int64_t pos = chunk_pos[c] + block_excl_scan_i64(kept, sh, &tot);
-#pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++) {
-            if (st[i] == RE_DROP) continue;
-            idx_nxt[pos] = ix[i];
-            keys_nxt[pos] = k[i];
-            edge_nxt[pos] = st[i];
-            pos++;
-        }
+// Segmented list (idx, keys) -> contiguous arrays; *total_out = entries.
+// Block b copies segment b mod NSEG, entries (b / NSEG) * 256 + t, stepping
+// by the blocks per segment.
+__global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__ idx,
+                                                    const uint64_t *__restrict__ keys,
+                                                    const int64_t *__restrict__ cnt, int64_t segcap,
+                                                    uint32_t *__restrict__ idx_out,
+                                                    uint64_t *__restrict__ keys_out,
+                                                    int64_t *__restrict__ total_out) {
+    __shared__ int64_t pre[NSEG + 1];
+    seg_prefix(cnt, pre);
+    const int sg = (int)(blockIdx.x % NSEG);
+    const int64_t per = gridDim.x / NSEG;
+    const int64_t n = cnt[sg], dst = pre[sg], src = sg * segcap;
+    for (int64_t i = (int64_t)(blockIdx.x / NSEG) * blockDim.x + threadIdx.x; i < n;
+         i += per * blockDim.x) {
+        idx_out[dst + i] = idx[src + i];
+        keys_out[dst + i] = keys[src + i];
     }
-}
-
-// Survivor count after a round: the chunk scan's total.
-__global__ void k_ref_total(const int64_t *__restrict__ chunk_pos,
-                            const int64_t *__restrict__ nch_ptr, int64_t *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = chunk_pos[*nch_ptr];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total_out = pre[NSEG];
 }
 
 }  // namespace hg

@@ -4,11 +4,11 @@
 //
 // Decomposition: SORT_BLOCKS persistent blocks; block b owns the contiguous
 // key tiles [b qq, (b+1) qq) of SORT_TILE keys.  Per pass: (1) per-block digit
-// histograms, (2) exclusive scan of the digit-major table hist[d][b],
-// (3) scatter: each block walks its tiles in order and ranks keys stably with
-// wave ballots (peers = lanes with the same digit) plus per-wave digit counts
-// in LDS, so equal digits keep their input order across lanes, waves, rounds
-// and blocks.
+// histograms, after which the last block to finish scans the digit-major
+// table hist[d][b] (only the blocks that hold keys), (2) scatter: each block
+// walks its tiles in order and ranks keys stably with wave ballots (peers =
+// lanes with the same digit) plus per-wave digit counts in LDS, so equal
+// digits keep their input order across lanes, waves, rounds and blocks.
 #include "hg_device.h"
 
 namespace hg {
@@ -26,18 +26,76 @@ __device__ __forceinline__ void sort_range(int64_t count, int64_t b, int64_t *lo
     *hi = min(count, (b + 1) * qq * SORT_TILE);
 }
 
+// Blocks of sort_range that hold keys: 0 .. sort_busy(count) - 1.
+__device__ __forceinline__ int64_t sort_busy(int64_t count) {
+    const int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
+    const int64_t qq = (tiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
+    return qq ? (tiles + qq - 1) / qq : 0;
+}
+
+// Per-block digit histograms of the blocks that hold keys; the last of them
+// to finish (ticket, self-resetting) turns them into the exclusive offsets
+// hoff[d][b] of the stable scatter.  Blocks without keys leave at once (the
+// scatter does not read their offsets).
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__restrict__ keys,
                                                             const int64_t *__restrict__ cnt_ptr,
-                                                            int shift, uint32_t *__restrict__ hist) {
+                                                            int shift, uint32_t *__restrict__ hist,
+                                                            int64_t *__restrict__ hoff,
+                                                            uint32_t *__restrict__ ticket) {
     __shared__ uint32_t h[RADIX];
-    h[threadIdx.x] = 0;
+    __shared__ int64_t scan_sh[17];
+    __shared__ bool last;
+    const int tid = threadIdx.x;
+    const int64_t count = *cnt_ptr;
+    const int nb = (int)sort_busy(count);
+    if ((int)blockIdx.x >= nb) return;   // no keys: nothing to count or scan
+    h[tid] = 0;
     __syncthreads();
     int64_t lo, hi;
-    sort_range(*cnt_ptr, blockIdx.x, &lo, &hi);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += SORT_THREADS)
+    sort_range(count, blockIdx.x, &lo, &hi);
+    for (int64_t i = lo + tid; i < hi; i += SORT_THREADS)
         atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
     __syncthreads();
-    hist[threadIdx.x * SORT_BLOCKS + blockIdx.x] = h[threadIdx.x];
+    hist[tid * SORT_BLOCKS + blockIdx.x] = h[tid];
+    __syncthreads();
+    if (tid == 0) {    // one device-scope fence per block publishes the block's row
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == (uint32_t)nb - 1;
+        if (last) __threadfence();
+    }
+    __syncthreads();
+    if (!last) return;
+    // thread d: the row of digit d over the busy blocks
+    // (eight independent loads per step keep the walk off the load latency)
+    const uint32_t *row = hist + (int64_t)tid * SORT_BLOCKS;
+    uint32_t tot = 0;
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = row[b + i];
+#pragma unroll
+        for (int i = 0; i < 8; i++) tot += v[i];
+    }
+    for (; b < nb; b++) tot += row[b];
+    int64_t all;
+    int64_t run = block_excl_scan_i64(tot, scan_sh, &all);
+    int64_t *orow = hoff + (int64_t)tid * SORT_BLOCKS;
+    for (b = 0; b + 8 <= nb; b += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = row[b + i];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            orow[b + i] = run;
+            run += v[i];
+        }
+    }
+    for (; b < nb; b++) {
+        orow[b] = run;
+        run += row[b];
+    }
+    if (tid == 0) *ticket = 0;
 }
 
 // Scatter of one pass.  Per tile of SORT_TILE keys (round r, wave w, lane l

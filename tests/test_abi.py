@@ -56,6 +56,7 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.hull_create(None, 0) == _lib.HULL_EINVAL
     assert lib.hull_destroy(None) == _lib.HULL_EINVAL
     assert lib.hull_compute(None, None, None, 0, None, None, 0, None) == _lib.HULL_EINVAL
+    assert lib.hull_candidate_counts(None, None, 4) == _lib.HULL_EINVAL
 
 
 def test_candidate_direction_table_correctly_rounded(lib):

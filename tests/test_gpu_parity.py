@@ -194,7 +194,14 @@ def test_refinement_keeps_the_hull(H, kind, n):
     xt, yt = dev(x), dev(y)
     want = oracle.compute(x, y, 0)
     assert np.array_equal(u32(H.compute(xt, yt)), want)
+    counts = H.candidate_counts()
+    slots, _ = oracle.extremes(x, y, 0)
+    surv = oracle.discard(x, y, oracle.polygon(x, y, slots))
+    assert counts[0] == len(surv)
+    # every round keeps the hull's vertices and never adds candidates
+    assert all(len(want) <= b <= a for a, b in zip(counts, counts[1:])), counts
     assert np.array_equal(u32(H.compute(xt, yt, refine=False)), want)
+    assert H.candidate_counts() == [len(surv)] + [-1] * 4
 
 
 def test_refinement_degenerate_inputs(H):
@@ -205,3 +212,31 @@ def test_refinement_degenerate_inputs(H):
         assert np.array_equal(u32(H.compute(dev(x), dev(y))), want), seed
     x, y, m = inputs.regular_polygon(48, 5000, 3)
     assert np.array_equal(u32(H.compute(dev(x), dev(y))), oracle.compute(x, y, 0))
+
+
+def test_long_chain(H):
+    """8191 strictly convex points on a parabola (every one a lower-hull
+    vertex) under 100k random points: the lower chain outgrows what one wave
+    stages in LDS, so the merge also walks bridges in global memory."""
+    r = np.random.default_rng(77)
+    k = np.arange(1, 8192, dtype=np.int64)
+    px, py = k * 2048, (k - 4096) ** 2
+    qx = r.integers(0, 1 << 24, size=100_000)
+    qy = r.integers(0, 1 << 24, size=100_000)
+    keep = qy > ((qx / 2048.0 - 4096.0) ** 2) + 4096     # well above the curve
+    x = inputs.to_float(np.concatenate([qx[keep][:40_000], px, qx[keep][40_000:]]))
+    y = inputs.to_float(np.concatenate([qy[keep][:40_000], py, qy[keep][40_000:]]))
+    want = oracle.compute(x, y, 0)
+    assert len(want) > 8000
+    H.set_directions(0)
+    xt, yt = dev(x), dev(y)
+    assert np.array_equal(u32(H.compute(xt, yt)), want)
+    assert np.array_equal(u32(H.compute(xt, yt, refine=False)), want)
+    assert np.array_equal(u32(H.compute(xt, yt, nofilter=True)), oracle.compute(x, y, nofilter=True))
+    # two copies in one batch
+    n = len(x)
+    xb, yb = np.concatenate([x, x]), np.concatenate([y, y])
+    hull, ho = H.compute_batched(dev(xb), dev(yb), dev(np.array([0, n, 2 * n], np.int64)))
+    hv, ho = u32(hull), ho.cpu().numpy()
+    assert np.array_equal(hv[ho[0]:ho[1]], want)
+    assert np.array_equal(hv[ho[1]:ho[2]].astype(np.int64), want.astype(np.int64) + n)
