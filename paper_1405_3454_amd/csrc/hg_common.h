@@ -60,6 +60,12 @@ constexpr int RE_CAP = MAX_SLOTS << REF_ROUNDS;
 constexpr uint16_t RE_NONE = 0xFFFF;              // kept, not assigned to an edge
 constexpr uint16_t RE_DROP = 0xFFFE;              // strictly inside the hull
 
+// A refinement edge a->b in grid units; ax == INT32_MIN: empty slot.
+struct REdge {
+    int32_t ax, ay, bx, by;
+};
+__host__ __device__ inline REdge redge_empty() { return REdge{INT32_MIN, 0, 0, 0}; }
+
 // Unordered survivor lists of the full method are kept in NSEG segments, each
 // with its own counter (appends spread over NSEG addresses instead of one):
 // segment i holds its entries at [i * segcap, i * segcap + count[i]).

@@ -119,23 +119,22 @@ struct Plan {
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
-        rfar1, segcnt, cidx, ckeys, total;
+        rfar1, segcnt, segmeta, cidx, ckeys, total;
     int64_t tcap, u0cap;
-    int64_t segcap;     // entries per segment of the full method's survivor lists
+    int64_t segcap;     // entries per segment of the refinement rounds' lists
+    int64_t nwave;      // discard waves = segments of the discard pass's list
 };
 
 static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Entries per segment that no segmented survivor list can exceed, for W
-// waves of the discard pass: wave w appends the survivors of its q =
-// ceil(T / W) tiles to segment w mod NSEG (at most T / NSEG + 2q tiles per
-// segment), and a refinement round appends chunk c of its input (at most
-// n / REF_CH + NSEG chunks) to segment c mod NSEG.
-static int64_t seg_capacity(int64_t n, int64_t tcap, int64_t W) {
+// Entries per segment of the refinement rounds' lists, for W waves of the
+// discard pass: wave w writes the survivors of its q = ceil(T / W) tiles to
+// region w, round 0 appends region w's kept entries to segment w mod NSEG (at
+// most T / NSEG + 2q tiles of points), and later rounds keep a segment's
+// entries in the same segment.
+static int64_t seg_capacity(int64_t tcap, int64_t W) {
     const int64_t q = (tcap + W - 1) / W;
-    const int64_t d = (tcap / NSEG + 2 * q + 1) * TILE;
-    const int64_t r = ((n / REF_CH + NSEG) / NSEG + 1) * REF_CH;
-    return std::max(d, r);
+    return (tcap / NSEG + 2 * q + 1) * TILE;
 }
 
 static Plan make_plan(int64_t n, int64_t S, int64_t W) {
@@ -148,8 +147,11 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     };
     p.tcap = n / TILE + 2 * S + 2;
     p.u0cap = n / CHAIN_C + 2;
-    p.segcap = seg_capacity(n, p.tcap, W);
-    const size_t lcap = (size_t)std::max<int64_t>(n, NSEG * p.segcap);   // list entries
+    p.segcap = seg_capacity(p.tcap, W);
+    p.nwave = W;
+    // list entries: the discard pass's regions end by (T + q) * TILE
+    const int64_t q = (p.tcap + W - 1) / W;
+    const size_t lcap = (size_t)std::max({n, (p.tcap + q) * TILE, NSEG * p.segcap});
     p.tile_off = take((S + 1) * 8);
     p.tile_set = take(p.tcap * 4);
     p.pval = take(p.tcap * MAX_SLOTS * 8);
@@ -189,7 +191,8 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.rtab1 = take(S * RE_CAP * sizeof(REdge));
     p.rfar0 = take(S * RE_CAP * 8);
     p.rfar1 = take(S * RE_CAP * 8);
-    p.segcnt = take((REF_ROUNDS + 1) * NSEG * 8);
+    p.segcnt = take((W + REF_ROUNDS * NSEG) * 8);   // stage 0: W regions, then NSEG per round
+    p.segmeta = take(2 * 8);                         // [0] region size, [1] segcap
     p.cidx = take(n * 4 + 16);
     p.ckeys = take(n * 8 + 16);
     p.total = o;
@@ -301,7 +304,9 @@ static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
 
 static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const float *y, int64_t n_total, int64_t S, bool learned, const uint32_t *slots_in,
-                       int n_in, uint32_t *slots_out, double *vals_out) {
+                       int n_in, uint32_t *slots_out, double *vals_out, bool ref_init = false) {
+    REdge *rtab = ref_init ? W<REdge>(ctx, p.rtab0) : nullptr;
+    unsigned long long *rfar = ref_init ? W<unsigned long long>(ctx, p.rfar0) : nullptr;
     const int64_t W1 = (int64_t)grid_k1(ctx, learned) * 4;
     auto *polys = W<Poly>(ctx, p.polys);
     auto *spans = W<Span>(ctx, p.spans);
@@ -310,7 +315,7 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<(unsigned)S, 256, 0, st>>>(                          \
         x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
         W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
-        spans, W<uint32_t>(ctx, p.redges)))
+        spans, W<uint32_t>(ctx, p.redges), rtab, rfar))
     const bool cum = ctx->preset == HULL_DIRS_CUMULATIVE;
     if (learned) {
         if (cum) K2(12, MAX_DIRS); else K2(16, MAX_DIRS);
@@ -352,9 +357,10 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     return HULL_OK;
 }
 
-// Step 3 for the full method: survivors appended to the segmented list
-// (surv, keys[, edges]) with segment counts seg_cnt[NSEG] (zero before);
-// with gfar, also the refinement's round-0 edge states and farthest points.
+// Step 3 for the full method: survivors written to one region per discard
+// wave of (surv, keys[, edges]), region counts to seg_cnt[p.nwave] and the
+// region size to segmeta[0]; with gfar, also the refinement's round-0 edge
+// states and farthest points.
 static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                               const float *y, int64_t n_total, const int64_t *off, int64_t n1,
                               int64_t S, int nedge, uint32_t *surv, uint64_t *keys,
@@ -364,15 +370,15 @@ static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, cons
     auto *polys = W<Poly>(ctx, p.polys);
     auto *spans = W<Span>(ctx, p.spans);
     const uint32_t *redges = W<uint32_t>(ctx, p.redges);
-    auto *c = reinterpret_cast<unsigned long long *>(seg_cnt);
-    const int64_t segcap = p.segcap;
+    int64_t *meta = W<int64_t>(ctx, p.segmeta);
     const int g = grid_k3(ctx);
+    if ((int64_t)g * 4 != p.nwave) return HULL_EINVAL;   // the plan's regions assume this grid
     const int ph = phase_of(x);
 #define K3A(NE, MODE)                                                                             \
     LAUNCH(K_DISCARD, (k_discard<NE, MODE><<<g, 256, 0, st>>>(x, y, n_total, ph, off, n1, S,    \
                                                                tile_off, tile_set, polys, spans,  \
                                                                redges, nullptr, nullptr, surv,    \
-                                                               keys, edges, c, segcap, gfar)))
+                                                               keys, edges, seg_cnt, meta, gfar)))
     if (gfar) {
         if (nedge <= FIXED_SLOTS) K3A(FIXED_SLOTS, DISCARD_ASSIGN);
         else K3A(MAX_SLOTS, DISCARD_ASSIGN);
@@ -423,10 +429,10 @@ static int chain_levels(int64_t ncap) {
 
 // Hull of the candidates (idx[i], keys[i]) i < *cnt, grouped into S sets by
 // the key's set field.  hoff (S+1) receives the per-set hull offsets, hull
-// the vertex indices.
+// the vertex indices, *h_out (optional) the total hull size.
 static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t *idx,
                     const uint64_t *keys, const int64_t *cnt, int64_t ncap, int64_t S,
-                    int64_t *hoff, uint32_t *hull) {
+                    int64_t *hoff, uint32_t *hull, int64_t *h_out = nullptr) {
     const uint64_t *sorted = nullptr;
     int rc = run_sort(ctx, p, st, keys, cnt, sort_passes(S), &sorted);
     if (rc) return rc;
@@ -456,6 +462,12 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     uint32_t *hcnt = W<uint32_t>(ctx, p.hcnt);
     uint64_t *hkeys = W<uint64_t>(ctx, p.hkeys);
     uint32_t *hpos = W<uint32_t>(ctx, p.hpos);
+    if (S == 1) {
+        LAUNCH(K_FINAL, k_hull_final1<<<1, 1024, 0, st>>>(lo[cur], up[cur], locnt[cur], upcnt[cur],
+                                                          hoff, hkeys, hpos, hull, h_out));
+        LAUNCH(K_LOOKUP, k_hull_lookup<<<2048, 256, 0, st>>>(idx, keys, cnt, S, hoff, hkeys, hpos, hull));
+        return HULL_OK;
+    }
     int64_t *scount = W<int64_t>(ctx, p.consts) + 1;   // = S
     LAUNCH(K_FINAL, k_fill_i64<<<64, 256, 0, st>>>(bounds, 4 * S, 0));
     LAUNCH(K_FINAL, k_fill_i64<<<1, 64, 0, st>>>(scount, 1, S));
@@ -468,6 +480,7 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
                                                               upcnt[cur], bounds, S, hoff, hkeys,
                                                               hpos, hull));
     LAUNCH(K_LOOKUP, k_hull_lookup<<<2048, 256, 0, st>>>(idx, keys, cnt, S, hoff, hkeys, hpos, hull));
+    if (h_out) LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(hoff + S, h_out));
     return HULL_OK;
 }
 
@@ -477,6 +490,11 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
 // polygon's edges.  Round r appends to stage r + 1; an even number of rounds
 // ends back in surv/keys0 (ping-pong through lo0/lo1/up1, which the hull stage
 // only uses afterwards).  ctx->counts[r] records the input total of round r.
+// Segment counts of list stage r (0: the discard pass's regions).
+static int64_t *seg_stage(const Plan &p, int64_t *segcnt, int r) {
+    return r == 0 ? segcnt : segcnt + p.nwave + (r - 1) * NSEG;
+}
+
 static_assert(HULL_NCOUNTS == 1 + REF_ROUNDS, "one count per refinement round");
 static_assert(REF_ROUNDS % 2 == 0, "refinement must end in the first buffer set");
 static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
@@ -488,28 +506,32 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
     unsigned long long *far[2] = {W<unsigned long long>(ctx, p.rfar0),
                                   W<unsigned long long>(ctx, p.rfar1)};
     int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
+    const int64_t *meta = W<int64_t>(ctx, p.segmeta);
     const unsigned g = (unsigned)(ctx->cus * 8);
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
-        int64_t *cin = segcnt + r * NSEG, *cout = segcnt + (r + 1) * NSEG;
+        int64_t *cin = seg_stage(p, segcnt, r), *cout = seg_stage(p, segcnt, r + 1);
+        const int nin = r == 0 ? (int)p.nwave : NSEG;
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
-            x, y, S, er, tab[a], far[a], tab[b], far[b], cin, cout, ctx->counts + r));
-        LAUNCH(K_REFINE, k_ref_pass<<<g, REF_THREADS, 0, st>>>(
-            idxs[a], keys[a], eds[a], cin, p.segcap, tab[b], far[b], idxs[b], keys[b], eds[b],
-            reinterpret_cast<unsigned long long *>(cout)));
+            x, y, S, er, tab[a], far[a], tab[b], far[b], cin, nin, cout, ctx->counts + r));
+        const unsigned gp = r == 0 ? std::max<unsigned>(g, (unsigned)p.nwave) : g;
+        LAUNCH(K_REFINE, k_ref_pass<<<gp, REF_THREADS, 0, st>>>(
+            idxs[a], keys[a], eds[a], cin, nin, meta + (r == 0 ? 0 : 1), tab[b], 2 * er, far[b],
+            idxs[b], keys[b], eds[b], reinterpret_cast<unsigned long long *>(cout), p.segcap));
     }
     return HULL_OK;
 }
 
-// Segmented list (surv, keys0) at segment counts cnt -> contiguous (cidx,
-// ckeys); the total goes to *total.
-static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, const int64_t *cnt,
-                      int64_t *total) {
-    const unsigned per = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, p.segcap / 1024));
-    LAUNCH(K_SCATTER, k_seg_gather<<<NSEG * per, 256, 0, st>>>(
-        W<uint32_t>(ctx, p.surv), W<uint64_t>(ctx, p.keys0), cnt, p.segcap,
-        W<uint32_t>(ctx, p.cidx), W<uint64_t>(ctx, p.ckeys), total));
+// Segmented list (surv, keys0) of stage `stage` -> contiguous (cidx, ckeys);
+// the total goes to *total.
+static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, int stage, int64_t *total) {
+    const int nseg = stage == 0 ? (int)p.nwave : NSEG;
+    LAUNCH(K_SCATTER, k_seg_gather<<<(unsigned)(ctx->cus * 8), 256, 0, st>>>(
+        W<uint32_t>(ctx, p.surv), W<uint64_t>(ctx, p.keys0),
+        seg_stage(p, W<int64_t>(ctx, p.segcnt), stage), nseg,
+        W<int64_t>(ctx, p.segmeta) + (stage == 0 ? 0 : 1), W<uint32_t>(ctx, p.cidx),
+        W<uint64_t>(ctx, p.ckeys), total));
     return HULL_OK;
 }
 
@@ -548,7 +570,8 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
     const bool refine = !(flags & (HULL_NOREFINE | HULL_NOFILTER));
     const int64_t *cnt = ctx->counts;
     int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
-    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(ctx->counts, HULL_NCOUNTS, segcnt));
+    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(ctx->counts, HULL_NCOUNTS,
+                                                   W<int64_t>(ctx, p.segmeta), p.segcap));
     if (flags & HULL_NOFILTER) {
         LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
                                                          surv_off));
@@ -560,15 +583,14 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
             if (rc) return rc;
         }
         if ((rc = run_extremes(ctx, p, st, x, y, n_total, off, n1, S, learned))) return rc;
-        if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, learned, nullptr, 0, nullptr, nullptr)))
+        if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, learned, nullptr, 0, nullptr, nullptr,
+                              refine)))
             return rc;
         unsigned long long *far0 = nullptr;
         uint16_t *edges = nullptr;
-        if (refine) {    // round-0 edge table; the discard pass fills its states
+        if (refine) {    // round-0 edge table from k_polygon; the discard pass fills its states
             far0 = W<unsigned long long>(ctx, p.rfar0);
             edges = W<uint16_t>(ctx, p.up0);
-            LAUNCH(K_REFINE_SPLIT, k_ref_init<<<(unsigned)S, 64, 0, st>>>(
-                x, y, W<Poly>(ctx, p.polys), W<REdge>(ctx, p.rtab0), far0));
         }
         if ((rc = run_discard_append(ctx, p, st, x, y, n_total, off, n1, S,
                                      learned ? MAX_SLOTS : FIXED_SLOTS, surv, keys, edges,
@@ -576,15 +598,12 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
             return rc;
         const int stage = refine ? REF_ROUNDS : 0;
         if (refine && (rc = run_refine(ctx, p, st, x, y, S))) return rc;
-        if ((rc = run_gather(ctx, p, st, segcnt + stage * NSEG, ctx->counts + stage))) return rc;
+        if ((rc = run_gather(ctx, p, st, stage, ctx->counts + stage))) return rc;
         surv = W<uint32_t>(ctx, p.cidx);
         keys = W<uint64_t>(ctx, p.ckeys);
         cnt = ctx->counts + stage;
     }
-    rc = run_hull(ctx, p, st, surv, keys, cnt, n_total, S, hoff, hull);
-    if (rc) return rc;
-    if (h_out) LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(hoff + S, h_out));
-    return HULL_OK;
+    return run_hull(ctx, p, st, surv, keys, cnt, n_total, S, hoff, hull, h_out);
 }
 
 // ---------------------------------------------------------------------------

@@ -439,14 +439,6 @@ __global__ __launch_bounds__(256) void k_seg_bounds(const uint64_t *__restrict__
     }
 }
 
-// Hull size per set: lower + upper - 2 shared ends; one point -> 1.
-__global__ void k_hull_counts(const int64_t *__restrict__ bounds, int64_t S,
-                              uint32_t *__restrict__ hcnt) {
-    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    int64_t hl = bounds[S + s] - bounds[s], hu = bounds[3 * S + s] - bounds[2 * S + s];
-    hcnt[s] = (uint32_t)(hl == 0 ? 0 : (hl == 1 ? 1 : hl + hu - 2));
-}
 
 // Number of keys in sorted c[lo..hi) that are < k.
 __device__ __forceinline__ int64_t count_less(const uint64_t *__restrict__ c, int64_t lo, int64_t hi,
@@ -459,9 +451,54 @@ __device__ __forceinline__ int64_t count_less(const uint64_t *__restrict__ c, in
     return a - lo;
 }
 
-// Lay out each set's hull: CCW position of every chain entry, a key-sorted
-// copy (hkeys, hpos) for the index lookup, and the output slots preset to
+// Lay out one chain entry k = c[i] of its set's hull (lower chain [ls, le),
+// upper [us, ue), output [o, o + h)): its CCW position, a key-sorted copy
+// (hkeys, hpos) for the index lookup, and its output slot preset to
 // HULL_NONE.
+__device__ __forceinline__ void emit_entry(bool upper, int64_t i, uint64_t k, int64_t ls,
+                                           int64_t le, int64_t us, int64_t ue, int64_t o,
+                                           int64_t h, const uint64_t *__restrict__ lo,
+                                           const uint64_t *__restrict__ up,
+                                           uint64_t *__restrict__ hkeys,
+                                           uint32_t *__restrict__ hpos,
+                                           uint32_t *__restrict__ hull) {
+    const int64_t hl = le - ls, hu = ue - us;
+    int64_t pos, rank;
+    if (!upper) {
+        int64_t r = i - ls;
+        if (hl == 1) {
+            pos = 0;
+            rank = 0;
+        } else {
+            pos = r;
+            rank = r + (hu > 2 ? count_less(up, us + 1, ue - 1, k) : 0);
+        }
+    } else {
+        int64_t r = i - us;
+        if (hl <= 1 || r == 0 || r == hu - 1) return;   // shared ends
+        pos = hl + (hu - 2 - r);
+        rank = (r - 1) + count_less(lo, ls, le, k);
+    }
+    if (pos >= h || rank >= h) return;   // inconsistent chains: never write outside
+    hkeys[o + rank] = k;
+    hpos[o + rank] = (uint32_t)pos;
+    hull[o + pos] = NONE;
+}
+
+// Hull size from the chain lengths: lower + upper - 2 shared ends; one
+// point -> 1.
+__device__ __forceinline__ int64_t hull_size(int64_t hl, int64_t hu) {
+    return hl == 0 ? 0 : (hl == 1 ? 1 : hl + hu - 2);
+}
+
+// Hull size per set.
+__global__ void k_hull_counts(const int64_t *__restrict__ bounds, int64_t S,
+                              uint32_t *__restrict__ hcnt) {
+    int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    hcnt[s] = (uint32_t)hull_size(bounds[S + s] - bounds[s], bounds[3 * S + s] - bounds[2 * S + s]);
+}
+
 __global__ __launch_bounds__(256) void k_hull_emit(const uint64_t *__restrict__ lo,
                                                    const uint64_t *__restrict__ up,
                                                    const uint32_t *__restrict__ lo_len,
@@ -479,29 +516,34 @@ __global__ __launch_bounds__(256) void k_hull_emit(const uint64_t *__restrict__ 
         uint64_t k = c[i];
         uint32_t s = key_set(k);
         if (s >= S) continue;
-        int64_t ls = bounds[s], le = bounds[S + s], us = bounds[2 * S + s], ue = bounds[3 * S + s];
-        int64_t hl = le - ls, hu = ue - us;
-        int64_t pos, rank;
-        if (!upper) {
-            int64_t r = i - ls;
-            if (hl == 1) {
-                pos = 0;
-                rank = 0;
-            } else {
-                pos = r;
-                rank = r + (hu > 2 ? count_less(up, us + 1, ue - 1, k) : 0);
-            }
-        } else {
-            int64_t r = i - us;
-            if (hl <= 1 || r == 0 || r == hu - 1) continue;   // shared ends
-            pos = hl + (hu - 2 - r);
-            rank = (r - 1) + count_less(lo, ls, le, k);
-        }
-        int64_t o = hoff[s], h = hoff[s + 1] - o;
-        if (pos >= h || rank >= h) continue;   // inconsistent chains: never write outside
-        hkeys[o + rank] = k;
-        hpos[o + rank] = (uint32_t)pos;
-        hull[o + pos] = NONE;
+        const int64_t o = hoff[s];
+        emit_entry(upper, i, k, bounds[s], bounds[S + s], bounds[2 * S + s], bounds[3 * S + s],
+                   o, hoff[s + 1] - o, lo, up, hkeys, hpos, hull);
+    }
+}
+
+// One set: offsets, hull size (also to *h_out when given) and layout in one
+// block (the chains hold set 0 only).
+__global__ __launch_bounds__(1024) void k_hull_final1(const uint64_t *__restrict__ lo,
+                                                      const uint64_t *__restrict__ up,
+                                                      const uint32_t *__restrict__ lo_len,
+                                                      const uint32_t *__restrict__ up_len,
+                                                      int64_t *__restrict__ hoff,
+                                                      uint64_t *__restrict__ hkeys,
+                                                      uint32_t *__restrict__ hpos,
+                                                      uint32_t *__restrict__ hull,
+                                                      int64_t *__restrict__ h_out) {
+    const int64_t le = lo_len[0], ue = up_len[0];
+    const int64_t h = hull_size(le, ue);
+    if (threadIdx.x == 0) {
+        hoff[0] = 0;
+        hoff[1] = h;
+        if (h_out) *h_out = h;
+    }
+    for (int64_t i = threadIdx.x; i < le + ue; i += blockDim.x) {
+        const bool upper = i >= le;
+        const int64_t j = upper ? i - le : i;
+        emit_entry(upper, j, upper ? up[j] : lo[j], 0, le, 0, ue, 0, h, lo, up, hkeys, hpos, hull);
     }
 }
 
@@ -549,10 +591,11 @@ __global__ __launch_bounds__(256) void k_gather_keys(const float *__restrict__ x
 }
 
 // Before a computation: the recorded stage counts to -1 (stages that do not
-// run keep it) and the discard pass's segment counts to 0.
-__global__ void k_counts_init(int64_t *__restrict__ c, int n, int64_t *__restrict__ seg0) {
+// run keep it) and the refinement lists' segment size to meta[1].
+__global__ void k_counts_init(int64_t *__restrict__ c, int n, int64_t *__restrict__ meta,
+                              int64_t segcap) {
     if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = -1;
-    if (blockIdx.x == 0 && (int)threadIdx.x < NSEG) seg0[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[1] = segcap;
 }
 
 __global__ void k_copy_count(const int64_t *__restrict__ src, int64_t *__restrict__ dst) {

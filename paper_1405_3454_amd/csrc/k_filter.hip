@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void k_polygon(
     const uint32_t *__restrict__ pidx, const uint32_t *__restrict__ slots_in, int n_in, Dirs dirs,
     const double *__restrict__ set_dirs, uint32_t *__restrict__ slots_out,
     double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans,
-    uint32_t *__restrict__ redges) {
+    uint32_t *__restrict__ redges, REdge *__restrict__ rtab, unsigned long long *__restrict__ rfar) {
     // NEV: fixed slots the extremes pass evaluated (12 when the 120-degree
     // group is a copy of the 30-degree one, else 16); NDIR learned slots.
     constexpr int NS = FIXED_SLOTS + NDIR;
@@ -794,6 +794,18 @@ __global__ __launch_bounds__(256) void k_polygon(
         redges[s * SPAN_ROWS + r] = re;
     }
     if (tid == 0) polys[s] = P;
+    if (rtab) {    // the refinement's round-0 edges (the polygon's) and cleared farthest keys
+        const int m = P.m >= 3 ? P.m : 0;
+        for (int e = tid; e < RE_CAP; e += blockDim.x) {
+            REdge r = redge_empty();
+            if (e < m) {
+                const int b = (e + 1) % m;
+                r = REdge{(int32_t)vx[e], (int32_t)vy[e], (int32_t)vx[b], (int32_t)vy[b]};
+            }
+            rtab[s * RE_CAP + e] = r;
+            rfar[s * RE_CAP + e] = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -806,14 +818,16 @@ __global__ __launch_bounds__(256) void k_polygon(
 //  - DISCARD_MASKS: per tile, survivor mask words (word 4c + j, bit l = point
 //    c*256 + 4l + j of the tile) and the survivor count, for the ordered
 //    scatter;
-//  - DISCARD_APPEND: each tile's survivors (index, key) appended at once to
-//    segment (wave mod NSEG) of the survivor list, one atomic per tile
-//    reserving their range (the hull stage does not need index order: it
-//    sorts by key, and maps keys back to the lowest index);
+//  - DISCARD_APPEND: the quick rejects join the queue too, flagged, and the
+//    64-lane batches write every survivor (index, key) to the wave's own
+//    region of the survivor list, [wave * q * TILE, ...) for q tiles per
+//    wave, with no atomics; seg_cnt[wave] gets the region's count and
+//    seg_meta[0] the region size q * TILE (the hull stage does not need
+//    index order: it sorts by key, and maps keys back to the lowest index);
 //  - DISCARD_ASSIGN: as APPEND, and each survivor also gets the first
-//    polygon edge it is strictly outside of (RE_NONE: on the boundary), with
-//    the farthest-point key of every edge raised: the refinement's round-0
-//    state, taken while the points are still in registers.
+//    polygon edge it is strictly outside of (RE_NONE: on the boundary), from
+//    the same edge evaluations, with the farthest-point key of every edge
+//    raised: the refinement's round-0 state.
 constexpr int QCAP = 320;
 constexpr int DISCARD_MASKS = 0, DISCARD_APPEND = 1, DISCARD_ASSIGN = 2;
 constexpr int EDGE_SLOTS = 32;        // edge arrays in LDS; slots >= m hold (0, 0, 1)
@@ -840,36 +854,89 @@ __device__ __forceinline__ void far_flush(DiscardLds &L, unsigned long long *gfa
     wave_sync();
 }
 
-__device__ __forceinline__ bool edge_in(const DiscardLds &L, uint32_t e, double px, double py) {
-    return edge_eval(L.ex[e], L.ey[e], L.c[e], px, py) > 0;
-}
+// Where an appending discard pass writes its survivors (see k_discard).
+struct AppendOut {
+    uint32_t *surv;
+    uint64_t *keys;
+    uint16_t *edges;       // DISCARD_ASSIGN only
+    int64_t at;            // next free entry of the wave's region (uniform)
+    int64_t tb;            // global index of the tile's first point
+    uint64_t setkey;       // set << 48
+    int pm;                // polygon vertices
+};
 
-template <int NEDGE>
+constexpr uint64_t Q_OUTSIDE = 1ull << 63;   // queue entry already known to be a survivor
+
+// Exact test of queue entries [from, from + count), one per lane, against the
+// edges meeting the point's row (all edges outside the rows).  MASKS: a
+// point not strictly inside sets its mask bit.  APPEND/ASSIGN: every
+// survivor (tested, or queued as known) is written to o's region, with
+// (ASSIGN) the first edge it is strictly outside of and that edge's
+// farthest-point key raised.
+template <int NEDGE, int MODE>
 __device__ __forceinline__ void drain(DiscardLds &L, int from, int count, int32_t ky_lo, int shift,
-                                      uint32_t ylim) {
+                                      uint32_t ylim, AppendOut &o) {
     const int lane = lane_id();
+    bool out = false;
+    uint64_t e = 0;
+    uint16_t e_out = RE_NONE;
+    double dist = 0.0;
     if (lane < count) {
-        const uint64_t e = L.q[from + lane];
+        e = L.q[from + lane];
         const int32_t kx = (int32_t)(e & 0xFFFFFF), ky = (int32_t)((e >> 24) & 0xFFFFFF);
         const double px = (double)kx, py = (double)ky;
-        const int pos = (int)(e >> 48);
         const uint32_t dy = (uint32_t)(ky - ky_lo);   // outside the rows: every edge
         const uint32_t re = dy <= ylim ? L.redge[dy >> shift] : ROW_EDGES_ALL;
-        bool inside;
+        bool inside = true;
         if (re != ROW_EDGES_ALL) {
             // all four evaluated (no short circuit): unused entries name an
             // always-satisfied edge
-            inside = ((int)edge_in(L, re & 0xFF, px, py) & (int)edge_in(L, (re >> 8) & 0xFF, px, py) &
-                      (int)edge_in(L, (re >> 16) & 0xFF, px, py) & (int)edge_in(L, re >> 24, px, py)) != 0;
-        } else {
-            inside = true;
 #pragma unroll
-            for (int k = 0; k < NEDGE; k++) inside = inside && edge_in(L, k, px, py);
+            for (int q4 = 0; q4 < 4; q4++) {
+                const int k = (re >> (8 * q4)) & 0xFF;
+                const double E = edge_eval(L.ex[k], L.ey[k], L.c[k], px, py);
+                inside = inside && E > 0;
+                if (MODE == DISCARD_ASSIGN && E < 0 && e_out == RE_NONE) { e_out = (uint16_t)k; dist = -E; }
+            }
+        } else {
+            // points outside the rows (rare): stop at the first edge that
+            // decides (not strictly inside; with ASSIGN, strictly outside)
+#pragma unroll 1
+            for (int k = 0; k < NEDGE; k++) {
+                const double E = edge_eval(L.ex[k], L.ey[k], L.c[k], px, py);
+                inside = inside && E > 0;
+                if (E < 0) {
+                    if (MODE == DISCARD_ASSIGN) { e_out = (uint16_t)k; dist = -E; }
+                    break;
+                }
+                if (MODE != DISCARD_ASSIGN && !inside) break;
+            }
         }
-        if (!inside) {
+        out = (e & Q_OUTSIDE) || !inside;
+        if (MODE == DISCARD_ASSIGN && o.pm < 3) e_out = RE_NONE;   // no refinement edges
+    }
+    if constexpr (MODE == DISCARD_MASKS) {
+        if (out) {
+            const int pos = (int)((e >> 48) & 0x3FF);
             const int c = pos >> 8, l = (pos >> 2) & 63, j = pos & 3;
             atomicOr(&L.mask[c * 4 + j], 1ull << l);
         }
+    } else {
+        const uint64_t m = __ballot(out);
+        if (out) {
+            const int64_t gi = o.tb + (int64_t)((e >> 48) & 0x3FF);
+            const int64_t pp = o.at + __popcll(m & lanemask_lt());
+            o.surv[pp] = (uint32_t)gi;
+            o.keys[pp] = o.setkey | ((e & 0xFFFFFF) << 24) | ((e >> 24) & 0xFFFFFF);
+            if constexpr (MODE == DISCARD_ASSIGN) {
+                o.edges[pp] = e_out;
+                if (e_out != RE_NONE) {
+                    const uint64_t fk = far_key(dist, (uint32_t)gi);
+                    if (L.far[e_out] < fk) atomicMax(&L.far[e_out], (unsigned long long)fk);
+                }
+            }
+        }
+        o.at += __popcll(m);
     }
 }
 
@@ -889,8 +956,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const int32_t *__restrict__ tile_set, const Poly *__restrict__ polys,
     const Span *__restrict__ spans, const uint32_t *__restrict__ redges,
     uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ surv,
-    uint64_t *__restrict__ keys, uint16_t *__restrict__ edges,
-    unsigned long long *__restrict__ seg_cnt, int64_t segcap, unsigned long long *__restrict__ gfar) {
+    uint64_t *__restrict__ keys, uint16_t *__restrict__ edges, int64_t *__restrict__ seg_cnt,
+    int64_t *__restrict__ seg_meta, unsigned long long *__restrict__ gfar) {
     __shared__ DiscardLds lds[4];
     DiscardLds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
@@ -899,7 +966,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const int64_t T = tile_off[S];
     const int64_t q = (T + W - 1) / W;
     const int64_t t0 = wave * q, t1 = min(t0 + q, T);
+    if (MODE != DISCARD_MASKS) {
+        if (wave == 0 && lane == 0) seg_meta[0] = q * TILE;
+        if (t0 >= t1 && lane == 0) seg_cnt[wave] = 0;
+    }
     if (t0 >= t1) return;
+    // DISCARD_APPEND/ASSIGN: this wave's output region starts at t0 * TILE
+    AppendOut ao{surv, keys, edges, t0 * TILE, 0, 0, 0};
 
     int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1, cur_s = -1;
     int32_t ky_lo = 0, shift = 0, ymin = 0, pm = 0;
@@ -915,6 +988,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                 else if (lane < MAX_SLOTS) L.far[lane] = 0;
             }
             cur_s = s;
+            ao.setkey = (uint64_t)s << 48;
             cur_end = tile_off[s + 1];
             o0 = set_begin(off, s);
             o1 = set_end(off, n1, s);
@@ -926,6 +1000,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             ylim = (uint32_t)max(P->yspan, 0);
             shift = P->shift;
             pm = P->m;
+            ao.pm = pm;
             ymin = P->ymin;
             yext = (uint32_t)(P->ymax - P->ymin);
             if (!has_rows) {     // nothing strictly inside: every point is outside
@@ -949,6 +1024,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         }
         int qn = 0;
         const int64_t tb = abase + (t - tile0) * TILE;
+        ao.tb = tb;
         // one tile (FULL: every position lies in the set, so the loads need
         // no guard): per chunk, classify its 4 points per lane, queue the
         // undecided ones (one ballot per chunk when there are none), drain
@@ -993,108 +1069,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                     sw[j] = outside & m_valid;
                     slow[j] = ~(outside | inside) & m_valid;
                 }
-                if (slow[0] | slow[1] | slow[2] | slow[3]) {   // some undecided point
+                // queued: the undecided points, and in the appending modes the
+                // survivors already known (flagged), so that the 64-lane
+                // drain writes every survivor
+                uint64_t push[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) push[j] = MODE == DISCARD_MASKS ? slow[j] : (slow[j] | sw[j]);
+                if (push[0] | push[1] | push[2] | push[3]) {
                     const uint64_t lt = lanemask_lt();
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
-                        if ((slow[j] >> lane) & 1) {
-                            const int p = qn + __popcll(slow[j] & lt);
+                        if ((push[j] >> lane) & 1) {
+                            const int p = qn + __popcll(push[j] & lt);
                             L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
                                      ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
-                                     ((uint64_t)(c * CHUNK + 4 * lane + j) << 48);
+                                     ((uint64_t)(c * CHUNK + 4 * lane + j) << 48) |
+                                     (((sw[j] >> lane) & 1) ? Q_OUTSIDE : 0);
                         }
-                        qn += __popcll(slow[j]);
+                        qn += __popcll(push[j]);
                     }
                 }
-                if (lane < 4) L.mask[c * 4 + lane] = lane == 0 ? sw[0] : lane == 1 ? sw[1] : lane == 2 ? sw[2] : sw[3];
+                if (MODE == DISCARD_MASKS && lane < 4)
+                    L.mask[c * 4 + lane] = lane == 0 ? sw[0] : lane == 1 ? sw[1] : lane == 2 ? sw[2] : sw[3];
                 wave_sync();
                 while (qn >= WAVE) {
                     qn -= WAVE;
-                    drain<NEDGE>(L, qn, WAVE, ky_lo, shift, ylim);
+                    drain<NEDGE, MODE>(L, qn, WAVE, ky_lo, shift, ylim, ao);
                 }
                 wave_sync();
             }
-            if (qn > 0) drain<NEDGE>(L, 0, qn, ky_lo, shift, ylim);
+            if (qn > 0) drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
             wave_sync();
-            if constexpr (MODE != DISCARD_MASKS) {
-                // append the tile's survivors: positions compacted into the
-                // (now empty) queue, then 64 at a time with their coordinates
-                // loaded again (the tile was just read: cache hits), so the
-                // epilogue holds no point registers across the tile
-                int tc = 0;
-#pragma unroll
-                for (int w = 0; w < TILE_WORDS; w++) tc += __popcll(L.mask[w]);
-                if (tc > 0) {
-                    const int seg = (int)(wave & (NSEG - 1));
-                    unsigned long long b0 = 0;
-                    if (lane == 0) b0 = atomicAdd(&seg_cnt[seg], (unsigned long long)tc);
-                    uint16_t *plist = reinterpret_cast<uint16_t *>(L.q);   // >= TILE slots
-                    const uint64_t lt = lanemask_lt();
-                    int done = 0;
-#pragma unroll
-                    for (int c = 0; c < TILE_CHUNKS; c++) {
-                        uint64_t M[4];
-                        int pre = 0, tot = 0;
-#pragma unroll
-                        for (int j = 0; j < 4; j++) {
-                            M[j] = L.mask[c * 4 + j];
-                            pre += __popcll(M[j] & lt);
-                            tot += __popcll(M[j]);
-                        }
-#pragma unroll
-                        for (int j = 0; j < 4; j++)
-                            if ((M[j] >> lane) & 1)
-                                plist[done + pre++] = (uint16_t)(c * CHUNK + 4 * lane + j);
-                        done += tot;
-                    }
-                    wave_sync();
-                    const int64_t base = seg * segcap +
-                        (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(b0 >> 32), 0) << 32) |
-                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b0, 0));
-                    for (int b = 0; b < tc; b += WAVE) {
-                        const int i = b + lane;
-                        if (i < tc) {
-                            const int64_t gi = tb + plist[i];
-                            const int32_t kx = (int32_t)(x[gi] * GRIDF);
-                            const int32_t ky = (int32_t)(y[gi] * GRIDF);
-                            const int64_t pp = base + i;
-                            surv[pp] = (uint32_t)gi;
-                            keys[pp] = ((uint64_t)cur_s << 48) | ((uint64_t)(uint32_t)kx << 24) |
-                                       (uint64_t)(uint32_t)ky;
-                            if constexpr (MODE == DISCARD_ASSIGN) {
-                                // first edge strictly outside: the row's (at most
-                                // four) edges decide for points of the rows
-                                uint16_t e_out = RE_NONE;
-                                double dist = 0.0;
-                                if (pm >= 3) {
-                                    const double px = (double)kx, py = (double)ky;
-                                    const uint32_t dyv = (uint32_t)(ky - ky_lo);
-                                    const uint32_t re = dyv <= ylim ? L.redge[dyv >> shift] : ROW_EDGES_ALL;
-                                    if (re != ROW_EDGES_ALL) {
-#pragma unroll
-                                        for (int q4 = 0; q4 < 4; q4++) {
-                                            const int e = (re >> (8 * q4)) & 0xFF;
-                                            const double E = edge_eval(L.ex[e], L.ey[e], L.c[e], px, py);
-                                            if (E < 0 && e_out == RE_NONE) { e_out = (uint16_t)e; dist = -E; }
-                                        }
-                                    } else {
-                                        for (int e = 0; e < pm; e++) {
-                                            const double E = edge_eval(L.ex[e], L.ey[e], L.c[e], px, py);
-                                            if (E < 0) { e_out = (uint16_t)e; dist = -E; break; }
-                                        }
-                                    }
-                                }
-                                edges[pp] = e_out;
-                                if (e_out != RE_NONE) {
-                                    const uint64_t fk = far_key(dist, (uint32_t)gi);
-                                    if (L.far[e_out] < fk) atomicMax(&L.far[e_out], (unsigned long long)fk);
-                                }
-                            }
-                        }
-                    }
-                    wave_sync();     // the queue is reused by the next tile
-                }
-            }
         };
         if (tb >= o0 && tb + TILE <= o1)
             tile(std::integral_constant<bool, true>());
@@ -1109,6 +1114,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         wave_sync();
     }
     if (MODE == DISCARD_ASSIGN) far_flush(L, gfar, cur_s);
+    if (MODE != DISCARD_MASKS && lane == 0) seg_cnt[wave] = ao.at - t0 * TILE;
 }
 
 // ---------------------------------------------------------------------------

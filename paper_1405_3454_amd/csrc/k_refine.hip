@@ -27,11 +27,6 @@ constexpr int REF_CH = 2048;                      // survivors per block step
 constexpr int REF_THREADS = 256;
 constexpr int REF_PER_THREAD = REF_CH / REF_THREADS;
 
-struct REdge {
-    int32_t ax, ay, bx, by;                       // grid units; ax == INT32_MIN: empty slot
-};
-
-__device__ __forceinline__ REdge redge_empty() { return REdge{INT32_MIN, 0, 0, 0}; }
 
 // Exact edge function of a->b at p: > 0 strictly left (inside), < 0 outside.
 __device__ __forceinline__ double redge_eval(const REdge &e, double px, double py) {
@@ -47,27 +42,6 @@ __device__ __forceinline__ void key_point(uint64_t k, int64_t *s, double *px, do
     *py = (double)(k & 0xFFFFFF);
 }
 
-// Round-0 edge table from the filter polygons; clears the farthest-point keys.
-__global__ __launch_bounds__(64) void k_ref_init(const float *__restrict__ x,
-                                                 const float *__restrict__ y,
-                                                 const Poly *__restrict__ polys,
-                                                 REdge *__restrict__ tab,
-                                                 unsigned long long *__restrict__ far) {
-    const int64_t s = blockIdx.x;
-    const Poly &P = polys[s];
-    const int m = P.m >= 3 ? P.m : 0;
-    for (int e = threadIdx.x; e < RE_CAP; e += blockDim.x) {
-        REdge r = redge_empty();
-        if (e < m) {
-            const uint32_t a = P.verts[e], b = P.verts[(e + 1) % m];
-            r = REdge{(int32_t)(x[a] * GRIDF), (int32_t)(y[a] * GRIDF), (int32_t)(x[b] * GRIDF),
-                      (int32_t)(y[b] * GRIDF)};
-        }
-        tab[s * RE_CAP + e] = r;
-        far[s * RE_CAP + e] = 0;
-    }
-}
-
 // Split every edge of round r at its farthest outside point: children 2e
 // (a->f) and 2e+1 (f->b); an edge without outside points keeps itself as
 // child 2e.  Clears the next round's farthest-point keys and the segment
@@ -78,14 +52,18 @@ __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
                                                    const unsigned long long *__restrict__ far,
                                                    REdge *__restrict__ tab_nxt,
                                                    unsigned long long *__restrict__ far_nxt,
-                                                   const int64_t *__restrict__ cnt_in,
+                                                   const int64_t *__restrict__ cnt_in, int nseg_in,
                                                    int64_t *__restrict__ cnt_nxt,
                                                    int64_t *__restrict__ total_in) {
+    __shared__ int64_t sh[17];
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < NSEG) {
-        cnt_nxt[t] = 0;
-        const int64_t v = wave_sum_i64(cnt_in[t]);
-        if (t == 0) *total_in = v;
+    if (blockIdx.x == 0) {     // the whole block: record the input total
+        int64_t acc = 0;
+        for (int j = threadIdx.x; j < nseg_in; j += blockDim.x) acc += cnt_in[j];
+        int64_t tot;
+        block_excl_scan_i64(acc, sh, &tot);
+        if (threadIdx.x == 0) *total_in = tot;
+        if (threadIdx.x < NSEG) cnt_nxt[threadIdx.x] = 0;
     }
     if (t >= S * er) return;
     const int64_t s = t / er;
@@ -125,68 +103,58 @@ __device__ __forceinline__ void far_put(bool local, RefFar &L, unsigned long lon
     }
 }
 
-// Chunks of REF_CH entries of a segmented list: prefix of the per-segment
-// chunk counts (NSEG + 1 entries, computed by the block's first wave).
-__device__ __forceinline__ void seg_chunks(const int64_t *__restrict__ cnt, int64_t *pre) {
-    if (threadIdx.x < WAVE) {
-        const int64_t nc = (cnt[threadIdx.x] + REF_CH - 1) / REF_CH;
-        const int64_t inc = wave_incl_scan_i64(nc);
-        pre[threadIdx.x] = inc - nc;
-        if (threadIdx.x == WAVE - 1) pre[NSEG] = inc;
+// Blocks of a grid over the segments of a list: bps blocks per segment,
+// `lanes` segments at a time (every segment, when there are more of them than
+// blocks, goes to one block).
+struct SegWalk {
+    int64_t bps, lanes;
+    __device__ SegWalk(int64_t nseg) {
+        bps = max((int64_t)1, (int64_t)gridDim.x / max(nseg, (int64_t)1));
+        lanes = (int64_t)gridDim.x / bps;
     }
-    __syncthreads();
-}
+    __device__ bool idle() const { return (int64_t)blockIdx.x >= bps * lanes; }
+    __device__ int64_t first_seg() const { return (int64_t)blockIdx.x / bps; }
+    __device__ int64_t first_part() const { return (int64_t)blockIdx.x % bps; }
+};
 
-// Exclusive prefix of the segment counts themselves (NSEG + 1 entries).
-__device__ __forceinline__ void seg_prefix(const int64_t *__restrict__ cnt, int64_t *pre) {
-    if (threadIdx.x < WAVE) {
-        const int64_t v = cnt[threadIdx.x];
-        const int64_t inc = wave_incl_scan_i64(v);
-        pre[threadIdx.x] = inc - v;
-        if (threadIdx.x == WAVE - 1) pre[NSEG] = inc;
-    }
-    __syncthreads();
-}
-
-// Segment of chunk c: the last i with pre[i] <= c (one ballot per wave).
-__device__ __forceinline__ int seg_of(const int64_t *pre, int64_t c) {
-    const uint64_t m = __ballot(pre[lane_id()] <= c);
-    return 63 - __clzll((long long)m);
-}
-
-// One round over the survivors, a chunk of REF_CH entries of one segment per
-// block step (thread t holds entries t * REF_PER_THREAD ...).  Each survivor
-// is classified against the two children of its edge (RE_DROP, RE_NONE or the
-// new edge id); the kept ones are appended to segment (chunk mod NSEG) of the
-// next list, the block's kept count reserving their range with one atomic.
-// The farthest-point key of each new edge is raised.  (Round 0's edge states
-// come from the discard pass.)
+// One round over the survivors: input segment sg (region sg * segcap_in,
+// cnt_in[sg] entries) in chunks of REF_CH, thread t holding entries
+// t * REF_PER_THREAD ... of a chunk.  Each survivor is classified against the
+// two children of its edge (RE_DROP, RE_NONE or the new edge id); the kept
+// ones are appended to output segment sg mod NSEG, the block's kept count
+// reserving their range with one atomic.  The farthest-point key of each new
+// edge is raised.  (Round 0's input is the discard pass's per-wave regions,
+// with their edge states.)
 __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
-    const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int64_t segcap,
-    const REdge *__restrict__ tab_nxt, unsigned long long *__restrict__ far,
-    uint32_t *__restrict__ idx_out, uint64_t *__restrict__ keys_out,
-    uint16_t *__restrict__ edge_out, unsigned long long *__restrict__ cnt_out) {
-    static_assert(NSEG == WAVE, "segment lookups use one lane per segment");
+    const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int nseg_in,
+    const int64_t *__restrict__ segcap_in, const REdge *__restrict__ tab_nxt, int er2,
+    unsigned long long *__restrict__ far, uint32_t *__restrict__ idx_out,
+    uint64_t *__restrict__ keys_out, uint16_t *__restrict__ edge_out,
+    unsigned long long *__restrict__ cnt_out, int64_t segcap_out) {
     __shared__ RefFar L;
+    __shared__ REdge ltab[RE_CAP];          // the chunk's set's child edges (er2 of them)
     __shared__ int64_t scan_sh[17];
-    __shared__ int64_t pre[NSEG + 1];
     __shared__ unsigned long long out_base;
     const int tid = threadIdx.x;
-    seg_chunks(cnt_in, pre);
-    const int64_t nch = pre[NSEG];
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int sg = seg_of(pre, c);
-        const int64_t jb = sg * segcap + (c - pre[sg]) * REF_CH;
-        const int64_t je = min(sg * segcap + cnt_in[sg], jb + REF_CH);
+    const SegWalk wk(nseg_in);
+    if (wk.idle()) return;
+    const int64_t segcap = *segcap_in;
+    for (int64_t sg = wk.first_seg(); sg < nseg_in; sg += wk.lanes) {
+    const int64_t n_sg = cnt_in[sg];
+    for (int64_t ch = wk.first_part(); ch * REF_CH < n_sg; ch += wk.bps) {
+        const int64_t jb = sg * segcap + ch * REF_CH;
+        const int64_t je = sg * segcap + min(n_sg, (ch + 1) * REF_CH);
         const int64_t j0 = jb + (int64_t)tid * REF_PER_THREAD;
         uint64_t k[REF_PER_THREAD];
         uint16_t st[REF_PER_THREAD];
+        uint32_t ix[REF_PER_THREAD];
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
             const bool in = j0 + i < je;
             k[i] = in ? keys[j0 + i] : 0;
             st[i] = in ? edge[j0 + i] : RE_DROP;
+            ix[i] = in ? idx[j0 + i] : 0;
         }
         // one set in the whole chunk?  (survivors of different sets can
         // interleave, so both ends alone do not tell)
@@ -196,8 +164,10 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
         for (int i = 0; i < REF_PER_THREAD; i++)
             same = same && (j0 + i >= je || (int64_t)(k[i] >> 48) == s0);
         const bool local = __syncthreads_and(same) != 0;
-        if (local)
+        if (local) {
             for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
+            for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[s0 * RE_CAP + e];
+        }
         __syncthreads();
         int kept = 0;
 #pragma unroll
@@ -209,8 +179,9 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             uint16_t out = RE_NONE;
             double dist = 0.0;
             if (st[i] != RE_NONE) {
-                const REdge c0 = tab_nxt[s * RE_CAP + 2 * st[i]];
-                const REdge c1 = tab_nxt[s * RE_CAP + 2 * st[i] + 1];
+                const int e0 = 2 * st[i];
+                const REdge c0 = local ? ltab[e0] : tab_nxt[s * RE_CAP + e0];
+                const REdge c1 = local ? ltab[e0 + 1] : tab_nxt[s * RE_CAP + e0 + 1];
                 if (c1.ax == INT32_MIN) {            // edge without a split point
                     const double E0 = redge_eval(c0, px, py);
                     if (E0 < 0) { out = (uint16_t)(2 * st[i]); dist = -E0; }
@@ -221,20 +192,20 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
                     else if (E2 < 0) { out = (uint16_t)(2 * st[i] + 1); dist = -E2; }
                 }
             }
-            if (out != RE_NONE && out != RE_DROP) far_put(local, L, far, s, out, far_key(dist, idx[j0 + i]));
+            if (out != RE_NONE && out != RE_DROP) far_put(local, L, far, s, out, far_key(dist, ix[i]));
             st[i] = out;
             kept += out != RE_DROP;
         }
-        const int og = (int)(c & (NSEG - 1));
+        const int og = (int)(sg & (NSEG - 1));
         int64_t tot;
         int64_t pos = block_excl_scan_i64(kept, scan_sh, &tot);
         if (tid == 0) out_base = tot ? atomicAdd(&cnt_out[og], (unsigned long long)tot) : 0;
         __syncthreads();
-        pos += og * segcap + (int64_t)out_base;
+        pos += og * segcap_out + (int64_t)out_base;
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
             if (st[i] == RE_DROP) continue;
-            idx_out[pos] = idx[j0 + i];
+            idx_out[pos] = ix[i];
             keys_out[pos] = k[i];
             edge_out[pos] = st[i];
             pos++;
@@ -247,28 +218,45 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             }
         __syncthreads();
     }
+    }
 }
 
-// Segmented list (idx, keys) -> contiguous arrays; *total_out = entries.
-// Block b copies segment b mod NSEG, entries (b / NSEG) * 256 + t, stepping
-// by the blocks per segment.
+// Segmented list (idx, keys) -> contiguous arrays in segment order;
+// *total_out = entries.  Each block carries the output offset of its
+// segments forward (its own segments come `lanes` apart).
 __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__ idx,
                                                     const uint64_t *__restrict__ keys,
-                                                    const int64_t *__restrict__ cnt, int64_t segcap,
+                                                    const int64_t *__restrict__ cnt, int nseg,
+                                                    const int64_t *__restrict__ segcap_in,
                                                     uint32_t *__restrict__ idx_out,
                                                     uint64_t *__restrict__ keys_out,
                                                     int64_t *__restrict__ total_out) {
-    __shared__ int64_t pre[NSEG + 1];
-    seg_prefix(cnt, pre);
-    const int sg = (int)(blockIdx.x % NSEG);
-    const int64_t per = gridDim.x / NSEG;
-    const int64_t n = cnt[sg], dst = pre[sg], src = sg * segcap;
-    for (int64_t i = (int64_t)(blockIdx.x / NSEG) * blockDim.x + threadIdx.x; i < n;
-         i += per * blockDim.x) {
-        idx_out[dst + i] = idx[src + i];
-        keys_out[dst + i] = keys[src + i];
+    __shared__ int64_t sh[17];
+    const SegWalk wk(nseg);
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0) {
+        int64_t acc = 0;
+        for (int j = tid; j < nseg; j += blockDim.x) acc += cnt[j];
+        int64_t tot;
+        block_excl_scan_i64(acc, sh, &tot);
+        if (tid == 0) *total_out = tot;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *total_out = pre[NSEG];
+    if (wk.idle()) return;
+    const int64_t segcap = *segcap_in;
+    int64_t dst = 0, done = 0;          // dst = sum of cnt[0 .. done)
+    for (int64_t sg = wk.first_seg(); sg < nseg; sg += wk.lanes) {
+        int64_t acc = 0;
+        for (int64_t j = done + tid; j < sg; j += blockDim.x) acc += cnt[j];
+        int64_t add;
+        block_excl_scan_i64(acc, sh, &add);
+        dst += add;
+        done = sg;
+        const int64_t n = cnt[sg], src = sg * segcap;
+        for (int64_t i = wk.first_part() * blockDim.x + tid; i < n; i += wk.bps * blockDim.x) {
+            idx_out[dst + i] = idx[src + i];
+            keys_out[dst + i] = keys[src + i];
+        }
+    }
 }
 
 }  // namespace hg
