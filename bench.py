@@ -300,8 +300,12 @@ def main():
     total_pts = len(KINDS) * n
     per_kernel = {name: {"ms_total": round(ms / args.steps, 4), "launches_per_step": c / args.steps,
                          "ms_mean": round(ms / c, 4)} for name, (ms, c) in kt.items()}
-    # roofline of the dominant kernel by time per step; algorithmic bytes per launch
-    alg_bytes = {"extremes": 8.0 * n, "discard": 8.0 * n}
+    # roofline of the dominant kernel by time per step; algorithmic bytes per
+    # launch, averaged over the four sets: the extremes pass reads x and y
+    # (8 B per point); the full method's discard pass reads them and writes
+    # each survivor's index, key and round-0 edge (4 + 8 + 2 B)
+    surv_mean = sum((1.0 - disc[k]) * n for k in KINDS) / len(KINDS)
+    alg_bytes = {"extremes": 8.0 * n, "discard": 8.0 * n + 14.0 * surv_mean}
     # categories that time one kernel each (scan and misc group small helpers)
     dom = max(((k, v) for k, v in kt.items() if k not in ("scan", "misc")),
               key=lambda kv: kv[1][0])[0]

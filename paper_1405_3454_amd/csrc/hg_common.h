@@ -66,10 +66,6 @@ struct REdge {
 };
 __host__ __device__ inline REdge redge_empty() { return REdge{INT32_MIN, 0, 0, 0}; }
 
-// Unordered survivor lists of the full method are kept in NSEG segments, each
-// with its own counter (appends spread over NSEG addresses instead of one):
-// segment i holds its entries at [i * segcap, i * segcap + count[i]).
-constexpr int NSEG = 64;
 
 // Kernel kinds for the per-kernel event timer.
 enum Kind {

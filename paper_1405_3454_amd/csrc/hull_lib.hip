@@ -121,21 +121,10 @@ struct Plan {
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
         rfar1, segcnt, segmeta, cidx, ckeys, total;
     int64_t tcap, u0cap;
-    int64_t segcap;     // entries per segment of the refinement rounds' lists
-    int64_t nwave;      // discard waves = segments of the discard pass's list
+    int64_t nwave;      // discard waves = regions of the full method's survivor lists
 };
 
 static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
-
-// Entries per segment of the refinement rounds' lists, for W waves of the
-// discard pass: wave w writes the survivors of its q = ceil(T / W) tiles to
-// region w, round 0 appends region w's kept entries to segment w mod NSEG (at
-// most T / NSEG + 2q tiles of points), and later rounds keep a segment's
-// entries in the same segment.
-static int64_t seg_capacity(int64_t tcap, int64_t W) {
-    const int64_t q = (tcap + W - 1) / W;
-    return (tcap / NSEG + 2 * q + 1) * TILE;
-}
 
 static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     Plan p;
@@ -147,11 +136,10 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     };
     p.tcap = n / TILE + 2 * S + 2;
     p.u0cap = n / CHAIN_C + 2;
-    p.segcap = seg_capacity(p.tcap, W);
     p.nwave = W;
-    // list entries: the discard pass's regions end by (T + q) * TILE
-    const int64_t q = (p.tcap + W - 1) / W;
-    const size_t lcap = (size_t)std::max({n, (p.tcap + q) * TILE, NSEG * p.segcap});
+    // list entries: the discard pass's regions (q = ceil(T / W) tiles of
+    // points per wave) end by T * TILE
+    const size_t lcap = (size_t)std::max(n, p.tcap * TILE);
     p.tile_off = take((S + 1) * 8);
     p.tile_set = take(p.tcap * 4);
     p.pval = take(p.tcap * MAX_SLOTS * 8);
@@ -191,8 +179,8 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.rtab1 = take(S * RE_CAP * sizeof(REdge));
     p.rfar0 = take(S * RE_CAP * 8);
     p.rfar1 = take(S * RE_CAP * 8);
-    p.segcnt = take((W + REF_ROUNDS * NSEG) * 8);   // stage 0: W regions, then NSEG per round
-    p.segmeta = take(2 * 8);                         // [0] region size, [1] segcap
+    p.segcnt = take((REF_ROUNDS + 1) * W * 8);      // region counts per list stage
+    p.segmeta = take(8);                             // region size (q * TILE)
     p.cidx = take(n * 4 + 16);
     p.ckeys = take(n * 8 + 16);
     p.total = o;
@@ -489,10 +477,17 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
 // segment counts at stage 0 of segcnt): QuickHull splits of the filter
 // polygon's edges.  Round r appends to stage r + 1; an even number of rounds
 // ends back in surv/keys0 (ping-pong through lo0/lo1/up1, which the hull stage
-// only uses afterwards).  ctx->counts[r] records the input total of round r.
-// Segment counts of list stage r (0: the discard pass's regions).
+// only uses afterwards).
+// Region counts of list stage r (0: the discard pass's output).
 static int64_t *seg_stage(const Plan &p, int64_t *segcnt, int r) {
-    return r == 0 ? segcnt : segcnt + p.nwave + (r - 1) * NSEG;
+    return segcnt + r * p.nwave;
+}
+
+// Region size of list stage r in discard regions (q * TILE entries).
+static int64_t region_mult(int r) {
+    int64_t m = 1;
+    for (int i = 2; i <= r; i++) m *= REF_GROUP;
+    return m;
 }
 
 static_assert(HULL_NCOUNTS == 1 + REF_ROUNDS, "one count per refinement round");
@@ -507,31 +502,29 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
                                   W<unsigned long long>(ctx, p.rfar1)};
     int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
     const int64_t *meta = W<int64_t>(ctx, p.segmeta);
-    const unsigned g = (unsigned)(ctx->cus * 8);
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
         int64_t *cin = seg_stage(p, segcnt, r), *cout = seg_stage(p, segcnt, r + 1);
-        const int nin = r == 0 ? (int)p.nwave : NSEG;
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
-            x, y, S, er, tab[a], far[a], tab[b], far[b], cin, nin, cout, ctx->counts + r));
-        const unsigned gp = r == 0 ? std::max<unsigned>(g, (unsigned)p.nwave) : g;
-        LAUNCH(K_REFINE, k_ref_pass<<<gp, REF_THREADS, 0, st>>>(
-            idxs[a], keys[a], eds[a], cin, nin, meta + (r == 0 ? 0 : 1), tab[b], 2 * er, far[b],
-            idxs[b], keys[b], eds[b], reinterpret_cast<unsigned long long *>(cout), p.segcap));
+            x, y, S, er, tab[a], far[a], tab[b], far[b]));
+        const int64_t nin = stage_regions(p.nwave, r), nout = stage_regions(p.nwave, r + 1);
+        const int kg = r == 0 ? 1 : REF_GROUP;
+        LAUNCH(K_REFINE, k_ref_pass<<<(unsigned)nout, REF_THREADS, 0, st>>>(
+            idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r), tab[b], 2 * er,
+            far[b], idxs[b], keys[b], eds[b], cout, S == 1 ? 1 : 0));
     }
     return HULL_OK;
 }
 
-// Segmented list (surv, keys0) of stage `stage` -> contiguous (cidx, ckeys);
-// the total goes to *total.
-static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, int stage, int64_t *total) {
-    const int nseg = stage == 0 ? (int)p.nwave : NSEG;
-    LAUNCH(K_SCATTER, k_seg_gather<<<(unsigned)(ctx->cus * 8), 256, 0, st>>>(
-        W<uint32_t>(ctx, p.surv), W<uint64_t>(ctx, p.keys0),
-        seg_stage(p, W<int64_t>(ctx, p.segcnt), stage), nseg,
-        W<int64_t>(ctx, p.segmeta) + (stage == 0 ? 0 : 1), W<uint32_t>(ctx, p.cidx),
-        W<uint64_t>(ctx, p.ckeys), total));
+// Region list (surv, keys0) of list stage `stage` -> contiguous (cidx,
+// ckeys); ctx->counts[r] gets the total of stage r <= stage.
+static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, int stage) {
+    const int64_t gb = std::max<int64_t>(stage + 1, std::min<int64_t>(256, p.nwave));
+    LAUNCH(K_SCATTER, k_seg_gather<<<(unsigned)gb, 256, 0, st>>>(
+        W<uint32_t>(ctx, p.surv), W<uint64_t>(ctx, p.keys0), W<int64_t>(ctx, p.segcnt),
+        (int)p.nwave, stage + 1, W<int64_t>(ctx, p.segmeta), region_mult(stage),
+        W<uint32_t>(ctx, p.cidx), W<uint64_t>(ctx, p.ckeys), ctx->counts));
     return HULL_OK;
 }
 
@@ -570,8 +563,7 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
     const bool refine = !(flags & (HULL_NOREFINE | HULL_NOFILTER));
     const int64_t *cnt = ctx->counts;
     int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
-    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(ctx->counts, HULL_NCOUNTS,
-                                                   W<int64_t>(ctx, p.segmeta), p.segcap));
+    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(ctx->counts, HULL_NCOUNTS));
     if (flags & HULL_NOFILTER) {
         LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
                                                          surv_off));
@@ -598,7 +590,7 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
             return rc;
         const int stage = refine ? REF_ROUNDS : 0;
         if (refine && (rc = run_refine(ctx, p, st, x, y, S))) return rc;
-        if ((rc = run_gather(ctx, p, st, stage, ctx->counts + stage))) return rc;
+        if ((rc = run_gather(ctx, p, st, stage))) return rc;
         surv = W<uint32_t>(ctx, p.cidx);
         keys = W<uint64_t>(ctx, p.ckeys);
         cnt = ctx->counts + stage;

@@ -591,11 +591,9 @@ __global__ __launch_bounds__(256) void k_gather_keys(const float *__restrict__ x
 }
 
 // Before a computation: the recorded stage counts to -1 (stages that do not
-// run keep it) and the refinement lists' segment size to meta[1].
-__global__ void k_counts_init(int64_t *__restrict__ c, int n, int64_t *__restrict__ meta,
-                              int64_t segcap) {
+// run keep it).
+__global__ void k_counts_init(int64_t *__restrict__ c, int n) {
     if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = -1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) meta[1] = segcap;
 }
 
 __global__ void k_copy_count(const int64_t *__restrict__ src, int64_t *__restrict__ dst) {

@@ -44,27 +44,14 @@ __device__ __forceinline__ void key_point(uint64_t k, int64_t *s, double *px, do
 
 // Split every edge of round r at its farthest outside point: children 2e
 // (a->f) and 2e+1 (f->b); an edge without outside points keeps itself as
-// child 2e.  Clears the next round's farthest-point keys and the segment
-// counts the round's pass appends to, and records the round's input total.
+// child 2e.  Clears the next round's farthest-point keys.
 __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
                                                    const float *__restrict__ y, int64_t S, int er,
                                                    const REdge *__restrict__ tab,
                                                    const unsigned long long *__restrict__ far,
                                                    REdge *__restrict__ tab_nxt,
-                                                   unsigned long long *__restrict__ far_nxt,
-                                                   const int64_t *__restrict__ cnt_in, int nseg_in,
-                                                   int64_t *__restrict__ cnt_nxt,
-                                                   int64_t *__restrict__ total_in) {
-    __shared__ int64_t sh[17];
+                                                   unsigned long long *__restrict__ far_nxt) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0) {     // the whole block: record the input total
-        int64_t acc = 0;
-        for (int j = threadIdx.x; j < nseg_in; j += blockDim.x) acc += cnt_in[j];
-        int64_t tot;
-        block_excl_scan_i64(acc, sh, &tot);
-        if (threadIdx.x == 0) *total_in = tot;
-        if (threadIdx.x < NSEG) cnt_nxt[threadIdx.x] = 0;
-    }
     if (t >= S * er) return;
     const int64_t s = t / er;
     const int e = (int)(t % er);
@@ -103,73 +90,89 @@ __device__ __forceinline__ void far_put(bool local, RefFar &L, unsigned long lon
     }
 }
 
-// Blocks of a grid over the segments of a list: bps blocks per segment,
-// `lanes` segments at a time (every segment, when there are more of them than
-// blocks, goes to one block).
-struct SegWalk {
-    int64_t bps, lanes;
-    __device__ SegWalk(int64_t nseg) {
-        bps = max((int64_t)1, (int64_t)gridDim.x / max(nseg, (int64_t)1));
-        lanes = (int64_t)gridDim.x / bps;
-    }
-    __device__ bool idle() const { return (int64_t)blockIdx.x >= bps * lanes; }
-    __device__ int64_t first_seg() const { return (int64_t)blockIdx.x / bps; }
-    __device__ int64_t first_part() const { return (int64_t)blockIdx.x % bps; }
-};
+constexpr int REF_GROUP = 4;                      // input regions per block after round 0
 
-// One round over the survivors: input segment sg (region sg * segcap_in,
-// cnt_in[sg] entries) in chunks of REF_CH, thread t holding entries
-// t * REF_PER_THREAD ... of a chunk.  Each survivor is classified against the
-// two children of its edge (RE_DROP, RE_NONE or the new edge id); the kept
-// ones are appended to output segment sg mod NSEG, the block's kept count
-// reserving their range with one atomic.  The farthest-point key of each new
-// edge is raised.  (Round 0's input is the discard pass's per-wave regions,
-// with their edge states.)
+// One round over the survivors.  A list is a row of regions (region r at
+// r * segcap, cnt[r] entries; round 0 reads the discard pass's, one per
+// wave).  Block g reads regions [g * kg, (g + 1) * kg) as one list, in
+// chunks of REF_CH (thread t holds list entries t, t + REF_THREADS, ...).
+// Each survivor is classified against the two children of its edge
+// (RE_DROP, RE_NONE or the new edge id); the kept ones are packed into region
+// g (size kg * segcap) of the next list, whose count the block writes at the
+// end: no atomics.  The farthest-point key of each new edge is raised.  (Round 0's
+// input is the discard pass's regions, with their edge states.)  With one set
+// (one_set), the set's child edges are staged once per block, before the
+// first chunk's loads return, and the farthest keys are raised once per block.
 __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
-    const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int nseg_in,
-    const int64_t *__restrict__ segcap_in, const REdge *__restrict__ tab_nxt, int er2,
+    const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int nreg_in, int kg,
+    const int64_t *__restrict__ region_size, int64_t mult, const REdge *__restrict__ tab_nxt, int er2,
     unsigned long long *__restrict__ far, uint32_t *__restrict__ idx_out,
     uint64_t *__restrict__ keys_out, uint16_t *__restrict__ edge_out,
-    unsigned long long *__restrict__ cnt_out, int64_t segcap_out) {
+    int64_t *__restrict__ cnt_out, int one_set) {
+    constexpr int NW = REF_THREADS / WAVE;
     __shared__ RefFar L;
     __shared__ REdge ltab[RE_CAP];          // the chunk's set's child edges (er2 of them)
-    __shared__ int64_t scan_sh[17];
-    __shared__ unsigned long long out_base;
-    const int tid = threadIdx.x;
-    const SegWalk wk(nseg_in);
-    if (wk.idle()) return;
-    const int64_t segcap = *segcap_in;
-    for (int64_t sg = wk.first_seg(); sg < nseg_in; sg += wk.lanes) {
-    const int64_t n_sg = cnt_in[sg];
-    for (int64_t ch = wk.first_part(); ch * REF_CH < n_sg; ch += wk.bps) {
-        const int64_t jb = sg * segcap + ch * REF_CH;
-        const int64_t je = sg * segcap + min(n_sg, (ch + 1) * REF_CH);
-        const int64_t j0 = jb + (int64_t)tid * REF_PER_THREAD;
+    __shared__ uint32_t kc[REF_PER_THREAD][NW];   // kept per (element row, wave) -> offsets
+    __shared__ uint32_t ktot;
+    __shared__ int64_t pre[REF_GROUP + 1];  // list offsets of the group's regions
+    const int tid = threadIdx.x, w = tid / WAVE;
+    const int64_t g = blockIdx.x;
+    const int64_t segcap = *region_size * mult;      // input region size
+    const int64_t r0 = g * kg, nr = max((int64_t)0, min((int64_t)kg, (int64_t)nreg_in - r0));
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int j = 0; j < nr; j++) {
+            pre[j] = run;
+            run += cnt_in[r0 + j];
+        }
+        pre[nr] = run;
+    }
+    __syncthreads();
+    const int64_t n_sg = pre[nr];
+    const int64_t region = r0 * segcap;     // output region g: [region, region + kg * segcap)
+    // list entry v -> its address (regions of the group in order)
+    auto addr = [&](int64_t v) {
+        int j = 0;
+        while (j + 1 < nr && pre[j + 1] <= v) j++;
+        return (r0 + j) * segcap + (v - pre[j]);
+    };
+    int64_t outn = 0;                       // entries packed into the region so far
+    if (one_set) {
+        for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
+        for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[e];
+    }
+    for (int64_t jb = 0; jb < n_sg; jb += REF_CH) {
+        const int64_t je = min(n_sg, jb + REF_CH);
+        const int64_t j0 = jb + tid;        // element i: j0 + i * REF_THREADS (coalesced)
         uint64_t k[REF_PER_THREAD];
         uint16_t st[REF_PER_THREAD];
         uint32_t ix[REF_PER_THREAD];
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
-            const bool in = j0 + i < je;
-            k[i] = in ? keys[j0 + i] : 0;
-            st[i] = in ? edge[j0 + i] : RE_DROP;
-            ix[i] = in ? idx[j0 + i] : 0;
+            const int64_t j = j0 + (int64_t)i * REF_THREADS;
+            const bool in = j < je;
+            const int64_t a = in ? addr(j) : 0;
+            k[i] = in ? keys[a] : 0;
+            st[i] = in ? edge[a] : RE_DROP;
+            ix[i] = in ? idx[a] : 0;
         }
-        // one set in the whole chunk?  (survivors of different sets can
-        // interleave, so both ends alone do not tell)
-        const int64_t s0 = (int64_t)(keys[jb] >> 48);
-        bool same = true;
+        // one set in the whole chunk?  (a region can span sets)
+        int64_t s0 = 0;
+        bool local = true;
+        if (!one_set) {
+            s0 = (int64_t)(keys[addr(jb)] >> 48);
+            bool same = true;
 #pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++)
-            same = same && (j0 + i >= je || (int64_t)(k[i] >> 48) == s0);
-        const bool local = __syncthreads_and(same) != 0;
-        if (local) {
-            for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
-            for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[s0 * RE_CAP + e];
+            for (int i = 0; i < REF_PER_THREAD; i++)
+                same = same && (j0 + (int64_t)i * REF_THREADS >= je || (int64_t)(k[i] >> 48) == s0);
+            local = __syncthreads_and(same) != 0;
+            if (local) {
+                for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
+                for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[s0 * RE_CAP + e];
+            }
         }
         __syncthreads();
-        int kept = 0;
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
             if (st[i] == RE_DROP) continue;
@@ -184,78 +187,120 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
                 const REdge c1 = local ? ltab[e0 + 1] : tab_nxt[s * RE_CAP + e0 + 1];
                 if (c1.ax == INT32_MIN) {            // edge without a split point
                     const double E0 = redge_eval(c0, px, py);
-                    if (E0 < 0) { out = (uint16_t)(2 * st[i]); dist = -E0; }
+                    if (E0 < 0) { out = (uint16_t)e0; dist = -E0; }
                 } else {
                     const double E1 = redge_eval(c0, px, py), E2 = redge_eval(c1, px, py);
                     if (E1 > 0 && E2 > 0) out = RE_DROP;
-                    else if (E1 < 0) { out = (uint16_t)(2 * st[i]); dist = -E1; }
-                    else if (E2 < 0) { out = (uint16_t)(2 * st[i] + 1); dist = -E2; }
+                    else if (E1 < 0) { out = (uint16_t)e0; dist = -E1; }
+                    else if (E2 < 0) { out = (uint16_t)(e0 + 1); dist = -E2; }
                 }
             }
             if (out != RE_NONE && out != RE_DROP) far_put(local, L, far, s, out, far_key(dist, ix[i]));
             st[i] = out;
-            kept += out != RE_DROP;
         }
-        const int og = (int)(sg & (NSEG - 1));
-        int64_t tot;
-        int64_t pos = block_excl_scan_i64(kept, scan_sh, &tot);
-        if (tid == 0) out_base = tot ? atomicAdd(&cnt_out[og], (unsigned long long)tot) : 0;
+        // kept entries packed in (element row, wave, lane) order: every row's
+        // stores from a wave go to consecutive slots
+        uint64_t bm[REF_PER_THREAD];
+#pragma unroll
+        for (int i = 0; i < REF_PER_THREAD; i++) {
+            bm[i] = __ballot(st[i] != RE_DROP);
+            if (lane_id() == 0) kc[i][w] = (uint32_t)__popcll(bm[i]);
+        }
         __syncthreads();
-        pos += og * segcap_out + (int64_t)out_base;
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (int i = 0; i < REF_PER_THREAD; i++)
+                for (int ww = 0; ww < NW; ww++) {
+                    const uint32_t c = kc[i][ww];
+                    kc[i][ww] = run;
+                    run += c;
+                }
+            ktot = run;
+        }
+        __syncthreads();
+        const uint64_t lt = lanemask_lt();
+        const int64_t base = region + outn;
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
             if (st[i] == RE_DROP) continue;
+            const int64_t pos = base + kc[i][w] + __popcll(bm[i] & lt);
             idx_out[pos] = ix[i];
             keys_out[pos] = k[i];
             edge_out[pos] = st[i];
-            pos++;
+        }
+        outn += ktot;
+        if (!one_set) {
+            __syncthreads();
+            if (local)
+                for (int e = tid; e < RE_CAP; e += REF_THREADS) {
+                    const unsigned long long v = L.v[e];
+                    if (v) far_update(&far[s0 * RE_CAP + e], v);
+                }
         }
         __syncthreads();
-        if (local)
-            for (int e = tid; e < RE_CAP; e += REF_THREADS) {
-                const unsigned long long v = L.v[e];
-                if (v) far_update(&far[s0 * RE_CAP + e], v);
-            }
+    }
+    if (one_set) {
         __syncthreads();
+        for (int e = tid; e < er2; e += REF_THREADS) {
+            const unsigned long long v = L.v[e];
+            if (v) far_update(&far[e], v);
+        }
     }
-    }
+    if (tid == 0) cnt_out[g] = outn;
 }
 
-// Segmented list (idx, keys) -> contiguous arrays in segment order;
-// *total_out = entries.  Each block carries the output offset of its
-// segments forward (its own segments come `lanes` apart).
+// Regions of list stage r (0: the discard pass's, one per wave; round r
+// reads them and writes stage r + 1, grouping REF_GROUP regions from round 1
+// on).
+__host__ __device__ inline int64_t stage_regions(int64_t nwave, int r) {
+    int64_t n = nwave;
+    for (int i = 2; i <= r; i++) n = (n + REF_GROUP - 1) / REF_GROUP;
+    return n;
+}
+
+// Region list (idx, keys) of list stage nstage - 1 (region counts of stage r
+// at cnt_all + r * nwave) -> contiguous arrays in region order.  Block b
+// copies the consecutive regions [b * per, (b + 1) * per), starting at the
+// sum of the counts before them; totals[r] gets the entries of stage r for
+// every r < nstage.
 __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__ idx,
                                                     const uint64_t *__restrict__ keys,
-                                                    const int64_t *__restrict__ cnt, int nseg,
-                                                    const int64_t *__restrict__ segcap_in,
+                                                    const int64_t *__restrict__ cnt_all, int nwave,
+                                                    int nstage,
+                                                    const int64_t *__restrict__ region_size,
+                                                    int64_t mult,
                                                     uint32_t *__restrict__ idx_out,
                                                     uint64_t *__restrict__ keys_out,
-                                                    int64_t *__restrict__ total_out) {
+                                                    int64_t *__restrict__ totals) {
     __shared__ int64_t sh[17];
-    const SegWalk wk(nseg);
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0) {
-        int64_t acc = 0;
-        for (int j = tid; j < nseg; j += blockDim.x) acc += cnt[j];
-        int64_t tot;
-        block_excl_scan_i64(acc, sh, &tot);
-        if (tid == 0) *total_out = tot;
+    if ((int)blockIdx.x < nstage) {
+        const int64_t *c = cnt_all + (int64_t)blockIdx.x * nwave;
+        const int64_t nr = stage_regions(nwave, (int)blockIdx.x);
+        int64_t a = 0;
+        for (int64_t j = tid; j < nr; j += blockDim.x) a += c[j];
+        int64_t t;
+        block_excl_scan_i64(a, sh, &t);
+        if (tid == 0) totals[blockIdx.x] = t;
     }
-    if (wk.idle()) return;
-    const int64_t segcap = *segcap_in;
-    int64_t dst = 0, done = 0;          // dst = sum of cnt[0 .. done)
-    for (int64_t sg = wk.first_seg(); sg < nseg; sg += wk.lanes) {
-        int64_t acc = 0;
-        for (int64_t j = done + tid; j < sg; j += blockDim.x) acc += cnt[j];
-        int64_t add;
-        block_excl_scan_i64(acc, sh, &add);
-        dst += add;
-        done = sg;
+    // stage nstage - 1: its regions, of size region_size * mult
+    const int64_t *cnt = cnt_all + (int64_t)(nstage - 1) * nwave;
+    const int64_t nseg = stage_regions(nwave, nstage - 1);
+    const int64_t per = (nseg + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = min((int64_t)nseg, (int64_t)blockIdx.x * per);
+    const int64_t g1 = min((int64_t)nseg, g0 + per);
+    int64_t acc = 0;
+    for (int64_t j = tid; j < g0; j += blockDim.x) acc += cnt[j];
+    int64_t dst;
+    block_excl_scan_i64(acc, sh, &dst);
+    const int64_t segcap = *region_size * mult;
+    for (int64_t sg = g0; sg < g1; sg++) {
         const int64_t n = cnt[sg], src = sg * segcap;
-        for (int64_t i = wk.first_part() * blockDim.x + tid; i < n; i += wk.bps * blockDim.x) {
+        for (int64_t i = tid; i < n; i += blockDim.x) {
             idx_out[dst + i] = idx[src + i];
             keys_out[dst + i] = keys[src + i];
         }
+        dst += n;
     }
 }
 
