@@ -36,6 +36,7 @@ struct Poly {
     int32_t shift;      // row = (ky - ky_lo) >> shift
     int32_t ymin, ymax; // the polygon's y-range (grid units)
     int32_t pad[2];
+    int32_t vx[MAX_SLOTS], vy[MAX_SLOTS];   // vertices (grid units); edge e runs from e to e + 1
 };
 
 // One row of the polygon's y-range (ky in [y0, y1]):

@@ -300,7 +300,7 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     auto *spans = W<Span>(ctx, p.spans);
     const double *sd = W<double>(ctx, p.setdirs);
 #define K2(NEV, ND)                                                                           \
-    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<(unsigned)S, 256, 0, st>>>(                          \
+    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<(unsigned)S, POLY_THREADS, 0, st>>>(                 \
         x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
         W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
         spans, W<uint32_t>(ctx, p.redges), rtab, rfar))
@@ -311,6 +311,8 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
         if (cum) K2(12, 0); else K2(16, 0);
     }
 #undef K2
+    LAUNCH(K_POLYGON, k_rows<<<dim3((unsigned)S, SPAN_ROWS / ROWS_PER_BLOCK), 256, 0, st>>>(
+        polys, spans, W<uint32_t>(ctx, p.redges)));
     return HULL_OK;
 }
 

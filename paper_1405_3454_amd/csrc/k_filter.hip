@@ -467,8 +467,10 @@ __device__ __forceinline__ double edge_eval(double ex, double ey, double c, doub
     return fma(ex, py, fma(-ey, px, c));
 }
 
+constexpr int POLY_THREADS = 512;
+
 template <int NEV, int NDIR>
-__global__ __launch_bounds__(256) void k_polygon(
+__global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int64_t S,
     const int64_t *__restrict__ tile_off, int64_t W1, const double *__restrict__ pval,
     const uint32_t *__restrict__ pidx, const uint32_t *__restrict__ slots_in, int n_in, Dirs dirs,
@@ -479,7 +481,7 @@ __global__ __launch_bounds__(256) void k_polygon(
     // group is a copy of the 30-degree one, else 16); NDIR learned slots.
     constexpr int NS = FIXED_SLOTS + NDIR;
     constexpr int NE = NEV + NDIR;
-    __shared__ SlotBest wbest[4][MAX_SLOTS];
+    __shared__ SlotBest wbest[POLY_THREADS / WAVE][MAX_SLOTS];
     __shared__ uint32_t sl[MAX_SLOTS];
     __shared__ double gx[MAX_SLOTS], gy[MAX_SLOTS];   // slot points (grid units)
     __shared__ double sx[MAX_SLOTS], sy[MAX_SLOTS];   // sorted by (x, y, index, slot)
@@ -669,6 +671,8 @@ __global__ __launch_bounds__(256) void k_polygon(
                 vx[e] = sx[st[e]];
                 vy[e] = sy[st[e]];
             }
+            P.vx[e] = e < h ? (int32_t)sx[st[e]] : 0;
+            P.vy[e] = e < h ? (int32_t)sy[st[e]] : 0;
             if (e < h && h >= 3) {
                 int a = st[e], b = st[(e + 1) % h];
                 double ex = sx[b] - sx[a], ey = sy[b] - sy[a];
@@ -707,92 +711,7 @@ __global__ __launch_bounds__(256) void k_polygon(
     }
     __syncthreads();
 
-    // Rows: quick-accept span from the edges at the row's ends, shrunk to
-    // integers and kept only if its four corners are strictly inside; the
-    // polygon's x-extent over the row (vertices in the row and the edges'
-    // crossings of its two boundary lines); the edges whose y-range meets it.
-    for (int r = tid; r < SPAN_ROWS; r += blockDim.x) {
-        Span sp{1, 0, INT32_MAX, INT32_MIN};
-        uint32_t re = ROW_EDGES_ALL;
-        if (P.yspan >= 0) {
-            int64_t y0 = (int64_t)P.ky_lo + ((int64_t)r << P.shift);
-            int64_t y1 = min(y0 + (int64_t(1) << P.shift) - 1, (int64_t)P.ky_lo + P.yspan);
-            if (y0 <= (int64_t)P.ky_lo + P.yspan) {
-                const double fy0 = (double)y0, fy1 = (double)y1;
-                double xl = -1e300, xr = 1e300, mnx = 1e300, mxx = -1e300;
-                bool ok = true;
-                int ne = 0;
-                re = 0;
-                for (int e = 0; e < P.m; e++) {
-                    const double ex = P.ex[e], ey = P.ey[e];
-                    const double ax = vx[e], ay = vy[e];     // edge e runs from vertex e to e+1
-                    const double by = ay + ey;
-                    if (ey > 0) {
-                        xr = fmin(xr, fmin(ax + ex * (fy0 - ay) / ey, ax + ex * (fy1 - ay) / ey));
-                    } else if (ey < 0) {
-                        xl = fmax(xl, fmax(ax + ex * (fy0 - ay) / ey, ax + ex * (fy1 - ay) / ey));
-                    } else if (ex > 0) {
-                        if (fy0 <= ay) ok = false;      // bottom edge
-                    } else if (ex < 0) {
-                        if (fy1 >= ay) ok = false;      // top edge
-                    }
-                    if (ay >= fy0 && ay <= fy1) {
-                        mnx = fmin(mnx, ax);
-                        mxx = fmax(mxx, ax);
-                    }
-                    const double elo = fmin(ay, by), ehi = fmax(ay, by);
-                    if (ey != 0) {
-                        for (int b2 = 0; b2 < 2; b2++) {
-                            const double yy = b2 ? fy1 : fy0;
-                            if (elo <= yy && yy <= ehi) {
-                                const double xx = ax + ex * (yy - ay) / ey;
-                                mnx = fmin(mnx, xx);
-                                mxx = fmax(mxx, xx);
-                            }
-                        }
-                    }
-                    if (elo <= fy1 && ehi >= fy0) {
-                        if (ne < 4) re |= (uint32_t)e << (8 * ne);
-                        ne++;
-                    }
-                }
-                if (ne > 4) re = ROW_EDGES_ALL;
-                else
-                    for (int k = ne; k < 4; k++) re |= ROW_EDGE_NONE << (8 * k);
-                // the crossings carry at most a few ulps of rounding; one grid
-                // unit of margin keeps the outer test conservative
-                if (mnx <= mxx) {
-                    sp.ol = (int32_t)floor(mnx) - 1;
-                    sp.orr = (int32_t)ceil(mxx) + 1;
-                } else {
-                    sp.ol = INT32_MIN;      // unreachable: keep every point for the exact test
-                    sp.orr = INT32_MAX;
-                    re = ROW_EDGES_ALL;
-                }
-                if (ok && xl > -1e299 && xr < 1e299) {
-                    double fl = floor(xl) + 1.0, fr = ceil(xr) - 1.0;
-                    for (int attempt = 0; attempt < 3 && fl <= fr; attempt++) {
-                        bool good = true;
-                        double cx[2] = {fl, fr}, cy[2] = {fy0, fy1};
-                        for (int e = 0; e < P.m && good; e++)
-                            for (int a2 = 0; a2 < 2; a2++)
-                                for (int b2 = 0; b2 < 2; b2++)
-                                    if (!(edge_eval(P.ex[e], P.ey[e], P.c[e], cx[a2], cy[b2]) > 0))
-                                        good = false;
-                        if (good) {
-                            sp.xl = (int32_t)fl;
-                            sp.xr = (int32_t)fr;
-                            break;
-                        }
-                        fl += 2.0;
-                        fr -= 2.0;
-                    }
-                }
-            }
-        }
-        spans[s * SPAN_ROWS + r] = sp;
-        redges[s * SPAN_ROWS + r] = re;
-    }
+    __syncthreads();
     if (tid == 0) polys[s] = P;
     if (rtab) {    // the refinement's round-0 edges (the polygon's) and cleared farthest keys
         const int m = P.m >= 3 ? P.m : 0;
@@ -805,6 +724,141 @@ __global__ __launch_bounds__(256) void k_polygon(
             rtab[s * RE_CAP + e] = r;
             rfar[s * RE_CAP + e] = 0;
         }
+    }
+}
+
+// Rows of each set's polygon (after k_polygon): quick-accept span from the
+// edges at the row's ends, shrunk to integers and kept only if its four
+// corners are strictly inside; the polygon's x-extent over the row (vertices
+// in the row and the edges' crossings of its two boundary lines); the edges
+// whose y-range meets it.  Block (s, b) does rows 16b .. 16b + 15 of set s,
+// 16 lanes per row, lane l taking edges l and l + 16; the lanes' results meet
+// by shuffles within the row's 16 lanes.
+constexpr int ROWS_PER_BLOCK = 16;
+
+__device__ __forceinline__ double row_min(double v) {
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double row_max(double v) {
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ uint32_t row_or(uint32_t v) {
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_rows(const Poly *__restrict__ polys,
+                                              Span *__restrict__ spans,
+                                              uint32_t *__restrict__ redges) {
+    static_assert(MAX_SLOTS <= 32, "two edges per lane");
+    const int64_t s = blockIdx.x;
+    const int tid = threadIdx.x, el = tid & 15;
+    const int r = blockIdx.y * ROWS_PER_BLOCK + (tid >> 4);
+    const Poly &P = polys[s];
+    const int m = P.m;
+    Span sp{1, 0, INT32_MAX, INT32_MIN};
+    uint32_t re = ROW_EDGES_ALL;
+    const int64_t ytop = (int64_t)P.ky_lo + P.yspan;
+    const int64_t y0 = (int64_t)P.ky_lo + ((int64_t)r << P.shift);
+    // (uniform per row: all 16 lanes of a row take the same branches)
+    if (P.yspan >= 0 && y0 <= ytop) {
+        const int64_t y1 = min(y0 + (int64_t(1) << P.shift) - 1, ytop);
+        const double fy0 = (double)y0, fy1 = (double)y1;
+        double xl = -1e300, xr = 1e300, mnx = 1e300, mxx = -1e300;
+        uint32_t bad = 0, meets = 0;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int e = el + 16 * h;
+            if (e >= m) continue;
+            const double ex = P.ex[e], ey = P.ey[e];
+            const double ax = (double)P.vx[e], ay = (double)P.vy[e];
+            const double by = ay + ey;
+            if (ey > 0) {
+                xr = fmin(xr, fmin(ax + ex * (fy0 - ay) / ey, ax + ex * (fy1 - ay) / ey));
+            } else if (ey < 0) {
+                xl = fmax(xl, fmax(ax + ex * (fy0 - ay) / ey, ax + ex * (fy1 - ay) / ey));
+            } else if (ex > 0) {
+                if (fy0 <= ay) bad = 1;      // bottom edge
+            } else if (ex < 0) {
+                if (fy1 >= ay) bad = 1;      // top edge
+            }
+            if (ay >= fy0 && ay <= fy1) {
+                mnx = fmin(mnx, ax);
+                mxx = fmax(mxx, ax);
+            }
+            const double elo = fmin(ay, by), ehi = fmax(ay, by);
+            if (ey != 0) {
+                for (int b2 = 0; b2 < 2; b2++) {
+                    const double yy = b2 ? fy1 : fy0;
+                    if (elo <= yy && yy <= ehi) {
+                        const double xx = ax + ex * (yy - ay) / ey;
+                        mnx = fmin(mnx, xx);
+                        mxx = fmax(mxx, xx);
+                    }
+                }
+            }
+            if (elo <= fy1 && ehi >= fy0) meets |= 1u << e;
+        }
+        xl = row_max(xl);
+        xr = row_min(xr);
+        mnx = row_min(mnx);
+        mxx = row_max(mxx);
+        bad = row_or(bad);
+        meets = row_or(meets);
+        // the lowest four edges meeting the row, in order
+        const int ne = __popc(meets);
+        if (ne > 4) {
+            re = ROW_EDGES_ALL;
+        } else {
+            re = 0;
+            uint32_t mm = meets;
+            for (int k = 0; k < 4; k++) {
+                const uint32_t e = mm ? (uint32_t)__ffs(mm) - 1 : ROW_EDGE_NONE;
+                re |= e << (8 * k);
+                mm &= mm - 1;
+            }
+        }
+        // the crossings carry at most a few ulps of rounding; one grid unit of
+        // margin keeps the outer test conservative
+        if (mnx <= mxx) {
+            sp.ol = (int32_t)floor(mnx) - 1;
+            sp.orr = (int32_t)ceil(mxx) + 1;
+        } else {
+            sp.ol = INT32_MIN;      // unreachable: keep every point for the exact test
+            sp.orr = INT32_MAX;
+            re = ROW_EDGES_ALL;
+        }
+        if (!bad && xl > -1e299 && xr < 1e299) {
+            double fl = floor(xl) + 1.0, fr = ceil(xr) - 1.0;
+            for (int attempt = 0; attempt < 3 && fl <= fr; attempt++) {
+                uint32_t fail = 0;
+                const double cx[2] = {fl, fr}, cy[2] = {fy0, fy1};
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int e = el + 16 * h;
+                    if (e >= m) continue;
+                    for (int a2 = 0; a2 < 2; a2++)
+                        for (int b2 = 0; b2 < 2; b2++)
+                            if (!(edge_eval(P.ex[e], P.ey[e], P.c[e], cx[a2], cy[b2]) > 0)) fail = 1;
+                }
+                if (!row_or(fail)) {
+                    sp.xl = (int32_t)fl;
+                    sp.xr = (int32_t)fr;
+                    break;
+                }
+                fl += 2.0;
+                fr -= 2.0;
+            }
+        }
+    }
+    if (el == 0 && r < SPAN_ROWS) {
+        spans[s * SPAN_ROWS + r] = sp;
+        redges[s * SPAN_ROWS + r] = re;
     }
 }
 
