@@ -119,7 +119,7 @@ struct Plan {
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
-        rfar1, segcnt, segmeta, cidx, ckeys, total;
+        rfar1, segcnt, segmeta, cidx, ckeys, bpart, pticket, total;
     int64_t tcap, u0cap;
     int64_t nwave;      // discard waves = regions of the full method's survivor lists
 };
@@ -181,6 +181,8 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.rfar1 = take(S * RE_CAP * 8);
     p.segcnt = take((REF_ROUNDS + 1) * W * 8);      // region counts per list stage
     p.segmeta = take(8);                             // region size (q * TILE)
+    p.bpart = take(S * POLY_SPLIT * MAX_SLOTS * sizeof(SlotBest));
+    p.pticket = take(S * 4);
     p.cidx = take(n * 4 + 16);
     p.ckeys = take(n * 8 + 16);
     p.total = o;
@@ -260,7 +262,8 @@ static int run_validate(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
 static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const int64_t *off, int64_t n1, int64_t S) {
     int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
-    LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, phase_of(x), tile_off));
+    LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, phase_of(x), tile_off,
+                                                         W<uint32_t>(ctx, p.pticket)));
     LAUNCH(K_TILEMAP, k_tile_sets<<<(unsigned)std::min<int64_t>(ctx->cus * 4, (p.tcap + 255) / 256), 256,
                                      0, st>>>(tile_off, S, W<int32_t>(ctx, p.tile_set)));
     return HULL_OK;
@@ -300,10 +303,12 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     auto *spans = W<Span>(ctx, p.spans);
     const double *sd = W<double>(ctx, p.setdirs);
 #define K2(NEV, ND)                                                                           \
-    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<(unsigned)S, POLY_THREADS, 0, st>>>(                 \
+    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<dim3((unsigned)S, slots_in ? 1 : POLY_SPLIT),       \
+                                           POLY_THREADS, 0, st>>>(                             \
         x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
         W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
-        spans, W<uint32_t>(ctx, p.redges), rtab, rfar))
+        spans, W<uint32_t>(ctx, p.redges), rtab, rfar, W<SlotBest>(ctx, p.bpart),             \
+        W<uint32_t>(ctx, p.pticket)))
     const bool cum = ctx->preset == HULL_DIRS_CUMULATIVE;
     if (learned) {
         if (cum) K2(12, MAX_DIRS); else K2(16, MAX_DIRS);

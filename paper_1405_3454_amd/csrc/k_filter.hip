@@ -27,8 +27,11 @@ __device__ __forceinline__ int64_t tile_base(int64_t o, int phase) {
 // counts), tile_off[S] = T.  One block of 1024 threads.
 __global__ __launch_bounds__(1024) void k_tile_offsets(const int64_t *__restrict__ off,
                                                        int64_t n1, int64_t S, int64_t unit,
-                                                       int phase, int64_t *__restrict__ tile_off) {
+                                                       int phase, int64_t *__restrict__ tile_off,
+                                                       uint32_t *__restrict__ zero) {
     __shared__ int64_t sh[17];
+    if (zero)     // per-set tickets of the polygon kernel
+        for (int64_t s = threadIdx.x; s < S; s += blockDim.x) zero[s] = 0;
     int64_t carry = 0;
     for (int64_t base = 0; base < S; base += blockDim.x) {
         int64_t s = base + threadIdx.x;
@@ -468,6 +471,7 @@ __device__ __forceinline__ double edge_eval(double ex, double ey, double c, doub
 }
 
 constexpr int POLY_THREADS = 512;
+constexpr int POLY_SPLIT = 16;     // blocks per set sharing the extremes pass's partials
 
 template <int NEV, int NDIR>
 __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
@@ -476,9 +480,14 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     const uint32_t *__restrict__ pidx, const uint32_t *__restrict__ slots_in, int n_in, Dirs dirs,
     const double *__restrict__ set_dirs, uint32_t *__restrict__ slots_out,
     double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans,
-    uint32_t *__restrict__ redges, REdge *__restrict__ rtab, unsigned long long *__restrict__ rfar) {
+    uint32_t *__restrict__ redges, REdge *__restrict__ rtab, unsigned long long *__restrict__ rfar,
+    SlotBest *__restrict__ bpart, uint32_t *__restrict__ ticket) {
     // NEV: fixed slots the extremes pass evaluated (12 when the 120-degree
     // group is a copy of the 30-degree one, else 16); NDIR learned slots.
+    // Grid (S, POLY_SPLIT): block (s, y) reduces its share of set s's
+    // partials; the last of the set's blocks to finish (per-set ticket,
+    // zeroed by k_tile_offsets, reset here) combines the shares in bpart and
+    // builds the polygon.  With slots_in the grid is (S, 1).
     constexpr int NS = FIXED_SLOTS + NDIR;
     constexpr int NE = NEV + NDIR;
     __shared__ SlotBest wbest[POLY_THREADS / WAVE][MAX_SLOTS];
@@ -489,6 +498,7 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     __shared__ int st[2 * MAX_SLOTS + 2];
     __shared__ double vx[MAX_SLOTS], vy[MAX_SLOTS];   // polygon vertices
     __shared__ int nvalid;
+    __shared__ bool last;
     __shared__ Poly P;
     const int64_t s = blockIdx.x;
     const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
@@ -515,8 +525,9 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
             bi[k] = NONE;
         }
         // two runs per iteration so that both runs' loads are in flight together
-        for (int64_t r = tid; r < nruns; r += 2 * blockDim.x) {
-            const int64_t r2 = r + blockDim.x;
+        const int64_t step = (int64_t)gridDim.y * blockDim.x;
+        for (int64_t r = (int64_t)blockIdx.y * blockDim.x + tid; r < nruns; r += 2 * step) {
+            const int64_t r2 = r + step;
             const int64_t t = r == 0 ? ta : m0 + (r - 1) * q;
             const int64_t t2 = r2 < nruns ? m0 + (r2 - 1) * q : t;
             double v1[NE], v2[NE];
@@ -568,9 +579,37 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
                     i = b.i;
                 }
             }
+            wbest[0][tid] = SlotBest{v, i};
+        }
+        if (gridDim.y > 1) {     // publish this block's share; the set's last block goes on
+            // (the share is written by the first wave, whose fence publishes it)
+            if (tid < NE) bpart[(s * gridDim.y + blockIdx.y) * MAX_SLOTS + tid] = wbest[0][tid];
+            __syncthreads();
+            if (tid == 0) {
+                __threadfence();
+                last = atomicAdd(&ticket[s], 1u) == gridDim.y - 1;
+                if (last) {
+                    __threadfence();
+                    ticket[s] = 0;
+                }
+            }
+            __syncthreads();
+            if (!last) return;
+            if (tid < NE) {
+                const bool mn = slot_is_min(tid, NEV);
+                SlotBest b0 = bpart[(s * gridDim.y) * MAX_SLOTS + tid];
+                for (int yy = 1; yy < (int)gridDim.y; yy++) {
+                    const SlotBest b = bpart[(s * gridDim.y + yy) * MAX_SLOTS + tid];
+                    if (b.i != NONE && (b0.i == NONE || better(mn, b.v, b.i, b0.v, b0.i))) b0 = b;
+                }
+                wbest[0][tid] = b0;
+            }
+            __syncthreads();
+        }
+        if (tid < NE) {
             // partial slot k < NEV holds fixed slot k; learned slots follow
             int dst = tid < NEV ? tid : FIXED_SLOTS + (tid - NEV);
-            sl[dst] = i;
+            sl[dst] = wbest[0][tid].i;
         }
         if (NDIR == 0 && tid >= FIXED_SLOTS && tid < MAX_SLOTS) sl[tid] = NONE;
         __syncthreads();

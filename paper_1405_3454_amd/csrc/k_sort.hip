@@ -57,9 +57,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__re
         atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
     __syncthreads();
     hist[tid * SORT_BLOCKS + blockIdx.x] = h[tid];
+    __threadfence();   // every wave publishes its part of the block's column
     __syncthreads();
-    if (tid == 0) {    // one device-scope fence per block publishes the block's row
-        __threadfence();
+    if (tid == 0) {
         last = atomicAdd(ticket, 1u) == (uint32_t)nb - 1;
         if (last) __threadfence();
     }
