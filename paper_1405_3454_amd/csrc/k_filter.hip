@@ -496,6 +496,7 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     __shared__ double sx[MAX_SLOTS], sy[MAX_SLOTS];   // sorted by (x, y, index, slot)
     __shared__ uint32_t si[MAX_SLOTS];
     __shared__ int st[2 * MAX_SLOTS + 2];
+    __shared__ int lc[MAX_SLOTS], uc[MAX_SLOTS], hcount;   // lower / upper chain positions
     __shared__ double vx[MAX_SLOTS], vy[MAX_SLOTS];   // polygon vertices
     __shared__ int nvalid;
     __shared__ bool last;
@@ -552,19 +553,12 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
                 }
             }
         }
+        // the wave's best per slot: extreme value, then the lowest index
+        // holding it (lanes without a candidate hold the identity, +-inf)
 #pragma unroll
         for (int k = 0; k < NE; k++) {
-            double v = bv[k];
-            uint32_t i = bi[k];
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                double v2 = __shfl_xor(v, o);
-                uint32_t i2 = __shfl_xor(i, o);
-                if (i2 != NONE && (i == NONE || better(slot_is_min(k, NEV), v2, i2, v, i))) {
-                    v = v2;
-                    i = i2;
-                }
-            }
+            const double v = slot_is_min(k, NEV) ? wave_extreme<true>(bv[k]) : wave_extreme<false>(bv[k]);
+            const uint32_t i = wave_min_u32(bv[k] == v ? bi[k] : NONE);
             if (lane == 0) wbest[w][k] = SlotBest{v, i};
         }
         __syncthreads();
@@ -671,37 +665,67 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     }
     __syncthreads();
 
-    // Andrew's monotone chain on the sorted slot points (thread 0, LDS)
-    if (tid == 0) {
+    // Andrew's chains on the sorted slot points, by the first wave: repeated
+    // coordinates dropped (the lowest index stays first), then the lower and
+    // the upper chain pruned in parallel: a point on or beyond the segment of
+    // its two neighbours is no strict vertex, and once a pass drops nothing
+    // each list turns strictly one way at every point (at most MAX_SLOTS
+    // passes: each earlier pass drops a point)
+    if (w == 0) {
+        const uint64_t lt = lanemask_lt();
         const int k = nvalid;
-        int u = 0;
-        for (int j = 0; j < k; j++)
-            if (u == 0 || sx[j] != sx[u - 1] || sy[j] != sy[u - 1]) {
-                sx[u] = sx[j];
-                sy[u] = sy[j];
-                si[u] = si[j];
-                u++;
-            }
-        int h = 0;
-        if (u == 1) {
-            st[0] = 0;
-            h = 1;
-        } else if (u >= 2) {
-            for (int j = 0; j < u; j++) {
-                while (h >= 2 && orient(sx[st[h - 2]], sy[st[h - 2]], sx[st[h - 1]], sy[st[h - 1]],
-                                        sx[j], sy[j]) <= 0)
-                    h--;
-                st[h++] = j;
-            }
-            int lo = h + 1;
-            for (int j = u - 2; j >= 0; j--) {
-                while (h >= lo && orient(sx[st[h - 2]], sy[st[h - 2]], sx[st[h - 1]], sy[st[h - 1]],
-                                         sx[j], sy[j]) <= 0)
-                    h--;
-                st[h++] = j;
-            }
-            h--;
+        bool keep = false;
+        double ax = 0.0, ay = 0.0;
+        uint32_t ai = 0;
+        if (lane < k) {
+            ax = sx[lane];
+            ay = sy[lane];
+            ai = si[lane];
+            keep = lane == 0 || ax != sx[lane - 1] || ay != sy[lane - 1];
         }
+        const uint64_t bk = __ballot(keep);
+        const int u = __popcll(bk);
+        wave_sync();
+        if (keep) {
+            const int p = __popcll(bk & lt);
+            sx[p] = ax;
+            sy[p] = ay;
+            si[p] = ai;
+            lc[p] = p;
+            uc[p] = p;
+        }
+        wave_sync();
+        int nl = u, nu = u;
+        for (int pass = 0; pass < MAX_SLOTS; pass++) {
+            bool kl = lane < nl, ku = lane < nu;
+            const int ml = kl ? lc[lane] : 0, mu = ku ? uc[lane] : 0;
+            if (lane > 0 && lane + 1 < nl) {
+                const int pa = lc[lane - 1], pc = lc[lane + 1];
+                if (orient(sx[pa], sy[pa], sx[ml], sy[ml], sx[pc], sy[pc]) <= 0) kl = false;
+            }
+            if (lane > 0 && lane + 1 < nu) {
+                const int pa = uc[lane - 1], pc = uc[lane + 1];
+                if (orient(sx[pa], sy[pa], sx[mu], sy[mu], sx[pc], sy[pc]) >= 0) ku = false;
+            }
+            const uint64_t bl = __ballot(kl), bu = __ballot(ku);
+            wave_sync();
+            if (kl) lc[__popcll(bl & lt)] = ml;
+            if (ku) uc[__popcll(bu & lt)] = mu;
+            wave_sync();
+            const int nl2 = __popcll(bl), nu2 = __popcll(bu);
+            if (nl2 == nl && nu2 == nu) break;
+            nl = nl2;
+            nu = nu2;
+        }
+        // counter-clockwise from the lowest point: the lower chain, then the
+        // upper chain's interior backwards
+        const int h = u == 0 ? 0 : (u == 1 ? 1 : nl + nu - 2);
+        if (lane < h) st[lane] = lane < nl ? lc[lane] : uc[nu - 2 - (lane - nl)];
+        if (lane == 0) hcount = h;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int h = hcount;
         P.m = h;
         int ylo = 0x7fffffff, yhi = -1;
         for (int e = 0; e < MAX_SLOTS; e++) {
