@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--log2n", type=int, default=27)
     ap.add_argument("--preset", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26,
+    ap.add_argument("--cpu-sample", type=int, default=1 << 27,
                     help="points of each set the CPU oracle is timed on")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--batch-sets", type=int, default=4096)

@@ -302,9 +302,12 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     auto *polys = W<Poly>(ctx, p.polys);
     auto *spans = W<Span>(ctx, p.spans);
     const double *sd = W<double>(ctx, p.setdirs);
+    // blocks per set sharing the reduction of the extremes partials: about one
+    // per POLY_THREADS of the set's runs (W1 / S on average)
+    const unsigned split = slots_in ? 1u
+        : (unsigned)std::max<int64_t>(1, std::min<int64_t>(POLY_SPLIT, W1 / (S * POLY_THREADS / 16)));
 #define K2(NEV, ND)                                                                           \
-    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<dim3((unsigned)S, slots_in ? 1 : POLY_SPLIT),       \
-                                           POLY_THREADS, 0, st>>>(                             \
+    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<dim3((unsigned)S, split), POLY_THREADS, 0, st>>>(     \
         x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
         W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
         spans, W<uint32_t>(ctx, p.redges), rtab, rfar, W<SlotBest>(ctx, p.bpart),             \

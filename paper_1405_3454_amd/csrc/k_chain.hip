@@ -8,9 +8,9 @@
 //     lower and the upper chain of its chunk (duplicates dropped; a point
 //     goes while it does not make a strict turn, so collinear points go).
 //  2. k_chain_merge: one wave per group of CHAIN_G neighbouring chains joins
-//     them: the chains side by side are pruned like a chunk (below), or, for
-//     groups too large for LDS, joined left to right, the tail of the chain
-//     built so far and the head of the next one walked to their common
+//     them: at the first level the chains side by side are pruned like a
+//     chunk (below); above it they are joined left to right, the tail of the
+//     chain built so far and the head of the next one walked to their common
 //     tangent (the bridge) at each junction.  Repeated until one chain per
 //     kind is left.
 //  3. Per set: the lower chain followed by the upper chain's interior in
@@ -319,13 +319,14 @@ __device__ __forceinline__ int64_t bridge(PO o, int64_t len, int64_t tailseg, PC
 }
 
 // Merge of CHAIN_G neighbouring chains by one wave.  Groups that fit are
-// staged in LDS and pruned in parallel (serial chain only when the passes run
-// out); larger ones walk the junction bridges in global memory.
+// staged in LDS: at level 0 (many short chains) pruned in parallel (serial
+// chain only when the passes run out), above it (few long chains) joined by
+// serial bridge walks; larger groups walk the bridges in global memory.
 constexpr int MERGE_CAP = 4096;           // keys staged per wave (32 KB)
 
 template <bool UPPER>
 __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__restrict__ cin,
-                            int64_t U, int64_t R, int64_t v, uint64_t *__restrict__ out,
+                            int64_t U, int64_t R, int64_t v, int lev, uint64_t *__restrict__ out,
                             uint32_t *__restrict__ cout, uint64_t *__restrict__ buf) {
     const int lane = lane_id();
     const int64_t base = v * R * CHAIN_G;
@@ -336,9 +337,48 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
     int64_t incl = wave_incl_scan_i64(mine);
     const int64_t M = __shfl(incl, WAVE - 1);
     int64_t len = 0, tailseg = 0;
-    if (M <= MERGE_CAP) {
-        // the group's chains side by side form one x-sorted list holding every
-        // vertex of the merged chain: prune it in place like a level-0 chunk
+    const int nonempty = __popcll(__ballot(mine > 0));
+    if (M <= MERGE_CAP && (nonempty <= 1 || lev > 0)) {
+        // a single chain is copied; a few long chains (the upper levels) are
+        // joined left to right in LDS, walking each junction to its bridge
+        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+            const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
+            const uint64_t *src = in + (u0 + g) * R;
+            for (int64_t i = lane; i < m; i += WAVE) buf[og + i] = src[i];
+        }
+        wave_sync();
+        if (nonempty <= 1) {
+            len = M;
+        } else {
+            for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+                const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
+                if (m == 0) continue;
+                const uint64_t *c = buf + og;
+                int64_t b;
+                len = bridge<UPPER>(buf, len, tailseg, c, m, &b);
+                if (b < m) {
+                    int64_t ls = last_seg_start(c, b, m);
+                    int64_t newtail;
+                    if (ls > b) newtail = len + (ls - b);
+                    else newtail = (len > 0 && key_set(buf[len - 1]) == key_set(c[b])) ? tailseg : len;
+                    // move c[b..m) down to buf[len..): len <= og + b, copy forward
+                    for (int64_t i0 = 0; i0 < m - b; i0 += WAVE) {
+                        int64_t i = i0 + lane;
+                        uint64_t val = i < m - b ? c[b + i] : 0;
+                        wave_sync();
+                        if (i < m - b) buf[len + i] = val;
+                        wave_sync();
+                    }
+                    len += m - b;
+                    tailseg = newtail;
+                }
+            }
+        }
+        for (int64_t i = lane; i < len; i += WAVE) o[i] = buf[i];
+    } else if (M <= MERGE_CAP) {
+        // level 0: many short chains side by side form one x-sorted list
+        // holding every vertex of the merged chain: prune it in place like a
+        // level-0 chunk
         for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
             const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
             const uint64_t *src = in + (u0 + g) * R;
@@ -407,8 +447,8 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
         (blockIdx.y == 0 ? lo_cout : up_cout)[0] = 0;
     uint64_t *buf = mbuf[threadIdx.x >> 6];
     for (int64_t v = wave; v < V; v += nw) {        // groups the count actually has
-        if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lo_out, lo_cout, buf);
-        else merge_group<true>(up_in, up_cin, U, R, v, up_out, up_cout, buf);
+        if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lev, lo_out, lo_cout, buf);
+        else merge_group<true>(up_in, up_cin, U, R, v, lev, up_out, up_cout, buf);
         wave_sync();
     }
 }
