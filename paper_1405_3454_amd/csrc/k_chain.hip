@@ -338,18 +338,23 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
     const int64_t M = __shfl(incl, WAVE - 1);
     int64_t len = 0, tailseg = 0;
     const int nonempty = __popcll(__ballot(mine > 0));
-    if (M <= MERGE_CAP && (nonempty <= 1 || lev > 0)) {
-        // a single chain is copied; a few long chains (the upper levels) are
-        // joined left to right in LDS, walking each junction to its bridge
+    if (nonempty <= 1) {     // one chain: copied as it is
+        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+            const int64_t m = __shfl(mine, g);
+            const uint64_t *src = in + (u0 + g) * R;
+            for (int64_t i = lane; i < m; i += WAVE) o[i] = src[i];
+        }
+        len = M;
+    } else if (M <= MERGE_CAP && lev > 0) {
+        // a few long chains (the upper levels): joined left to right in LDS,
+        // walking each junction to its bridge
         for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
             const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
             const uint64_t *src = in + (u0 + g) * R;
             for (int64_t i = lane; i < m; i += WAVE) buf[og + i] = src[i];
         }
         wave_sync();
-        if (nonempty <= 1) {
-            len = M;
-        } else {
+        {
             for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
                 const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
                 if (m == 0) continue;
