@@ -496,7 +496,7 @@ static int64_t *seg_stage(const Plan &p, int64_t *segcnt, int r) {
 // Region size of list stage r in discard regions (q * TILE entries).
 static int64_t region_mult(int r) {
     int64_t m = 1;
-    for (int i = 2; i <= r; i++) m *= REF_GROUP;
+    for (int i = 0; i < r; i++) m *= ref_group(i);
     return m;
 }
 
@@ -519,7 +519,7 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
             x, y, S, er, tab[a], far[a], tab[b], far[b]));
         const int64_t nin = stage_regions(p.nwave, r), nout = stage_regions(p.nwave, r + 1);
-        const int kg = r == 0 ? 1 : REF_GROUP;
+        const int kg = ref_group(r);
         LAUNCH(K_REFINE, k_ref_pass<<<(unsigned)nout, REF_THREADS, 0, st>>>(
             idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r), tab[b], 2 * er,
             far[b], idxs[b], keys[b], eds[b], cout, S == 1 ? 1 : 0));

@@ -13,7 +13,7 @@
 // drops change the work, never the hull.  Repeated coordinates share every
 // test, so all copies of a point stay or go together, and the hull stage picks
 // the lowest index among them whatever order the kept survivors are in: each
-// round appends them with one atomic allocation per chunk.
+// round packs them into its blocks' own output regions.
 //
 // Distances are exact edge functions in grid units (binary64, |E| < 2^52 on
 // the grid); the farthest point per edge is the maximum of the packed key
@@ -90,7 +90,9 @@ __device__ __forceinline__ void far_put(bool local, RefFar &L, unsigned long lon
     }
 }
 
-constexpr int REF_GROUP = 4;                      // input regions per block after round 0
+constexpr int REF_GROUP = 4;                      // most input regions one block reads
+// input regions per block in round r: fuller chunks early, enough blocks late
+__host__ __device__ inline int ref_group(int r) { return r == 0 ? 4 : 2; }
 
 // One round over the survivors.  A list is a row of regions (region r at
 // r * segcap, cnt[r] entries; round 0 reads the discard pass's, one per
@@ -250,11 +252,10 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
 }
 
 // Regions of list stage r (0: the discard pass's, one per wave; round r
-// reads them and writes stage r + 1, grouping REF_GROUP regions from round 1
-// on).
+// reads them and writes stage r + 1, one region per group of ref_group(r)).
 __host__ __device__ inline int64_t stage_regions(int64_t nwave, int r) {
     int64_t n = nwave;
-    for (int i = 2; i <= r; i++) n = (n + REF_GROUP - 1) / REF_GROUP;
+    for (int i = 0; i < r; i++) n = (n + ref_group(i) - 1) / ref_group(i);
     return n;
 }
 
