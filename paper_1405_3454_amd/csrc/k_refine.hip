@@ -209,15 +209,13 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             if (lane_id() == 0) kc[i][w] = (uint32_t)__popcll(bm[i]);
         }
         __syncthreads();
-        if (tid == 0) {
-            uint32_t run = 0;
-            for (int i = 0; i < REF_PER_THREAD; i++)
-                for (int ww = 0; ww < NW; ww++) {
-                    const uint32_t c = kc[i][ww];
-                    kc[i][ww] = run;
-                    run += c;
-                }
-            ktot = run;
+        if (tid < WAVE) {     // exclusive prefix over (row, wave) in one wave
+            static_assert(REF_PER_THREAD * NW <= WAVE, "one lane per (row, wave)");
+            uint32_t *flat = &kc[0][0];
+            const uint32_t c = tid < REF_PER_THREAD * NW ? flat[tid] : 0;
+            const uint32_t inc = (uint32_t)wave_incl_scan_i64(c);
+            if (tid < REF_PER_THREAD * NW) flat[tid] = inc - c;
+            if (tid == WAVE - 1) ktot = inc;
         }
         __syncthreads();
         const uint64_t lt = lanemask_lt();
