@@ -132,6 +132,10 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     }
     __syncthreads();
     const int64_t n_sg = pre[nr];
+    if (n_sg == 0) {                        // nothing to read: an empty region, no far keys
+        if (tid == 0) cnt_out[g] = 0;
+        return;
+    }
     const int64_t region = r0 * segcap;     // output region g: [region, region + kg * segcap)
     // list entry v -> its address (regions of the group in order)
     auto addr = [&](int64_t v) {

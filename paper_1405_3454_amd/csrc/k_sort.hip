@@ -4,8 +4,8 @@
 //
 // Decomposition: SORT_BLOCKS persistent blocks; block b owns the contiguous
 // key tiles [b qq, (b+1) qq) of SORT_TILE keys.  Per pass: (1) per-block digit
-// histograms, after which the last block to finish scans the digit-major
-// table hist[d][b] (only the blocks that hold keys), (2) scatter: each block
+// histograms, after which the last block to finish scans the table
+// hist[b][d] digit-major (only the blocks that hold keys), (2) scatter: each block
 // walks its tiles in order and ranks keys stably with wave ballots (peers =
 // lanes with the same digit) plus per-wave digit counts in LDS, so equal
 // digits keep their input order across lanes, waves, rounds and blocks.
@@ -35,8 +35,10 @@ __device__ __forceinline__ int64_t sort_busy(int64_t count) {
 
 // Per-block digit histograms of the blocks that hold keys; the last of them
 // to finish (ticket, self-resetting) turns them into the exclusive offsets
-// hoff[d][b] of the stable scatter.  Blocks without keys leave at once (the
-// scatter does not read their offsets).
+// hoff[b][d] of the stable scatter.  Both tables are block-major, so a block
+// writes its column, and the last block reads each block's, with consecutive
+// lanes on consecutive words.  Blocks without keys leave at once (the scatter
+// does not read their offsets).
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__restrict__ keys,
                                                             const int64_t *__restrict__ cnt_ptr,
                                                             int shift, uint32_t *__restrict__ hist,
@@ -53,10 +55,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__re
     __syncthreads();
     int64_t lo, hi;
     sort_range(count, blockIdx.x, &lo, &hi);
-    for (int64_t i = lo + tid; i < hi; i += SORT_THREADS)
-        atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+    for (int64_t base = lo; base < hi; base += SORT_TILE) {     // a tile's loads, then its counts
+        uint32_t d[SORT_ROUNDS];
+#pragma unroll
+        for (int r = 0; r < SORT_ROUNDS; r++) {
+            const int64_t i = base + r * SORT_THREADS + tid;
+            d[r] = i < hi ? (uint32_t)(keys[i] >> shift) & (RADIX - 1) : (uint32_t)RADIX;
+        }
+#pragma unroll
+        for (int r = 0; r < SORT_ROUNDS; r++)
+            if (d[r] < RADIX) atomicAdd(&h[d[r]], 1u);
+    }
     __syncthreads();
-    hist[tid * SORT_BLOCKS + blockIdx.x] = h[tid];
+    hist[(int64_t)blockIdx.x * RADIX + tid] = h[tid];
     __threadfence();   // every wave publishes its part of the block's column
     __syncthreads();
     if (tid == 0) {
@@ -65,35 +76,43 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__re
     }
     __syncthreads();
     if (!last) return;
-    // thread d: the row of digit d over the busy blocks
-    // (eight independent loads per step keep the walk off the load latency)
-    const uint32_t *row = hist + (int64_t)tid * SORT_BLOCKS;
+    // thread d: digit d over the busy blocks, up to HB independent loads per
+    // step (in groups of HG, skipped past the last busy block); with at most
+    // HB busy blocks the values stay in registers for the second walk
+    constexpr int HB = 64, HG = 8;
+    uint32_t v[HB];
+    auto load = [&](int b0) {
+#pragma unroll
+        for (int gi = 0; gi < HB / HG; gi++) {
+            const bool any = b0 + gi * HG < nb;
+#pragma unroll
+            for (int i = 0; i < HG; i++) {
+                const int bb = b0 + gi * HG + i;
+                v[gi * HG + i] = any && bb < nb ? hist[(int64_t)bb * RADIX + tid] : 0u;
+            }
+        }
+    };
     uint32_t tot = 0;
-    int b = 0;
-    for (; b + 8 <= nb; b += 8) {
-        uint32_t v[8];
+    for (int b0 = 0; b0 < nb; b0 += HB) {
+        load(b0);
 #pragma unroll
-        for (int i = 0; i < 8; i++) v[i] = row[b + i];
-#pragma unroll
-        for (int i = 0; i < 8; i++) tot += v[i];
+        for (int i = 0; i < HB; i++) tot += v[i];
     }
-    for (; b < nb; b++) tot += row[b];
     int64_t all;
     int64_t run = block_excl_scan_i64(tot, scan_sh, &all);
-    int64_t *orow = hoff + (int64_t)tid * SORT_BLOCKS;
-    for (b = 0; b + 8 <= nb; b += 8) {
-        uint32_t v[8];
+    for (int b0 = 0; b0 < nb; b0 += HB) {
+        if (nb > HB) load(b0);
 #pragma unroll
-        for (int i = 0; i < 8; i++) v[i] = row[b + i];
+        for (int gi = 0; gi < HB / HG; gi++) {
+            if (b0 + gi * HG < nb) {
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            orow[b + i] = run;
-            run += v[i];
+                for (int i = 0; i < HG; i++) {
+                    const int bb = b0 + gi * HG + i;
+                    if (bb < nb) hoff[(int64_t)bb * RADIX + tid] = run;
+                    run += v[gi * HG + i];
+                }
+            }
         }
-    }
-    for (; b < nb; b++) {
-        orow[b] = run;
-        run += row[b];
     }
     if (tid == 0) *ticket = 0;
 }
@@ -114,7 +133,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint64_t *_
     __shared__ int64_t scan_sh[17];
     __shared__ uint64_t buf[SORT_TILE];
     const int tid = threadIdx.x, w = tid >> 6;
-    run[tid] = hoff[tid * SORT_BLOCKS + blockIdx.x];
+    run[tid] = hoff[(int64_t)blockIdx.x * RADIX + tid];
     int64_t lo, hi;
     sort_range(*cnt_ptr, blockIdx.x, &lo, &hi);
     const uint64_t lt = lanemask_lt();
