@@ -451,7 +451,7 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
         int64_t vcap = (ucap + CHAIN_G - 1) / CHAIN_G;
         dim3 grid((unsigned)std::min(gmax, std::max<int64_t>(1, (vcap + 3) / 4)), 2);
         LAUNCH(K_CHAIN_COMPACT, k_chain_merge<<<grid, 256, 0, st>>>(
-            lo[cur], up[cur], locnt[cur], upcnt[cur], cnt, lev, lo[1 - cur], up[1 - cur],
+            lo[cur], up[cur], locnt[cur], upcnt[cur], cnt, lev, L, lo[1 - cur], up[1 - cur],
             locnt[1 - cur], upcnt[1 - cur]));
         cur = 1 - cur;
         R *= CHAIN_G;

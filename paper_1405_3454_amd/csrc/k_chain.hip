@@ -436,6 +436,7 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
                                                      const uint32_t *__restrict__ lo_cin,
                                                      const uint32_t *__restrict__ up_cin,
                                                      const int64_t *__restrict__ cnt_ptr, int lev,
+                                                     int nlev,
                                                      uint64_t *__restrict__ lo_out,
                                                      uint64_t *__restrict__ up_out,
                                                      uint32_t *__restrict__ lo_cout,
@@ -443,8 +444,19 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     __shared__ uint64_t mbuf[4][MERGE_CAP];
     const int64_t cnt = *cnt_ptr;
     int64_t R = CHAIN_C;
-    for (int l = 0; l < lev; l++) R *= CHAIN_G;
+    int first1 = -1;                                      // first level with at most one chain
+    for (int l = 0; l < lev; l++) {
+        if (first1 < 0 && (cnt + R - 1) / R <= 1) first1 = l;
+        R *= CHAIN_G;
+    }
     const int64_t U = (cnt + R - 1) / R;                  // chains at this level
+    if (first1 < 0 && U <= 1) first1 = lev;
+    // Levels that merge (U > 1) are 0 .. first1 - 1 and alternate the two
+    // buffers from the first.  After them the single chain stays where the
+    // last one left it, in the buffer of parity first1; only the last level
+    // moves it into this level's output buffer, and only if it is not there
+    // yet (and records an empty chain when there are no candidates).
+    if (U <= 1 && (lev != nlev - 1 || (U == 1 && (first1 & 1) != (lev & 1)))) return;
     const int64_t V = (U + CHAIN_G - 1) / CHAIN_G;        // groups
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
