@@ -491,6 +491,7 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     constexpr int NS = FIXED_SLOTS + NDIR;
     constexpr int NE = NEV + NDIR;
     __shared__ SlotBest wbest[POLY_THREADS / WAVE][MAX_SLOTS];
+    __shared__ SlotBest spart[POLY_SPLIT][MAX_SLOTS];  // the set's shares (last block)
     __shared__ uint32_t sl[MAX_SLOTS];
     __shared__ double gx[MAX_SLOTS], gy[MAX_SLOTS];   // slot points (grid units)
     __shared__ double sx[MAX_SLOTS], sy[MAX_SLOTS];   // sorted by (x, y, index, slot)
@@ -518,49 +519,46 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
             m0 = (ta / q + 1) * q;
             nruns = 1 + (m0 < tb ? (tb - 1 - m0) / q + 1 : 0);
         }
-        double bv[NE];
-        uint32_t bi[NE];
-#pragma unroll
-        for (int k = 0; k < NE; k++) {
-            bv[k] = slot_is_min(k, NEV) ? INFINITY : -INFINITY;
-            bi[k] = NONE;
-        }
-        // two runs per iteration so that both runs' loads are in flight together
-        const int64_t step = (int64_t)gridDim.y * blockDim.x;
-        for (int64_t r = (int64_t)blockIdx.y * blockDim.x + tid; r < nruns; r += 2 * step) {
-            const int64_t r2 = r + step;
-            const int64_t t = r == 0 ? ta : m0 + (r - 1) * q;
-            const int64_t t2 = r2 < nruns ? m0 + (r2 - 1) * q : t;
-            double v1[NE], v2[NE];
-            uint32_t i1[NE], i2[NE];
-#pragma unroll
-            for (int k = 0; k < NE; k++) {
-                v1[k] = pval[t * MAX_SLOTS + k];
-                i1[k] = pidx[t * MAX_SLOTS + k];
-                v2[k] = pval[t2 * MAX_SLOTS + k];
-                i2[k] = pidx[t2 * MAX_SLOTS + k];
+        // a wave reads LPR consecutive slots of RPW runs per load, so a load
+        // covers whole partial records; lane (sub, k) keeps the best (value,
+        // then lowest index) of slot k over the runs it reads
+        constexpr int LPR = NE <= 16 ? 16 : 32;
+        constexpr int RPW = WAVE / LPR;
+        const int k = lane & (LPR - 1), sub = lane / LPR;
+        const bool mn = k < NE && slot_is_min(k, NEV);
+        double bv = mn ? INFINITY : -INFINITY;
+        uint32_t bi = NONE;
+        const int64_t nw = (int64_t)gridDim.y * (blockDim.x >> 6);      // waves sharing the set
+        const int64_t wg = (int64_t)blockIdx.y * (blockDim.x >> 6) + w;
+        for (int64_t r0 = wg * RPW; r0 < nruns; r0 += 2 * nw * RPW) {  // two records in flight
+            const int64_t ra = r0 + sub, rb = r0 + nw * RPW + sub;
+            const bool ina = k < NE && ra < nruns, inb = k < NE && rb < nruns;
+            const int64_t qa = ra == 0 ? ta : m0 + (ra - 1) * q;
+            const int64_t qb = rb == 0 ? ta : m0 + (rb - 1) * q;
+            const double va = ina ? pval[qa * MAX_SLOTS + k] : 0.0;
+            const uint32_t ia = ina ? pidx[qa * MAX_SLOTS + k] : NONE;
+            const double vb = inb ? pval[qb * MAX_SLOTS + k] : 0.0;
+            const uint32_t ib = inb ? pidx[qb * MAX_SLOTS + k] : NONE;
+            if (ia != NONE && better(mn, va, ia, bv, bi)) {
+                bv = va;
+                bi = ia;
             }
-#pragma unroll
-            for (int k = 0; k < NE; k++) {
-                const bool mn = slot_is_min(k, NEV);
-                if (i1[k] != NONE && better(mn, v1[k], i1[k], bv[k], bi[k])) {
-                    bv[k] = v1[k];
-                    bi[k] = i1[k];
-                }
-                if (i2[k] != NONE && better(mn, v2[k], i2[k], bv[k], bi[k])) {
-                    bv[k] = v2[k];
-                    bi[k] = i2[k];
-                }
+            if (ib != NONE && better(mn, vb, ib, bv, bi)) {
+                bv = vb;
+                bi = ib;
             }
         }
-        // the wave's best per slot: extreme value, then the lowest index
-        // holding it (lanes without a candidate hold the identity, +-inf)
+        // combine the RPW lanes of each slot (whole wave active)
 #pragma unroll
-        for (int k = 0; k < NE; k++) {
-            const double v = slot_is_min(k, NEV) ? wave_extreme<true>(bv[k]) : wave_extreme<false>(bv[k]);
-            const uint32_t i = wave_min_u32(bv[k] == v ? bi[k] : NONE);
-            if (lane == 0) wbest[w][k] = SlotBest{v, i};
+        for (int off = LPR; off < WAVE; off <<= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const uint32_t oi = (uint32_t)__shfl_xor((int)bi, off);
+            if (oi != NONE && (bi == NONE || better(mn, ov, oi, bv, bi))) {
+                bv = ov;
+                bi = oi;
+            }
         }
+        if (sub == 0 && k < NE) wbest[w][k] = SlotBest{bv, bi};
         __syncthreads();
         if (tid < NE) {
             const bool mn = slot_is_min(tid, NEV);
@@ -589,11 +587,15 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
             }
             __syncthreads();
             if (!last) return;
+            // every share in one step of loads, then reduced in LDS
+            for (int j = tid; j < (int)gridDim.y * MAX_SLOTS; j += blockDim.x)
+                spart[j / MAX_SLOTS][j % MAX_SLOTS] = bpart[(s * gridDim.y) * MAX_SLOTS + j];
+            __syncthreads();
             if (tid < NE) {
                 const bool mn = slot_is_min(tid, NEV);
-                SlotBest b0 = bpart[(s * gridDim.y) * MAX_SLOTS + tid];
+                SlotBest b0 = spart[0][tid];
                 for (int yy = 1; yy < (int)gridDim.y; yy++) {
-                    const SlotBest b = bpart[(s * gridDim.y + yy) * MAX_SLOTS + tid];
+                    const SlotBest b = spart[yy][tid];
                     if (b.i != NONE && (b0.i == NONE || better(mn, b.v, b.i, b0.v, b0.i))) b0 = b;
                 }
                 wbest[0][tid] = b0;
@@ -724,58 +726,70 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
         if (lane == 0) hcount = h;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (w == 0) {     // lane e: vertex e and the edge from it to vertex e + 1
         const int h = hcount;
-        P.m = h;
-        int ylo = 0x7fffffff, yhi = -1;
-        for (int e = 0; e < MAX_SLOTS; e++) {
-            P.verts[e] = e < h ? si[st[e]] : NONE;
+        const int e = lane;
+        const bool ev = e < h && h >= 3;
+        int ya = 0;
+        if (e < MAX_SLOTS) {
+            double ax = 0.0, ay = 0.0;
             if (e < h) {
-                vx[e] = sx[st[e]];
-                vy[e] = sy[st[e]];
+                ax = sx[st[e]];
+                ay = sy[st[e]];
+                vx[e] = ax;
+                vy[e] = ay;
             }
-            P.vx[e] = e < h ? (int32_t)sx[st[e]] : 0;
-            P.vy[e] = e < h ? (int32_t)sy[st[e]] : 0;
-            if (e < h && h >= 3) {
-                int a = st[e], b = st[(e + 1) % h];
-                double ex = sx[b] - sx[a], ey = sy[b] - sy[a];
+            P.verts[e] = e < h ? si[st[e]] : NONE;
+            P.vx[e] = e < h ? (int32_t)ax : 0;
+            P.vy[e] = e < h ? (int32_t)ay : 0;
+            if (ev) {
+                const int bb = st[(e + 1) % h];
+                const double ex = sx[bb] - ax, ey = sy[bb] - ay;
                 P.ex[e] = ex;
                 P.ey[e] = ey;
-                P.c[e] = fma(ey, sx[a], -(ex * sy[a]));
-                ylo = min(ylo, (int)sy[a]);
-                yhi = max(yhi, (int)sy[a]);
+                P.c[e] = fma(ey, ax, -(ex * ay));
+                ya = (int)ay;
             } else {
                 P.ex[e] = 0.0;
                 P.ey[e] = 0.0;
                 P.c[e] = 1.0;
             }
         }
-        if (h < 3) {
-            P.c[0] = -1.0;    // nothing strictly inside
-            P.yspan = -1;
-            P.ky_lo = 0;
-            P.shift = 0;
-            P.ymin = 1;
-            P.ymax = 0;
-        } else {
-            // the rows stop a thin sliver (1/1024 of the height) short of
-            // the top and bottom vertices, where the polygon narrows to a
-            // point or an edge and a row could hold no quick-accept span;
-            // points in the slivers take the exact test
-            const int d = (yhi - ylo) >> 10;
-            P.ymin = ylo;
-            P.ymax = yhi;
-            P.ky_lo = ylo + d;
-            P.yspan = (yhi - d) - (ylo + d);
-            int sh = 0;
-            while ((P.yspan >> sh) >= SPAN_ROWS) sh++;
-            P.shift = sh;
+        // the vertices' y-range (grid units, below 2^24)
+        const int ylo = (int)wave_min_u32(ev ? (uint32_t)ya : 0xFFFFFFFFu);
+        const int yhi = 0x7FFFFFFF - (int)wave_min_u32(ev ? (uint32_t)(0x7FFFFFFF - ya) : 0xFFFFFFFFu);
+        if (lane == 0) {
+            P.m = h;
+            if (h < 3) {
+                P.c[0] = -1.0;    // nothing strictly inside
+                P.yspan = -1;
+                P.ky_lo = 0;
+                P.shift = 0;
+                P.ymin = 1;
+                P.ymax = 0;
+            } else {
+                // the rows stop a thin sliver (1/1024 of the height) short of
+                // the top and bottom vertices, where the polygon narrows to a
+                // point or an edge and a row could hold no quick-accept span;
+                // points in the slivers take the exact test
+                const int d = (yhi - ylo) >> 10;
+                P.ymin = ylo;
+                P.ymax = yhi;
+                P.ky_lo = ylo + d;
+                P.yspan = (yhi - d) - (ylo + d);
+                int sh = 0;
+                while ((P.yspan >> sh) >= SPAN_ROWS) sh++;
+                P.shift = sh;
+            }
         }
     }
     __syncthreads();
-
-    __syncthreads();
-    if (tid == 0) polys[s] = P;
+    {   // the record, a word per thread
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&P);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(polys + s);
+        static_assert(sizeof(Poly) % 4 == 0, "Poly is copied in words");
+        for (int i = tid; i < (int)(sizeof(Poly) / 4); i += (int)blockDim.x) dst[i] = src[i];
+    }
     if (rtab) {    // the refinement's round-0 edges (the polygon's) and cleared farthest keys
         const int m = P.m >= 3 ? P.m : 0;
         for (int e = tid; e < RE_CAP; e += blockDim.x) {
