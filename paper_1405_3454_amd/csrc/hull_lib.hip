@@ -402,6 +402,8 @@ static int run_sort(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint64_t
     int64_t *hoffs = W<int64_t>(ctx, p.hoffs);
     const uint64_t *in = keys;
     uint64_t *out = A;
+    // small counts: sorted at once into the buffer the last pass would fill
+    LAUNCH(K_SORT_HIST, k_sort_small<<<1, SMALL_THREADS, 0, st>>>(keys, cnt, passes % 2 ? A : B));
     for (int ps = 0; ps < passes; ps++) {
         LAUNCH(K_SORT_HIST, k_sort_hist<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
             in, cnt, 8 * ps, hist, hoffs, ctx->tickets + 1));

@@ -18,6 +18,8 @@ constexpr int SORT_ROUNDS = 8;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ROUNDS;   // 2048 keys
 constexpr int SORT_BLOCKS = 512;
 constexpr int RADIX = 256;
+constexpr int SORT_SMALL = 4096;      // up to this many keys one block sorts them (k_sort_small)
+constexpr int SMALL_THREADS = 1024;
 
 __device__ __forceinline__ void sort_range(int64_t count, int64_t b, int64_t *lo, int64_t *hi) {
     int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
@@ -31,6 +33,39 @@ __device__ __forceinline__ int64_t sort_busy(int64_t count) {
     const int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
     const int64_t qq = (tiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
     return qq ? (tiles + qq - 1) / qq : 0;
+}
+
+// At most SORT_SMALL keys: one block sorts them in LDS (bitonic network over
+// the next power of two, padded with the largest key) and writes them where
+// the radix passes would have left them; the passes then return at once.
+// Above SORT_SMALL it returns at once.  The sort is by key only, so equal
+// keys are interchangeable and the result is the radix sort's.
+__global__ __launch_bounds__(SMALL_THREADS) void k_sort_small(const uint64_t *__restrict__ keys,
+                                                              const int64_t *__restrict__ cnt_ptr,
+                                                              uint64_t *__restrict__ out) {
+    __shared__ uint64_t b[SORT_SMALL];
+    const int64_t count = *cnt_ptr;
+    if (count > SORT_SMALL || count <= 0) return;
+    const int n = (int)count, tid = threadIdx.x;
+    int m = 2;
+    while (m < n) m <<= 1;
+    for (int i = tid; i < m; i += SMALL_THREADS) b[i] = i < n ? keys[i] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = tid; t < (m >> 1); t += SMALL_THREADS) {
+                const int i = 2 * j * (t / j) + (t % j), l = i + j;    // pair (i, l), i < l
+                const bool up = (i & k) == 0;                         // ascending run
+                const uint64_t a = b[i], c = b[l];
+                if ((a > c) == up) {
+                    b[i] = c;
+                    b[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < n; i += SMALL_THREADS) out[i] = b[i];
 }
 
 // Per-block digit histograms of the blocks that hold keys; the last of them
@@ -49,6 +84,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__re
     __shared__ bool last;
     const int tid = threadIdx.x;
     const int64_t count = *cnt_ptr;
+    if (count <= SORT_SMALL) return;     // k_sort_small has sorted them
     const int nb = (int)sort_busy(count);
     if ((int)blockIdx.x >= nb) return;   // no keys: nothing to count or scan
     h[tid] = 0;
@@ -133,6 +169,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint64_t *_
     __shared__ int64_t scan_sh[17];
     __shared__ uint64_t buf[SORT_TILE];
     const int tid = threadIdx.x, w = tid >> 6;
+    if (*cnt_ptr <= SORT_SMALL) return;  // k_sort_small has sorted them
     run[tid] = hoff[(int64_t)blockIdx.x * RADIX + tid];
     int64_t lo, hi;
     sort_range(*cnt_ptr, blockIdx.x, &lo, &hi);

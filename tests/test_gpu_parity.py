@@ -122,6 +122,17 @@ def test_hull_of_subset(H):
     assert np.array_equal(u32(h), oracle.hull_subset(x, y, idx))
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 4095, 4096, 4097, 9000])
+def test_hull_of_subset_sort_switch(H, m):
+    """Subsets around the size where the one-block sort hands over to the
+    radix passes: the same hull either way."""
+    import torch
+    x, y = inputs.disk(20_000, 21)
+    idx = np.sort(np.random.default_rng(m).choice(len(x), m, replace=False)).astype(np.uint32)
+    h = H.hull_of_subset(dev(x), dev(y), torch.from_numpy(idx.view(np.int32)).to("cuda:0"))
+    assert np.array_equal(u32(h), oracle.hull_subset(x, y, idx))
+
+
 def test_determinism(H):
     x, y = inputs.annulus(500_000, 4)
     xt, yt = dev(x), dev(y)
