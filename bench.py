@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {"discard": 1.1824e9, "extremes": 1.1084e9}
 TRAFFIC_SOURCES = ("paper_1405_3454_amd/csrc/k_filter.hip", "paper_1405_3454_amd/csrc/hg_common.h",
                    "paper_1405_3454_amd/csrc/hg_device.h")
-TRAFFIC_SHA = "f4bd74dea90fd075"
+TRAFFIC_SHA = "e3d576b5bf7a17c1"
 
 
 def _traffic(kernel, log2n):
