@@ -119,7 +119,7 @@ struct Plan {
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
-        rfar1, segcnt, segmeta, cidx, ckeys, bpart, pticket, total;
+        rfar1, rfar2, segcnt, segmeta, cidx, ckeys, bpart, pticket, total;
     int64_t tcap, u0cap;
     int64_t nwave;      // discard waves = regions of the full method's survivor lists
 };
@@ -179,6 +179,7 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.rtab1 = take(S * RE_CAP * sizeof(REdge));
     p.rfar0 = take(S * RE_CAP * 8);
     p.rfar1 = take(S * RE_CAP * 8);
+    p.rfar2 = take(RE_CAP * 8);          // one set: third farthest-key buffer of the rounds
     p.segcnt = take((REF_ROUNDS + 1) * W * 8);      // region counts per list stage
     p.segmeta = take(8);                             // region size (q * TILE)
     p.bpart = take(S * POLY_SPLIT * MAX_SLOTS * sizeof(SlotBest));
@@ -514,17 +515,28 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
                                   W<unsigned long long>(ctx, p.rfar1)};
     int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
     const int64_t *meta = W<int64_t>(ctx, p.segmeta);
+    // one set: pass r splits the parents (tab[r % 2], F[r % 3]) itself, raises
+    // F[(r + 1) % 3] (cleared before: k_counts_init, then the pass before)
+    // and clears F[(r + 2) % 3], which no pass reads until two rounds later
+    unsigned long long *F[3] = {far[0], far[1], W<unsigned long long>(ctx, p.rfar2)};
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
         int64_t *cin = seg_stage(p, segcnt, r), *cout = seg_stage(p, segcnt, r + 1);
-        LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
-            x, y, S, er, tab[a], far[a], tab[b], far[b]));
         const int64_t nin = stage_regions(p.nwave, r), nout = stage_regions(p.nwave, r + 1);
         const int kg = ref_group(r);
+        if (S == 1) {
+            LAUNCH(K_REFINE, k_ref_pass<<<(unsigned)nout, REF_THREADS, 0, st>>>(
+                idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r), tab[b], 2 * er,
+                F[(r + 1) % 3], idxs[b], keys[b], eds[b], cout, 1, x, y, tab[a], F[r % 3], tab[b],
+                F[(r + 2) % 3]));
+            continue;
+        }
+        LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
+            x, y, S, er, tab[a], far[a], tab[b], far[b]));
         LAUNCH(K_REFINE, k_ref_pass<<<(unsigned)nout, REF_THREADS, 0, st>>>(
             idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r), tab[b], 2 * er,
-            far[b], idxs[b], keys[b], eds[b], cout, S == 1 ? 1 : 0));
+            far[b], idxs[b], keys[b], eds[b], cout, 0, x, y, nullptr, nullptr, nullptr, nullptr));
     }
     return HULL_OK;
 }
@@ -575,7 +587,10 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
     const bool refine = !(flags & (HULL_NOREFINE | HULL_NOFILTER));
     const int64_t *cnt = ctx->counts;
     int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
-    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(ctx->counts, HULL_NCOUNTS));
+    // one set: the farthest keys of refinement round 0's children start cleared
+    const bool one_ref = S == 1 && refine;
+    LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(
+        ctx->counts, HULL_NCOUNTS, one_ref ? W<unsigned long long>(ctx, p.rfar1) : nullptr, RE_CAP));
     if (flags & HULL_NOFILTER) {
         LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
                                                          surv_off));

@@ -649,8 +649,12 @@ __global__ __launch_bounds__(256) void k_gather_keys(const float *__restrict__ x
 
 // Before a computation: the recorded stage counts to -1 (stages that do not
 // run keep it).
-__global__ void k_counts_init(int64_t *__restrict__ c, int n) {
+// Counts of a computation set to -1; clr[0, nclr) (optional) cleared.
+__global__ void k_counts_init(int64_t *__restrict__ c, int n, unsigned long long *__restrict__ clr,
+                              int nclr) {
     if (blockIdx.x == 0 && (int)threadIdx.x < n) c[threadIdx.x] = -1;
+    if (clr)
+        for (int i = threadIdx.x; i < nclr; i += blockDim.x) clr[i] = 0;
 }
 
 __global__ void k_copy_count(const int64_t *__restrict__ src, int64_t *__restrict__ dst) {

@@ -42,9 +42,25 @@ __device__ __forceinline__ void key_point(uint64_t k, int64_t *s, double *px, do
     *py = (double)(k & 0xFFFFFF);
 }
 
-// Split every edge of round r at its farthest outside point: children 2e
-// (a->f) and 2e+1 (f->b); an edge without outside points keeps itself as
-// child 2e.  Clears the next round's farthest-point keys.
+// Children of edge cur at its farthest outside point (key k): 2e = a->f and
+// 2e+1 = f->b; an edge without outside points keeps itself as child 2e.
+__device__ __forceinline__ void split_pair(const float *__restrict__ x, const float *__restrict__ y,
+                                           const REdge &cur, uint64_t k, REdge *c0, REdge *c1) {
+    *c0 = redge_empty();
+    *c1 = redge_empty();
+    if (cur.ax == INT32_MIN) return;
+    if (k == 0) {
+        *c0 = cur;
+        return;
+    }
+    const uint32_t f = ~(uint32_t)k;
+    const int32_t fx = (int32_t)(x[f] * GRIDF), fy = (int32_t)(y[f] * GRIDF);
+    *c0 = REdge{cur.ax, cur.ay, fx, fy};
+    *c1 = REdge{fx, fy, cur.bx, cur.by};
+}
+
+// Split every edge of round r (er per set) at its farthest outside point and
+// clear the children's farthest-point keys.
 __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
                                                    const float *__restrict__ y, int64_t S, int er,
                                                    const REdge *__restrict__ tab,
@@ -55,19 +71,8 @@ __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
     if (t >= S * er) return;
     const int64_t s = t / er;
     const int e = (int)(t % er);
-    const REdge cur = tab[s * RE_CAP + e];
-    REdge c0 = redge_empty(), c1 = redge_empty();
-    if (cur.ax != INT32_MIN) {
-        const uint64_t k = far[s * RE_CAP + e];
-        if (k == 0) {
-            c0 = cur;
-        } else {
-            const uint32_t f = ~(uint32_t)k;
-            const int32_t fx = (int32_t)(x[f] * GRIDF), fy = (int32_t)(y[f] * GRIDF);
-            c0 = REdge{cur.ax, cur.ay, fx, fy};
-            c1 = REdge{fx, fy, cur.bx, cur.by};
-        }
-    }
+    REdge c0, c1;
+    split_pair(x, y, tab[s * RE_CAP + e], far[s * RE_CAP + e], &c0, &c1);
     tab_nxt[s * RE_CAP + 2 * e] = c0;
     tab_nxt[s * RE_CAP + 2 * e + 1] = c1;
     far_nxt[s * RE_CAP + 2 * e] = 0;
@@ -111,7 +116,10 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     const int64_t *__restrict__ region_size, int64_t mult, const REdge *__restrict__ tab_nxt, int er2,
     unsigned long long *__restrict__ far, uint32_t *__restrict__ idx_out,
     uint64_t *__restrict__ keys_out, uint16_t *__restrict__ edge_out,
-    int64_t *__restrict__ cnt_out, int one_set) {
+    int64_t *__restrict__ cnt_out, int one_set, const float *__restrict__ x,
+    const float *__restrict__ y, const REdge *__restrict__ tab_par,
+    const unsigned long long *__restrict__ far_par, REdge *__restrict__ tab_out,
+    unsigned long long *__restrict__ far_clr) {
     constexpr int NW = REF_THREADS / WAVE;
     __shared__ RefFar L;
     __shared__ REdge ltab[RE_CAP];          // the chunk's set's child edges (er2 of them)
@@ -132,8 +140,28 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     }
     __syncthreads();
     const int64_t n_sg = pre[nr];
+    // One set with tab_par: the block splits the er2 / 2 parent edges itself
+    // (children into LDS); block 0 also publishes them for the next round and
+    // clears the farthest keys the round after this one raises.
+    auto split_here = [&](bool to_lds) {
+        for (int e = tid; e < er2 / 2; e += REF_THREADS) {
+            REdge c0, c1;
+            split_pair(x, y, tab_par[e], far_par[e], &c0, &c1);
+            if (to_lds) {
+                ltab[2 * e] = c0;
+                ltab[2 * e + 1] = c1;
+            }
+            if (g == 0) {
+                tab_out[2 * e] = c0;
+                tab_out[2 * e + 1] = c1;
+            }
+        }
+        if (g == 0)
+            for (int e = tid; e < RE_CAP; e += REF_THREADS) far_clr[e] = 0;
+    };
     if (n_sg == 0) {                        // nothing to read: an empty region, no far keys
         if (tid == 0) cnt_out[g] = 0;
+        if (tab_par && g == 0) split_here(false);
         return;
     }
     const int64_t region = r0 * segcap;     // output region g: [region, region + kg * segcap)
@@ -146,7 +174,10 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     int64_t outn = 0;                       // entries packed into the region so far
     if (one_set) {
         for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
-        for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[e];
+        if (tab_par)
+            split_here(true);
+        else
+            for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[e];
     }
     for (int64_t jb = 0; jb < n_sg; jb += REF_CH) {
         const int64_t je = min(n_sg, jb + REF_CH);
