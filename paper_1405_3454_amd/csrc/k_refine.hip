@@ -23,9 +23,9 @@
 
 namespace hg {
 
-constexpr int REF_CH = 2048;                      // survivors per block step
-constexpr int REF_THREADS = 256;
-constexpr int REF_PER_THREAD = REF_CH / REF_THREADS;
+constexpr int REF_PER_THREAD = 8;                 // survivors per thread and block step
+constexpr int REF_THREADS = 256;                  // pass block size
+constexpr int REF_THREADS_LATE = 512;             // one set, rounds after 0 (fewer blocks)
 
 
 // Exact edge function of a->b at p: > 0 strictly left (inside), < 0 outside.
@@ -102,7 +102,7 @@ __host__ __device__ inline int ref_group(int r) { return r == 0 ? 4 : 2; }
 // One round over the survivors.  A list is a row of regions (region r at
 // r * segcap, cnt[r] entries; round 0 reads the discard pass's, one per
 // wave).  Block g reads regions [g * kg, (g + 1) * kg) as one list, in
-// chunks of REF_CH (thread t holds list entries t, t + REF_THREADS, ...).
+// chunks of RT * REF_PER_THREAD (thread t holds list entries t, t + RT, ...).
 // Each survivor is classified against the two children of its edge
 // (RE_DROP, RE_NONE or the new edge id); the kept ones are packed into region
 // g (size kg * segcap) of the next list, whose count the block writes at the
@@ -110,7 +110,8 @@ __host__ __device__ inline int ref_group(int r) { return r == 0 ? 4 : 2; }
 // input is the discard pass's regions, with their edge states.)  With one set
 // (one_set), the set's child edges are staged once per block, before the
 // first chunk's loads return, and the farthest keys are raised once per block.
-__global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
+template <int RT>
+__global__ __launch_bounds__(RT) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
     const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int nreg_in, int kg,
     const int64_t *__restrict__ region_size, int64_t mult, const REdge *__restrict__ tab_nxt, int er2,
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     const float *__restrict__ y, const REdge *__restrict__ tab_par,
     const unsigned long long *__restrict__ far_par, REdge *__restrict__ tab_out,
     unsigned long long *__restrict__ far_clr) {
-    constexpr int NW = REF_THREADS / WAVE;
+    constexpr int NW = RT / WAVE;
     __shared__ RefFar L;
     __shared__ REdge ltab[RE_CAP];          // the chunk's set's child edges (er2 of them)
     __shared__ uint32_t kc[REF_PER_THREAD][NW];   // kept per (element row, wave) -> offsets
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     // (children into LDS); block 0 also publishes them for the next round and
     // clears the farthest keys the round after this one raises.
     auto split_here = [&](bool to_lds) {
-        for (int e = tid; e < er2 / 2; e += REF_THREADS) {
+        for (int e = tid; e < er2 / 2; e += RT) {
             REdge c0, c1;
             split_pair(x, y, tab_par[e], far_par[e], &c0, &c1);
             if (to_lds) {
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             }
         }
         if (g == 0)
-            for (int e = tid; e < RE_CAP; e += REF_THREADS) far_clr[e] = 0;
+            for (int e = tid; e < RE_CAP; e += RT) far_clr[e] = 0;
     };
     if (n_sg == 0) {                        // nothing to read: an empty region, no far keys
         if (tid == 0) cnt_out[g] = 0;
@@ -173,21 +174,21 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     };
     int64_t outn = 0;                       // entries packed into the region so far
     if (one_set) {
-        for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
+        for (int e = tid; e < RE_CAP; e += RT) L.v[e] = 0;
         if (tab_par)
             split_here(true);
         else
-            for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[e];
+            for (int e = tid; e < er2; e += RT) ltab[e] = tab_nxt[e];
     }
-    for (int64_t jb = 0; jb < n_sg; jb += REF_CH) {
-        const int64_t je = min(n_sg, jb + REF_CH);
-        const int64_t j0 = jb + tid;        // element i: j0 + i * REF_THREADS (coalesced)
+    for (int64_t jb = 0; jb < n_sg; jb += (RT * REF_PER_THREAD)) {
+        const int64_t je = min(n_sg, jb + (RT * REF_PER_THREAD));
+        const int64_t j0 = jb + tid;        // element i: j0 + i * RT (coalesced)
         uint64_t k[REF_PER_THREAD];
         uint16_t st[REF_PER_THREAD];
         uint32_t ix[REF_PER_THREAD];
 #pragma unroll
         for (int i = 0; i < REF_PER_THREAD; i++) {
-            const int64_t j = j0 + (int64_t)i * REF_THREADS;
+            const int64_t j = j0 + (int64_t)i * RT;
             const bool in = j < je;
             const int64_t a = in ? addr(j) : 0;
             k[i] = in ? keys[a] : 0;
@@ -202,11 +203,11 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
             bool same = true;
 #pragma unroll
             for (int i = 0; i < REF_PER_THREAD; i++)
-                same = same && (j0 + (int64_t)i * REF_THREADS >= je || (int64_t)(k[i] >> 48) == s0);
+                same = same && (j0 + (int64_t)i * RT >= je || (int64_t)(k[i] >> 48) == s0);
             local = __syncthreads_and(same) != 0;
             if (local) {
-                for (int e = tid; e < RE_CAP; e += REF_THREADS) L.v[e] = 0;
-                for (int e = tid; e < er2; e += REF_THREADS) ltab[e] = tab_nxt[s0 * RE_CAP + e];
+                for (int e = tid; e < RE_CAP; e += RT) L.v[e] = 0;
+                for (int e = tid; e < er2; e += RT) ltab[e] = tab_nxt[s0 * RE_CAP + e];
             }
         }
         __syncthreads();
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
         if (!one_set) {
             __syncthreads();
             if (local)
-                for (int e = tid; e < RE_CAP; e += REF_THREADS) {
+                for (int e = tid; e < RE_CAP; e += RT) {
                     const unsigned long long v = L.v[e];
                     if (v) far_update(&far[s0 * RE_CAP + e], v);
                 }
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(REF_THREADS) void k_ref_pass(
     }
     if (one_set) {
         __syncthreads();
-        for (int e = tid; e < er2; e += REF_THREADS) {
+        for (int e = tid; e < er2; e += RT) {
             const unsigned long long v = L.v[e];
             if (v) far_update(&far[e], v);
         }
