@@ -1134,7 +1134,7 @@ static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const 
     (void)n_total;
     if (!ctx->learned.loaded) return HULL_ENOMODEL;
     bf16_t *hist = W<bf16_t>(ctx, p.learn);
-    LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, 256, 0, st>>>(x, y, off, n1, S, hist, nullptr));
+    LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, HIST_THREADS, 0, st>>>(x, y, off, n1, S, hist, nullptr));
     RC(mlp_forward(ctx, st, hist, S));
     LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(ctx->learned.scores, S, ctx->dir_gap, nullptr,
                                                                  W<double>(ctx, p.setdirs)));
@@ -1192,7 +1192,7 @@ int hull_histogram_batched(hull_ctx *ctx, const float *x, const float *y, const 
     HIPCHECK(hipSetDevice(ctx->device));
     const int64_t n1 = offsets ? 0 : n_total;
     if (!offsets && S != 1) return HULL_EINVAL;
-    LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, n1, S, hist, hist_f32));
+    LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, HIST_THREADS, 0, st>>>(x, y, offsets, n1, S, hist, hist_f32));
     return HULL_OK;
 }
 

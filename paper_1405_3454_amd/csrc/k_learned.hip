@@ -82,13 +82,18 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32
 // of its features are kept: origin (x0 - (w - wx) / 2, y0 - (w - wy) / 2),
 // bin = (k - origin) * 32 / w in integer arithmetic; value = count * 1024 / ns
 // (binary64 product and quotient, then float, then bf16).
-__global__ __launch_bounds__(256) void k_hist32(const float *__restrict__ x,
-                                                const float *__restrict__ y,
-                                                const int64_t *__restrict__ off, int64_t n1,
-                                                int64_t S, bf16_t *__restrict__ hist,
-                                                float *__restrict__ hist_f) {
+constexpr int HIST_THREADS = 1024;
+constexpr int HPER = HSAMPLE / HIST_THREADS;    // samples per thread, held in registers
+static_assert(HSAMPLE % HIST_THREADS == 0, "the samples split evenly over the threads");
+
+__global__ __launch_bounds__(HIST_THREADS) void k_hist32(const float *__restrict__ x,
+                                                         const float *__restrict__ y,
+                                                         const int64_t *__restrict__ off, int64_t n1,
+                                                         int64_t S, bf16_t *__restrict__ hist,
+                                                         float *__restrict__ hist_f) {
+    constexpr int NW = HIST_THREADS / WAVE;
     __shared__ uint32_t cnt[HBINS];
-    __shared__ int32_t bb[4][8];
+    __shared__ int32_t bb[NW][4];
     const int64_t s = blockIdx.x;
     const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
     const int64_t a = set_begin(off, s), n = set_end(off, n1, s) - a;
@@ -101,12 +106,23 @@ __global__ __launch_bounds__(256) void k_hist32(const float *__restrict__ x,
         }
         return;
     }
+    // every sample point j * stride (j < ns <= HSAMPLE) loaded once, all of a
+    // thread's loads issued together
     const int64_t stride = (n + HSAMPLE - 1) / HSAMPLE;
     const int64_t ns = (n + stride - 1) / stride;
+    int32_t kx[HPER], ky[HPER];
+#pragma unroll
+    for (int i = 0; i < HPER; i++) {
+        const int64_t j = tid + (int64_t)i * HIST_THREADS;
+        kx[i] = j < ns ? (int32_t)(x[a + j * stride] * GRIDF) : 0;
+        ky[i] = j < ns ? (int32_t)(y[a + j * stride] * GRIDF) : 0;
+    }
     int32_t x0 = 0x7fffffff, x1 = -1, y0 = 0x7fffffff, y1 = -1;
-    for (int64_t j = tid; j < ns; j += blockDim.x) {
-        int32_t kx = (int32_t)(x[a + j * stride] * GRIDF), ky = (int32_t)(y[a + j * stride] * GRIDF);
-        x0 = min(x0, kx); x1 = max(x1, kx); y0 = min(y0, ky); y1 = max(y1, ky);
+#pragma unroll
+    for (int i = 0; i < HPER; i++) {
+        if (tid + (int64_t)i * HIST_THREADS < ns) {
+            x0 = min(x0, kx[i]); x1 = max(x1, kx[i]); y0 = min(y0, ky[i]); y1 = max(y1, ky[i]);
+        }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -116,16 +132,22 @@ __global__ __launch_bounds__(256) void k_hist32(const float *__restrict__ x,
     if (lane == 0) { bb[w][0] = x0; bb[w][1] = x1; bb[w][2] = y0; bb[w][3] = y1; }
     __syncthreads();
     x0 = bb[0][0]; x1 = bb[0][1]; y0 = bb[0][2]; y1 = bb[0][3];
-    for (int ww = 1; ww < (int)(blockDim.x >> 6); ww++) {
+    for (int ww = 1; ww < NW; ww++) {
         x0 = min(x0, bb[ww][0]); x1 = max(x1, bb[ww][1]);
         y0 = min(y0, bb[ww][2]); y1 = max(y1, bb[ww][3]);
     }
     const int64_t wx = (int64_t)x1 - x0 + 1, wy = (int64_t)y1 - y0 + 1, wd = max(wx, wy);
     const int64_t cx0 = x0 - (wd - wx) / 2, cy0 = y0 - (wd - wy) / 2;
-    for (int64_t j = tid; j < ns; j += blockDim.x) {
-        int64_t kx = (int32_t)(x[a + j * stride] * GRIDF), ky = (int32_t)(y[a + j * stride] * GRIDF);
-        int64_t bx = (kx - cx0) * 32 / wd, by = (ky - cy0) * 32 / wd;
-        atomicAdd(&cnt[by * 32 + bx], 1u);
+    // bin = floor((k - c0) * 32 / wd): 0 <= k - c0 < wd <= 2^24, so the
+    // product stays below 2^29 and a 32-bit division is exact
+    const uint32_t uwd = (uint32_t)wd;
+#pragma unroll
+    for (int i = 0; i < HPER; i++) {
+        if (tid + (int64_t)i * HIST_THREADS < ns) {
+            const uint32_t bx = (uint32_t)((int64_t)kx[i] - cx0) * 32u / uwd;
+            const uint32_t by = (uint32_t)((int64_t)ky[i] - cy0) * 32u / uwd;
+            atomicAdd(&cnt[by * 32 + bx], 1u);
+        }
     }
     __syncthreads();
     for (int b = tid; b < HBINS; b += blockDim.x) {
