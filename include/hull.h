@@ -19,8 +19,9 @@
  *    16-byte block, never anything beyond x[n-1].  The exactness guarantees hold for
  *    coordinates that are multiples of 2^-24 in [0, 1) (HULL_VALIDATE checks
  *    this); on that grid every orientation test is exact in binary64.
- *  - Indices are uint32 positions into x/y (so n <= 2^32 - 1), global even in
- *    the batched calls.  HULL_NONE marks an empty slot.
+ *  - Indices are uint32 positions into x/y, global even in the batched
+ *    calls; HULL_NONE = 2^32 - 1 marks an empty slot, so n <= 2^32 - 2
+ *    (larger n: HULL_ETOOBIG).
  *  - Every output array is caller-owned device memory; counts are written to
  *    device memory (int64).  Calls are asynchronous on `stream` (a hipStream_t
  *    passed as void*, NULL = the null stream) and never synchronise, except
@@ -59,7 +60,7 @@ typedef struct hull_ctx hull_ctx;
 
 #define HULL_OK 0
 #define HULL_EINVAL (-1)   /* null pointer, bad size, bad preset, misaligned */
-#define HULL_ETOOBIG (-2)  /* n >= 2^32 */
+#define HULL_ETOOBIG (-2)  /* n > 2^32 - 2 (index 2^32 - 1 is HULL_NONE) */
 #define HULL_ENOMEM (-3)   /* workspace allocation failed */
 #define HULL_EHIP (-4)     /* HIP runtime error, see hull_last_hip_error() */
 #define HULL_EDOMAIN (-5)  /* HULL_VALIDATE: coordinate off the 2^-24 grid of [0,1) */
@@ -162,7 +163,7 @@ int hull_graph_launch(hull_ctx *ctx, void *stream);
 
 /* ---- launch tuning ------------------------------------------------------
  * Time the candidate launch shapes of the filter kernels on these inputs
- * and keep the fastest (per size bucket).  Synchronises. */
+ * and keep the fastest.  Synchronises. */
 int hull_autotune(hull_ctx *ctx, const float *x, const float *y,
                   const int64_t *offsets, int64_t S, int64_t n_total, void *stream);
 /* Read (get != 0) or set the chosen waves-per-CU of the filter kernels. */
@@ -184,8 +185,9 @@ int hull_mlp_set_params(hull_ctx *ctx, const float *params_host, int64_t count);
 int hull_mlp_get_params(hull_ctx *ctx, float *params_host, int64_t count);
 /* hist: device bf16 bits [S][1024]; hist_f32: device float [S][1024] or NULL.
  * offsets NULL means one set of n_total points (S must be 1).  The sample
- * is every ceil(n/16384)-th point; bins span the sample's bounding box;
- * value = count * 1024 / sample size. */
+ * is every ceil(n/16384)-th point; the bins cover a square window centred
+ * on the sample's bounding box, its side the box's longer side (so the
+ * set's aspect ratio is kept); value = count * 1024 / sample size. */
 int hull_histogram_batched(hull_ctx *ctx, const float *x, const float *y,
                            const int64_t *offsets, int64_t S, int64_t n_total,
                            uint16_t *hist, float *hist_f32, void *stream);

@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size: 2^27 points per set, in the launch
-configuration bench.py times (default tuning), for each distribution.
+configuration bench.py times (default tuning), for each distribution and
+both direction presets ({0, 30, 45, 60} and the cumulative {0, 30, 75, 120}).
 
 The oracle runs the whole method on the same arrays (about 10-30 s per set on
 one core); extreme slots and values, the survivor list and the hull must be
@@ -17,6 +18,16 @@ N = 1 << 27
 SEEDS = {"square": 101, "disk": 102, "gaussian": 103, "annulus": 104}   # bench.py's inputs
 
 
+_SETS = {}
+
+
+def _points(kind):
+    """The benchmark's set of this kind (drawn once per module)."""
+    if kind not in _SETS:
+        _SETS[kind] = inputs.DISTRIBUTIONS[kind](N, SEEDS[kind])
+    return _SETS[kind]
+
+
 @pytest.fixture(scope="module")
 def H():
     import torch
@@ -27,20 +38,22 @@ def H():
     h.close()
 
 
+@pytest.mark.parametrize("preset", [0, 1])
 @pytest.mark.parametrize("kind", ["square", "disk", "gaussian", "annulus"])
-def test_full_size(H, kind):
+def test_full_size(H, kind, preset):
     import torch
     from paper_1405_3454_amd.api import as_u32
-    x, y = inputs.DISTRIBUTIONS[kind](N, SEEDS[kind])
+    x, y = _points(kind)
     xt = torch.from_numpy(x).to("cuda:0")
     yt = torch.from_numpy(y).to("cuda:0")
-    H.set_directions(0)
+    H.set_directions(preset)
     slots, vals = H.extremes(xt, yt)
     surv = H.discard(xt, yt, slots)
     hull = H.compute(xt, yt)
     g_slots, g_vals, g_surv, g_hull = as_u32(slots), vals.cpu().numpy(), as_u32(surv), as_u32(hull)
     del xt, yt
-    o_slots, o_vals = oracle.extremes(x, y)
+    H.set_directions(0)
+    o_slots, o_vals = oracle.extremes(x, y, preset)
     assert np.array_equal(g_slots, o_slots)
     assert np.array_equal(g_vals.view(np.uint64), o_vals.view(np.uint64))
     o_verts = oracle.polygon(x, y, o_slots)

@@ -63,6 +63,20 @@ def _hist_batch(H, B, seed):
     return hb, hf.cpu().numpy()
 
 
+def elementwise_excess(got, ref):
+    """Largest |got - ref| / (1e-2 |ref| + 2^-8 max|ref|) over the elements:
+    at most 1 when every element is within 1 % of its reference value, or
+    within one bf16 rounding step (2^-8) of the block's largest magnitude.
+    The second term covers elements whose reference value is a sum that
+    nearly cancels: there a single bf16 activation rounded the other way
+    (fp32 accumulation order on the GPU vs binary64 in the reference) moves
+    the element by about 2^-8 of one of its terms."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    tol = 1e-2 * np.abs(ref) + 2.0 ** -8 * np.abs(ref).max()
+    return float((np.abs(got - ref) / np.maximum(tol, 1e-300)).max())
+
+
 def test_forward_backward_against_binary64(H):
     import torch
     p = mlp.he_init(11)
@@ -71,14 +85,16 @@ def test_forward_backward_against_binary64(H):
     hb, hf = _hist_batch(H, 100, 5)
     scores = H.mlp_forward(hb).cpu().numpy()
     want, cache = mlp.forward(p, hf, emulate=True)
-    err = np.abs(scores - want).max() / np.abs(want).max()
-    assert err < 1e-2, err
+    ex = elementwise_excess(scores, want)
+    print("scores: worst element at %.3f of the tolerance" % ex)
+    assert ex <= 1.0, ex
     dS = np.random.default_rng(6).standard_normal((100, 64)).astype(np.float32)
     g = H.mlp_backward(hb, torch.from_numpy(dS).to("cuda:0")).cpu().numpy().astype(np.float64)
     gw = mlp.backward(cache, dS, emulate=True)
     for part, (a, b) in zip(("W1", "b1", "W2", "b2", "W3", "b3"), zip(mlp.split(g), mlp.split(gw))):
-        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        assert rel < 2e-2, (part, rel)
+        ex = elementwise_excess(a, b)
+        print("%s: worst element at %.3f of the tolerance" % (part, ex))
+        assert ex <= 1.0, (part, ex)
 
 
 @pytest.mark.parametrize("gap", [0, 1, 2, 3])
@@ -159,23 +175,40 @@ def test_label_targets_parity(H):
 
 
 def test_train_step_matches_binary64_adam(H):
-    """One training step on the GPU moves the parameters like the binary64
-    loss gradient + Adam step (within the bf16 tolerance)."""
+    """One training step on the GPU against the binary64 loss gradient and
+    Adam step.  The loss matches within the bf16 tolerance.  Adam's first
+    step is lr * g / (|g| + eps') per element, i.e. +-lr wherever the
+    gradient is clearly non-zero: every parameter whose reference gradient
+    exceeds the elementwise gradient tolerance must move by the reference
+    step (same sign, magnitude within 1e-3 lr plus float32 rounding of the
+    parameter), and no parameter may move by more than lr (1 + 1e-3)."""
     import torch
     p = mlp.he_init(31)
     H.mlp_set_params(p)
     hb, hf = _hist_batch(H, 64, 14)
     gain = np.abs(np.random.default_rng(2).standard_normal((64, 64))).astype(np.float32) * 0.01
-    loss = H.mlp_train_step(hb, torch.from_numpy(gain).to("cuda:0"), 1e-3).item()
+    lr = 1e-3
+    loss = H.mlp_train_step(hb, torch.from_numpy(gain).to("cuda:0"), lr).item()
     S, cache = mlp.forward(p, hf, emulate=True)
     L, dS = mlp.loss_and_grad(S, gain)
     assert loss == pytest.approx(L, rel=2e-2)
     g = mlp.backward(cache, dS, emulate=True)
-    p2, _, _ = mlp.adam(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    p2, _, _ = mlp.adam(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, lr)
     got = H.mlp_get_params().astype(np.float64)
-    moved = np.abs(p2 - p) > 5e-4      # parameters whose first step is clearly +-lr
-    assert moved.mean() > 0.05
-    assert np.mean(np.sign(got - p)[moved] == np.sign(p2 - p)[moved]) > 0.95
+    step_got, step_ref = got - p, p2 - p
+    ulp = np.spacing(np.abs(p).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(step_got) <= lr * (1 + 1e-3) + ulp)
+    checked = 0
+    for a, b, pg, pu in zip(mlp.split(step_got), mlp.split(step_ref), mlp.split(g), mlp.split(ulp)):
+        sure = np.abs(pg) > 1e-2 * np.abs(pg) + 2.0 ** -8 * np.abs(pg).max()
+        # eps (1e-8) shortens a step by lr eps / |g|; the GPU's gradient may
+        # differ from the reference's by up to the tolerance, hence the
+        # second term
+        bound = lr * (1e-3 + 4e-8 / np.abs(pg[sure])) + pu[sure]
+        assert np.all(np.sign(a[sure]) == np.sign(b[sure]))
+        assert np.all(np.abs(a[sure] - b[sure]) <= bound)
+        checked += int(sure.sum())
+    assert checked > 0.05 * len(p)
 
 
 def test_training_gains_over_plain(H):

@@ -137,9 +137,45 @@ def test_determinism(H):
     x, y = inputs.annulus(500_000, 4)
     xt, yt = dev(x), dev(y)
     a = u32(H.compute(xt, yt))
-    for bpc in ((2, 2), (16, 16), (8, 8)):
-        H.set_tuning(*bpc)
-        assert np.array_equal(u32(H.compute(xt, yt)), a)
+    default = H.tuning()
+    try:
+        for bpc in ((2, 2), (16, 16), (8, 8)):
+            H.set_tuning(*bpc)
+            assert np.array_equal(u32(H.compute(xt, yt)), a)
+    finally:
+        H.set_tuning(*default)
+    assert H.tuning() == default
+
+
+@pytest.mark.parametrize("preset", [0, 1])
+@pytest.mark.parametrize("kind", KINDS)
+def test_multi_tile_runs(H, kind, preset):
+    """One block per CU for both filter passes (1024 waves) with 3.1M
+    points: every wave walks three or four tiles of the set, so the
+    extremes pass resolves its ties across the tiles of a run (the per-lane
+    best and record-tile logic) for each preset, against the oracle."""
+    default = H.tuning()
+    H.set_tuning(1, 1)
+    try:
+        x, y = inputs.DISTRIBUTIONS[kind](3_100_000, 900 + preset)
+        check_all(H, x, y, preset, "%s preset=%d q>=3" % (kind, preset))
+    finally:
+        H.set_tuning(*default)
+
+
+@pytest.mark.parametrize("preset", [0, 1])
+@pytest.mark.parametrize("side", [3, 40])
+def test_multi_tile_ties(H, side, preset):
+    """Lattices of 3.1M points with 1024 waves: every extreme value is met
+    by thousands of points spread over every tile of every run, so the
+    lowest index must be found across tiles and runs."""
+    default = H.tuning()
+    H.set_tuning(1, 1)
+    try:
+        x, y = inputs.small_grid(3_100_000, side, 60 + side, (5000, 7000))
+        check_all(H, x, y, preset, "grid side=%d preset=%d q>=3" % (side, preset))
+    finally:
+        H.set_tuning(*default)
 
 
 def test_validate_flag(H):

@@ -118,6 +118,26 @@ def test_regular_48gon_closed_form(p, angles):
     assert list(oracle.compute(x, y, p)) == list(hull)
 
 
+@pytest.mark.parametrize("phase", [0.0, 2.0, -2.5])
+def test_extremes_dirs_regular_64gon(phase):
+    """Closed form for the learned projection: a regular 64-gon whose vertex
+    j sits at angle phase + 360 j / 64 (within half a step of the candidate
+    direction 2 pi j / 64), with interior points.  The point of largest
+    cos(phi_d) x + sin(phi_d) y is vertex d for every d: a swapped pair of
+    constants (s x + c y) picks vertex 16 - d, a sign slip (c x - s y)
+    vertex -d, a minimum instead of a maximum vertex d + 32."""
+    x, y, m = inputs.regular_polygon(64, 5000, seed=11, phase_deg=phase)
+    c, s = oracle.direction_table()
+    slots, vals = oracle.extremes_dirs(x, y, c, s)
+    assert list(slots) == list(range(64))
+    xd, yd = x.astype(np.float64), y.astype(np.float64)
+    assert np.array_equal(vals, c * xd[:64] + s * yd[:64])
+    # and on a shuffled copy, the slot follows the vertex to its new index
+    perm = np.random.default_rng(5).permutation(len(x))
+    slots2, _ = oracle.extremes_dirs(x[perm], y[perm], c, s)
+    assert list(perm[slots2]) == list(range(64))
+
+
 def test_extremes_tie_break_lowest_index():
     # points 2, 4, 6 share the minimum x; 1, 5 share the maximum y
     kx = [5, 6, 1, 7, 1, 3, 1]
