@@ -24,6 +24,9 @@ NONE = 0xFFFFFFFF
 # direction presets (Sec. 2 Step 1, Figure 1, Sec. 5)
 PRESET_PAPER = 0       # rotations 0, 30, 45, 60 degrees
 PRESET_CUMULATIVE = 1  # 30, 45, 45 read cumulatively: 0, 30, 75, 120 degrees
+# presets 2..7: G = p - 1 groups at 90 j / G degrees (4G evenly spaced
+# directions); preset 2 is the min/max x and y quadrilateral (Sec. 1, ref. [3])
+EVEN_PRESETS = {2: 4, 3: 8, 4: 12, 5: 16, 6: 20, 7: 24}
 
 
 def build(force=True):
@@ -87,9 +90,10 @@ def _pts(x, y):
 
 
 def preset(p=PRESET_PAPER):
-    """(cos, sin) binary64 constants of a direction preset, 4 groups each."""
-    c = np.zeros(4, np.float64)
-    s = np.zeros(4, np.float64)
+    """(cos, sin) binary64 constants of a direction preset: 4 groups for
+    presets 0 and 1, G = p - 1 evenly spaced groups for presets 2..7."""
+    c = np.zeros(6, np.float64)
+    s = np.zeros(6, np.float64)
     g = lib().oracle_preset(p, _p(c), _p(s))
     if g < 0:
         raise ValueError("unknown preset %r" % p)

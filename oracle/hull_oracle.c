@@ -61,12 +61,44 @@ static const double PRESET0_S[4] = {0.0, 0.5, COS45, COS30};
 static const double PRESET1_C[4] = {1.0, COS30, COS75, -0.5};
 static const double PRESET1_S[4] = {0.0, 0.5, SIN75, COS30};
 
-/* Copy preset `preset` into c[4], s[4]; return the number of groups or -1. */
+/* presets 2..7: direction families beyond the paper's table.  Preset 1 + G
+ * has G rotation groups at 90 j / G degrees, j = 0..G-1, so its 4G extreme
+ * directions are evenly spaced 90 / G degrees apart.  G = 1 is the plain
+ * min/max x and y quadrilateral that the paper cites as the simplest
+ * preprocessing filter (Sec. 1, ref. [3]).  Rows: cos(90 j / G) for
+ * j = 0..5 (unused entries 0); the sines follow from
+ * sin(90 j / G) = cos(90 (G - j) / G). */
+static const double EVEN_COS[6][6] = {
+    /* G = 1: 0 */
+    {1.0, 0, 0, 0, 0, 0},
+    /* G = 2: 0, 45 */
+    {1.0, 0x1.6a09e667f3bcdp-1, 0, 0, 0, 0},
+    /* G = 3: 0, 30, 60 */
+    {1.0, 0x1.bb67ae8584caap-1, 0x1p-1, 0, 0, 0},
+    /* G = 4: 0, 22.5, 45, 67.5 */
+    {1.0, 0x1.d906bcf328d46p-1, 0x1.6a09e667f3bcdp-1, 0x1.87de2a6aea963p-2, 0, 0},
+    /* G = 5: 0, 18, 36, 54, 72 */
+    {1.0, 0x1.e6f0e134454ffp-1, 0x1.9e3779b97f4a8p-1, 0x1.2cf2304755a5ep-1,
+     0x1.3c6ef372fe950p-2, 0},
+    /* G = 6: 0, 15, 30, 45, 60, 75 */
+    {1.0, 0x1.ee8dd4748bf15p-1, 0x1.bb67ae8584caap-1, 0x1.6a09e667f3bcdp-1, 0x1p-1,
+     0x1.0907dc1930690p-2}};
+
+/* Copy preset `preset` into c[], s[] (room for 6 groups); return the number
+ * of groups or -1. */
 int oracle_preset(int preset, double *c, double *s)
 {
     const double *pc, *ps;
     if (preset == 0) { pc = PRESET0_C; ps = PRESET0_S; }
     else if (preset == 1) { pc = PRESET1_C; ps = PRESET1_S; }
+    else if (preset >= 2 && preset <= 7) {
+        int G = preset - 1;
+        for (int j = 0; j < G; j++) {
+            c[j] = EVEN_COS[G - 1][j];
+            s[j] = j == 0 ? 0.0 : EVEN_COS[G - 1][G - j];
+        }
+        return G;
+    }
     else return -1;
     for (int g = 0; g < 4; g++) { c[g] = pc[g]; s[g] = ps[g]; }
     return 4;

@@ -428,3 +428,84 @@ def test_label_targets_degenerate():
     assert not t.any() and list(o) == [-1] * 4
     t, o = oracle.label_targets(x[:0], y[:0], rounds=4)
     assert not t.any() and list(o) == [-1] * 4
+
+
+# -- direction families: the min/max quadrilateral (Sec. 1, ref. [3]) and 4G
+#    evenly spaced directions ----------------------------------------------
+
+EVEN = sorted(oracle.EVEN_PRESETS.items())       # (preset, directions)
+
+
+def _even_angles(p):
+    G = oracle.EVEN_PRESETS[p] // 4
+    return [90.0 * j / G for j in range(G)]
+
+
+@pytest.mark.parametrize("p,ndir", EVEN)
+def test_even_preset_constants_correctly_rounded(p, ndir):
+    c, s = oracle.preset(p)
+    G = ndir // 4
+    assert len(c) == G
+    for j in range(G):
+        cc, ss = _cr_cos_sin(j, 4 * G)          # 90 j / G degrees = 2 pi j / (4 G)
+        assert c[j] == cc and s[j] == ss, (p, j, c[j].hex(), cc.hex(), s[j].hex(), ss.hex())
+
+
+@pytest.mark.parametrize("p,ndir", EVEN)
+def test_even_preset_regular_polygon_closed_form(p, ndir):
+    """A regular N-gon whose vertex spacing divides 90/G degrees: slot k of
+    group j is the vertex at the slot's direction (slot order and rotation
+    sign as for the paper's presets), the filter polygon is the set of those
+    vertices, and with G >= 2 its inradius exceeds the interior points'
+    radius, so only the N-gon's own vertices survive."""
+    G = ndir // 4
+    N = 40 if G == 5 else 48
+    x, y, m = inputs.regular_polygon(N, 3000, seed=8)
+    slots, _ = oracle.extremes(x, y, p)
+    assert len(slots) == ndir
+    want = [round(a / (360 / N)) % N for a in _slot_angles(_even_angles(p))]
+    assert list(slots) == want
+    verts = oracle.polygon(x, y, slots)
+    assert sorted(verts) == sorted(set(int(s) for s in slots))
+    assert len(verts) == ndir
+    surv = oracle.discard(x, y, verts)
+    if G >= 2:
+        assert list(surv) == list(range(N))
+    else:       # the quadrilateral's inradius 0.4/sqrt(2) < 0.3: brute force
+        vx, vy = _brute.polygon_grid(x, y, verts)
+        kx, ky = to_grid(x), to_grid(y)
+        want = [i for i in range(len(x)) if not _brute.strictly_inside(int(kx[i]), int(ky[i]), vx, vy)]
+        assert list(surv) == want
+        assert set(range(N)) <= set(int(v) for v in surv)
+    assert list(oracle.compute(x, y, p)) == list(oracle.hull_subset(x, y))
+
+
+def test_even_closed_form_values():
+    # disk remaining with 4 axis directions: 1 - 2/pi; with 16 even ones 2.550 %
+    assert _remaining_closed_form(_dirs([0])) == pytest.approx(1 - 2 / math.pi, abs=1e-12)
+    assert _remaining_closed_form(_dirs([0])) == pytest.approx(0.3634, abs=5e-5)
+    assert _remaining_closed_form(_dirs([0, 22.5, 45, 67.5])) == pytest.approx(0.02550, abs=5e-5)
+
+
+@pytest.mark.parametrize("p,ndir", EVEN)
+def test_even_disk_remaining_fraction(p, ndir):
+    n = 1_000_000
+    x, y = inputs.disk(n, 2024)
+    _, surv = oracle.compute(x, y, p, want_survivors=True)
+    frac = len(surv) / n
+    assert frac == pytest.approx(_remaining_closed_form(_dirs(_even_angles(p))), abs=1.5e-3)
+
+
+@pytest.mark.parametrize("p,ndir", EVEN)
+def test_even_method_invariants(p, ndir):
+    x, y = inputs.DISTRIBUTIONS["gaussian"](20000, 21 + p)
+    hull, surv = oracle.compute(x, y, p, want_survivors=True)
+    assert list(hull) == list(oracle.compute(x, y, nofilter=True))
+    # a family whose directions include another's finds the same extreme
+    # points for the shared ones (same constants, same arithmetic), so its
+    # polygon contains the other's and it keeps a subset of the survivors:
+    # 4 in every family, 8 in 16 and 24, 12 in 24
+    supersets = {2: [3, 4, 5, 6, 7], 3: [5, 7], 4: [7]}
+    for q in supersets.get(p, []):
+        _, s2 = oracle.compute(x, y, q, want_survivors=True)
+        assert set(int(v) for v in s2) <= set(int(v) for v in surv), (p, q)
