@@ -81,6 +81,49 @@ def cpu_baseline(data, sample):
             "seconds": round(t, 3)}
 
 
+def host_cpu():
+    """Model and thread counts of the host (for the CPU baselines)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable_threads": usable}
+
+
+def cpu_baseline_batched(xs, ys, offs, workers):
+    """The CPU oracle on whole sets of the batched workload: once on one
+    thread, once with the sets spread over `workers` threads (the oracle is
+    plain single-threaded C; its ctypes calls release the GIL)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build(force=False)
+    S = len(offs) - 1
+    jobs = [(xs[offs[s]:offs[s + 1]], ys[offs[s]:offs[s + 1]]) for s in range(S)]
+    pts = int(offs[-1])
+    t0 = time.perf_counter()
+    for a, b in jobs:
+        oracle.compute(a, b)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda ab: oracle.compute(ab[0], ab[1]), jobs))
+    tn = time.perf_counter() - t0
+    return {"one_core": {"value": pts / t1 / 1e9, "unit": "Gpoints/s", "cores": 1,
+                         "kind": "oracle", "seconds": round(t1, 3)},
+            "all_cores": {"value": pts / tn / 1e9, "unit": "Gpoints/s", "cores": workers,
+                          "kind": "oracle", "seconds": round(tn, 3)},
+            "sample": "the first %d sets of the batch (%d points), whole method per set" % (S, pts)}
+
+
 def _time(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -97,6 +140,89 @@ def _discard_fraction_batched(H, x, y, off):
     slots = H.extremes_batched(x, y, off)
     _, so = H.discard_batched(x, y, off, slots)
     return 1.0 - float(so[-1].item()) / x.numel()
+
+
+def bench_latency(dev, reps=50):
+    """One set of 100,000 uniform-square points (about 0.8 MB, cache
+    resident): latency of the whole method per call, both presets of the
+    paper, eager calls and graph replays; median of `reps`."""
+    import torch
+    from paper_1405_3454_amd import inputs
+    from paper_1405_3454_amd.api import Hull
+    x, y = inputs.square(100_000, 100)
+    xt, yt = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    off = torch.tensor([0, len(x)], dtype=torch.int64, device=dev)
+    hull = torch.empty(len(x), dtype=torch.int32, device=dev)
+    hc = torch.zeros(1, dtype=torch.int64, device=dev)
+    ho = torch.zeros(2, dtype=torch.int64, device=dev)
+    res = {}
+    for preset in (0, 1):
+        H = Hull(0, preset=preset)
+        out = {}
+        for name, fn in (("eager_us", lambda: H.compute_into(xt, yt, hull, hc)),
+                         ("graph_us", lambda: H.graph_launch())):
+            if name == "graph_us":
+                H.graph_capture(xt, yt, off, hull, ho)
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            out[name] = round(float(np.median(ts)) * 1e6, 1)
+        H.close()
+        res[PRESET_NAMES[preset]] = out
+    return {"workload": "one set of 100,000 uniform-square points, float32 k*2^-24",
+            "median_of": reps, **res}
+
+
+PRESET_NAMES = {0: "0/30/45/60 (paper)", 1: "0/30/75/120 (cumulative)", 2: "4 even (quadrilateral)",
+                3: "8 even", 4: "12 even", 5: "16 even", 6: "20 even", 7: "24 even"}
+
+
+def bench_directions(args, X, Y, n):
+    """Discard-vs-cost curve of the direction families: the whole method on
+    the same four sets under every preset (extremes pass cost grows with the
+    direction count, the discard fraction with it)."""
+    import torch
+    from paper_1405_3454_amd.api import Hull
+    dev = X[KINDS[0]].device
+    hull = torch.empty(n, dtype=torch.int32, device=dev)
+    hcnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    surv = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    steps = max(2, args.steps // 2)
+    curve = []
+    for preset in range(8):
+        H = Hull(0, preset=preset)
+
+        def step():
+            for k in KINDS:
+                H.compute_into(X[k], Y[k], hull, hcnt)
+        t = _time(step, steps, 1)
+        H.timing(True)
+        H.timing_reset()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        kt = H.timing_read()
+        H.timing(False)
+        disc = {}
+        for k in KINDS:
+            slots, _ = H.extremes(X[k], Y[k])
+            H.discard_into(X[k], Y[k], slots, surv, cnt)
+            disc[k] = round(1.0 - cnt.item() / n, 6)
+        H.close()
+        us = {name: round(ms / c * 1e3, 1) for name, (ms, c) in kt.items()
+              if name in ("extremes", "discard", "refine_pass", "polygon")}
+        curve.append({"preset": preset, "directions": PRESET_NAMES[preset],
+                      "gpts": round(len(KINDS) * n / t / 1e9, 3), "ms_per_step": round(t * 1e3, 3),
+                      "us_mean_per_launch": us, "discard_fraction": disc})
+    del hull, surv
+    return curve
 
 
 def bench_batched(args, dev):
@@ -135,6 +261,12 @@ def bench_batched(args, dev):
     t_graph = _time(H.graph_launch, args.steps, 1)
     disc = _discard_fraction_batched(H, x, y, off)
     H.close()
+    cpu = None
+    if not args.no_cpu:
+        K = min(S, args.cpu_batch_sets)
+        a = int(offs[K])
+        cpu = cpu_baseline_batched(x[:a].cpu().numpy(), y[:a].cpu().numpy(), offs[:K + 1],
+                                   min(16, host_cpu()["usable_threads"]))
     res = {"workload": "%d sets, sizes log-uniform [1e3, 1e6], square/disk/gaussian/annulus" % S,
            "points": int(n),
            "per_set_gpts": round(n / t_set / 1e9, 3),
@@ -145,6 +277,8 @@ def bench_batched(args, dev):
            "speedup_graph_vs_per_set": round(t_set / t_graph, 2),
            "discard_fraction": round(disc, 6),
            "tuning": tuning}
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     del x, y, hull
     torch.cuda.empty_cache()
     return res
@@ -220,6 +354,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27,
                     help="points of each set the CPU oracle is timed on")
+    ap.add_argument("--cpu-batch-sets", type=int, default=1024,
+                    help="sets of the batched workload the CPU oracle is timed on")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--batch-sets", type=int, default=4096)
     ap.add_argument("--train-sets", type=int, default=200000)
@@ -286,6 +422,32 @@ def main():
     kt = H.timing_read()
     H.timing(False)
 
+    # per set: refinement and radix-sort passes against their algorithmic
+    # bytes (a refinement round reads its input entries and writes the kept
+    # ones, 14 B each; a radix pass reads and writes every key and index,
+    # 16 B; up to 4096 keys are sorted in one block and no pass runs)
+    passes = {}
+    for k in KINDS:
+        H.timing(True)
+        H.timing_reset()
+        for _ in range(args.steps):
+            H.compute_into(X[k], Y[k], hull[k], hcnt[k])
+        torch.cuda.synchronize()
+        kk = H.timing_read()
+        H.timing(False)
+        cc = H.candidate_counts()
+        ref_bytes = sum(14.0 * (cc[r] + cc[r + 1]) for r in range(len(cc) - 1)) if min(cc) >= 0 else 0.0
+        keys = cc[-1]
+        sort_bytes = 16.0 * keys * 6 if keys > 4096 else 0.0
+        row = {"candidates": cc}
+        for name, kinds, b in (("refine", ("refine_pass",), ref_bytes),
+                               ("sort", ("sort_hist", "sort_scatter"), sort_bytes)):
+            ms = sum(kk[c][0] for c in kinds if c in kk) / args.steps
+            row[name] = {"us": round(ms * 1e3, 1), "alg_bytes": int(b),
+                         "gbs": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                         "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+        passes[k] = row
+
     # survivors per set (discard fraction) from one extra discard call each
     disc = {}
     hs = {}
@@ -338,13 +500,15 @@ def main():
         "config": {"workload": "4 sets x 2^%d points (square, disk r=0.5, gaussian s=0.15, "
                                "annulus 0.45..0.5), float32 k*2^-24" % args.log2n,
                    "points_per_step": total_pts,
-                   "directions": "0/30/45/60" if args.preset == 0 else "0/30/75/120"},
+                   "directions": PRESET_NAMES[args.preset]},
         "roofline": roof,
         "hbm_gbs": {k: round(v, 1) for k, v in hbm.items()},
         "discard_fraction": {k: round(v, 6) for k, v in disc.items()},
         "hull_vertices": hs,
         "per_kernel": per_kernel,
+        "hull_stage_passes": passes,
     }
+    out["latency_100k"] = bench_latency(dev)
     if not args.skip_extra:
         # unfiltered arm: the same hull without the filter (sort + chain of all points)
         hull_u = torch.empty(n, dtype=torch.int32, device=dev)
@@ -358,6 +522,7 @@ def main():
                              "ms_per_step": round(t_u * 1e3, 3),
                              "speedup_of_filter": round(t_u / dt, 3)}
         del hull_u
+        out["direction_families"] = bench_directions(args, X, Y, n)
         H.close()
         del X, Y, hull
         torch.cuda.empty_cache()
@@ -365,6 +530,7 @@ def main():
         out["learned"] = bench_learned(args, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(data, min(n, args.cpu_sample))
+        out["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(out), flush=True)
     if args.skip_extra:
         H.close()

@@ -33,9 +33,11 @@
  *    s = sin t) the rotated coordinates are u = c*x - s*y and v = s*x + c*y,
  *    each product rounded to binary64 and then the sum (no fused multiply-add).
  *    slots[4g+0] = argmin u, [4g+1] = argmax u, [4g+2] = argmin v,
- *    [4g+3] = argmax v; ties go to the lowest index.  With HULL_LEARNED eight
- *    more slots follow: argmax of c*x + s*y along eight directions chosen per
- *    set by the learned proposal.
+ *    [4g+3] = argmax v; ties go to the lowest index.  A set has
+ *    hull_slot_count() slots: max(16, 4G) fixed positions for a preset of G
+ *    groups (positions past 4G hold HULL_NONE), then, with HULL_LEARNED, the
+ *    argmax of c*x + s*y along eight directions chosen per set by the learned
+ *    proposal (only for presets of at most 16 fixed slots).
  *  - Polygon and hull vertex lists are counter-clockwise, start at the
  *    lexicographically smallest (x, y), exclude collinear points and name a
  *    repeated coordinate pair by its lowest index.
@@ -70,6 +72,14 @@ typedef struct hull_ctx hull_ctx;
 /* direction presets (angles of the rotated copies, Sec. 2 Step 1) */
 #define HULL_DIRS_PAPER 0      /* 0, 30, 45, 60 degrees (Figure 1, Sec. 5) */
 #define HULL_DIRS_CUMULATIVE 1 /* 30, 45, 45 of Sec. 2 read cumulatively: 0, 30, 75, 120 */
+/* Direction families beyond the paper's table: G = 1..6 rotation groups at
+ * 90 j / G degrees (j = 0..G-1), i.e. 4G evenly spaced extreme directions.
+ * G = 1 is the min/max x and y quadrilateral, the simplest preprocessing
+ * filter the paper cites (Sec. 1, ref. [3]); G = 4 gives 16 evenly spaced
+ * directions, as many as the paper's table. */
+#define HULL_DIRS_EVEN(G) (1 + (G))
+#define HULL_DIRS_QUAD HULL_DIRS_EVEN(1)
+#define HULL_NUM_PRESETS 8
 
 /* flags */
 #define HULL_NOFILTER 1 /* hull of all points, no preprocessing (Sec. 3, case (1)) */
@@ -91,19 +101,29 @@ typedef struct hull_ctx hull_ctx;
 int hull_create(hull_ctx **ctx, int device);
 /* Free the context, its workspace, graphs and network weights. */
 int hull_destroy(hull_ctx *ctx);
-/* Select the rotation angles of Step 1 (HULL_DIRS_*); default PAPER. */
+/* Select the rotation angles of Step 1 (HULL_DIRS_*, 0 <= preset <
+ * HULL_NUM_PRESETS); default PAPER.  HULL_EINVAL for an unknown preset. */
 int hull_set_directions(hull_ctx *ctx, int preset);
+/* Slots per set that hull_extremes(_batched) writes for this context's
+ * preset with these flags (only HULL_LEARNED matters): 16 for the paper's
+ * presets, max(16, 4G) for an even family, plus 8 with HULL_LEARNED.
+ * HULL_EINVAL for a null ctx, or HULL_LEARNED with more than 16 fixed slots. */
+int hull_slot_count(hull_ctx *ctx, int flags);
 /* Host-only: copy a direction table into c[], s[] (capacity cap).
- * which = 0: the current preset's 4 rotation groups (needs ctx);
- * which = 1: the 64 candidate directions 2*pi*d/64 of the learned proposal.
- * Returns the number of entries or a negative code. */
+ * which = 0: the rotation groups of ctx's preset (PAPER if ctx is NULL);
+ * which = 1: the 64 candidate directions 2*pi*d/64 of the learned proposal;
+ * which = 16 + p: the rotation groups of preset p (ctx not needed).
+ * Returns the number of entries or a negative code (HULL_EINVAL for a null
+ * array, an unknown table or cap below the table's size). */
 int hull_direction_table(hull_ctx *ctx, int which, double *c, double *s, int cap);
 const char *hull_strerror(int code);
 int hull_last_hip_error(hull_ctx *ctx);
 
 /* ---- Step 1: extreme points (Sec. 2, Step 1) --------------------------- */
-/* slots: device uint32[16] (or [24] with HULL_LEARNED); vals: device
- * double[same] with the extreme values, or NULL.  n == 0 gives HULL_NONE. */
+/* slots: device uint32[hull_slot_count(ctx, flags)]; vals: device
+ * double[same] with the extreme values (NaN for HULL_NONE slots), or NULL.
+ * n == 0 gives HULL_NONE.  HULL_EINVAL for HULL_LEARNED with a preset of
+ * more than 16 fixed slots; HULL_ENOMODEL without network weights. */
 int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n,
                   uint32_t *slots, double *vals, int flags, void *stream);
 
@@ -141,7 +161,8 @@ int hull_compute(hull_ctx *ctx, const float *x, const float *y, int64_t n,
  * [offsets[s], offsets[s+1]).  Indices stay global. */
 int hull_extremes_batched(hull_ctx *ctx, const float *x, const float *y,
                           const int64_t *offsets, int64_t S, int64_t n_total,
-                          uint32_t *slots /* [S*16|24] */, int flags, void *stream);
+                          uint32_t *slots /* [S * hull_slot_count] */, int flags,
+                          void *stream);
 int hull_discard_batched(hull_ctx *ctx, const float *x, const float *y,
                          const int64_t *offsets, int64_t S, int64_t n_total,
                          const uint32_t *slots, int n_slots, uint32_t *surv,

@@ -17,6 +17,16 @@ HULL_ENOMODEL = -7
 
 HULL_DIRS_PAPER = 0
 HULL_DIRS_CUMULATIVE = 1
+HULL_NUM_PRESETS = 8
+
+
+def HULL_DIRS_EVEN(groups):
+    """Preset of `groups` rotation groups at 90 j / groups degrees (4 * groups
+    evenly spaced directions); groups = 1 is the min/max quadrilateral."""
+    return 1 + groups
+
+
+HULL_DIRS_QUAD = HULL_DIRS_EVEN(1)
 
 HULL_NOFILTER = 1
 HULL_LEARNED = 2
@@ -36,6 +46,7 @@ SIGNATURES = {
     "hull_destroy": (I, [P]),
     "hull_set_directions": (I, [P, I]),
     "hull_direction_table": (I, [P, I, P, P, I]),
+    "hull_slot_count": (I, [P, I]),
     "hull_strerror": (ctypes.c_char_p, [I]),
     "hull_last_hip_error": (I, [P]),
     "hull_extremes": (I, [P, P, P, I64, P, P, I, P]),

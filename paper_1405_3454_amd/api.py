@@ -10,8 +10,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (HULL_DIRS_CUMULATIVE, HULL_DIRS_PAPER, HULL_LEARNED, HULL_NOFILTER,
-                   HULL_VALIDATE, HULL_NOREFINE, check, lib)
+from ._lib import (HULL_DIRS_CUMULATIVE, HULL_DIRS_EVEN, HULL_DIRS_PAPER, HULL_DIRS_QUAD,
+                   HULL_LEARNED, HULL_NOFILTER, HULL_NOREFINE, HULL_VALIDATE, check, lib)
 
 FIXED_SLOTS = 16
 MAX_SLOTS = 24
@@ -72,6 +72,10 @@ class Hull:
         check(lib().hull_set_directions(self._h, int(preset)), "hull_set_directions")
         self.preset = preset
 
+    def slot_count(self, learned=False):
+        """Slots per set of the extremes calls for the current preset."""
+        return check(lib().hull_slot_count(self._h, _flags(learned=learned)), "hull_slot_count")
+
     def direction_table(self, which=0):
         c = np.zeros(64, np.float64)
         s = np.zeros(64, np.float64)
@@ -99,7 +103,7 @@ class Hull:
     # -- single set --------------------------------------------------------
     def extremes(self, x, y, learned=False, validate=False, stream=None):
         n = _pts(x, y)
-        k = MAX_SLOTS if learned else FIXED_SLOTS
+        k = self.slot_count(learned)
         slots = torch.empty(k, dtype=torch.int32, device=x.device)
         vals = torch.empty(k, dtype=torch.float64, device=x.device)
         check(lib().hull_extremes(self._h, _ptr(x), _ptr(y), n, _ptr(slots), _ptr(vals),
@@ -162,7 +166,7 @@ class Hull:
     def extremes_batched(self, x, y, offsets, learned=False, validate=False, stream=None):
         n = _pts(x, y)
         S = offsets.numel() - 1
-        k = MAX_SLOTS if learned else FIXED_SLOTS
+        k = self.slot_count(learned)
         slots = torch.empty(S * k, dtype=torch.int32, device=x.device)
         check(lib().hull_extremes_batched(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n,
                                           _ptr(slots), _flags(learned=learned, validate=validate),
@@ -326,4 +330,5 @@ def split_csr(flat, offsets):
 
 
 __all__ = ["Hull", "as_u32", "split_csr", "HULL_DIRS_PAPER", "HULL_DIRS_CUMULATIVE",
+           "HULL_DIRS_EVEN", "HULL_DIRS_QUAD",
            "HULL_NOFILTER", "HULL_LEARNED", "HULL_VALIDATE", "HULL_NOREFINE", "_lib"]

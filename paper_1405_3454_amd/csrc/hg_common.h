@@ -75,10 +75,25 @@ enum Kind {
     K_FINAL, K_LOOKUP, K_VALIDATE, K_MISC, K_HIST32, K_MLP, K_LABELS, K_REFINE, K_REFINE_SPLIT, K_NKINDS
 };
 
+// Direction presets (rotation groups of Step 1).  Preset 0: 0/30/45/60
+// degrees; preset 1: 0/30/75/120 (its last group repeats the 30-degree one);
+// preset 1 + G (G = 1..6): G groups at 90 j / G degrees, 4G evenly spaced
+// extreme directions (G = 1: the min/max x and y quadrilateral).
+constexpr int NUM_PRESETS = 8;
+constexpr int MAX_GROUPS = 6;
+__host__ __device__ constexpr int preset_groups(int P) { return P <= 1 ? 4 : P - 1; }
+// groups the extremes pass evaluates (preset 1 copies its fourth group)
+__host__ __device__ constexpr int preset_eval_groups(int P) { return P == 1 ? 3 : preset_groups(P); }
+// fixed slot positions: at least 16, so that learned slots start at 16 when
+// the fixed table has no more than 16 slots; unused positions hold NONE
+__host__ __device__ constexpr int preset_fixed_slots(int P) {
+    return 4 * preset_groups(P) > FIXED_SLOTS ? 4 * preset_groups(P) : FIXED_SLOTS;
+}
+
 // Direction constants for one launch.  Preset groups: (gc[g], gs[g]).
 struct Dirs {
-    double gc[4];
-    double gs[4];
+    double gc[MAX_GROUPS];
+    double gs[MAX_GROUPS];
 };
 
 }  // namespace hg

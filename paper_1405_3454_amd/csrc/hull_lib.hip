@@ -25,14 +25,23 @@ static const double H_C45 = 0x1.6a09e667f3bcdp-1;
 static const double H_C75 = 0x1.0907dc1930690p-2;
 static const double H_S75 = 0x1.ee8dd4748bf15p-1;
 
+static bool preset_valid(int preset) { return preset >= 0 && preset < NUM_PRESETS; }
+
 static Dirs preset_dirs(int preset) {
-    Dirs d;
+    Dirs d = {};
     if (preset == HULL_DIRS_PAPER) {
         const double c[4] = {1.0, H_C30, H_C45, 0.5}, s[4] = {0.0, 0.5, H_C45, H_C30};
         for (int g = 0; g < 4; g++) { d.gc[g] = c[g]; d.gs[g] = s[g]; }
-    } else {
+    } else if (preset == HULL_DIRS_CUMULATIVE) {
         const double c[4] = {1.0, H_C30, H_C75, -0.5}, s[4] = {0.0, 0.5, H_S75, H_C30};
         for (int g = 0; g < 4; g++) { d.gc[g] = c[g]; d.gs[g] = s[g]; }
+    } else {
+        // G evenly spaced groups: cos(90 j / G), sin(90 j / G) = cos(90 (G - j) / G)
+        const int G = preset_groups(preset);
+        for (int j = 0; j < G; j++) {
+            d.gc[j] = EVEN_COS[G][j];
+            d.gs[j] = EVEN_COS[G][G - j];
+        }
     }
     return d;
 }
@@ -66,6 +75,13 @@ struct hull_ctx {
     // learned proposal
     LearnedState learned;
 };
+
+// Slots of one set's extremes: the preset's fixed positions, then the
+// learned directions.  Learned slots need a fixed table of at most 16.
+static int slot_count(const hull_ctx *ctx, bool learned) {
+    return preset_fixed_slots(ctx->preset) + (learned ? MAX_DIRS : 0);
+}
+static bool learned_ok(const hull_ctx *ctx) { return preset_fixed_slots(ctx->preset) == FIXED_SLOTS; }
 
 static const char *kKindNames[K_NKINDS] = {
     "tile_map", "extremes", "polygon", "discard", "scan", "scatter", "keys",
@@ -116,6 +132,7 @@ static int launch(hull_ctx *ctx, int kind, hipStream_t st, F &&f) {
 // ---------------------------------------------------------------------------
 // Workspace plan.  All sizes are upper bounds derived from (n_total, S).
 struct Plan {
+    char *base = nullptr;   // device workspace the offsets below point into
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
         hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
@@ -124,7 +141,7 @@ struct Plan {
     int64_t nwave;      // discard waves = regions of the full method's survivor lists
 };
 
-static size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+static constexpr size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 
 static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     Plan p;
@@ -212,9 +229,10 @@ static int ensure_ws(hull_ctx *ctx, size_t bytes, hipStream_t st) {
     return HULL_OK;
 }
 
+// Buffer at offset `off` of the plan's workspace.
 template <typename T>
-static T *W(hull_ctx *ctx, size_t off) {
-    return reinterpret_cast<T *>(ctx->ws + off);
+static T *W(const Plan &p, size_t off) {
+    return reinterpret_cast<T *>(p.base + off);
 }
 
 static int check_points(const float *x, const float *y, int64_t n) {
@@ -230,9 +248,55 @@ static int check_points(const float *x, const float *y, int64_t n) {
 // align their tiles to absolute 16-byte boundaries.
 static int phase_of(const float *x) { return (int)(((uintptr_t)x >> 2) & 3); }
 
-// the learned variant of the extremes pass holds ~190 VGPRs: 2 waves per SIMD
+// The extremes pass instantiated for a preset (learned: with eight learned
+// directions), as a host handle for occupancy queries.
+static const void *k1_kernel(int preset, bool learned) {
+#define K1F(PR) (learned ? (const void *)k_extremes<PR, MAX_DIRS> : (const void *)k_extremes<PR, 0>)
+    switch (preset) {
+    case 0: return K1F(0);
+    case 1: return K1F(1);
+    case 2: return K1F(2);
+    case 3: return K1F(3);
+    case 4: return K1F(4);
+    case 5: return K1F(5);
+    case 6: return (const void *)k_extremes<6, 0>;
+    case 7: return (const void *)k_extremes<7, 0>;
+    default: return nullptr;
+    }
+#undef K1F
+}
+
+// Blocks of 256 threads per CU that stay resident for a kernel (its register
+// and LDS use), cached per kernel in a fixed table (hull_create fills it for
+// every extremes variant, so later calls neither query nor allocate); 1 if
+// the query fails.
+static int resident_blocks(const void *fn) {
+    static std::mutex mu;
+    static const void *keys[32];
+    static int vals[32];
+    static int used = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < used; i++)
+        if (keys[i] == fn) return vals[i];
+    int b = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, 256, 0) != hipSuccess || b < 1) {
+        (void)hipGetLastError();
+        b = 1;
+    }
+    if (used < 32) {
+        keys[used] = fn;
+        vals[used] = b;
+        used++;
+    }
+    return b;
+}
+
+// Grid of the persistent extremes pass: the tuned blocks per CU, capped at
+// what stays resident (the variants hold 100 to 254 VGPRs: 2 to 4 waves per
+// SIMD), so that every block runs in the first wave of blocks.
 static int grid_k1(hull_ctx *ctx, bool learned = false) {
-    return ctx->cus * (learned ? std::min(ctx->k1_bpc, 2) : ctx->k1_bpc);
+    const bool l = learned && learned_ok(ctx);
+    return ctx->cus * std::min(ctx->k1_bpc, resident_blocks(k1_kernel(ctx->preset, l)));
 }
 static int grid_k3(hull_ctx *ctx) { return ctx->cus * ctx->k3_bpc; }
 
@@ -242,7 +306,7 @@ static int grid_k3(hull_ctx *ctx) { return ctx->cus * ctx->k3_bpc; }
 // Exclusive scan of u32 counts (count at *cnt) into out[0..count] (int64).
 static int run_scan(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t *in,
                     const int64_t *cnt, int64_t *out) {
-    int64_t *bs = W<int64_t>(ctx, p.scan_bs);
+    int64_t *bs = W<int64_t>(p, p.scan_bs);
     LAUNCH(K_SCAN, k_scan_reduce<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs, out,
                                                                        ctx->tickets + 0));
     LAUNCH(K_SCAN, k_scan_down<<<SCAN_BLOCKS, SCAN_THREADS, 0, st>>>(in, cnt, bs, out));
@@ -251,7 +315,7 @@ static int run_scan(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
 
 static int run_validate(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                         const float *y, int64_t n, const int64_t *off, int64_t S) {
-    int *err = W<int>(ctx, p.err);
+    int *err = W<int>(p, p.err);
     LAUNCH(K_VALIDATE, k_fill_i64<<<1, 64, 0, st>>>(reinterpret_cast<int64_t *>(err), 1, 0));
     LAUNCH(K_VALIDATE, k_validate<<<1024, 256, 0, st>>>(x, y, n, off, S, err));
     int h = 0;
@@ -262,11 +326,11 @@ static int run_validate(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
 
 static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const int64_t *off, int64_t n1, int64_t S) {
-    int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
+    int64_t *tile_off = W<int64_t>(p, p.tile_off);
     LAUNCH(K_TILEMAP, k_tile_offsets<<<1, 1024, 0, st>>>(off, n1, S, TILE, phase_of(x), tile_off,
-                                                         W<uint32_t>(ctx, p.pticket)));
+                                                         W<uint32_t>(p, p.pticket)));
     LAUNCH(K_TILEMAP, k_tile_sets<<<(unsigned)std::min<int64_t>(ctx->cus * 4, (p.tcap + 255) / 256), 256,
-                                     0, st>>>(tile_off, S, W<int32_t>(ctx, p.tile_set)));
+                                     0, st>>>(tile_off, S, W<int32_t>(p, p.tile_set)));
     return HULL_OK;
 }
 
@@ -274,21 +338,28 @@ static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
 static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                         const float *y, int64_t n_total, const int64_t *off, int64_t n1,
                         int64_t S, bool learned) {
-    const int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
-    const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
-    double *pval = W<double>(ctx, p.pval);
-    uint32_t *pidx = W<uint32_t>(ctx, p.pidx);
-    const double *sd = W<double>(ctx, p.setdirs);
+    const int64_t *tile_off = W<int64_t>(p, p.tile_off);
+    const int32_t *tile_set = W<int32_t>(p, p.tile_set);
+    double *pval = W<double>(p, p.pval);
+    uint32_t *pidx = W<uint32_t>(p, p.pidx);
+    const double *sd = W<double>(p, p.setdirs);
     const int g = grid_k1(ctx, learned);
     const Dirs d = ctx->dirs;
 #define K1(PR, ND)                                                                           \
     LAUNCH(K_EXTREMES, k_extremes<PR, ND><<<g, 256, 0, st>>>(x, y, n_total, phase_of(x), off, \
                                                              n1, S, tile_off, tile_set, d, sd, \
                                                              pval, pidx))
-    if (ctx->preset == HULL_DIRS_PAPER) {
-        if (learned) K1(0, MAX_DIRS); else K1(0, 0);
-    } else {
-        if (learned) K1(1, MAX_DIRS); else K1(1, 0);
+    if (learned && !learned_ok(ctx)) return HULL_EINVAL;
+    switch (ctx->preset) {
+    case 0: if (learned) K1(0, MAX_DIRS); else K1(0, 0); break;
+    case 1: if (learned) K1(1, MAX_DIRS); else K1(1, 0); break;
+    case 2: if (learned) K1(2, MAX_DIRS); else K1(2, 0); break;
+    case 3: if (learned) K1(3, MAX_DIRS); else K1(3, 0); break;
+    case 4: if (learned) K1(4, MAX_DIRS); else K1(4, 0); break;
+    case 5: if (learned) K1(5, MAX_DIRS); else K1(5, 0); break;
+    case 6: K1(6, 0); break;
+    case 7: K1(7, 0); break;
+    default: return HULL_EINVAL;
     }
 #undef K1
     return HULL_OK;
@@ -297,31 +368,37 @@ static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
 static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const float *y, int64_t n_total, int64_t S, bool learned, const uint32_t *slots_in,
                        int n_in, uint32_t *slots_out, double *vals_out, bool ref_init = false) {
-    REdge *rtab = ref_init ? W<REdge>(ctx, p.rtab0) : nullptr;
-    unsigned long long *rfar = ref_init ? W<unsigned long long>(ctx, p.rfar0) : nullptr;
+    REdge *rtab = ref_init ? W<REdge>(p, p.rtab0) : nullptr;
+    unsigned long long *rfar = ref_init ? W<unsigned long long>(p, p.rfar0) : nullptr;
     const int64_t W1 = (int64_t)grid_k1(ctx, learned) * 4;
-    auto *polys = W<Poly>(ctx, p.polys);
-    auto *spans = W<Span>(ctx, p.spans);
-    const double *sd = W<double>(ctx, p.setdirs);
+    auto *polys = W<Poly>(p, p.polys);
+    auto *spans = W<Span>(p, p.spans);
+    const double *sd = W<double>(p, p.setdirs);
     // blocks per set sharing the reduction of the extremes partials: about one
     // per POLY_THREADS of the set's runs (W1 / S on average)
     const unsigned split = slots_in ? 1u
         : (unsigned)std::max<int64_t>(1, std::min<int64_t>(POLY_SPLIT, W1 / (S * POLY_THREADS / 16)));
-#define K2(NEV, ND)                                                                           \
-    LAUNCH(K_POLYGON, k_polygon<NEV, ND><<<dim3((unsigned)S, split), POLY_THREADS, 0, st>>>(     \
-        x, y, n_total, S, W<int64_t>(ctx, p.tile_off), W1, W<double>(ctx, p.pval),             \
-        W<uint32_t>(ctx, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
-        spans, W<uint32_t>(ctx, p.redges), rtab, rfar, W<SlotBest>(ctx, p.bpart),             \
-        W<uint32_t>(ctx, p.pticket)))
-    const bool cum = ctx->preset == HULL_DIRS_CUMULATIVE;
-    if (learned) {
-        if (cum) K2(12, MAX_DIRS); else K2(16, MAX_DIRS);
-    } else {
-        if (cum) K2(12, 0); else K2(16, 0);
+#define K2(PR, ND)                                                                            \
+    LAUNCH(K_POLYGON, k_polygon<PR, ND><<<dim3((unsigned)S, split), POLY_THREADS, 0, st>>>(      \
+        x, y, n_total, S, W<int64_t>(p, p.tile_off), W1, W<double>(p, p.pval),             \
+        W<uint32_t>(p, p.pidx), slots_in, n_in, ctx->dirs, sd, slots_out, vals_out, polys,  \
+        spans, W<uint32_t>(p, p.redges), rtab, rfar, W<SlotBest>(p, p.bpart),             \
+        W<uint32_t>(p, p.pticket)))
+    if (learned && !learned_ok(ctx)) return HULL_EINVAL;
+    switch (ctx->preset) {
+    case 0: if (learned) K2(0, MAX_DIRS); else K2(0, 0); break;
+    case 1: if (learned) K2(1, MAX_DIRS); else K2(1, 0); break;
+    case 2: if (learned) K2(2, MAX_DIRS); else K2(2, 0); break;
+    case 3: if (learned) K2(3, MAX_DIRS); else K2(3, 0); break;
+    case 4: if (learned) K2(4, MAX_DIRS); else K2(4, 0); break;
+    case 5: if (learned) K2(5, MAX_DIRS); else K2(5, 0); break;
+    case 6: K2(6, 0); break;
+    case 7: K2(7, 0); break;
+    default: return HULL_EINVAL;
     }
 #undef K2
     LAUNCH(K_POLYGON, k_rows<<<dim3((unsigned)S, SPAN_ROWS / ROWS_PER_BLOCK), 256, 0, st>>>(
-        polys, spans, W<uint32_t>(ctx, p.redges)));
+        polys, spans, W<uint32_t>(p, p.redges)));
     return HULL_OK;
 }
 
@@ -330,14 +407,14 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
 static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const float *y, int64_t n_total, const int64_t *off, int64_t n1,
                        int64_t S, int nedge, uint32_t *surv, int64_t *surv_off, uint64_t *keys) {
-    const int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
-    const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
-    auto *polys = W<Poly>(ctx, p.polys);
-    auto *spans = W<Span>(ctx, p.spans);
-    const uint32_t *redges = W<uint32_t>(ctx, p.redges);
-    uint64_t *masks = W<uint64_t>(ctx, p.masks);
-    uint32_t *tcnt = W<uint32_t>(ctx, p.tile_cnt);
-    int64_t *tpos = W<int64_t>(ctx, p.tile_pos);
+    const int64_t *tile_off = W<int64_t>(p, p.tile_off);
+    const int32_t *tile_set = W<int32_t>(p, p.tile_set);
+    auto *polys = W<Poly>(p, p.polys);
+    auto *spans = W<Span>(p, p.spans);
+    const uint32_t *redges = W<uint32_t>(p, p.redges);
+    uint64_t *masks = W<uint64_t>(p, p.masks);
+    uint32_t *tcnt = W<uint32_t>(p, p.tile_cnt);
+    int64_t *tpos = W<int64_t>(p, p.tile_pos);
     const int g = grid_k3(ctx);
     if (nedge <= FIXED_SLOTS)
         LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS, DISCARD_MASKS><<<g, 256, 0, st>>>(
@@ -364,12 +441,12 @@ static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, cons
                               const float *y, int64_t n_total, const int64_t *off, int64_t n1,
                               int64_t S, int nedge, uint32_t *surv, uint64_t *keys,
                               uint16_t *edges, int64_t *seg_cnt, unsigned long long *gfar) {
-    const int64_t *tile_off = W<int64_t>(ctx, p.tile_off);
-    const int32_t *tile_set = W<int32_t>(ctx, p.tile_set);
-    auto *polys = W<Poly>(ctx, p.polys);
-    auto *spans = W<Span>(ctx, p.spans);
-    const uint32_t *redges = W<uint32_t>(ctx, p.redges);
-    int64_t *meta = W<int64_t>(ctx, p.segmeta);
+    const int64_t *tile_off = W<int64_t>(p, p.tile_off);
+    const int32_t *tile_set = W<int32_t>(p, p.tile_set);
+    auto *polys = W<Poly>(p, p.polys);
+    auto *spans = W<Span>(p, p.spans);
+    const uint32_t *redges = W<uint32_t>(p, p.redges);
+    int64_t *meta = W<int64_t>(p, p.segmeta);
     const int g = grid_k3(ctx);
     if ((int64_t)g * 4 != p.nwave) return HULL_EINVAL;   // the plan's regions assume this grid
     const int ph = phase_of(x);
@@ -398,9 +475,9 @@ static int sort_passes(int64_t S) {
 // Sort keys (count at *cnt) ascending; returns the buffer holding the result.
 static int run_sort(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint64_t *keys,
                     const int64_t *cnt, int passes, const uint64_t **sorted) {
-    uint64_t *A = W<uint64_t>(ctx, p.keysA), *B = W<uint64_t>(ctx, p.keysB);
-    uint32_t *hist = W<uint32_t>(ctx, p.hist);
-    int64_t *hoffs = W<int64_t>(ctx, p.hoffs);
+    uint64_t *A = W<uint64_t>(p, p.keysA), *B = W<uint64_t>(p, p.keysB);
+    uint32_t *hist = W<uint32_t>(p, p.hist);
+    int64_t *hoffs = W<int64_t>(p, p.hoffs);
     const uint64_t *in = keys;
     uint64_t *out = A;
     // small counts: sorted at once into the buffer the last pass would fill
@@ -437,9 +514,9 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     const uint64_t *sorted = nullptr;
     int rc = run_sort(ctx, p, st, keys, cnt, sort_passes(S), &sorted);
     if (rc) return rc;
-    uint64_t *lo[2] = {W<uint64_t>(ctx, p.lo0), W<uint64_t>(ctx, p.lo1)};
-    uint64_t *up[2] = {W<uint64_t>(ctx, p.up0), W<uint64_t>(ctx, p.up1)};
-    uint32_t *cc = W<uint32_t>(ctx, p.ccnt);
+    uint64_t *lo[2] = {W<uint64_t>(p, p.lo0), W<uint64_t>(p, p.lo1)};
+    uint64_t *up[2] = {W<uint64_t>(p, p.up0), W<uint64_t>(p, p.up1)};
+    uint32_t *cc = W<uint32_t>(p, p.ccnt);
     uint32_t *locnt[2] = {cc, cc + p.u0cap};
     uint32_t *upcnt[2] = {cc + 2 * p.u0cap, cc + 3 * p.u0cap};
     const int64_t u0 = (ncap + CHAIN_C - 1) / CHAIN_C;
@@ -459,17 +536,17 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
         cur = 1 - cur;
         R *= CHAIN_G;
     }
-    int64_t *bounds = W<int64_t>(ctx, p.bounds);
-    uint32_t *hcnt = W<uint32_t>(ctx, p.hcnt);
-    uint64_t *hkeys = W<uint64_t>(ctx, p.hkeys);
-    uint32_t *hpos = W<uint32_t>(ctx, p.hpos);
+    int64_t *bounds = W<int64_t>(p, p.bounds);
+    uint32_t *hcnt = W<uint32_t>(p, p.hcnt);
+    uint64_t *hkeys = W<uint64_t>(p, p.hkeys);
+    uint32_t *hpos = W<uint32_t>(p, p.hpos);
     if (S == 1) {
         LAUNCH(K_FINAL, k_hull_final1<<<1, 1024, 0, st>>>(lo[cur], up[cur], locnt[cur], upcnt[cur],
                                                           hoff, hkeys, hpos, hull, h_out));
         LAUNCH(K_LOOKUP, k_hull_lookup<<<2048, 256, 0, st>>>(idx, keys, cnt, S, hoff, hkeys, hpos, hull));
         return HULL_OK;
     }
-    int64_t *scount = W<int64_t>(ctx, p.consts) + 1;   // = S
+    int64_t *scount = W<int64_t>(p, p.consts) + 1;   // = S
     LAUNCH(K_FINAL, k_fill_i64<<<64, 256, 0, st>>>(bounds, 4 * S, 0));
     LAUNCH(K_FINAL, k_fill_i64<<<1, 64, 0, st>>>(scount, 1, S));
     LAUNCH(K_FINAL, k_seg_bounds<<<dim3(256, 2), 256, 0, st>>>(lo[cur], up[cur], locnt[cur],
@@ -507,18 +584,18 @@ static_assert(HULL_NCOUNTS == 1 + REF_ROUNDS, "one count per refinement round");
 static_assert(REF_ROUNDS % 2 == 0, "refinement must end in the first buffer set");
 static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                       const float *y, int64_t S) {
-    uint32_t *idxs[2] = {W<uint32_t>(ctx, p.surv), W<uint32_t>(ctx, p.lo0)};
-    uint64_t *keys[2] = {W<uint64_t>(ctx, p.keys0), W<uint64_t>(ctx, p.lo1)};
-    uint16_t *eds[2] = {W<uint16_t>(ctx, p.up0), W<uint16_t>(ctx, p.up1)};
-    REdge *tab[2] = {W<REdge>(ctx, p.rtab0), W<REdge>(ctx, p.rtab1)};
-    unsigned long long *far[2] = {W<unsigned long long>(ctx, p.rfar0),
-                                  W<unsigned long long>(ctx, p.rfar1)};
-    int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
-    const int64_t *meta = W<int64_t>(ctx, p.segmeta);
+    uint32_t *idxs[2] = {W<uint32_t>(p, p.surv), W<uint32_t>(p, p.lo0)};
+    uint64_t *keys[2] = {W<uint64_t>(p, p.keys0), W<uint64_t>(p, p.lo1)};
+    uint16_t *eds[2] = {W<uint16_t>(p, p.up0), W<uint16_t>(p, p.up1)};
+    REdge *tab[2] = {W<REdge>(p, p.rtab0), W<REdge>(p, p.rtab1)};
+    unsigned long long *far[2] = {W<unsigned long long>(p, p.rfar0),
+                                  W<unsigned long long>(p, p.rfar1)};
+    int64_t *segcnt = W<int64_t>(p, p.segcnt);
+    const int64_t *meta = W<int64_t>(p, p.segmeta);
     // one set: pass r splits the parents (tab[r % 2], F[r % 3]) itself, raises
     // F[(r + 1) % 3] (cleared before: k_counts_init, then the pass before)
     // and clears F[(r + 2) % 3], which no pass reads until two rounds later
-    unsigned long long *F[3] = {far[0], far[1], W<unsigned long long>(ctx, p.rfar2)};
+    unsigned long long *F[3] = {far[0], far[1], W<unsigned long long>(p, p.rfar2)};
     for (int r = 0; r < REF_ROUNDS; r++) {
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
@@ -548,9 +625,9 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
 static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, int stage) {
     const int64_t gb = std::max<int64_t>(stage + 1, std::min<int64_t>(256, p.nwave));
     LAUNCH(K_SCATTER, k_seg_gather<<<(unsigned)gb, 256, 0, st>>>(
-        W<uint32_t>(ctx, p.surv), W<uint64_t>(ctx, p.keys0), W<int64_t>(ctx, p.segcnt),
-        (int)p.nwave, stage + 1, W<int64_t>(ctx, p.segmeta), region_mult(stage),
-        W<uint32_t>(ctx, p.cidx), W<uint64_t>(ctx, p.ckeys), ctx->counts));
+        W<uint32_t>(p, p.surv), W<uint64_t>(p, p.keys0), W<int64_t>(p, p.segcnt),
+        (int)p.nwave, stage + 1, W<int64_t>(p, p.segmeta), region_mult(stage),
+        W<uint32_t>(p, p.cidx), W<uint64_t>(p, p.ckeys), ctx->counts));
     return HULL_OK;
 }
 
@@ -566,6 +643,7 @@ static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p)
     HIPCHECK(hipSetDevice(ctx->device));
     *p = make_plan(n, S, (int64_t)grid_k3(ctx) * 4);
     int rc = ensure_ws(ctx, p->total, st);
+    p->base = ctx->ws;
     return rc;
 }
 
@@ -581,18 +659,19 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
         if (rc) return rc;
     }
     const bool learned = (flags & HULL_LEARNED) && !(flags & HULL_NOFILTER);
+    if (learned && !learned_ok(ctx)) return HULL_EINVAL;
     if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
-    uint32_t *surv = W<uint32_t>(ctx, p.surv);
-    uint64_t *keys = W<uint64_t>(ctx, p.keys0);
-    int64_t *surv_off = W<int64_t>(ctx, p.surv_off);
-    int64_t *hoff = hoff_out ? hoff_out : W<int64_t>(ctx, p.hoff);
+    uint32_t *surv = W<uint32_t>(p, p.surv);
+    uint64_t *keys = W<uint64_t>(p, p.keys0);
+    int64_t *surv_off = W<int64_t>(p, p.surv_off);
+    int64_t *hoff = hoff_out ? hoff_out : W<int64_t>(p, p.hoff);
     const bool refine = !(flags & (HULL_NOREFINE | HULL_NOFILTER));
     const int64_t *cnt = ctx->counts;
-    int64_t *segcnt = W<int64_t>(ctx, p.segcnt);
+    int64_t *segcnt = W<int64_t>(p, p.segcnt);
     // one set: the farthest keys of refinement round 0's children start cleared
     const bool one_ref = S == 1 && refine;
     LAUNCH(K_MISC, k_counts_init<<<1, 64, 0, st>>>(
-        ctx->counts, HULL_NCOUNTS, one_ref ? W<unsigned long long>(ctx, p.rfar1) : nullptr, RE_CAP));
+        ctx->counts, HULL_NCOUNTS, one_ref ? W<unsigned long long>(p, p.rfar1) : nullptr, RE_CAP));
     if (flags & HULL_NOFILTER) {
         LAUNCH(K_KEYS, k_all_keys<<<2048, 256, 0, st>>>(x, y, off, n1, S, n_total, surv, keys,
                                                          surv_off));
@@ -610,18 +689,18 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
         unsigned long long *far0 = nullptr;
         uint16_t *edges = nullptr;
         if (refine) {    // round-0 edge table from k_polygon; the discard pass fills its states
-            far0 = W<unsigned long long>(ctx, p.rfar0);
-            edges = W<uint16_t>(ctx, p.up0);
+            far0 = W<unsigned long long>(p, p.rfar0);
+            edges = W<uint16_t>(p, p.up0);
         }
         if ((rc = run_discard_append(ctx, p, st, x, y, n_total, off, n1, S,
-                                     learned ? MAX_SLOTS : FIXED_SLOTS, surv, keys, edges,
+                                     slot_count(ctx, learned), surv, keys, edges,
                                      segcnt, far0)))
             return rc;
         const int stage = refine ? REF_ROUNDS : 0;
         if (refine && (rc = run_refine(ctx, p, st, x, y, S))) return rc;
         if ((rc = run_gather(ctx, p, st, stage))) return rc;
-        surv = W<uint32_t>(ctx, p.cidx);
-        keys = W<uint64_t>(ctx, p.ckeys);
+        surv = W<uint32_t>(p, p.cidx);
+        keys = W<uint64_t>(p, p.ckeys);
         cnt = ctx->counts + stage;
     }
     return run_hull(ctx, p, st, surv, keys, cnt, n_total, S, hoff, hull, h_out);
@@ -667,6 +746,11 @@ int hull_create(hull_ctx **out, int device) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
         ctx->cus = cus;
+    // the occupancy of every extremes variant, so that later calls query nothing
+    for (int pr = 0; pr < NUM_PRESETS; pr++) {
+        (void)resident_blocks(k1_kernel(pr, false));
+        if (preset_fixed_slots(pr) == FIXED_SLOTS) (void)resident_blocks(k1_kernel(pr, true));
+    }
     if (hipMalloc(&ctx->counts, HULL_NCOUNTS * sizeof(int64_t)) != hipSuccess ||
         hipMemset(ctx->counts, 0xff, HULL_NCOUNTS * sizeof(int64_t)) != hipSuccess ||
         hipMalloc(&ctx->tickets, 8 * sizeof(uint32_t)) != hipSuccess ||
@@ -699,19 +783,28 @@ int hull_destroy(hull_ctx *ctx) {
 }
 
 int hull_set_directions(hull_ctx *ctx, int preset) {
-    if (!ctx || (preset != HULL_DIRS_PAPER && preset != HULL_DIRS_CUMULATIVE)) return HULL_EINVAL;
+    if (!ctx || !preset_valid(preset)) return HULL_EINVAL;
     ctx->preset = preset;
     ctx->dirs = preset_dirs(preset);
     return HULL_OK;
 }
 
+int hull_slot_count(hull_ctx *ctx, int flags) {
+    if (!ctx) return HULL_EINVAL;
+    const bool learned = flags & HULL_LEARNED;
+    if (learned && !learned_ok(ctx)) return HULL_EINVAL;
+    return slot_count(ctx, learned);
+}
+
 int hull_direction_table(hull_ctx *ctx, int which, double *c, double *s, int cap) {
     if (!c || !s) return HULL_EINVAL;
-    if (which == 0) {
-        Dirs d = preset_dirs(ctx ? ctx->preset : HULL_DIRS_PAPER);
-        if (cap < 4) return HULL_EINVAL;
-        for (int g = 0; g < 4; g++) { c[g] = d.gc[g]; s[g] = d.gs[g]; }
-        return 4;
+    if (which == 0 || (which >= 16 && which < 16 + NUM_PRESETS)) {
+        const int preset = which ? which - 16 : ctx ? ctx->preset : HULL_DIRS_PAPER;
+        const Dirs d = preset_dirs(preset);
+        const int G = preset_groups(preset);
+        if (cap < G) return HULL_EINVAL;
+        for (int g = 0; g < G; g++) { c[g] = d.gc[g]; s[g] = d.gs[g]; }
+        return G;
     }
     if (which == 1) {
         if (cap < NCAND) return HULL_EINVAL;
@@ -731,6 +824,7 @@ int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n, uint
     if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
     if (flags & HULL_VALIDATE && (rc = run_validate(ctx, p, st, x, y, n, nullptr, 1))) return rc;
     const bool learned = flags & HULL_LEARNED;
+    if (learned && !learned_ok(ctx)) return HULL_EINVAL;
     if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
     if ((rc = run_tilemap(ctx, p, st, x, nullptr, n, 1))) return rc;
     if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n, nullptr, n, 1))) return rc;
@@ -747,7 +841,7 @@ int hull_polygon(hull_ctx *ctx, const float *x, const float *y, int64_t n, const
     Plan p;
     if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
     if ((rc = run_polygon(ctx, p, st, x, y, n, 1, false, slots, n_slots, nullptr, nullptr))) return rc;
-    LAUNCH(K_MISC, k_poly_out<<<1, 64, 0, st>>>(W<Poly>(ctx, p.polys), n_slots, verts, m));
+    LAUNCH(K_MISC, k_poly_out<<<1, 64, 0, st>>>(W<Poly>(p, p.polys), n_slots, verts, m));
     return HULL_OK;
 }
 
@@ -762,7 +856,7 @@ int hull_discard(hull_ctx *ctx, const float *x, const float *y, int64_t n, const
     if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
     if ((rc = run_tilemap(ctx, p, st, x, nullptr, n, 1))) return rc;
     if ((rc = run_polygon(ctx, p, st, x, y, n, 1, false, slots, n_slots, nullptr, nullptr))) return rc;
-    int64_t *so = W<int64_t>(ctx, p.surv_off);
+    int64_t *so = W<int64_t>(p, p.surv_off);
     if ((rc = run_discard(ctx, p, st, x, y, n, nullptr, n, 1, n_slots, surv, so, nullptr)))
         return rc;
     LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(so + 1, n_surv));
@@ -777,9 +871,9 @@ int hull_of_subset(hull_ctx *ctx, const float *x, const float *y, int64_t n, con
     hipStream_t st = (hipStream_t)stream;
     Plan p;
     if ((rc = prepare(ctx, k_cap, 1, st, &p))) return rc;
-    uint64_t *keys = W<uint64_t>(ctx, p.keys0);
+    uint64_t *keys = W<uint64_t>(p, p.keys0);
     LAUNCH(K_KEYS, k_gather_keys<<<1024, 256, 0, st>>>(x, y, n, idx, k_dev, keys));
-    int64_t *hoff = W<int64_t>(ctx, p.hoff);
+    int64_t *hoff = W<int64_t>(p, p.hoff);
     if ((rc = run_hull(ctx, p, st, idx, keys, k_dev, k_cap, 1, hoff, hull))) return rc;
     LAUNCH(K_MISC, k_copy_count<<<1, 64, 0, st>>>(hoff + 1, h));
     return HULL_OK;
@@ -810,6 +904,7 @@ int hull_extremes_batched(hull_ctx *ctx, const float *x, const float *y, const i
     if (flags & HULL_VALIDATE && (rc = run_validate(ctx, p, st, x, y, n_total, offsets, S)))
         return rc;
     const bool learned = flags & HULL_LEARNED;
+    if (learned && !learned_ok(ctx)) return HULL_EINVAL;
     if (learned && !ctx->learned.loaded) return HULL_ENOMODEL;
     if ((rc = run_tilemap(ctx, p, st, x, offsets, 0, S))) return rc;
     if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n_total, offsets, 0, S))) return rc;
@@ -854,8 +949,10 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int6
     HIPCHECK(hipSetDevice(ctx->device));
     Plan p = make_plan(n_total, S, (int64_t)grid_k3(ctx) * 4);
     if ((rc = ensure_ws(ctx, p.total, st))) return rc;
+    p.base = ctx->ws;
     if ((flags & HULL_LEARNED) && !(flags & HULL_NOFILTER)) {
         // the network's buffers are sized before capture: nothing allocates inside
+        if (!learned_ok(ctx)) return HULL_EINVAL;
         if (!ctx->learned.loaded) return HULL_ENOMODEL;
         if ((rc = init_cand_table())) return rc;
         if ((rc = learned_ensure(ctx, S, st))) return rc;
@@ -940,8 +1037,8 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     const int cand[] = {1, 2, 3, 4, 6, 8};
     float best1 = 1e30f, best3 = 1e30f;
     int b1 = ctx->k1_bpc, b3 = ctx->k3_bpc;
-    uint32_t *surv = W<uint32_t>(ctx, p.surv);
-    int64_t *so = W<int64_t>(ctx, p.surv_off);
+    uint32_t *surv = W<uint32_t>(p, p.surv);
+    int64_t *so = W<int64_t>(p, p.surv_off);
     for (int c : cand) {
         ctx->k1_bpc = c;
         ctx->k3_bpc = c;
@@ -956,7 +1053,7 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
             if (rep) t1 += ms;
             if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr))) break;
             HIPCHECK(hipEventRecord(a, st));
-            if ((rc = run_discard(ctx, p, st, x, y, n_total, offsets, n1, S, FIXED_SLOTS, surv, so,
+            if ((rc = run_discard(ctx, p, st, x, y, n_total, offsets, n1, S, slot_count(ctx, false), surv, so,
                                   nullptr)))
                 break;
             HIPCHECK(hipEventRecord(b, st));
@@ -1133,11 +1230,11 @@ static int run_learned_dirs(hull_ctx *ctx, const Plan &p, hipStream_t st, const 
                             int64_t S) {
     (void)n_total;
     if (!ctx->learned.loaded) return HULL_ENOMODEL;
-    bf16_t *hist = W<bf16_t>(ctx, p.learn);
+    bf16_t *hist = W<bf16_t>(p, p.learn);
     LAUNCH(K_HIST32, k_hist32<<<(unsigned)S, HIST_THREADS, 0, st>>>(x, y, off, n1, S, hist, nullptr));
     RC(mlp_forward(ctx, st, hist, S));
     LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(ctx->learned.scores, S, ctx->dir_gap, nullptr,
-                                                                 W<double>(ctx, p.setdirs)));
+                                                                 W<double>(p, p.setdirs)));
     return HULL_OK;
 }
 
@@ -1256,13 +1353,13 @@ int hull_top_directions(hull_ctx *ctx, const float *scores, int64_t S, int32_t *
     Plan p;
     RC(prepare(ctx, 0, S, st, &p));
     LAUNCH(K_MLP, k_top8<<<(unsigned)((S + 3) / 4), 256, 0, st>>>(scores, S, ctx->dir_gap, dirs,
-                                                                 W<double>(ctx, p.setdirs)));
+                                                                 W<double>(p, p.setdirs)));
     return HULL_OK;
 }
 
 int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
                         int64_t S, int64_t n_total, float *gain, void *stream) {
-    if (!ctx || !gain) return HULL_EINVAL;
+    if (!ctx || !gain || !learned_ok(ctx)) return HULL_EINVAL;
     int rc = check_batch(x, y, offsets, S, n_total);
     if (rc) return rc;
     RC(init_cand_table());
@@ -1272,12 +1369,12 @@ int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int
     RC(run_tilemap(ctx, p, st, x, offsets, 0, S));
     RC(run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, false));
     RC(run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr));
-    uint32_t *surv = W<uint32_t>(ctx, p.surv);
-    int64_t *so = W<int64_t>(ctx, p.surv_off);
-    RC(run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, FIXED_SLOTS, surv, so, nullptr));
-    uint32_t *cand = W<uint32_t>(ctx, p.cand);
+    uint32_t *surv = W<uint32_t>(p, p.surv);
+    int64_t *so = W<int64_t>(p, p.surv_off);
+    RC(run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, slot_count(ctx, false), surv, so, nullptr));
+    uint32_t *cand = W<uint32_t>(p, p.cand);
     LAUNCH(K_LABELS, k_cand_extremes<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, cand));
-    LAUNCH(K_LABELS, k_labels<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, W<Poly>(ctx, p.polys),
+    LAUNCH(K_LABELS, k_labels<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, W<Poly>(p, p.polys),
                                                           cand, surv, so, gain));
     return HULL_OK;
 }
@@ -1285,7 +1382,8 @@ int hull_labels_batched(hull_ctx *ctx, const float *x, const float *y, const int
 int hull_label_targets_batched(hull_ctx *ctx, const float *x, const float *y,
                                const int64_t *offsets, int64_t S, int64_t n_total, int rounds,
                                float *target, int32_t *order, void *stream) {
-    if (!ctx || !target || !order || rounds < 1 || rounds > LT_MAXR) return HULL_EINVAL;
+    if (!ctx || !target || !order || rounds < 1 || rounds > LT_MAXR || !learned_ok(ctx))
+        return HULL_EINVAL;
     int rc = check_batch(x, y, offsets, S, n_total);
     if (rc) return rc;
     RC(init_cand_table());
@@ -1295,13 +1393,13 @@ int hull_label_targets_batched(hull_ctx *ctx, const float *x, const float *y,
     RC(run_tilemap(ctx, p, st, x, offsets, 0, S));
     RC(run_extremes(ctx, p, st, x, y, n_total, offsets, 0, S, false));
     RC(run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr));
-    uint32_t *surv = W<uint32_t>(ctx, p.surv);
-    int64_t *so = W<int64_t>(ctx, p.surv_off);
-    RC(run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, FIXED_SLOTS, surv, so, nullptr));
-    uint32_t *cand = W<uint32_t>(ctx, p.cand);
+    uint32_t *surv = W<uint32_t>(p, p.surv);
+    int64_t *so = W<int64_t>(p, p.surv_off);
+    RC(run_discard(ctx, p, st, x, y, n_total, offsets, 0, S, slot_count(ctx, false), surv, so, nullptr));
+    uint32_t *cand = W<uint32_t>(p, p.cand);
     LAUNCH(K_LABELS, k_cand_extremes<<<(unsigned)S, 256, 0, st>>>(x, y, offsets, 0, S, cand));
     LAUNCH(K_LABELS, k_label_targets<<<(unsigned)S, 256, 0, st>>>(
-        x, y, offsets, 0, S, W<Poly>(ctx, p.polys), cand, surv, so, rounds, target, order));
+        x, y, offsets, 0, S, W<Poly>(p, p.polys), cand, surv, so, rounds, target, order));
     return HULL_OK;
 }
 

@@ -188,20 +188,38 @@ __device__ __forceinline__ void load4_full(const float *__restrict__ x, const fl
 // comparisons see these keys; the reported values are recomputed from the
 // winning points.  Under PRESET 1 u_120 = -v_30 and v_120 = u_30 bit for bit,
 // so slots 12..15 are copies of 7, 6, 4, 5 made when the polygon is built.
-// PRESET 2 evaluates the four groups of Dirs as written.
+//
+// PRESET 1 + G (G = 1..6) has G groups at 90 j / G degrees.  Since
+// sin(90 j / G) = cos(90 (G - j) / G), the groups j and G - j use the same
+// two products c x and c y, so the pass needs 2 (G - 1) products and as
+// many sums; group 0 is x and y themselves.
 constexpr double C30 = 0x1.bb67ae8584caap-1;
 constexpr double C30X2 = 0x1.bb67ae8584caap+0;   // 2 cos30, exact
 constexpr double C45 = 0x1.6a09e667f3bcdp-1;
 constexpr double C75 = 0x1.0907dc1930690p-2;
 constexpr double S75 = 0x1.ee8dd4748bf15p-1;
 
+// EVEN_COS[G][j] = cos(90 j / G degrees), correctly rounded, j = 0..G
+// (the last entry of each row, cos 90, is exactly 0).
+constexpr double EVEN_COS[MAX_GROUPS + 1][MAX_GROUPS + 1] = {
+    {1.0, 0, 0, 0, 0, 0, 0},
+    {1.0, 0.0, 0, 0, 0, 0, 0},
+    {1.0, 0x1.6a09e667f3bcdp-1, 0.0, 0, 0, 0, 0},
+    {1.0, 0x1.bb67ae8584caap-1, 0x1p-1, 0.0, 0, 0, 0},
+    {1.0, 0x1.d906bcf328d46p-1, 0x1.6a09e667f3bcdp-1, 0x1.87de2a6aea963p-2, 0.0, 0, 0},
+    {1.0, 0x1.e6f0e134454ffp-1, 0x1.9e3779b97f4a8p-1, 0x1.2cf2304755a5ep-1,
+     0x1.3c6ef372fe950p-2, 0.0, 0},
+    {1.0, 0x1.ee8dd4748bf15p-1, 0x1.bb67ae8584caap-1, 0x1.6a09e667f3bcdp-1, 0x1p-1,
+     0x1.0907dc1930690p-2, 0.0}};
+
 template <int PRESET>
 struct Proj {
-    static constexpr int NG = PRESET == 1 ? 3 : 4;   // groups actually evaluated
-    __device__ __forceinline__ static void uv(const Dirs &d, double xd, double yd, double u[4],
-                                              double v[4]) {
+    static constexpr int NG = preset_eval_groups(PRESET);   // groups actually evaluated
+    __device__ __forceinline__ static void uv(const Dirs &d, double xd, double yd,
+                                              double u[MAX_GROUPS], double v[MAX_GROUPS]) {
 #pragma clang fp contract(off)
-        if (PRESET == 0) {
+        (void)d;
+        if constexpr (PRESET == 0) {
             const double p = C30X2 * xd, q = C30X2 * yd, r = C45 * xd, t = C45 * yd;
             u[0] = xd;
             v[0] = yd;
@@ -211,7 +229,7 @@ struct Proj {
             v[2] = r + t;
             u[3] = xd - q;       // 2 u_60
             v[3] = p + yd;       // 2 v_60
-        } else if (PRESET == 1) {
+        } else if constexpr (PRESET == 1) {
             const double p = C30X2 * xd, q = C30X2 * yd;
             u[0] = xd;
             v[0] = yd;
@@ -219,13 +237,17 @@ struct Proj {
             v[1] = xd + q;
             u[2] = C75 * xd - S75 * yd;
             v[2] = S75 * xd + C75 * yd;
-            u[3] = 0.0;
-            v[3] = 0.0;
         } else {
+            constexpr int G = PRESET - 1;
+            u[0] = xd;
+            v[0] = yd;
 #pragma unroll
-            for (int g = 0; g < 4; g++) {
-                u[g] = d.gc[g] * xd - d.gs[g] * yd;
-                v[g] = d.gs[g] * xd + d.gc[g] * yd;
+            for (int j = 1; j < G; j++) {
+                // the same constants give the same rounded products, which
+                // the compiler computes once for groups j and G - j
+                const double c = EVEN_COS[G][j], s = EVEN_COS[G][G - j];
+                u[j] = c * xd - s * yd;
+                v[j] = s * xd + c * yd;
             }
         }
     }
@@ -247,7 +269,7 @@ template <int PRESET, int NDIR>
 __device__ __forceinline__ void slot_keys(const Dirs &d, const double *dc, const double *ds,
                                           double xd, double yd, double *key) {
     constexpr int NF = 4 * Proj<PRESET>::NG;
-    double u[4], v[4];
+    double u[MAX_GROUPS], v[MAX_GROUPS];
     Proj<PRESET>::uv(d, xd, yd, u, v);
 #pragma unroll
     for (int k = 0; k < NF; k++) key[k] = (k & 2) ? v[k >> 2] : u[k >> 2];
@@ -473,7 +495,7 @@ __device__ __forceinline__ double edge_eval(double ex, double ey, double c, doub
 constexpr int POLY_THREADS = 512;
 constexpr int POLY_SPLIT = 16;     // blocks per set sharing the extremes pass's partials
 
-template <int NEV, int NDIR>
+template <int PRESET, int NDIR>
 __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int64_t S,
     const int64_t *__restrict__ tile_off, int64_t W1, const double *__restrict__ pval,
@@ -482,14 +504,18 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
     double *__restrict__ vals_out, Poly *__restrict__ polys, Span *__restrict__ spans,
     uint32_t *__restrict__ redges, REdge *__restrict__ rtab, unsigned long long *__restrict__ rfar,
     SlotBest *__restrict__ bpart, uint32_t *__restrict__ ticket) {
-    // NEV: fixed slots the extremes pass evaluated (12 when the 120-degree
-    // group is a copy of the 30-degree one, else 16); NDIR learned slots.
+    // NEV: fixed slots the extremes pass evaluated (12 for preset 1, whose
+    // 120-degree group is a copy of the 30-degree one); NFIX: fixed slot
+    // positions (at least 16; learned slots follow, NDIR of them).
     // Grid (S, POLY_SPLIT): block (s, y) reduces its share of set s's
     // partials; the last of the set's blocks to finish (per-set ticket,
     // zeroed by k_tile_offsets, reset here) combines the shares in bpart and
     // builds the polygon.  With slots_in the grid is (S, 1).
-    constexpr int NS = FIXED_SLOTS + NDIR;
+    constexpr int NEV = 4 * Proj<PRESET>::NG;
+    constexpr int NFIX = preset_fixed_slots(PRESET);
+    constexpr int NS = NFIX + NDIR;
     constexpr int NE = NEV + NDIR;
+    static_assert(NS <= MAX_SLOTS, "learned slots need a fixed table of at most 16 slots");
     __shared__ SlotBest wbest[POLY_THREADS / WAVE][MAX_SLOTS];
     __shared__ SlotBest spart[POLY_SPLIT][MAX_SLOTS];  // the set's shares (last block)
     __shared__ uint32_t sl[MAX_SLOTS];
@@ -604,12 +630,13 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
         }
         if (tid < NE) {
             // partial slot k < NEV holds fixed slot k; learned slots follow
-            int dst = tid < NEV ? tid : FIXED_SLOTS + (tid - NEV);
+            int dst = tid < NEV ? tid : NFIX + (tid - NEV);
             sl[dst] = wbest[0][tid].i;
         }
-        if (NDIR == 0 && tid >= FIXED_SLOTS && tid < MAX_SLOTS) sl[tid] = NONE;
+        // positions no slot fills (preset 1's fourth group is filled below)
+        if (tid < MAX_SLOTS && (tid >= NS || (tid >= NEV && tid < NFIX))) sl[tid] = NONE;
         __syncthreads();
-        if (NEV == 12 && tid == 0) {   // 120-degree group repeats the 30-degree one
+        if (PRESET == 1 && tid == 0) {   // 120-degree group repeats the 30-degree one
             sl[12] = sl[7];
             sl[13] = sl[6];
             sl[14] = sl[4];
@@ -625,12 +652,12 @@ __global__ __launch_bounds__(POLY_THREADS) void k_polygon(
         double val = NAN;
         if (i != NONE) {
             double xd = x[i], yd = y[i];
-            if (tid < FIXED_SLOTS) {
+            if (tid < NFIX) {
                 int g = tid >> 2, t = tid & 3;
                 double c = dirs.gc[g], sn = dirs.gs[g];
                 val = t < 2 ? c * xd - sn * yd : sn * xd + c * yd;
             } else {
-                int d = tid - FIXED_SLOTS;
+                int d = tid - NFIX;
                 val = proj_dir(set_dirs[(s * MAX_DIRS + d) * 2], set_dirs[(s * MAX_DIRS + d) * 2 + 1],
                                xd, yd);
             }

@@ -86,3 +86,41 @@ def test_preset_table_matches_paper_angles(lib):
         a = mpmath.pi * deg / 180
         assert c[g] == (1.0 if deg == 0 else float(mpmath.cos(a)))
         assert s[g] == (0.0 if deg == 0 else float(mpmath.sin(a)))
+
+
+@pytest.mark.parametrize("preset", range(8))
+def test_every_preset_table_correctly_rounded(lib, preset):
+    """The library's own constants for every preset (which = 16 + preset,
+    no device needed) against mpmath: presets 0 and 1 at the paper's angles,
+    presets 1 + G at 90 j / G degrees."""
+    c = np.zeros(8)
+    s = np.zeros(8)
+    n = lib.hull_direction_table(None, 16 + preset, c.ctypes.data_as(ctypes.c_void_p),
+                                 s.ctypes.data_as(ctypes.c_void_p), 8)
+    if preset == 0:
+        degs = [0, 30, 45, 60]
+    elif preset == 1:
+        degs = [0, 30, 75, 120]
+    else:
+        G = preset - 1
+        degs = [mpmath.mpf(90) * j / G for j in range(G)]
+    assert n == len(degs)
+    mpmath.mp.prec = 300
+    for g, deg in enumerate(degs):
+        a = mpmath.pi * deg / 180
+        want_c = 1.0 if deg == 0 else float(mpmath.cos(a))
+        want_s = 0.0 if deg == 0 else float(mpmath.sin(a))
+        assert c[g] == want_c and s[g] == want_s, (preset, g)
+
+
+def test_unknown_tables_rejected(lib):
+    from paper_1405_3454_amd import _lib
+    c = np.zeros(64)
+    s = np.zeros(64)
+    for which in (2, 15, 24, -1):
+        assert lib.hull_direction_table(None, which, c.ctypes.data_as(ctypes.c_void_p),
+                                        s.ctypes.data_as(ctypes.c_void_p), 64) == _lib.HULL_EINVAL
+    # capacity below the table's size
+    assert lib.hull_direction_table(None, 16 + 7, c.ctypes.data_as(ctypes.c_void_p),
+                                    s.ctypes.data_as(ctypes.c_void_p), 5) == _lib.HULL_EINVAL
+    assert lib.hull_slot_count(None, 0) == _lib.HULL_EINVAL
