@@ -68,6 +68,7 @@ typedef struct hull_ctx hull_ctx;
 #define HULL_EDOMAIN (-5)  /* HULL_VALIDATE: coordinate off the 2^-24 grid of [0,1) */
 #define HULL_ECAPTURE (-6) /* workspace would have to grow during stream capture */
 #define HULL_ENOMODEL (-7) /* HULL_LEARNED without loaded network weights */
+#define HULL_ESCRATCH (-8) /* input larger than hull_extremes_noalloc's fixed scratch */
 
 /* direction presets (angles of the rotated copies, Sec. 2 Step 1) */
 #define HULL_DIRS_PAPER 0      /* 0, 30, 45, 60 degrees (Figure 1, Sec. 5) */
@@ -126,6 +127,21 @@ int hull_last_hip_error(hull_ctx *ctx);
  * more than 16 fixed slots; HULL_ENOMODEL without network weights. */
 int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n,
                   uint32_t *slots, double *vals, int flags, void *stream);
+
+/* Allocation-free form of hull_extremes, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and results as
+ * hull_extremes (plain slots only: flags must be 0), but its working memory
+ * is a fixed array of HULL_NOALLOC_SCRATCH_BYTES in device memory that the
+ * library holds on each device from hull_create until the process ends; the
+ * call itself allocates and frees nothing and records no timing events.
+ * Limits: n <= HULL_NOALLOC_MAX_POINTS, else HULL_ESCRATCH.  Every call on
+ * one device shares that device's array, so calls that overlap on one
+ * device (two streams, two threads, two contexts) race: serialise them. */
+#define HULL_NOALLOC_MAX_POINTS (1LL << 27)
+#define HULL_NOALLOC_SCRATCH_BYTES (40u << 20)
+int hull_extremes_noalloc(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                          uint32_t *slots, double *vals, int flags, void *stream);
 
 /* ---- Step 2: convex polygon of the extremes (Sec. 2, Step 2) ----------- */
 /* slots: device uint32[n_slots] (n_slots <= 24, HULL_NONE entries ignored).

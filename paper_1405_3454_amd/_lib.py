@@ -14,6 +14,8 @@ HULL_EHIP = -4
 HULL_EDOMAIN = -5
 HULL_ECAPTURE = -6
 HULL_ENOMODEL = -7
+HULL_ESCRATCH = -8
+HULL_NOALLOC_MAX_POINTS = 1 << 27
 
 HULL_DIRS_PAPER = 0
 HULL_DIRS_CUMULATIVE = 1
@@ -50,6 +52,7 @@ SIGNATURES = {
     "hull_strerror": (ctypes.c_char_p, [I]),
     "hull_last_hip_error": (I, [P]),
     "hull_extremes": (I, [P, P, P, I64, P, P, I, P]),
+    "hull_extremes_noalloc": (I, [P, P, P, I64, P, P, I, P]),
     "hull_polygon": (I, [P, P, P, I64, P, I, P, P, P]),
     "hull_discard": (I, [P, P, P, I64, P, I, P, P, P]),
     "hull_of_subset": (I, [P, P, P, I64, P, P, I64, P, P, P]),

@@ -56,6 +56,7 @@ struct hull_ctx {
     hipError_t last = hipSuccess;
     char *ws = nullptr;
     size_t ws_cap = 0;
+    char *scratch = nullptr;            // this device's copy of the fixed scratch array
     int64_t *counts = nullptr;          // candidates per stage of the last computation
     uint32_t *tickets = nullptr;        // last-block tickets (zero between launches)
     std::vector<char *> retired;        // old workspaces a graph may still use
@@ -205,6 +206,61 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.ckeys = take(n * 8 + 16);
     p.total = o;
     return p;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free Step 1 (hull_extremes_noalloc).  Its buffers live in one
+// fixed device array: each device that loads the library holds its own copy
+// until the process ends, and no call allocates or frees device memory.
+// Host code never uses the array's name as an address: hull_create looks up
+// the device's copy with hipGetSymbolAddress (once per device) and every
+// kernel gets that pointer.
+constexpr int64_t NOALLOC_MAX_POINTS = HULL_NOALLOC_MAX_POINTS;
+constexpr size_t NOALLOC_SCRATCH_BYTES = HULL_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Layout of Step 1 for one set of n points (tile map, run partials, the
+// polygon kernel's shares and ticket, its polygon and rows); the other plan
+// entries are unused by that path and stay 0.
+static constexpr Plan make_plan_extremes(int64_t n) {
+    Plan p{};
+    size_t o = 0;
+    p.tcap = n / TILE + 4;
+    p.nwave = 0;
+    p.tile_off = o; o += al(2 * 8);
+    p.tile_set = o; o += al(p.tcap * 4);
+    p.pval = o; o += al(p.tcap * MAX_SLOTS * 8);
+    p.pidx = o; o += al(p.tcap * MAX_SLOTS * 4);
+    p.polys = o; o += al(sizeof(Poly));
+    p.spans = o; o += al(SPAN_ROWS * sizeof(Span));
+    p.redges = o; o += al(SPAN_ROWS * 4);
+    p.setdirs = o; o += al(MAX_DIRS * 2 * 8);
+    p.bpart = o; o += al(POLY_SPLIT * MAX_SLOTS * sizeof(SlotBest));
+    p.pticket = o; o += al(4);
+    p.total = o;
+    return p;
+}
+static_assert(make_plan_extremes(NOALLOC_MAX_POINTS).total <= NOALLOC_SCRATCH_BYTES,
+              "the scratch array must hold Step 1 at the largest accepted size");
+
+// Per-device address of `scratch`, looked up once per device.
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[256];
+
+static int scratch_setup(int device, char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= 256) return HULL_EINVAL;
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        // the caller has made `device` current
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return HULL_EHIP;
+        }
+        g_scratch_ptr[device] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return HULL_OK;
 }
 
 static int ensure_ws(hull_ctx *ctx, size_t bytes, hipStream_t st) {
@@ -721,6 +777,7 @@ const char *hull_strerror(int code) {
     case HULL_EDOMAIN: return "coordinate outside the 2^-24 grid of [0,1) or bad offsets";
     case HULL_ECAPTURE: return "workspace must grow but the stream is being captured";
     case HULL_ENOMODEL: return "learned proposal requested without network weights";
+    case HULL_ESCRATCH: return "input larger than the fixed scratch of the allocation-free call";
     default: return "unknown error";
     }
 }
@@ -746,7 +803,12 @@ int hull_create(hull_ctx **out, int device) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
         ctx->cus = cus;
-    // the occupancy of every extremes variant, so that later calls query nothing
+    // this device's scratch array (allocation-free entry point) and the
+    // occupancy of every extremes variant, so that later calls query nothing
+    if (scratch_setup(device, &ctx->scratch) != HULL_OK) {
+        delete ctx;
+        return HULL_EHIP;
+    }
     for (int pr = 0; pr < NUM_PRESETS; pr++) {
         (void)resident_blocks(k1_kernel(pr, false));
         if (preset_fixed_slots(pr) == FIXED_SLOTS) (void)resident_blocks(k1_kernel(pr, true));
@@ -830,6 +892,29 @@ int hull_extremes(hull_ctx *ctx, const float *x, const float *y, int64_t n, uint
     if (learned && (rc = run_learned_dirs(ctx, p, st, x, y, n, nullptr, n, 1))) return rc;
     if ((rc = run_extremes(ctx, p, st, x, y, n, nullptr, n, 1, learned))) return rc;
     return run_polygon(ctx, p, st, x, y, n, 1, learned, nullptr, 0, slots, vals);
+}
+
+int hull_extremes_noalloc(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                          uint32_t *slots, double *vals, int flags, void *stream) {
+    if (!ctx || !slots || flags != 0) return HULL_EINVAL;
+    int rc = check_points(x, y, n);
+    if (rc) return rc;
+    if (n > NOALLOC_MAX_POINTS) return HULL_ESCRATCH;
+    if (!ctx->scratch) return HULL_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipSetDevice(ctx->device));
+    Plan p = make_plan_extremes(n);
+    p.base = ctx->scratch;
+    // no timing events here: the event pool may have to grow
+    const bool was_timing = ctx->timing;
+    ctx->timing = false;
+    // the tile map zeroes the polygon kernel's ticket; every other buffer is
+    // written before it is read
+    if (!(rc = run_tilemap(ctx, p, st, x, nullptr, n, 1)) &&
+        !(rc = run_extremes(ctx, p, st, x, y, n, nullptr, n, 1, false)))
+        rc = run_polygon(ctx, p, st, x, y, n, 1, false, nullptr, 0, slots, vals);
+    ctx->timing = was_timing;
+    return rc;
 }
 
 int hull_polygon(hull_ctx *ctx, const float *x, const float *y, int64_t n, const uint32_t *slots,
