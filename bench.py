@@ -225,6 +225,43 @@ def bench_directions(args, X, Y, n):
     return curve
 
 
+def bench_host(args, X, Y, n):
+    """Host-resident input (the paper's setting): the disk set of the main
+    workload held in host memory, hull_compute_host with chunks of 2^24
+    points; PCIe-inclusive, so it is context, never the headline value."""
+    import torch
+    from paper_1405_3454_amd.api import Hull
+    xh = X["disk"].cpu()
+    yh = Y["disk"].cpu()
+    xp, yp = xh.pin_memory(), yh.pin_memory()
+    H = Hull(0)
+    res = {"workload": "disk r=0.5, 2^%d points in host memory, chunks of 2^24" % int(np.log2(n))}
+    ref = None
+    for name, a, b, budget in (("pageable_streamed_twice", xh, yh, 0),
+                               ("pageable_one_crossing", xh, yh, 1 << 40),
+                               ("pinned_streamed_twice", xp, yp, 0),
+                               ("pinned_one_crossing", xp, yp, 1 << 40)):
+        H.compute_host(a, b, chunk_points=1 << 24, device_budget=budget, cap=n // 8)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, surv, hull = H.compute_host(a, b, chunk_points=1 << 24, device_budget=budget,
+                                           cap=n // 8)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = min(ts)
+        crossings = 1 if budget else 2
+        hv = hull.cpu()
+        if ref is None:
+            ref = hv
+        res[name] = {"gpts": round(n / t / 1e9, 3), "ms": round(t * 1e3, 2),
+                     "pcie_gbs": round(crossings * 8.0 * n / t / 1e9, 1),
+                     "same_hull": bool(torch.equal(ref, hv))}
+    H.close()
+    return res
+
+
 def bench_batched(args, dev):
     """Batched plain method: 4096 sets, sizes log-uniform in [1e3, 1e6], kinds
     uniform over square/disk/gaussian/annulus.  Per-set calls vs one batched
@@ -523,6 +560,7 @@ def main():
                              "speedup_of_filter": round(t_u / dt, 3)}
         del hull_u
         out["direction_families"] = bench_directions(args, X, Y, n)
+        out["host_resident"] = bench_host(args, X, Y, n)
         H.close()
         del X, Y, hull
         torch.cuda.empty_cache()

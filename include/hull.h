@@ -69,6 +69,7 @@ typedef struct hull_ctx hull_ctx;
 #define HULL_ECAPTURE (-6) /* workspace would have to grow during stream capture */
 #define HULL_ENOMODEL (-7) /* HULL_LEARNED without loaded network weights */
 #define HULL_ESCRATCH (-8) /* input larger than hull_extremes_noalloc's fixed scratch */
+#define HULL_EOVERFLOW (-9) /* more survivors than the caller's output capacity */
 
 /* direction presets (angles of the rotated copies, Sec. 2 Step 1) */
 #define HULL_DIRS_PAPER 0      /* 0, 30, 45, 60 degrees (Figure 1, Sec. 5) */
@@ -170,6 +171,34 @@ int hull_of_subset(hull_ctx *ctx, const float *x, const float *y, int64_t n,
  * points).  hull: device uint32 (capacity n); *h: device int64. */
 int hull_compute(hull_ctx *ctx, const float *x, const float *y, int64_t n,
                  uint32_t *hull, int64_t *h, int flags, void *stream);
+
+/* ---- host-resident input (the paper's setting, Sec. 3) ----------------
+ * The whole method for a set that lives in HOST memory (pageable or pinned),
+ * as on the paper's 1 GB card: the points cross PCIe in chunks of
+ * chunk_points (0: 2^24; rounded up to a multiple of 1024), copies
+ * overlapped with the kernels on a second stream.  Pass 1 runs Step 1 on
+ * each chunk and reduces the extremes across chunks (better value, then
+ * lower index: the same slots as hull_extremes on the whole set); pass 2
+ * builds the polygon of those extremes and runs Step 3 on each chunk,
+ * appending its survivors.  Chunks beyond two streaming buffers stay on the
+ * device after pass 1 while they fit in device_budget bytes (8 B per point;
+ * a budget for the whole set means one crossing); the rest cross again.
+ * The hull of the survivors runs on the device (sort + monotone chain; no
+ * refinement rounds).
+ *   slots: device uint32[hull_slot_count(ctx, 0)] or NULL;
+ *   surv: device uint32[cap], survivors in ascending index order; *n_surv
+ *         (device int64) their count;
+ *   hull: device uint32[cap]; *h (device int64) its size.
+ * Synchronises the stream (the staging buffers are reused, and the survivor
+ * count sizes the hull stage).  flags must be 0.  Errors: HULL_EINVAL,
+ * HULL_ETOOBIG, HULL_ENOMEM (chunk buffers, staging or workspace),
+ * HULL_EHIP, HULL_EOVERFLOW when more than cap points survive (*n_surv then
+ * holds the true count, only the first cap survivors are written and no
+ * hull is computed). */
+int hull_compute_host(hull_ctx *ctx, const float *x, const float *y, int64_t n,
+                      int64_t chunk_points, int64_t device_budget, uint32_t *slots,
+                      uint32_t *surv, int64_t *n_surv, int64_t cap, uint32_t *hull,
+                      int64_t *h, int flags, void *stream);
 
 /* ---- batched forms (many sets, CSR offsets) ----------------------------
  * offsets: device int64[S+1], non-decreasing, offsets[0] = 0,

@@ -15,6 +15,7 @@ HULL_EDOMAIN = -5
 HULL_ECAPTURE = -6
 HULL_ENOMODEL = -7
 HULL_ESCRATCH = -8
+HULL_EOVERFLOW = -9
 HULL_NOALLOC_MAX_POINTS = 1 << 27
 
 HULL_DIRS_PAPER = 0
@@ -57,6 +58,7 @@ SIGNATURES = {
     "hull_discard": (I, [P, P, P, I64, P, I, P, P, P]),
     "hull_of_subset": (I, [P, P, P, I64, P, P, I64, P, P, P]),
     "hull_compute": (I, [P, P, P, I64, P, P, I, P]),
+    "hull_compute_host": (I, [P, P, P, I64, I64, I64, P, P, P, I64, P, P, I, P]),
     "hull_extremes_batched": (I, [P, P, P, P, I64, I64, P, I, P]),
     "hull_discard_batched": (I, [P, P, P, P, I64, I64, P, I, P, P, P]),
     "hull_compute_batched": (I, [P, P, P, P, I64, I64, P, P, I, P]),

@@ -162,6 +162,34 @@ class Hull:
         self.compute_into(x, y, hull, h, nofilter, learned, validate, stream, refine)
         return hull[: int(h.item())]
 
+    # -- host-resident input ----------------------------------------------
+    def compute_host(self, x, y, chunk_points=0, device_budget=0, cap=None, stream=None):
+        """The whole method on a set in host memory: x, y are float32 numpy
+        arrays or CPU torch tensors (pinned or not).  Returns (slots,
+        survivors, hull) as device int32 tensors; cap bounds the survivors
+        (default n)."""
+        if isinstance(x, np.ndarray):
+            x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))
+            y = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32))
+        if x.dtype != torch.float32 or y.dtype != torch.float32 or x.is_cuda or y.is_cuda:
+            raise TypeError("x, y must be float32 host arrays")
+        if not (x.is_contiguous() and y.is_contiguous()) or x.shape != y.shape or x.dim() != 1:
+            raise ValueError("x, y must be contiguous 1-D arrays of equal length")
+        n = x.numel()
+        cap = n if cap is None else int(cap)
+        dev = self.device
+        slots = torch.empty(self.slot_count(), dtype=torch.int32, device=dev)
+        surv = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+        hull = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+        ns = torch.zeros(1, dtype=torch.int64, device=dev)
+        h = torch.zeros(1, dtype=torch.int64, device=dev)
+        xp = ctypes.c_void_p(x.data_ptr()) if n else None
+        yp = ctypes.c_void_p(y.data_ptr()) if n else None
+        check(lib().hull_compute_host(self._h, xp, yp, n, int(chunk_points), int(device_budget),
+                                      _ptr(slots), _ptr(surv), _ptr(ns), cap, _ptr(hull), _ptr(h),
+                                      0, _stream(stream)), "hull_compute_host")
+        return slots, surv[: int(ns.item())], hull[: int(h.item())]
+
     # -- batched -----------------------------------------------------------
     def extremes_batched(self, x, y, offsets, learned=False, validate=False, stream=None):
         n = _pts(x, y)

@@ -39,18 +39,22 @@ struct Poly {
     int32_t vx[MAX_SLOTS], vy[MAX_SLOTS];   // vertices (grid units); edge e runs from e to e + 1
 };
 
-// One row of the polygon's y-range (ky in [y0, y1]):
-//  - every grid point of the row with xl <= kx <= xr is strictly inside the
-//    polygon (verified exactly at the rectangle's corners; xl > xr: none);
-//  - every grid point of the row with kx <= ol or kx >= orr is not strictly
-//    inside (the polygon's x-extent over the row, widened by a grid unit).
+// One row of the polygon's y-range (ky in [y0, y1]), as two integer ranges
+// tested with one unsigned comparison each, (uint32)(kx - start) <= width:
+//  - quick-accept span [xl, xl + xw]: every grid point of the row in it is
+//    strictly inside the polygon (verified exactly at the rectangle's
+//    corners; no span: xl = SPAN_FAR);
+//  - extent [ob, ob + ow]: the grid points strictly between the polygon's
+//    x-extent over the row, widened by a grid unit on each side; a point of
+//    the row outside it is not strictly inside the polygon.
 // Per row a second word lists the edges whose y-range meets the row (one byte
 // each, ROW_EDGE_NONE = unused, ROW_EDGES_ALL = more than four): for a point
 // of the row, being strictly inside those edges is the same as being
 // strictly inside the polygon.
 struct Span {
-    int32_t xl, xr, ol, orr;
+    int32_t xl, xw, ob, ow;
 };
+constexpr int32_t SPAN_FAR = 1 << 30;           // start of an empty range (kx < 2^24)
 constexpr uint32_t ROW_EDGE_NONE = 31;          // index of an always-satisfied edge
 constexpr uint32_t ROW_EDGES_ALL = 0xFFFFFFFFu;
 

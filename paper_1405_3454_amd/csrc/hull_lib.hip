@@ -47,6 +47,9 @@ static Dirs preset_dirs(int preset) {
 }
 
 // ---------------------------------------------------------------------------
+struct StreamBufs;                  // host-resident input path (hull_stream.hip)
+static void stream_free(StreamBufs *b);
+
 struct hull_ctx {
     int device = 0;
     int preset = HULL_DIRS_PAPER;
@@ -75,6 +78,8 @@ struct hull_ctx {
     hipGraphExec_t gexec = nullptr;
     // learned proposal
     LearnedState learned;
+    // host-resident input: chunk buffers, staging, copy stream
+    StreamBufs *sb = nullptr;
 };
 
 // Slots of one set's extremes: the preset's fixed positions, then the
@@ -460,9 +465,12 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
 
 // Step 3 + compaction.  surv_off gets the per-set survivor offsets (S+1);
 // keys (optional) the sort keys of the survivors.
+// out_base (optional, device): append after that many entries of surv/keys,
+// writing no entry at or past cap.
 static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                        const float *y, int64_t n_total, const int64_t *off, int64_t n1,
-                       int64_t S, int nedge, uint32_t *surv, int64_t *surv_off, uint64_t *keys) {
+                       int64_t S, int nedge, uint32_t *surv, int64_t *surv_off, uint64_t *keys,
+                       const int64_t *out_base = nullptr, int64_t cap = INT64_MAX) {
     const int64_t *tile_off = W<int64_t>(p, p.tile_off);
     const int32_t *tile_set = W<int32_t>(p, p.tile_set);
     auto *polys = W<Poly>(p, p.polys);
@@ -485,7 +493,7 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
                                                                                   surv_off));
     LAUNCH(K_SCATTER, k_scatter<<<g, 256, 0, st>>>(x, y, n_total, phase_of(x), off, S, tile_off, tile_set, masks, tcnt,
-                                                   tpos, surv, keys));
+                                                   tpos, surv, keys, out_base, cap));
     return HULL_OK;
 }
 
@@ -778,6 +786,7 @@ const char *hull_strerror(int code) {
     case HULL_ECAPTURE: return "workspace must grow but the stream is being captured";
     case HULL_ENOMODEL: return "learned proposal requested without network weights";
     case HULL_ESCRATCH: return "input larger than the fixed scratch of the allocation-free call";
+    case HULL_EOVERFLOW: return "more survivors than the output capacity";
     default: return "unknown error";
     }
 }
@@ -836,6 +845,7 @@ int hull_destroy(hull_ctx *ctx) {
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     learned_free(ctx->learned);
+    stream_free(ctx->sb);
     for (char *r : ctx->retired) (void)hipFree(r);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->counts) (void)hipFree(ctx->counts);
@@ -1489,3 +1499,5 @@ int hull_label_targets_batched(hull_ctx *ctx, const float *x, const float *y,
 }
 
 }  // extern "C"
+
+#include "hull_stream.hip"

@@ -865,7 +865,7 @@ __global__ __launch_bounds__(256) void k_rows(const Poly *__restrict__ polys,
     const int r = blockIdx.y * ROWS_PER_BLOCK + (tid >> 4);
     const Poly &P = polys[s];
     const int m = P.m;
-    Span sp{1, 0, INT32_MAX, INT32_MIN};
+    Span sp{SPAN_FAR, 0, SPAN_FAR, 0};     // no span; nothing strictly inside the extent
     uint32_t re = ROW_EDGES_ALL;
     const int64_t ytop = (int64_t)P.ky_lo + P.yspan;
     const int64_t y0 = (int64_t)P.ky_lo + ((int64_t)r << P.shift);
@@ -930,11 +930,15 @@ __global__ __launch_bounds__(256) void k_rows(const Poly *__restrict__ polys,
         // the crossings carry at most a few ulps of rounding; one grid unit of
         // margin keeps the outer test conservative
         if (mnx <= mxx) {
-            sp.ol = (int32_t)floor(mnx) - 1;
-            sp.orr = (int32_t)ceil(mxx) + 1;
+            // strictly between ol = floor(mnx) - 1 and orr = ceil(mxx) + 1
+            const int32_t ol = (int32_t)floor(mnx) - 1, orr = (int32_t)ceil(mxx) + 1;
+            sp.ob = ol + 1;
+            sp.ow = orr - ol - 2;      // >= 1: orr - ol >= 3
         } else {
-            sp.ol = INT32_MIN;      // unreachable: keep every point for the exact test
-            sp.orr = INT32_MAX;
+            // unreachable: every point of the row in the extent, so that it
+            // gets the exact test
+            sp.ob = -SPAN_FAR;
+            sp.ow = INT32_MIN;         // as uint32: 2^31
             re = ROW_EDGES_ALL;
         }
         if (!bad && xl > -1e299 && xr < 1e299) {
@@ -952,7 +956,7 @@ __global__ __launch_bounds__(256) void k_rows(const Poly *__restrict__ polys,
                 }
                 if (!row_or(fail)) {
                     sp.xl = (int32_t)fl;
-                    sp.xr = (int32_t)fr;
+                    sp.xw = (int32_t)(fr - fl);
                     break;
                 }
                 fl += 2.0;
@@ -1024,6 +1028,10 @@ struct AppendOut {
 };
 
 constexpr uint64_t Q_OUTSIDE = 1ull << 63;   // queue entry already known to be a survivor
+// Appending modes keep queue entries across tiles: an entry's position is
+// (tile - base tile) * TILE + position in the tile, below 2^15, so a queue
+// spans at most Q_TILES tiles before it is drained whatever its length.
+constexpr int Q_TILES = 32;
 
 // Exact test of queue entries [from, from + count), one per lane, against the
 // edges meeting the point's row (all edges outside the rows).  MASKS: a
@@ -1082,7 +1090,7 @@ __device__ __forceinline__ void drain(DiscardLds &L, int from, int count, int32_
     } else {
         const uint64_t m = __ballot(out);
         if (out) {
-            const int64_t gi = o.tb + (int64_t)((e >> 48) & 0x3FF);
+            const int64_t gi = o.tb + (int64_t)((e >> 48) & 0x7FFF);
             const int64_t pp = o.at + __popcll(m & lanemask_lt());
             o.surv[pp] = (uint32_t)gi;
             o.keys[pp] = o.setkey | ((e & 0xFFFFFF) << 24) | ((e >> 24) & 0xFFFFFF);
@@ -1133,6 +1141,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     AppendOut ao{surv, keys, edges, t0 * TILE, 0, 0, 0};
 
     int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1, cur_s = -1;
+    int qn = 0;                 // queued points (wave-uniform)
+    int64_t qt = 0;             // appending modes: tile the queue's positions count from
     int32_t ky_lo = 0, shift = 0, ymin = 0, pm = 0;
     uint32_t ylim = 0;          // in the rows: (ky - ky_lo) <= ylim (unsigned)
     uint32_t yext = 0;          // in the polygon's y-range: (ky - ymin) <= yext
@@ -1140,6 +1150,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 
     for (int64_t t = t0; t < t1; ++t) {
         if (t >= cur_end) {     // a new set starts (looked up once per set)
+            // the queue holds the previous set's points: test them against
+            // its polygon first
+            if (MODE != DISCARD_MASKS && qn > 0) {
+                wave_sync();
+                drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
+                qn = 0;
+                wave_sync();
+            }
             const int64_t s = __builtin_amdgcn_readfirstlane(tile_set[t]);
             if (MODE == DISCARD_ASSIGN) {
                 if (cur_s >= 0) far_flush(L, gfar, cur_s);
@@ -1180,9 +1198,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
             }
             wave_sync();
         }
-        int qn = 0;
         const int64_t tb = abase + (t - tile0) * TILE;
-        ao.tb = tb;
+        if (MODE != DISCARD_MASKS) {
+            // positions count from tile qt; past Q_TILES tiles the queue is
+            // drained whatever its length
+            if (qn > 0 && t - qt >= Q_TILES) {
+                wave_sync();
+                drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
+                qn = 0;
+                wave_sync();
+            }
+            if (qn == 0) qt = t;
+        } else {
+            qt = t;
+        }
+        ao.tb = abase + (qt - tile0) * TILE;
+        const int tpos = (int)(t - qt) * TILE;   // position of the tile's first point in the queue
         // one tile (FULL: every position lies in the set, so the loads need
         // no guard): per chunk, classify its 4 points per lane, queue the
         // undecided ones (one ballot per chunk when there are none), drain
@@ -1219,10 +1250,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                                                   : __ballot(a + j >= o0) & __ballot(a + j < o1);
                     const uint64_t m_rows = __ballot(dy[j] <= ylim);
                     const uint64_t m_ext = __ballot((uint32_t)(ky[j] - ymin) <= yext);
-                    // one comparison per ballot: no short-circuit branches
-                    const uint64_t m_span = __ballot(kx[j] >= sp[j].xl) & __ballot(kx[j] <= sp[j].xr);
-                    const uint64_t m_out = __ballot(kx[j] <= sp[j].ol) | __ballot(kx[j] >= sp[j].orr);
-                    const uint64_t outside = ~m_ext | (m_rows & m_out);
+                    // one unsigned range comparison per ballot: xl <= kx <= xr
+                    // (quick-accept span), ol < kx < orr (inside the row's
+                    // extent); the rows store the ranges as (start, width)
+                    const uint64_t m_span = __ballot((uint32_t)(kx[j] - sp[j].xl) <= (uint32_t)sp[j].xw);
+                    const uint64_t m_in = __ballot((uint32_t)(kx[j] - sp[j].ob) <= (uint32_t)sp[j].ow);
+                    const uint64_t outside = ~m_ext | (m_rows & ~m_in);
                     const uint64_t inside = m_rows & m_span;
                     sw[j] = outside & m_valid;
                     slow[j] = ~(outside | inside) & m_valid;
@@ -1233,18 +1266,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                 uint64_t push[4];
 #pragma unroll
                 for (int j = 0; j < 4; j++) push[j] = MODE == DISCARD_MASKS ? slow[j] : (slow[j] | sw[j]);
-                if (push[0] | push[1] | push[2] | push[3]) {
-                    const uint64_t lt = lanemask_lt();
+                // Each lane writes an entry for every point of a non-empty
+                // ballot: the queued ones packed at qn, the others after them
+                // (overwritten later, or beyond the queue's end), so the
+                // writes need no branch; the queue holds qn + 64 entries.
 #pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        if ((push[j] >> lane) & 1) {
-                            const int p = qn + __popcll(push[j] & lt);
-                            L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
-                                     ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
-                                     ((uint64_t)(c * CHUNK + 4 * lane + j) << 48) |
-                                     (((sw[j] >> lane) & 1) ? Q_OUTSIDE : 0);
-                        }
-                        qn += __popcll(push[j]);
+                for (int j = 0; j < 4; j++) {
+                    if (push[j]) {
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(push[j] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)push[j], 0u));
+                        const int cnt = __popcll(push[j]);
+                        const bool mine = (push[j] >> lane) & 1;
+                        const int p = qn + (mine ? (int)below : cnt + lane - (int)below);
+                        L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
+                                 ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
+                                 ((uint64_t)(tpos + c * CHUNK + 4 * lane + j) << 48) |
+                                 (((sw[j] >> lane) & 1) ? Q_OUTSIDE : 0);
+                        qn += cnt;
                     }
                 }
                 if (MODE == DISCARD_MASKS && lane < 4)
@@ -1256,7 +1294,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                 }
                 wave_sync();
             }
-            if (qn > 0) drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
+            if (MODE == DISCARD_MASKS && qn > 0) {
+                drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
+                qn = 0;
+            }
             wave_sync();
         };
         if (tb >= o0 && tb + TILE <= o1)
@@ -1271,6 +1312,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         }
         wave_sync();
     }
+    if (MODE != DISCARD_MASKS && qn > 0) {
+        wave_sync();
+        drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
+    }
     if (MODE == DISCARD_ASSIGN) far_flush(L, gfar, cur_s);
     if (MODE != DISCARD_MASKS && lane == 0) seg_cnt[wave] = ao.at - t0 * TILE;
 }
@@ -1283,19 +1328,23 @@ __global__ __launch_bounds__(256) void k_scatter(
     const int64_t *__restrict__ off,
     int64_t S, const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set,
     const uint64_t *__restrict__ masks, const uint32_t *__restrict__ tile_cnt,
-    const int64_t *__restrict__ tile_pos, uint32_t *__restrict__ surv, uint64_t *__restrict__ keys) {
+    const int64_t *__restrict__ tile_pos, uint32_t *__restrict__ surv, uint64_t *__restrict__ keys,
+    const int64_t *__restrict__ out_base, int64_t cap) {
+    // out_base (optional): device count of entries already in surv/keys, to
+    // append after them; entries at or past cap are not written
     const int lane = lane_id();
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
     const int64_t T = tile_off[S];
     const uint64_t lt = lanemask_lt();
+    const int64_t ob = out_base ? *out_base : 0;
     for (int64_t t = wave; t < T; t += W) {
         const uint32_t tc = tile_cnt[t];
         if (tc == 0) continue;
         const int64_t s = tile_set[t];
         const int64_t o0 = set_begin(off, s);
         const int64_t tb = tile_base(o0, phase) + (t - tile_off[s]) * TILE;
-        int64_t base = tile_pos[t];
+        int64_t base = ob + tile_pos[t];
         // all loads of the tile are issued together: the 16 mask words, then
         // either the whole tile as float4 rows (many survivors) or one
         // gather per survivor
@@ -1336,8 +1385,8 @@ __global__ __launch_bounds__(256) void k_scatter(
                 if ((M[c * 4 + j] >> lane) & 1) {
                     const int64_t gi = tb + c * CHUNK + 4 * lane + j;
                     const int64_t p = base + pre + k;
-                    surv[p] = (uint32_t)gi;
-                    if (keys) {
+                    if (p < cap) surv[p] = (uint32_t)gi;
+                    if (keys && p < cap) {
                         const uint64_t kx = (uint64_t)(uint32_t)(xv[c][j] * GRIDF);
                         const uint64_t ky = (uint64_t)(uint32_t)(yv[c][j] * GRIDF);
                         keys[p] = ((uint64_t)s << 48) | (kx << 24) | ky;
