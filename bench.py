@@ -262,6 +262,50 @@ def bench_host(args, X, Y, n):
     return res
 
 
+def bench_3d(args, dev, log2n=24):
+    """The 3D form: one set of 2^24 points per shape (cube, ball, shell,
+    Gaussian), the whole method (two extremes passes, polyhedron, discard,
+    hull of the survivors by QuickHull rounds); synchronises per round."""
+    import torch
+    from paper_1405_3454_amd import inputs
+    from paper_1405_3454_amd.api import Hull
+    n = 1 << log2n
+    H = Hull(0)
+    res = {"workload": "one set of 2^%d points per shape, float32 k*2^-24 in [0,1)^3" % log2n}
+    for kind in ("cube", "ball", "shell", "gaussian"):
+        x, y, z = inputs.set3_torch(kind, n, 900 + len(kind), device=dev)
+        H.compute3(x, y, z)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, surv, hull = H.compute3(x, y, z)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        H.timing(True)
+        H.timing_reset()
+        H.compute3(x, y, z)
+        torch.cuda.synchronize()
+        kt = H.timing_read()
+        H.timing(False)
+        t = min(ts)
+        ext_ms = kt.get("extremes", (0.0, 1))[0]
+        disc_ms = kt.get("discard", (0.0, 1))[0]
+        res[kind] = {"gpts": round(n / t / 1e9, 3), "ms": round(t * 1e3, 3),
+                     "survivors": int(len(surv)), "hull_vertices": int(len(hull)),
+                     "discard_fraction": round(1.0 - len(surv) / n, 6),
+                     "extremes_us": round(ext_ms * 1e3, 1),
+                     "extremes_gbs": round(2 * 12.0 * n / (ext_ms * 1e-3) / 1e9, 1) if ext_ms else None,
+                     "discard_us": round(disc_ms * 1e3, 1),
+                     "discard_gbs": round(12.0 * n / (disc_ms * 1e-3) / 1e9, 1) if disc_ms else None,
+                     "hull_stage_ms": round((kt.get("refine_pass", (0.0, 1))[0] +
+                                             kt.get("refine_split", (0.0, 1))[0]), 3)}
+        del x, y, z
+    H.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(args, dev):
     """Batched plain method: 4096 sets, sizes log-uniform in [1e3, 1e6], kinds
     uniform over square/disk/gaussian/annulus.  Per-set calls vs one batched
@@ -393,7 +437,8 @@ def main():
                     help="points of each set the CPU oracle is timed on")
     ap.add_argument("--cpu-batch-sets", type=int, default=1024,
                     help="sets of the batched workload the CPU oracle is timed on")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no tuning before the timed steps)")
     ap.add_argument("--batch-sets", type=int, default=4096)
     ap.add_argument("--train-sets", type=int, default=200000)
     ap.add_argument("--skip-extra", action="store_true",
@@ -420,8 +465,7 @@ def main():
     if args.no_cpu:
         del data
     H = Hull(0, preset=args.preset)
-    if args.autotune:
-        H.autotune(X["disk"], Y["disk"])
+    tuning = [] if args.no_autotune else H.autotune(X["disk"], Y["disk"])
     hull = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in KINDS}
     hcnt = {k: torch.zeros(1, dtype=torch.int64, device=dev) for k in KINDS}
 
@@ -544,6 +588,7 @@ def main():
         "hull_vertices": hs,
         "per_kernel": per_kernel,
         "hull_stage_passes": passes,
+        "tuning": tuning,
     }
     out["latency_100k"] = bench_latency(dev)
     if not args.skip_extra:
@@ -565,6 +610,7 @@ def main():
         del X, Y, hull
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(args, dev)
+        out["three_d"] = bench_3d(args, dev)
         out["learned"] = bench_learned(args, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(data, min(n, args.cpu_sample))

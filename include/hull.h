@@ -228,12 +228,33 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y,
 int hull_graph_launch(hull_ctx *ctx, void *stream);
 
 /* ---- launch tuning ------------------------------------------------------
- * Time the candidate launch shapes of the filter kernels on these inputs
- * and keep the fastest.  Synchronises. */
+ * The two persistent filter kernels (0: the extremes pass, 1: the discard
+ * pass) launch with a shape: threads per block (128, 256 or 512), blocks
+ * per CU (1..16, capped at what stays resident for that kernel) and the
+ * fewest tiles of 1024 points (16 per lane) a wave walks (1..1024; small
+ * inputs get fewer waves).  Shapes are kept per size bucket: points below
+ * 2^14, 2^17, 2^20, 2^23, 2^26 and above, each for one set (S = 1) and for
+ * batches (S > 1); untuned buckets use the defaults (256, 3, 1) and
+ * (256, 4, 1).  No shape changes any result.
+ *
+ * hull_autotune times every candidate shape of both kernels on these
+ * inputs (the discard pass in the full method's mode) and keeps the
+ * fastest for their bucket.  Synchronises; allocates only outside capture. */
 int hull_autotune(hull_ctx *ctx, const float *x, const float *y,
                   const int64_t *offsets, int64_t S, int64_t n_total, void *stream);
-/* Read (get != 0) or set the chosen waves-per-CU of the filter kernels. */
+/* Read (get != 0) or set the default blocks per CU of the two kernels.
+ * Setting them also clears every tuned bucket. */
 int hull_tuning(hull_ctx *ctx, int get, int *k1_blocks_per_cu, int *k3_blocks_per_cu);
+/* Read (get != 0) or set the shape of kernel 0 or 1 for the bucket holding
+ * n points in S sets.  Get returns 1 when the bucket is tuned, 0 when it
+ * uses the default; set returns HULL_OK, or HULL_EINVAL for a shape outside
+ * the ranges above. */
+int hull_shape(hull_ctx *ctx, int get, int kernel, int64_t n, int64_t S, int *block_size,
+               int *blocks_per_cu, int *tiles_per_wave);
+/* The tuned buckets as rows of six int32 (kernel, size bucket 0..5,
+ * batched 0/1, block size, blocks per CU, tiles per wave); copies up to cap
+ * rows and returns how many are tuned. */
+int hull_tuning_table(hull_ctx *ctx, int32_t *rows, int cap);
 
 /* ---- learned direction proposal ----------------------------------------
  * This project's extension, not part of the paper's method.  A 32 x 32

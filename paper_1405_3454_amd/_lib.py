@@ -37,6 +37,7 @@ HULL_VALIDATE = 4
 HULL_NOREFINE = 8
 
 HULL_NONE = 0xFFFFFFFF
+HULL3_SLOTS = 42
 
 P = ctypes.c_void_p
 I = ctypes.c_int
@@ -59,6 +60,7 @@ SIGNATURES = {
     "hull_of_subset": (I, [P, P, P, I64, P, P, I64, P, P, P]),
     "hull_compute": (I, [P, P, P, I64, P, P, I, P]),
     "hull_compute_host": (I, [P, P, P, I64, I64, I64, P, P, P, I64, P, P, I, P]),
+    "hull3_compute": (I, [P, P, P, P, I64, P, P, P, P, P, I, P]),
     "hull_extremes_batched": (I, [P, P, P, P, I64, I64, P, I, P]),
     "hull_discard_batched": (I, [P, P, P, P, I64, I64, P, I, P, P, P]),
     "hull_compute_batched": (I, [P, P, P, P, I64, I64, P, P, I, P]),
@@ -66,6 +68,8 @@ SIGNATURES = {
     "hull_graph_launch": (I, [P, P]),
     "hull_autotune": (I, [P, P, P, P, I64, I64, P]),
     "hull_tuning": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "hull_shape": (I, [P, I, I, I64, I64, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "hull_tuning_table": (I, [P, P, I]),
     "hull_mlp_param_count": (I64, []),
     "hull_mlp_set_params": (I, [P, P, I64]),
     "hull_mlp_get_params": (I, [P, P, I64]),

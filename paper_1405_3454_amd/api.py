@@ -93,12 +93,37 @@ class Hull:
         a, b = ctypes.c_int(k1), ctypes.c_int(k3)
         check(lib().hull_tuning(self._h, 0, ctypes.byref(a), ctypes.byref(b)), "hull_tuning")
 
+    def shape(self, kernel, n, S=1):
+        """(block size, blocks per CU, tiles per wave, tuned) of kernel 0
+        (extremes pass) or 1 (discard pass) for n points in S sets."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        t = check(lib().hull_shape(self._h, 1, int(kernel), int(n), int(S), ctypes.byref(a),
+                                   ctypes.byref(b), ctypes.byref(c)), "hull_shape")
+        return a.value, b.value, c.value, bool(t)
+
+    def set_shape(self, kernel, n, S, block_size, blocks_per_cu, tiles_per_wave):
+        a, b, c = ctypes.c_int(block_size), ctypes.c_int(blocks_per_cu), ctypes.c_int(tiles_per_wave)
+        check(lib().hull_shape(self._h, 0, int(kernel), int(n), int(S), ctypes.byref(a),
+                               ctypes.byref(b), ctypes.byref(c)), "hull_shape")
+
+    BUCKET_LIMITS = ("<2^14", "<2^17", "<2^20", "<2^23", "<2^26", ">=2^26")
+
+    def tuning_table(self):
+        """Tuned buckets: list of dicts (kernel, points, batched, shape)."""
+        k = check(lib().hull_tuning_table(self._h, None, 0), "hull_tuning_table")
+        rows = np.zeros((max(k, 1), 6), np.int32)
+        k = check(lib().hull_tuning_table(self._h, rows.ctypes.data_as(ctypes.c_void_p), k),
+                  "hull_tuning_table")
+        return [{"kernel": ("extremes", "discard")[r[0]], "points": self.BUCKET_LIMITS[r[1]],
+                 "batched": bool(r[2]), "block_size": int(r[3]), "blocks_per_cu": int(r[4]),
+                 "tiles_per_wave": int(r[5])} for r in rows[:k]]
+
     def autotune(self, x, y, offsets=None, stream=None):
         n = _pts(x, y)
         S = 0 if offsets is None else offsets.numel() - 1
         check(lib().hull_autotune(self._h, _ptr(x), _ptr(y), _ptr(offsets), S, n, _stream(stream)),
               "hull_autotune")
-        return self.tuning()
+        return self.tuning_table()
 
     # -- single set --------------------------------------------------------
     def extremes(self, x, y, learned=False, validate=False, stream=None):
@@ -188,6 +213,25 @@ class Hull:
         check(lib().hull_compute_host(self._h, xp, yp, n, int(chunk_points), int(device_budget),
                                       _ptr(slots), _ptr(surv), _ptr(ns), cap, _ptr(hull), _ptr(h),
                                       0, _stream(stream)), "hull_compute_host")
+        return slots, surv[: int(ns.item())], hull[: int(h.item())]
+
+    # -- three dimensions -------------------------------------------------
+    def compute3(self, x, y, z, nofilter=False, stream=None):
+        """The 3D method on device float32 x, y, z (16-byte aligned): returns
+        (slots [42], survivors ascending, extreme points ascending) as int32
+        device tensors.  Synchronises."""
+        n = _pts(x, y)
+        if z.dtype != torch.float32 or not z.is_cuda or z.shape != x.shape or not z.is_contiguous():
+            raise ValueError("z must be a contiguous float32 device tensor like x")
+        dev = x.device
+        slots = torch.full((_lib.HULL3_SLOTS,), -1, dtype=torch.int32, device=dev)
+        surv = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+        hull = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+        ns = torch.zeros(1, dtype=torch.int64, device=dev)
+        h = torch.zeros(1, dtype=torch.int64, device=dev)
+        check(lib().hull3_compute(self._h, _ptr(x), _ptr(y), _ptr(z), n, _ptr(slots), _ptr(surv),
+                                  _ptr(ns), _ptr(hull), _ptr(h), HULL_NOFILTER if nofilter else 0,
+                                  _stream(stream)), "hull3_compute")
         return slots, surv[: int(ns.item())], hull[: int(h.item())]
 
     # -- batched -----------------------------------------------------------

@@ -15,6 +15,7 @@
 #include "k_chain.hip"
 #include "k_learned.hip"
 #include "k_refine.hip"
+#include "k_hull3d.hip"
 
 using namespace hg;
 
@@ -47,8 +48,26 @@ static Dirs preset_dirs(int preset) {
 }
 
 // ---------------------------------------------------------------------------
+// Launch shape of a persistent filter kernel: threads per block, blocks per
+// CU (capped at what stays resident) and the fewest tiles (1024 points, 16
+// per lane) a wave walks, which shrinks the grid for small inputs.
+struct Shape {
+    int bs, bpc, tpw;
+};
+constexpr int SHAPE_BS[3] = {128, 256, 512};
+// Size buckets of the tuning table: points below 2^14, 2^17, 2^20, 2^23,
+// 2^26 and above, each for one set and for batches.
+constexpr int NSIZE = 6, NBUCKETS = 2 * NSIZE;
+static int bucket_of(int64_t n, int64_t S) {
+    int b = 0;
+    while (b < NSIZE - 1 && n >= (int64_t(1) << (14 + 3 * b))) b++;
+    return b + (S > 1 ? NSIZE : 0);
+}
+
 struct StreamBufs;                  // host-resident input path (hull_stream.hip)
 static void stream_free(StreamBufs *b);
+struct Hull3Bufs;                   // the 3D path (hull3d_host.hip)
+static void hull3_free(Hull3Bufs *h);
 
 struct hull_ctx {
     int device = 0;
@@ -63,9 +82,11 @@ struct hull_ctx {
     int64_t *counts = nullptr;          // candidates per stage of the last computation
     uint32_t *tickets = nullptr;        // last-block tickets (zero between launches)
     std::vector<char *> retired;        // old workspaces a graph may still use
-    // blocks per CU of the persistent filter kernels: what stays resident
-    // (extremes: ~140 VGPRs -> 3 waves per SIMD; discard: ~112 -> 4)
-    int k1_bpc = 3, k3_bpc = 4;
+    // launch shapes of the persistent filter kernels (extremes pass, discard
+    // pass): defaults, and the autotuner's choices per size bucket
+    Shape def[2] = {{256, 3, 1}, {256, 4, 1}};
+    Shape tuned[2][NBUCKETS];
+    bool has_tuned[2][NBUCKETS] = {};
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -80,6 +101,8 @@ struct hull_ctx {
     LearnedState learned;
     // host-resident input: chunk buffers, staging, copy stream
     StreamBufs *sb = nullptr;
+    // the 3D path's buffers
+    Hull3Bufs *h3 = nullptr;
 };
 
 // Slots of one set's extremes: the preset's fixed positions, then the
@@ -203,12 +226,13 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.rfar0 = take(S * RE_CAP * 8);
     p.rfar1 = take(S * RE_CAP * 8);
     p.rfar2 = take(RE_CAP * 8);          // one set: third farthest-key buffer of the rounds
-    p.segcnt = take((REF_ROUNDS + 1) * W * 8);      // region counts per list stage
-    p.segmeta = take(8);                             // region size (q * TILE)
     p.bpart = take(S * POLY_SPLIT * MAX_SLOTS * sizeof(SlotBest));
     p.pticket = take(S * 4);
     p.cidx = take(n * 4 + 16);
     p.ckeys = take(n * 8 + 16);
+    // last: the only entries whose size depends on the discard pass's waves
+    p.segmeta = take(8);                             // region size (q * TILE)
+    p.segcnt = take((REF_ROUNDS + 1) * W * 8);      // region counts per list stage
     p.total = o;
     return p;
 }
@@ -310,56 +334,95 @@ static int check_points(const float *x, const float *y, int64_t n) {
 static int phase_of(const float *x) { return (int)(((uintptr_t)x >> 2) & 3); }
 
 // The extremes pass instantiated for a preset (learned: with eight learned
-// directions), as a host handle for occupancy queries.
-static const void *k1_kernel(int preset, bool learned) {
-#define K1F(PR) (learned ? (const void *)k_extremes<PR, MAX_DIRS> : (const void *)k_extremes<PR, 0>)
+// directions) and block size, as a host handle for occupancy queries.
+template <int PR, int ND>
+static const void *k1_fn(int bs) {
+    switch (bs) {
+    case 128: return (const void *)k_extremes<PR, ND, 128>;
+    case 512: return (const void *)k_extremes<PR, ND, 512>;
+    default: return (const void *)k_extremes<PR, ND, 256>;
+    }
+}
+static const void *k1_kernel(int preset, bool learned, int bs) {
     switch (preset) {
-    case 0: return K1F(0);
-    case 1: return K1F(1);
-    case 2: return K1F(2);
-    case 3: return K1F(3);
-    case 4: return K1F(4);
-    case 5: return K1F(5);
-    case 6: return (const void *)k_extremes<6, 0>;
-    case 7: return (const void *)k_extremes<7, 0>;
+    case 0: return learned ? k1_fn<0, MAX_DIRS>(bs) : k1_fn<0, 0>(bs);
+    case 1: return learned ? k1_fn<1, MAX_DIRS>(bs) : k1_fn<1, 0>(bs);
+    case 2: return learned ? k1_fn<2, MAX_DIRS>(bs) : k1_fn<2, 0>(bs);
+    case 3: return learned ? k1_fn<3, MAX_DIRS>(bs) : k1_fn<3, 0>(bs);
+    case 4: return learned ? k1_fn<4, MAX_DIRS>(bs) : k1_fn<4, 0>(bs);
+    case 5: return learned ? k1_fn<5, MAX_DIRS>(bs) : k1_fn<5, 0>(bs);
+    case 6: return k1_fn<6, 0>(bs);
+    case 7: return k1_fn<7, 0>(bs);
     default: return nullptr;
     }
-#undef K1F
+}
+// The full method's discard pass at a block size (all its modes share the
+// register cap of 4 waves per SIMD).
+static const void *k3_kernel(int bs) {
+    switch (bs) {
+    case 128: return (const void *)k_discard<FIXED_SLOTS, DISCARD_ASSIGN, 128>;
+    case 512: return (const void *)k_discard<FIXED_SLOTS, DISCARD_ASSIGN, 512>;
+    default: return (const void *)k_discard<FIXED_SLOTS, DISCARD_ASSIGN, 256>;
+    }
 }
 
-// Blocks of 256 threads per CU that stay resident for a kernel (its register
-// and LDS use), cached per kernel in a fixed table (hull_create fills it for
-// every extremes variant, so later calls neither query nor allocate); 1 if
-// the query fails.
-static int resident_blocks(const void *fn) {
+// Blocks of bs threads per CU that stay resident for a kernel (its register
+// and LDS use), cached per (kernel, block size) in a fixed table that
+// hull_create fills for every filter variant, so later calls neither query
+// nor allocate; 1 if the query fails.
+static int resident_blocks(const void *fn, int bs) {
     static std::mutex mu;
-    static const void *keys[32];
-    static int vals[32];
+    constexpr int CAP = 128;
+    static const void *keys[CAP];
+    static int kbs[CAP], vals[CAP];
     static int used = 0;
     std::lock_guard<std::mutex> lock(mu);
     for (int i = 0; i < used; i++)
-        if (keys[i] == fn) return vals[i];
+        if (keys[i] == fn && kbs[i] == bs) return vals[i];
     int b = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, 256, 0) != hipSuccess || b < 1) {
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, bs, 0) != hipSuccess || b < 1) {
         (void)hipGetLastError();
         b = 1;
     }
-    if (used < 32) {
+    if (used < CAP) {
         keys[used] = fn;
+        kbs[used] = bs;
         vals[used] = b;
         used++;
     }
     return b;
 }
 
-// Grid of the persistent extremes pass: the tuned blocks per CU, capped at
-// what stays resident (the variants hold 100 to 254 VGPRs: 2 to 4 waves per
-// SIMD), so that every block runs in the first wave of blocks.
-static int grid_k1(hull_ctx *ctx, bool learned = false) {
-    const bool l = learned && learned_ok(ctx);
-    return ctx->cus * std::min(ctx->k1_bpc, resident_blocks(k1_kernel(ctx->preset, l)));
+// Grid of a persistent filter kernel for n points in S sets: the bucket's
+// shape, blocks per CU capped at what stays resident (the extremes variants
+// hold 100 to 254 VGPRs: 2 to 4 waves per SIMD), and no more waves than
+// give each its tpw tiles.
+struct Launch {
+    int bs;
+    unsigned blocks;
+    int64_t waves;
+};
+static Shape shape_of(const hull_ctx *ctx, int kind, int64_t n, int64_t S) {
+    const int b = bucket_of(n, S);
+    return ctx->has_tuned[kind][b] ? ctx->tuned[kind][b] : ctx->def[kind];
 }
-static int grid_k3(hull_ctx *ctx) { return ctx->cus * ctx->k3_bpc; }
+static Launch make_launch(const hull_ctx *ctx, const Shape &sh, const void *fn, int64_t n, int64_t S) {
+    const int wpb = sh.bs / WAVE;
+    const int bpc = std::min(sh.bpc, resident_blocks(fn, sh.bs));
+    int64_t blocks = (int64_t)ctx->cus * bpc;
+    const int64_t tiles = n / TILE + 2 * S + 2;           // upper bound of the tile count
+    const int64_t want = (tiles + sh.tpw - 1) / sh.tpw;   // waves with tpw tiles each
+    blocks = std::max<int64_t>(1, std::min(blocks, (want + wpb - 1) / wpb));
+    return Launch{sh.bs, (unsigned)blocks, blocks * wpb};
+}
+static Launch k1_launch(const hull_ctx *ctx, int64_t n, int64_t S, bool learned) {
+    const Shape sh = shape_of(ctx, 0, n, S);
+    return make_launch(ctx, sh, k1_kernel(ctx->preset, learned && learned_ok(ctx), sh.bs), n, S);
+}
+static Launch k3_launch(const hull_ctx *ctx, int64_t n, int64_t S) {
+    const Shape sh = shape_of(ctx, 1, n, S);
+    return make_launch(ctx, sh, k3_kernel(sh.bs), n, S);
+}
 
 // ---------------------------------------------------------------------------
 // Launch sequences
@@ -395,6 +458,24 @@ static int run_tilemap(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     return HULL_OK;
 }
 
+// Launch the extremes pass / discard pass at a block size.
+template <int PR, int ND, typename... A>
+static void launch_k1(const Launch &L, hipStream_t st, A... a) {
+    switch (L.bs) {
+    case 128: k_extremes<PR, ND, 128><<<L.blocks, 128, 0, st>>>(a...); break;
+    case 512: k_extremes<PR, ND, 512><<<L.blocks, 512, 0, st>>>(a...); break;
+    default: k_extremes<PR, ND, 256><<<L.blocks, 256, 0, st>>>(a...); break;
+    }
+}
+template <int NE, int MODE, typename... A>
+static void launch_k3(const Launch &L, hipStream_t st, A... a) {
+    switch (L.bs) {
+    case 128: k_discard<NE, MODE, 128><<<L.blocks, 128, 0, st>>>(a...); break;
+    case 512: k_discard<NE, MODE, 512><<<L.blocks, 512, 0, st>>>(a...); break;
+    default: k_discard<NE, MODE, 256><<<L.blocks, 256, 0, st>>>(a...); break;
+    }
+}
+
 // Step 1 (+ partial reduction and polygon in k_polygon).
 static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                         const float *y, int64_t n_total, const int64_t *off, int64_t n1,
@@ -404,12 +485,11 @@ static int run_extremes(hull_ctx *ctx, const Plan &p, hipStream_t st, const floa
     double *pval = W<double>(p, p.pval);
     uint32_t *pidx = W<uint32_t>(p, p.pidx);
     const double *sd = W<double>(p, p.setdirs);
-    const int g = grid_k1(ctx, learned);
+    const Launch L = k1_launch(ctx, n_total, S, learned);
     const Dirs d = ctx->dirs;
 #define K1(PR, ND)                                                                           \
-    LAUNCH(K_EXTREMES, k_extremes<PR, ND><<<g, 256, 0, st>>>(x, y, n_total, phase_of(x), off, \
-                                                             n1, S, tile_off, tile_set, d, sd, \
-                                                             pval, pidx))
+    LAUNCH(K_EXTREMES, (launch_k1<PR, ND>(L, st, x, y, n_total, phase_of(x), off, n1, S,      \
+                                          tile_off, tile_set, d, sd, pval, pidx)))
     if (learned && !learned_ok(ctx)) return HULL_EINVAL;
     switch (ctx->preset) {
     case 0: if (learned) K1(0, MAX_DIRS); else K1(0, 0); break;
@@ -431,7 +511,7 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
                        int n_in, uint32_t *slots_out, double *vals_out, bool ref_init = false) {
     REdge *rtab = ref_init ? W<REdge>(p, p.rtab0) : nullptr;
     unsigned long long *rfar = ref_init ? W<unsigned long long>(p, p.rfar0) : nullptr;
-    const int64_t W1 = (int64_t)grid_k1(ctx, learned) * 4;
+    const int64_t W1 = k1_launch(ctx, n_total, S, learned).waves;   // the extremes pass's waves
     auto *polys = W<Poly>(p, p.polys);
     auto *spans = W<Span>(p, p.spans);
     const double *sd = W<double>(p, p.setdirs);
@@ -479,15 +559,21 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     uint64_t *masks = W<uint64_t>(p, p.masks);
     uint32_t *tcnt = W<uint32_t>(p, p.tile_cnt);
     int64_t *tpos = W<int64_t>(p, p.tile_pos);
-    const int g = grid_k3(ctx);
+    const Launch L = k3_launch(ctx, n_total, S);
+    const unsigned g = (unsigned)std::max<int64_t>(1, (L.waves + 3) / 4);   // scatter blocks: as many waves
+    uint32_t *nu = nullptr;
+    uint64_t *nk = nullptr;
+    uint16_t *ne = nullptr;
+    int64_t *nc = nullptr, *nm = nullptr;
+    unsigned long long *nf = nullptr;
     if (nedge <= FIXED_SLOTS)
-        LAUNCH(K_DISCARD, k_discard<FIXED_SLOTS, DISCARD_MASKS><<<g, 256, 0, st>>>(
-            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt,
-            nullptr, nullptr, nullptr, nullptr, 0, nullptr));
+        LAUNCH(K_DISCARD, (launch_k3<FIXED_SLOTS, DISCARD_MASKS>(
+            L, st, x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges,
+            masks, tcnt, nu, nk, ne, nc, nm, nf)));
     else
-        LAUNCH(K_DISCARD, k_discard<MAX_SLOTS, DISCARD_MASKS><<<g, 256, 0, st>>>(
-            x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges, masks, tcnt,
-            nullptr, nullptr, nullptr, nullptr, 0, nullptr));
+        LAUNCH(K_DISCARD, (launch_k3<MAX_SLOTS, DISCARD_MASKS>(
+            L, st, x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges,
+            masks, tcnt, nu, nk, ne, nc, nm, nf)));
     int rc = run_scan(ctx, p, st, tcnt, tile_off + S, tpos);
     if (rc) return rc;
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
@@ -511,14 +597,15 @@ static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, cons
     auto *spans = W<Span>(p, p.spans);
     const uint32_t *redges = W<uint32_t>(p, p.redges);
     int64_t *meta = W<int64_t>(p, p.segmeta);
-    const int g = grid_k3(ctx);
-    if ((int64_t)g * 4 != p.nwave) return HULL_EINVAL;   // the plan's regions assume this grid
+    const Launch L = k3_launch(ctx, n_total, S);
+    if (L.waves != p.nwave) return HULL_EINVAL;   // the plan's regions assume this grid
     const int ph = phase_of(x);
+    uint64_t *nmask = nullptr;
+    uint32_t *ncnt = nullptr;
 #define K3A(NE, MODE)                                                                             \
-    LAUNCH(K_DISCARD, (k_discard<NE, MODE><<<g, 256, 0, st>>>(x, y, n_total, ph, off, n1, S,    \
-                                                               tile_off, tile_set, polys, spans,  \
-                                                               redges, nullptr, nullptr, surv,    \
-                                                               keys, edges, seg_cnt, meta, gfar)))
+    LAUNCH(K_DISCARD, (launch_k3<NE, MODE>(L, st, x, y, n_total, ph, off, n1, S, tile_off,       \
+                                           tile_set, polys, spans, redges, nmask, ncnt, surv,    \
+                                           keys, edges, seg_cnt, meta, gfar)))
     if (gfar) {
         if (nedge <= FIXED_SLOTS) K3A(FIXED_SLOTS, DISCARD_ASSIGN);
         else K3A(MAX_SLOTS, DISCARD_ASSIGN);
@@ -705,7 +792,7 @@ static int init_cand_table();
 
 static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p) {
     HIPCHECK(hipSetDevice(ctx->device));
-    *p = make_plan(n, S, (int64_t)grid_k3(ctx) * 4);
+    *p = make_plan(n, S, k3_launch(ctx, n, S).waves);
     int rc = ensure_ws(ctx, p->total, st);
     p->base = ctx->ws;
     return rc;
@@ -818,9 +905,12 @@ int hull_create(hull_ctx **out, int device) {
         delete ctx;
         return HULL_EHIP;
     }
-    for (int pr = 0; pr < NUM_PRESETS; pr++) {
-        (void)resident_blocks(k1_kernel(pr, false));
-        if (preset_fixed_slots(pr) == FIXED_SLOTS) (void)resident_blocks(k1_kernel(pr, true));
+    for (int bs : SHAPE_BS) {
+        for (int pr = 0; pr < NUM_PRESETS; pr++) {
+            (void)resident_blocks(k1_kernel(pr, false, bs), bs);
+            if (preset_fixed_slots(pr) == FIXED_SLOTS) (void)resident_blocks(k1_kernel(pr, true, bs), bs);
+        }
+        (void)resident_blocks(k3_kernel(bs), bs);
     }
     if (hipMalloc(&ctx->counts, HULL_NCOUNTS * sizeof(int64_t)) != hipSuccess ||
         hipMemset(ctx->counts, 0xff, HULL_NCOUNTS * sizeof(int64_t)) != hipSuccess ||
@@ -846,6 +936,7 @@ int hull_destroy(hull_ctx *ctx) {
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     learned_free(ctx->learned);
     stream_free(ctx->sb);
+    hull3_free(ctx->h3);
     for (char *r : ctx->retired) (void)hipFree(r);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->counts) (void)hipFree(ctx->counts);
@@ -1042,7 +1133,7 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int6
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     HIPCHECK(hipSetDevice(ctx->device));
-    Plan p = make_plan(n_total, S, (int64_t)grid_k3(ctx) * 4);
+    Plan p = make_plan(n_total, S, k3_launch(ctx, n_total, S).waves);
     if ((rc = ensure_ws(ctx, p.total, st))) return rc;
     p.base = ctx->ws;
     if ((flags & HULL_LEARNED) && !(flags & HULL_NOFILTER)) {
@@ -1096,14 +1187,79 @@ int hull_graph_launch(hull_ctx *ctx, void *stream) {
 int hull_tuning(hull_ctx *ctx, int get, int *k1, int *k3) {
     if (!ctx || !k1 || !k3) return HULL_EINVAL;
     if (get) {
-        *k1 = ctx->k1_bpc;
-        *k3 = ctx->k3_bpc;
+        *k1 = ctx->def[0].bpc;
+        *k3 = ctx->def[1].bpc;
         return HULL_OK;
     }
     if (*k1 < 1 || *k1 > 64 || *k3 < 1 || *k3 > 64) return HULL_EINVAL;
-    ctx->k1_bpc = *k1;
-    ctx->k3_bpc = *k3;
+    ctx->def[0].bpc = *k1;
+    ctx->def[1].bpc = *k3;
+    // an explicit choice replaces every tuned bucket
+    for (int k = 0; k < 2; k++)
+        for (int b = 0; b < NBUCKETS; b++) ctx->has_tuned[k][b] = false;
     return HULL_OK;
+}
+
+static bool shape_valid(int bs, int bpc, int tpw) {
+    return (bs == 128 || bs == 256 || bs == 512) && bpc >= 1 && bpc <= 16 && tpw >= 1 && tpw <= 1024;
+}
+
+int hull_shape(hull_ctx *ctx, int get, int kernel, int64_t n, int64_t S, int *bs, int *bpc, int *tpw) {
+    if (!ctx || !bs || !bpc || !tpw || kernel < 0 || kernel > 1 || n < 0 || S < 1) return HULL_EINVAL;
+    const int b = bucket_of(n, S);
+    if (get) {
+        const Shape sh = shape_of(ctx, kernel, n, S);
+        *bs = sh.bs;
+        *bpc = sh.bpc;
+        *tpw = sh.tpw;
+        return ctx->has_tuned[kernel][b] ? 1 : 0;
+    }
+    if (!shape_valid(*bs, *bpc, *tpw)) return HULL_EINVAL;
+    ctx->tuned[kernel][b] = Shape{*bs, *bpc, *tpw};
+    ctx->has_tuned[kernel][b] = true;
+    return HULL_OK;
+}
+
+int hull_tuning_table(hull_ctx *ctx, int32_t *rows, int cap) {
+    if (!ctx || (!rows && cap > 0) || cap < 0) return HULL_EINVAL;
+    int k = 0;
+    for (int kernel = 0; kernel < 2; kernel++)
+        for (int b = 0; b < NBUCKETS; b++) {
+            if (!ctx->has_tuned[kernel][b]) continue;
+            if (k < cap) {
+                int32_t *r = rows + 6 * k;
+                r[0] = kernel;
+                r[1] = b % NSIZE;
+                r[2] = b >= NSIZE;
+                r[3] = ctx->tuned[kernel][b].bs;
+                r[4] = ctx->tuned[kernel][b].bpc;
+                r[5] = ctx->tuned[kernel][b].tpw;
+            }
+            k++;
+        }
+    return k;
+}
+
+// Candidate shapes of the tuner: each block size at 1..8 blocks per CU (the
+// same waves per CU counted once per block size) and 1, 4 or 16 tiles per
+// wave, the latter only where they shrink the grid.
+static std::vector<Shape> shape_candidates(const hull_ctx *ctx, int kind, int64_t n, int64_t S,
+                                           bool learned) {
+    std::vector<Shape> out;
+    std::vector<std::pair<int, int64_t>> seen;     // (block size, waves)
+    for (int bs : SHAPE_BS)
+        for (int bpc : {1, 2, 3, 4, 6, 8})
+            for (int tpw : {1, 4, 16}) {
+                const Shape sh{bs, bpc, tpw};
+                const void *fn = kind == 0 ? k1_kernel(ctx->preset, learned, bs) : k3_kernel(bs);
+                const Launch L = make_launch(ctx, sh, fn, n, S);
+                bool dup = false;
+                for (auto &q : seen) dup = dup || (q.first == bs && q.second == L.waves);
+                if (dup) continue;
+                seen.push_back({bs, L.waves});
+                out.push_back(sh);
+            }
+    return out;
 }
 
 int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
@@ -1119,52 +1275,82 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
         S = 1;
     }
     hipStream_t st = (hipStream_t)stream;
-    Plan p;
-    int rc = prepare(ctx, n_total, S, st, &p);
-    if (rc) return rc;
+    HIPCHECK(hipSetDevice(ctx->device));
+    const int b = bucket_of(n_total, S);
     const int64_t n1 = batched ? 0 : n_total;
-    if ((rc = run_tilemap(ctx, p, st, x, offsets, n1, S))) return rc;
+    const auto c1 = shape_candidates(ctx, 0, n_total, S, false);
+    const auto c3 = shape_candidates(ctx, 1, n_total, S, false);
+    // one workspace for every candidate: only the region counts at the
+    // plan's end depend on the discard pass's waves
+    int64_t wmax = 1;
+    for (const Shape &sh : c3) wmax = std::max(wmax, make_launch(ctx, sh, k3_kernel(sh.bs), n_total, S).waves);
+    Plan big = make_plan(n_total, S, wmax);
+    int rc = ensure_ws(ctx, big.total, st);
+    if (rc) return rc;
+    big.base = ctx->ws;
     const bool was_timing = ctx->timing;
     ctx->timing = false;
-    hipEvent_t a, b;
-    HIPCHECK(hipEventCreate(&a));
-    HIPCHECK(hipEventCreate(&b));
-    const int cand[] = {1, 2, 3, 4, 6, 8};
-    float best1 = 1e30f, best3 = 1e30f;
-    int b1 = ctx->k1_bpc, b3 = ctx->k3_bpc;
-    uint32_t *surv = W<uint32_t>(p, p.surv);
-    int64_t *so = W<int64_t>(p, p.surv_off);
-    for (int c : cand) {
-        ctx->k1_bpc = c;
-        ctx->k3_bpc = c;
-        float t1 = 0, t3 = 0;
+    hipEvent_t ea, eb;
+    HIPCHECK(hipEventCreate(&ea));
+    HIPCHECK(hipEventCreate(&eb));
+    auto timed = [&](auto &&fn, float *best_ms) -> int {
+        float tot = 0;
         for (int rep = 0; rep < 3; rep++) {
-            HIPCHECK(hipEventRecord(a, st));
-            if ((rc = run_extremes(ctx, p, st, x, y, n_total, offsets, n1, S, false))) break;
-            HIPCHECK(hipEventRecord(b, st));
-            HIPCHECK(hipEventSynchronize(b));
+            HIPCHECK(hipEventRecord(ea, st));
+            int r = fn();
+            if (r) return r;
+            HIPCHECK(hipEventRecord(eb, st));
+            HIPCHECK(hipEventSynchronize(eb));
             float ms = 0;
-            HIPCHECK(hipEventElapsedTime(&ms, a, b));
-            if (rep) t1 += ms;
-            if ((rc = run_polygon(ctx, p, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr))) break;
-            HIPCHECK(hipEventRecord(a, st));
-            if ((rc = run_discard(ctx, p, st, x, y, n_total, offsets, n1, S, slot_count(ctx, false), surv, so,
-                                  nullptr)))
-                break;
-            HIPCHECK(hipEventRecord(b, st));
-            HIPCHECK(hipEventSynchronize(b));
-            HIPCHECK(hipEventElapsedTime(&ms, a, b));
-            if (rep) t3 += ms;
+            HIPCHECK(hipEventElapsedTime(&ms, ea, eb));
+            if (rep) tot += ms;
         }
-        if (rc) break;
-        if (t1 < best1) { best1 = t1; b1 = c; }
-        if (t3 < best3) { best3 = t3; b3 = c; }
+        *best_ms = tot;
+        return HULL_OK;
+    };
+    const bool had1 = ctx->has_tuned[0][b], had3 = ctx->has_tuned[1][b];
+    const Shape old1 = ctx->tuned[0][b], old3 = ctx->tuned[1][b];
+    Shape best1 = shape_of(ctx, 0, n_total, S), best3 = shape_of(ctx, 1, n_total, S);
+    float t1 = 1e30f, t3 = 1e30f;
+    rc = run_tilemap(ctx, big, st, x, offsets, n1, S);
+    for (size_t i = 0; !rc && i < c1.size(); i++) {
+        ctx->tuned[0][b] = c1[i];
+        ctx->has_tuned[0][b] = true;
+        float ms = 0;
+        rc = timed([&]() { return run_extremes(ctx, big, st, x, y, n_total, offsets, n1, S, false); }, &ms);
+        if (!rc && ms < t1) { t1 = ms; best1 = c1[i]; }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    ctx->tuned[0][b] = best1;
+    ctx->has_tuned[0][b] = true;
+    // the full method's discard pass (refinement round 0 included) on the
+    // polygon of the best extremes shape
+    if (!rc) rc = run_extremes(ctx, big, st, x, y, n_total, offsets, n1, S, false);
+    if (!rc) rc = run_polygon(ctx, big, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr, true);
+    for (size_t i = 0; !rc && i < c3.size(); i++) {
+        ctx->tuned[1][b] = c3[i];
+        ctx->has_tuned[1][b] = true;
+        Plan pc = make_plan(n_total, S, k3_launch(ctx, n_total, S).waves);
+        pc.base = ctx->ws;
+        float ms = 0;
+        rc = timed([&]() {
+            return run_discard_append(ctx, pc, st, x, y, n_total, offsets, n1, S, slot_count(ctx, false),
+                                      W<uint32_t>(pc, pc.surv), W<uint64_t>(pc, pc.keys0),
+                                      W<uint16_t>(pc, pc.up0), W<int64_t>(pc, pc.segcnt),
+                                      W<unsigned long long>(pc, pc.rfar0));
+        }, &ms);
+        if (!rc && ms < t3) { t3 = ms; best3 = c3[i]; }
+    }
+    ctx->tuned[1][b] = best3;
+    ctx->has_tuned[1][b] = true;
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
     ctx->timing = was_timing;
-    ctx->k1_bpc = b1;
-    ctx->k3_bpc = b3;
+    if (rc) {   // keep the table as it was
+        ctx->tuned[0][b] = old1;
+        ctx->has_tuned[0][b] = had1;
+        ctx->tuned[1][b] = old3;
+        ctx->has_tuned[1][b] = had3;
+    }
     return rc;
 }
 
@@ -1501,3 +1687,4 @@ int hull_label_targets_batched(hull_ctx *ctx, const float *x, const float *y,
 }  // extern "C"
 
 #include "hull_stream.hip"
+#include "hull3d_host.hip"

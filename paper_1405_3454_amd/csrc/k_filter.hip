@@ -335,8 +335,8 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 // the set's first point o0: a copy never beats a genuine extreme, and if the
 // run's extreme is only met by copies, the run reports (key(o0), o0), a
 // genuine pair of the set.
-template <int PRESET, int NDIR>
-__global__ __launch_bounds__(256) void k_extremes(
+template <int PRESET, int NDIR, int BS = 256>
+__global__ __launch_bounds__(BS) void k_extremes(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int phase,
     const int64_t *__restrict__ off, int64_t n1, int64_t S,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ tile_set, Dirs dirs,
@@ -1115,8 +1115,8 @@ __device__ __forceinline__ uint32_t row0_sum_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
 }
 
-template <int NEDGE, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_discard(
+template <int NEDGE, int MODE, int BS = 256>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_discard(
     const float *__restrict__ x, const float *__restrict__ y, int64_t n_total, int phase,
     const int64_t *__restrict__ off, int64_t n1, int64_t S, const int64_t *__restrict__ tile_off,
     const int32_t *__restrict__ tile_set, const Poly *__restrict__ polys,
@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ surv,
     uint64_t *__restrict__ keys, uint16_t *__restrict__ edges, int64_t *__restrict__ seg_cnt,
     int64_t *__restrict__ seg_meta, unsigned long long *__restrict__ gfar) {
-    __shared__ DiscardLds lds[4];
+    __shared__ DiscardLds lds[BS / WAVE];
     DiscardLds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;

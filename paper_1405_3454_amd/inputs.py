@@ -173,6 +173,109 @@ DISTRIBUTIONS = {
 }
 
 
+# ---------------------------------------------------------------------------
+# Three dimensions (the 3D form of the method): three float32 arrays on the
+# grid of [0, 1)^3.
+
+def cube3(n, seed):
+    """Uniform in the unit cube."""
+    r = _rng(seed)
+    k = r.integers(0, GRID, size=(3, n), dtype=np.int32)
+    return to_float(k[0]), to_float(k[1]), to_float(k[2])
+
+
+def _reject3(n, seed, accept, factor):
+    r = _rng(seed)
+    out = np.empty((3, n), np.int32)
+    got = 0
+    while got < n:
+        m = max(1024, int((n - got) * factor) + 1024)
+        k = r.integers(0, GRID, size=(3, m), dtype=np.int32)
+        d = k.astype(np.int64) - HALF
+        ok = accept(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+        k = k[:, ok]
+        t = min(k.shape[1], n - got)
+        out[:, got:got + t] = k[:, :t]
+        got += t
+    return to_float(out[0]), to_float(out[1]), to_float(out[2])
+
+
+def ball3(n, seed):
+    """Uniform in the ball of radius 1/2 about the cube's centre (integer
+    rejection: |k - 2^23|^2 < 2^46)."""
+    return _reject3(n, seed, lambda d2: d2 < (1 << 46), 2.0)
+
+
+def shell3(n, seed):
+    """Uniform in the spherical shell 0.45 <= r < 0.5 (integer rejection)."""
+    lo = int(np.ceil(0.2025 * float(1 << 48)))
+    return _reject3(n, seed, lambda d2: (d2 < (1 << 46)) & (d2 >= lo), 8.0)
+
+
+def gaussian3(n, seed, sigma=0.15):
+    """3D normal about the centre, sigma 0.15, resampled into the cube."""
+    r = _rng(seed)
+    out = np.empty((3, n), np.int64)
+    got = 0
+    while got < n:
+        m = max(1024, int((n - got) * 1.2) + 1024)
+        v = 0.5 + sigma * r.standard_normal(size=(3, m))
+        ok = np.all((v >= 0.0) & (v < 1.0), axis=0)
+        v = v[:, ok]
+        t = min(v.shape[1], n - got)
+        out[:, got:got + t] = np.floor(v[:, :t] * GRID).astype(np.int64)
+        got += t
+    return to_float(out[0]), to_float(out[1]), to_float(out[2])
+
+
+def lattice3(n, side, seed, offset=0):
+    """n points of a side^3 integer lattice (duplicates, coplanar and
+    collinear points), offset by `offset` grid units."""
+    r = _rng(seed)
+    k = r.integers(0, side, size=(3, n)) + offset
+    return to_float(k[0]), to_float(k[1]), to_float(k[2])
+
+
+DISTRIBUTIONS3 = {"cube": cube3, "ball": ball3, "shell": shell3, "gaussian": gaussian3}
+
+
+def set3_torch(kind, n, seed, device="cuda:0"):
+    """One 3D set drawn on the device (cube, ball, shell, gaussian)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    if kind == "gaussian":
+        out = []
+        got = 0
+        while got < n:
+            v = 0.5 + 0.15 * torch.randn((3, int((n - got) * 1.2) + 1024), generator=g, device=device,
+                                         dtype=torch.float64)
+            v = v[:, ((v >= 0) & (v < 1)).all(0)]
+            out.append(v[:, : n - got])
+            got += out[-1].shape[1]
+        k = torch.floor(torch.cat(out, 1) * GRID).to(torch.int64)
+    else:
+        factor = {"cube": 1.0, "ball": 2.0, "shell": 8.0}[kind]
+        lo = int(np.ceil(0.2025 * float(1 << 48)))
+        out = []
+        got = 0
+        while got < n:
+            k = torch.randint(0, GRID, (3, int((n - got) * factor) + 1024), generator=g, device=device,
+                              dtype=torch.int64)
+            if kind != "cube":
+                d = k - HALF
+                d2 = (d * d).sum(0)
+                ok = d2 < (1 << 46)
+                if kind == "shell":
+                    ok &= d2 >= lo
+                k = k[:, ok]
+            out.append(k[:, : n - got])
+            got += out[-1].shape[1]
+        k = torch.cat(out, 1)
+    f = k.to(torch.float32) * float(_SCALE)
+    return f[0].clone(), f[1].clone(), f[2].clone()
+
+
 def regular_polygon(m, n_interior, seed, radius=0.4, phase_deg=0.0):
     """Vertices of a regular m-gon (radius 0.4 about (1/2, 1/2), vertex j at
     phase + 360 j / m degrees, rounded to the grid) followed by n_interior
