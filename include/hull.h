@@ -200,6 +200,36 @@ int hull_compute_host(hull_ctx *ctx, const float *x, const float *y, int64_t n,
                       uint32_t *surv, int64_t *n_surv, int64_t cap, uint32_t *hull,
                       int64_t *h, int flags, void *stream);
 
+/* ---- three dimensions (the extension the paper's Sec. 5 names) ---------
+ * The method for one set of points x[n], y[n], z[n] (device float32 on the
+ * 2^-24 grid of [0,1)^3, each array 16-byte aligned):
+ *  Step 1: extremes along rotations about each axis: for each rotation group
+ *    (c, s) of the context's preset (the paper's two four-group tables only;
+ *    other presets: HULL_EINVAL) and each plane (a, b) = (x, y), (y, z),
+ *    (z, x) -- rotations about z, x and y -- the extremes of u = c*a - s*b and
+ *    v = s*a + c*b (products rounded to binary64, then the sum), and of the
+ *    axis coordinate itself: six per rotation.  The 42 distinct slots:
+ *    [0..5] argmin/argmax of x, y, z; then 6 + 4 (3 k + g - 1) +
+ *    {argmin u, argmax u, argmin v, argmax v} for plane k = 0, 1, 2 and
+ *    group g = 1..3; lowest index on ties.
+ *  Step 2: the convex polyhedron of the slot points (exact predicates).
+ *  Step 3: every point strictly inside it is discarded; boundary points
+ *    survive; a polyhedron without interior discards nothing.
+ *  Step 4: the extreme points of the survivors (vertices of their convex
+ *    hull; points on an edge or a face that are not corners excluded; a
+ *    repeated coordinate triple named by its lowest index).
+ * slots: device uint32[42] or NULL; surv: device uint32[n] (survivors in
+ * ascending order) or NULL; *n_surv: device int64 or NULL; hull: device
+ * uint32[n], the extreme points in ascending index order; *h: device int64.
+ * flags: 0 or HULL_NOFILTER (hull of all points).  Synchronises (the hull
+ * stage sizes itself from the survivor count and runs in rounds).
+ * Errors: HULL_EINVAL (null output, misaligned input, bad flags or preset),
+ * HULL_ETOOBIG, HULL_ENOMEM, HULL_EHIP. */
+#define HULL3_SLOTS 42
+int hull3_compute(hull_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
+                  uint32_t *slots, uint32_t *surv, int64_t *n_surv, uint32_t *hull, int64_t *h,
+                  int flags, void *stream);
+
 /* ---- batched forms (many sets, CSR offsets) ----------------------------
  * offsets: device int64[S+1], non-decreasing, offsets[0] = 0,
  * offsets[S] = n_total (checked with HULL_VALIDATE).  Set s is points
