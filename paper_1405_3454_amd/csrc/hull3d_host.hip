@@ -101,6 +101,7 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
         const size_t b_ca = tb(nc * 4 + 16), b_cb = tb(nc * 4 + 16), b_fa = tb(nc * 4 + 16),
                      b_fb = tb(nc * 4 + 16), b_faces = tb(fcap * sizeof(Face3)),
                      b_planes = tb(fcap * sizeof(Plane3)), b_far = tb(fcap * 8), b_vis = tb(fcap * 4),
+                     b_repl = tb(fcap * sizeof(int2)),
                      b_corner = tb(nc * 8 + 16), b_ncorner = tb(16);
         if ((rc = grow(&B->b, &B->bcap, ob))) return rc;
         char *hb = B->b;
@@ -110,6 +111,7 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
         Plane3 *planes = reinterpret_cast<Plane3 *>(hb + b_planes);
         unsigned long long *far = reinterpret_cast<unsigned long long *>(hb + b_far);
         int *vis = reinterpret_cast<int *>(hb + b_vis);
+        int2 *repl = reinterpret_cast<int2 *>(hb + b_repl);
         uint64_t *corner = reinterpret_cast<uint64_t *>(hb + b_corner);
         int *ncorner = reinterpret_cast<int *>(hb + b_ncorner);
         if (nc > 0)
@@ -151,8 +153,10 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
             bool overflow = false;
             for (int round = 0;; round++) {
                 LAUNCH(K_REFINE, k3_assign<<<gs, 256, 0, st>>>(x, y, z, cand[cur], cf[cur], cand[1 - cur],
-                                                               cf[1 - cur], C, faces, planes, far, round == 0));
-                LAUNCH(K_REFINE_SPLIT, k3_insert<<<1, INS_THREADS, 0, st>>>(x, y, z, C, faces, planes, far, vis));
+                                                               cf[1 - cur], C, faces, planes, repl, far,
+                                                               round == 0));
+                LAUNCH(K_REFINE_SPLIT, k3_insert<<<1, INS_THREADS, 0, st>>>(x, y, z, C, faces, planes, far, vis,
+                                                                             repl));
                 HIPCHECK(hipMemcpyAsync(&hc, C, sizeof(hc), hipMemcpyDeviceToHost, st));
                 HIPCHECK(hipStreamSynchronize(st));
                 cur = 1 - cur;

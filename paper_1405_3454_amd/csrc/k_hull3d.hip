@@ -600,34 +600,53 @@ __global__ void k3_start(const float *__restrict__ x, const float *__restrict__ 
 }
 
 // A round's assignment (see above).  first: every candidate tests the start
-// faces.
+// faces.  A candidate whose face was removed follows the removals: the
+// insertion that removed a face created faces repl[f] = (first, count); the
+// candidate is beyond one of them (then it moves there, and on if that one
+// was removed too) or inside the hull that insertion made (then it drops).
+constexpr int CHAIN_MAX = 256;      // chain steps before a full scan
+
 __global__ __launch_bounds__(256) void k3_assign(const float *__restrict__ x, const float *__restrict__ y,
                                                  const float *__restrict__ z, const uint32_t *__restrict__ cin,
                                                  const int *__restrict__ fin, uint32_t *__restrict__ cout,
                                                  int *__restrict__ fout, Hull3Ctl *__restrict__ C,
                                                  const Face3 *__restrict__ faces,
-                                                 const Plane3 *__restrict__ planes,
+                                                 const Plane3 *__restrict__ planes, const int2 *__restrict__ repl,
                                                  unsigned long long *__restrict__ far, int first) {
     const int64_t nc = C->ncand;
-    const int lo = first ? 0 : C->born_lo, hi = C->nfaces;
+    const int nfaces = C->nfaces;
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < nc; t += int64_t(gridDim.x) * blockDim.x) {
         const uint32_t i = cin[t];
         const double px = pdx(x, i), py = pdx(y, i), pz = pdx(z, i);
-        int f = first ? -1 : fin[t];
+        int f = -1;
         double d = 0;
-        if (f >= 0 && faces[f].alive) {
-            d = plane_dist(planes[f], px, py, pz);
-        } else {
-            f = -1;
+        auto best_of = [&](int lo, int hi, bool alive_only) {
+            int bf = -1;
+            double bd = 0;
             for (int g = lo; g < hi; g++) {
-                if (!faces[g].alive) continue;
+                if (alive_only && !faces[g].alive) continue;
                 if (plane_sign(planes[g], px, py, pz) > 0) {
                     const double dg = plane_dist(planes[g], px, py, pz);
-                    if (f < 0 || dg > d) { f = g; d = dg; }
+                    if (bf < 0 || dg > bd) { bf = g; bd = dg; }
                 }
             }
+            return bf;
+        };
+        if (first) {
+            f = best_of(0, nfaces, true);
+        } else {
+            int g = fin[t];
+            int steps = 0;
+            while (g >= 0 && !faces[g].alive && steps < CHAIN_MAX) {
+                const int2 r = repl[g];
+                g = best_of(r.x, r.x + r.y, false);
+                steps++;
+            }
+            if (g >= 0 && !faces[g].alive) g = best_of(0, nfaces, true);   // chain too long
+            f = g;
         }
         if (f < 0) continue;
+        d = plane_dist(planes[f], px, py, pz);
         const int o = atomicAdd(&C->nout, 1);
         cout[o] = i;
         fout[o] = f;
@@ -637,23 +656,32 @@ __global__ __launch_bounds__(256) void k3_assign(const float *__restrict__ x, co
 }
 
 constexpr int INS_THREADS = 1024;
-constexpr int INS_LIST = 4096;      // points inserted per round at most
-constexpr int HZ_CAP = 4096;        // horizon edges of one insertion
+constexpr int INS_LIST = 2048;      // points inserted per round at most
+constexpr int HZ_CAP = 2048;        // horizon edges of one insertion
+constexpr int VIS_CAP = 2048;       // faces one insertion removes
 
-// A round's insertions, one block: each face's farthest candidate.
+// A round's insertions, one block: each face's farthest candidate q, in turn.
+// The faces q sees are found from the face it was assigned to, which it
+// sees while that face lives (else q waits for the next round), by a
+// breadth-first walk over neighbours: the faces a point sees form one
+// connected patch whose border is the horizon.
 __global__ __launch_bounds__(INS_THREADS) void k3_insert(const float *__restrict__ x, const float *__restrict__ y,
                                                          const float *__restrict__ z, Hull3Ctl *__restrict__ C,
                                                          Face3 *__restrict__ faces, Plane3 *__restrict__ planes,
                                                          unsigned long long *__restrict__ far,
-                                                         int *__restrict__ vis) {
+                                                         int *__restrict__ vis, int2 *__restrict__ repl) {
     __shared__ uint32_t list[INS_LIST];
-    __shared__ int nl, nvis, nh, nf0, stop, bad;
+    __shared__ int lface[INS_LIST];
+    __shared__ int nl, nh, nv, nf0, bad, over;
+    __shared__ int fr_n[2];
     __shared__ int hz_f[HZ_CAP], hz_e[HZ_CAP];
+    __shared__ int vlist[VIS_CAP];
+    __shared__ int front[2][VIS_CAP];
     const int tid = threadIdx.x;
     if (tid == 0) {
         nl = 0;
-        stop = 0;
         bad = 0;
+        over = 0;
         nf0 = C->nfaces;
         C->inserted = 0;
         C->ncand = C->nout;     // the assignment's output is the next input
@@ -665,7 +693,7 @@ __global__ __launch_bounds__(INS_THREADS) void k3_insert(const float *__restrict
         const unsigned long long k = far[f];
         if (k && faces[f].alive) {
             const int s = atomicAdd(&nl, 1);
-            if (s < INS_LIST) list[s] = ~(uint32_t)k;
+            if (s < INS_LIST) { list[s] = ~(uint32_t)k; lface[s] = f; }
         }
         far[f] = 0;
     }
@@ -674,37 +702,54 @@ __global__ __launch_bounds__(INS_THREADS) void k3_insert(const float *__restrict
     int inserted = 0;
     for (int li = 0; li < L; li++) {
         const uint32_t q = list[li];
+        const int fq = lface[li];
+        if (!faces[fq].alive) continue;      // removed by an earlier insertion: next round
         const double qx = pdx(x, q), qy = pdx(y, q), qz = pdx(z, q);
-        if (tid == 0) { nvis = 0; nh = 0; }
-        __syncthreads();
+        const int tag = (int)q;              // faces seen by q carry its index
         const int F = C->nfaces;
-        const int tag = (int)q;     // faces seen by q carry its index
-        for (int f = tid; f < F; f += blockDim.x) {
-            if (faces[f].alive && plane_sign(planes[f], qx, qy, qz) > 0) {
-                vis[f] = tag;
-                atomicAdd(&nvis, 1);
-            } else if (vis[f] == tag) {
-                vis[f] = -1;        // a stale mark from an earlier round
-            }
+        if (tid == 0) {
+            nh = 0;
+            nv = 1;
+            vlist[0] = fq;
+            vis[fq] = tag;
+            front[0][0] = fq;
+            fr_n[0] = 1;
+            fr_n[1] = 0;
         }
         __syncthreads();
-        const int nv = nvis;
-        __syncthreads();      // every thread has read nvis before thread 0 resets it
-        if (nv == 0) continue;
-        for (int f = tid; f < F; f += blockDim.x) {
-            if (vis[f] != tag || !faces[f].alive) continue;
-            for (int e = 0; e < 3; e++) {
+        int cur = 0;
+        for (;;) {
+            const int nfr = fr_n[cur];
+            __syncthreads();
+            if (nfr == 0 || over) break;
+            if (tid == 0) fr_n[1 - cur] = 0;
+            __syncthreads();
+            for (int w = tid; w < 3 * nfr; w += blockDim.x) {
+                const int f = front[cur][w / 3], e = w % 3;
                 const int g = faces[f].nb[e];
-                if (vis[g] != tag || !faces[g].alive) {
+                const int old = vis[g];
+                if (old == tag) continue;
+                if (plane_sign(planes[g], qx, qy, qz) > 0) {
+                    if (atomicCAS(&vis[g], old, tag) == old) {
+                        const int sv = atomicAdd(&nv, 1), sf = atomicAdd(&fr_n[1 - cur], 1);
+                        if (sv < VIS_CAP && sf < VIS_CAP) {
+                            vlist[sv] = g;
+                            front[1 - cur][sf] = g;
+                        } else {
+                            over = 1;
+                        }
+                    }
+                } else {
                     const int h = atomicAdd(&nh, 1);
-                    if (h < HZ_CAP) { hz_f[h] = f; hz_e[h] = e; }
+                    if (h < HZ_CAP) { hz_f[h] = f; hz_e[h] = e; } else over = 1;
                 }
             }
+            __syncthreads();
+            cur = 1 - cur;
         }
-        __syncthreads();
-        const int H = nh;
-        if (H > HZ_CAP || F + H > C->fcap) {
-            if (tid == 0) { C->overflow = 1; stop = 1; }
+        const int H = nh, NV = nv;
+        if (over || F + H > C->fcap) {
+            if (tid == 0) C->overflow = 1;
             __syncthreads();
             break;
         }
@@ -747,8 +792,11 @@ __global__ __launch_bounds__(INS_THREADS) void k3_insert(const float *__restrict
                 if (faces[g].v[e2] == b && faces[g].v[(e2 + 1) % 3] == a) faces[g].nb[e2] = F + h;
         }
         __syncthreads();
-        for (int f = tid; f < F; f += blockDim.x)
-            if (vis[f] == tag) faces[f].alive = 0;
+        for (int k = tid; k < NV; k += blockDim.x) {
+            const int f = vlist[k];
+            faces[f].alive = 0;
+            repl[f] = make_int2(F, H);
+        }
         if (tid == 0) C->nfaces = F + H;
         inserted++;
         __syncthreads();
