@@ -221,11 +221,18 @@ int hull_compute_host(hull_ctx *ctx, const float *x, const float *y, int64_t n,
  * slots: device uint32[42] or NULL; surv: device uint32[n] (survivors in
  * ascending order) or NULL; *n_surv: device int64 or NULL; hull: device
  * uint32[n], the extreme points in ascending index order; *h: device int64.
- * flags: 0 or HULL_NOFILTER (hull of all points).  Synchronises (the hull
- * stage sizes itself from the survivor count and runs in rounds).
+ * The hull stage runs in rounds: every face's farthest candidate is
+ * proposed, and the proposals whose faces seen and horizon neighbours no
+ * higher proposal claims are inserted together; with HULL3_SERIAL one block
+ * inserts every face's farthest candidate in turn instead (the same result;
+ * a slower form kept for checking and for proposals that see more than 512
+ * faces, which the parallel rounds hand to it).
+ * flags: 0, HULL_NOFILTER (hull of all points), HULL3_SERIAL.  Synchronises
+ * (the hull stage sizes itself from the survivor count).
  * Errors: HULL_EINVAL (null output, misaligned input, bad flags or preset),
  * HULL_ETOOBIG, HULL_ENOMEM, HULL_EHIP. */
 #define HULL3_SLOTS 42
+#define HULL3_SERIAL 16 /* hull stage: one insertion at a time, one block */
 int hull3_compute(hull_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
                   uint32_t *slots, uint32_t *surv, int64_t *n_surv, uint32_t *hull, int64_t *h,
                   int flags, void *stream);

@@ -17,6 +17,7 @@ HULL_ENOMODEL = -7
 HULL_ESCRATCH = -8
 HULL_EOVERFLOW = -9
 HULL_NOALLOC_MAX_POINTS = 1 << 27
+HULL_NOALLOC_SCRATCH_BYTES = 40 << 20
 
 HULL_DIRS_PAPER = 0
 HULL_DIRS_CUMULATIVE = 1
@@ -37,7 +38,11 @@ HULL_VALIDATE = 4
 HULL_NOREFINE = 8
 
 HULL_NONE = 0xFFFFFFFF
+HULL_NCOUNTS = 5
+HULL_FIXED_SLOTS = 16
+HULL_MAX_SLOTS = 24
 HULL3_SLOTS = 42
+HULL3_SERIAL = 16
 
 P = ctypes.c_void_p
 I = ctypes.c_int

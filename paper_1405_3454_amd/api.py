@@ -216,10 +216,11 @@ class Hull:
         return slots, surv[: int(ns.item())], hull[: int(h.item())]
 
     # -- three dimensions -------------------------------------------------
-    def compute3(self, x, y, z, nofilter=False, stream=None):
+    def compute3(self, x, y, z, nofilter=False, serial=False, stream=None):
         """The 3D method on device float32 x, y, z (16-byte aligned): returns
         (slots [42], survivors ascending, extreme points ascending) as int32
-        device tensors.  Synchronises."""
+        device tensors.  serial: the hull stage inserts one point at a time
+        in one block.  Synchronises."""
         n = _pts(x, y)
         if z.dtype != torch.float32 or not z.is_cuda or z.shape != x.shape or not z.is_contiguous():
             raise ValueError("z must be a contiguous float32 device tensor like x")
@@ -230,7 +231,8 @@ class Hull:
         ns = torch.zeros(1, dtype=torch.int64, device=dev)
         h = torch.zeros(1, dtype=torch.int64, device=dev)
         check(lib().hull3_compute(self._h, _ptr(x), _ptr(y), _ptr(z), n, _ptr(slots), _ptr(surv),
-                                  _ptr(ns), _ptr(hull), _ptr(h), HULL_NOFILTER if nofilter else 0,
+                                  _ptr(ns), _ptr(hull), _ptr(h),
+                                  (HULL_NOFILTER if nofilter else 0) | (_lib.HULL3_SERIAL if serial else 0),
                                   _stream(stream)), "hull3_compute")
         return slots, surv[: int(ns.item())], hull[: int(h.item())]
 

@@ -35,7 +35,7 @@ static int grow(char **p, size_t *cap, size_t want) {
 extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, const float *z, int64_t n,
                              uint32_t *slots, uint32_t *surv, int64_t *n_surv, uint32_t *hull,
                              int64_t *h, int flags, void *stream) {
-    if (!ctx || !hull || !h || n < 0 || (flags & ~HULL_NOFILTER)) return HULL_EINVAL;
+    if (!ctx || !hull || !h || n < 0 || (flags & ~(HULL_NOFILTER | HULL3_SERIAL))) return HULL_EINVAL;
     if (n >= (int64_t(1) << 32) - 1) return HULL_ETOOBIG;
     if (n > 0 && (!x || !y || !z)) return HULL_EINVAL;
     if (((uintptr_t)x | (uintptr_t)y | (uintptr_t)z) & 15) return HULL_EINVAL;
@@ -98,15 +98,23 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
     for (int64_t fcap = std::min<int64_t>(8 * nc + 1024, int64_t(1) << 24);; fcap *= 2) {
         size_t ob = 0;
         auto tb = [&](size_t bytes) { size_t r = ob; ob += al(bytes); return r; };
-        const size_t b_ca = tb(nc * 4 + 16), b_cb = tb(nc * 4 + 16), b_fa = tb(nc * 4 + 16),
-                     b_fb = tb(nc * 4 + 16), b_faces = tb(fcap * sizeof(Face3)),
+        const size_t b_idx = tb(nc * 4 + 16), b_ca = tb(nc * 16 + 16), b_cb = tb(nc * 16 + 16),
+                     b_fa = tb(nc * 4 + 16), b_fb = tb(nc * 4 + 16), b_faces = tb(fcap * sizeof(Face3)),
                      b_planes = tb(fcap * sizeof(Plane3)), b_far = tb(fcap * 8), b_vis = tb(fcap * 4),
-                     b_repl = tb(fcap * sizeof(int2)),
+                     b_repl = tb(fcap * sizeof(int2)), b_claim = tb(fcap * 8),
+                     b_pairs = tb(PAIR_CAP * sizeof(Pair3)), b_pn = tb(PAIR_CAP * sizeof(int2)),
+                     b_pv = tb((size_t)PAIR_CAP * PV_CAP * 4), b_ph = tb((size_t)PAIR_CAP * PV_CAP * 4),
                      b_corner = tb(nc * 8 + 16), b_ncorner = tb(16);
         if ((rc = grow(&B->b, &B->bcap, ob))) return rc;
         char *hb = B->b;
-        uint32_t *cand[2] = {reinterpret_cast<uint32_t *>(hb + b_ca), reinterpret_cast<uint32_t *>(hb + b_cb)};
+        uint32_t *cidx = reinterpret_cast<uint32_t *>(hb + b_idx);
+        float4 *cand[2] = {reinterpret_cast<float4 *>(hb + b_ca), reinterpret_cast<float4 *>(hb + b_cb)};
         int *cf[2] = {reinterpret_cast<int *>(hb + b_fa), reinterpret_cast<int *>(hb + b_fb)};
+        unsigned long long *claim = reinterpret_cast<unsigned long long *>(hb + b_claim);
+        Pair3 *pairs = reinterpret_cast<Pair3 *>(hb + b_pairs);
+        int2 *pn = reinterpret_cast<int2 *>(hb + b_pn);
+        int *pvis = reinterpret_cast<int *>(hb + b_pv);
+        int *phz = reinterpret_cast<int *>(hb + b_ph);
         Face3 *faces = reinterpret_cast<Face3 *>(hb + b_faces);
         Plane3 *planes = reinterpret_cast<Plane3 *>(hb + b_planes);
         unsigned long long *far = reinterpret_cast<unsigned long long *>(hb + b_far);
@@ -115,18 +123,18 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
         uint64_t *corner = reinterpret_cast<uint64_t *>(hb + b_corner);
         int *ncorner = reinterpret_cast<int *>(hb + b_ncorner);
         if (nc > 0)
-            HIPCHECK(hipMemcpyAsync(cand[0], sv, nc * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHECK(hipMemcpyAsync(cidx, sv, nc * 4, hipMemcpyDeviceToDevice, st));
         LAUNCH(K_MISC, k3_ctl_init<<<1, 64, 0, st>>>(C, (int)fcap));
         const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 4, (nc + 255) / 256));
         for (int phase = 1; phase <= 3; phase++)
-            LAUNCH(K_MISC, k3_seed<<<gs, 256, 0, st>>>(x, y, z, cand[0], nc, phase, C));
-        LAUNCH(K_MISC, k3_start<<<1, 64, 0, st>>>(x, y, z, cand[0], nc, C, faces, planes, far));
+            LAUNCH(K_MISC, k3_seed<<<gs, 256, 0, st>>>(x, y, z, cidx, nc, phase, C));
+        LAUNCH(K_MISC, k3_start<<<1, 64, 0, st>>>(x, y, z, cidx, nc, C, faces, planes, far));
         Hull3Ctl hc;
         HIPCHECK(hipMemcpyAsync(&hc, C, sizeof(hc), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
         if (hc.state == 2) {
-            LAUNCH(K_MISC, k3_line<<<gs, 256, 0, st>>>(x, y, z, cand[0], nc, 0, C));
-            LAUNCH(K_MISC, k3_line<<<gs, 256, 0, st>>>(x, y, z, cand[0], nc, 1, C));
+            LAUNCH(K_MISC, k3_line<<<gs, 256, 0, st>>>(x, y, z, cidx, nc, 0, C));
+            LAUNCH(K_MISC, k3_line<<<gs, 256, 0, st>>>(x, y, z, cidx, nc, 1, C));
         }
         if (hc.state >= 2) {
             LAUNCH(K_MISC, k3_small_out<<<1, 64, 0, st>>>(C, hull, h));
@@ -139,31 +147,47 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
         if (hc.state == 1) {
             // flat: the 2D hull of the coordinates kept in the plane
             uint64_t *keys = W<uint64_t>(ph, ph.keys0);
-            LAUNCH(K_KEYS, k3_flat_keys<<<gs, 256, 0, st>>>(x, y, z, cand[0], nc, C, keys));
+            LAUNCH(K_KEYS, k3_flat_keys<<<gs, 256, 0, st>>>(x, y, z, cidx, nc, C, keys));
             LAUNCH(K_MISC, k_fill_i64<<<1, 64, 0, st>>>(scount, 1, nc));
             uint32_t *h2 = W<uint32_t>(ph, ph.cidx);
             int64_t *hoff = W<int64_t>(ph, ph.hoff);
-            if ((rc = run_hull(ctx, ph, st, cand[0], keys, scount, std::max<int64_t>(nc, 1), 1, hoff, h2,
+            if ((rc = run_hull(ctx, ph, st, cidx, keys, scount, std::max<int64_t>(nc, 1), 1, hoff, h2,
                                hcount)))
                 return rc;
             LAUNCH(K_MISC, k3_u64_of<<<256, 256, 0, st>>>(h2, hcount, corner));
         } else {
             LAUNCH(K_MISC, k3_fill_i32<<<256, 256, 0, st>>>(vis, fcap, -1));
+            LAUNCH(K_MISC, k_fill_i64<<<256, 256, 0, st>>>(reinterpret_cast<int64_t *>(claim), fcap, 0));
+            LAUNCH(K_MISC, k3_gather<<<gs, 256, 0, st>>>(x, y, z, cidx, nc, cand[0]));
+            const unsigned gp = (unsigned)(ctx->cus * 4), gv = (unsigned)(ctx->cus * 16);
             int cur = 0;
-            bool overflow = false;
+            const bool all_serial = flags & HULL3_SERIAL;
+            bool overflow = false, serial = all_serial;
             for (int round = 0;; round++) {
-                LAUNCH(K_REFINE, k3_assign<<<gs, 256, 0, st>>>(x, y, z, cand[cur], cf[cur], cand[1 - cur],
-                                                               cf[1 - cur], C, faces, planes, repl, far,
-                                                               round == 0));
-                LAUNCH(K_REFINE_SPLIT, k3_insert<<<1, INS_THREADS, 0, st>>>(x, y, z, C, faces, planes, far, vis,
-                                                                             repl));
+                LAUNCH(K_REFINE, k3_assign<<<gs, 256, 0, st>>>(cand[cur], cf[cur], cand[1 - cur], cf[1 - cur], C,
+                                                               faces, planes, repl, far, round == 0));
+                if (serial) {
+                    // one block inserts every face's farthest candidate in turn
+                    LAUNCH(K_REFINE_SPLIT, k3_insert<<<1, INS_THREADS, 0, st>>>(x, y, z, C, faces, planes, far,
+                                                                                 vis, repl));
+                } else {
+                    LAUNCH(K_REFINE_SPLIT, k3_pick<<<gp, 256, 0, st>>>(C, far, pairs, round));
+                    LAUNCH(K_REFINE_SPLIT, k3_visible<<<gv, 64, 0, st>>>(x, y, z, C, faces, planes, pairs, pvis, phz,
+                                                                          pn, claim));
+                    LAUNCH(K_REFINE_SPLIT, k3_apply<<<gv, 64, 0, st>>>(x, y, z, C, faces, planes, far, vis, repl,
+                                                                        pairs, pvis, phz, pn, claim));
+                    LAUNCH(K_MISC, k3_round_end<<<1, 64, 0, st>>>(C));
+                }
                 HIPCHECK(hipMemcpyAsync(&hc, C, sizeof(hc), hipMemcpyDeviceToHost, st));
                 HIPCHECK(hipStreamSynchronize(st));
                 cur = 1 - cur;
                 if (hc.overflow == 2) return HULL_EHIP;      // internal: the mesh lost its shape
                 if (hc.overflow) { overflow = true; break; }
                 if (hc.ncand == 0) break;
-                if (round > 100000) return HULL_EHIP;
+                if (round >= (1 << 20) - 2) return HULL_EHIP;
+                // a round whose proposals all exceeded the per-proposal room
+                // is followed by one serial round
+                serial = all_serial || (!serial && hc.inserted == 0);
             }
             if (overflow) {
                 if (fcap >= (int64_t(1) << 28)) return HULL_ENOMEM;

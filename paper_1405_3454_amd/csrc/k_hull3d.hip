@@ -456,7 +456,7 @@ struct Hull3Ctl {
     int state;                    // 0 solid, 1 flat, 2 collinear, 3 one point, 4 empty
     int nfaces, fcap, born_lo;
     int ncand, nout, inserted, overflow;
-    int ncorner, lo_idx, hi_idx, pad;
+    int ncorner, lo_idx, hi_idx, npair;
     uint32_t p[4];                // start simplex
     int64_t nrm[3];               // flat sets: their plane's normal
 };
@@ -599,27 +599,40 @@ __global__ void k3_start(const float *__restrict__ x, const float *__restrict__ 
     C->nfaces = 4;
 }
 
+// Candidates of the hull stage carry their coordinates: (x, y, z, index
+// bits), so the rounds stream them instead of gathering from the inputs.
+__global__ __launch_bounds__(256) void k3_gather(const float *__restrict__ x, const float *__restrict__ y,
+                                                 const float *__restrict__ z, const uint32_t *__restrict__ idx,
+                                                 int64_t n, float4 *__restrict__ out) {
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t i = idx[t];
+        out[t] = make_float4(x[i], y[i], z[i], __uint_as_float(i));
+    }
+}
+
 // A round's assignment (see above).  first: every candidate tests the start
 // faces.  A candidate whose face was removed follows the removals: the
 // insertion that removed a face created faces repl[f] = (first, count); the
 // candidate is beyond one of them (then it moves there, and on if that one
 // was removed too) or inside the hull that insertion made (then it drops).
+// The kept candidates are appended per wave, in their order.
 constexpr int CHAIN_MAX = 256;      // chain steps before a full scan
 
-__global__ __launch_bounds__(256) void k3_assign(const float *__restrict__ x, const float *__restrict__ y,
-                                                 const float *__restrict__ z, const uint32_t *__restrict__ cin,
-                                                 const int *__restrict__ fin, uint32_t *__restrict__ cout,
-                                                 int *__restrict__ fout, Hull3Ctl *__restrict__ C,
-                                                 const Face3 *__restrict__ faces,
+__global__ __launch_bounds__(256) void k3_assign(const float4 *__restrict__ cin, const int *__restrict__ fin,
+                                                 float4 *__restrict__ cout, int *__restrict__ fout,
+                                                 Hull3Ctl *__restrict__ C, const Face3 *__restrict__ faces,
                                                  const Plane3 *__restrict__ planes, const int2 *__restrict__ repl,
                                                  unsigned long long *__restrict__ far, int first) {
     const int64_t nc = C->ncand;
     const int nfaces = C->nfaces;
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < nc; t += int64_t(gridDim.x) * blockDim.x) {
-        const uint32_t i = cin[t];
-        const double px = pdx(x, i), py = pdx(y, i), pz = pdx(z, i);
-        int f = -1;
-        double d = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    // whole waves run the loop together (the appends are per wave)
+    const int64_t ncw = (nc + WAVE - 1) / WAVE * WAVE;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < ncw; t += stride) {
+        const bool live = t < nc;
+        float4 c = live ? cin[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const double px = (double)(int64_t)(c.x * GRIDF), py = (double)(int64_t)(c.y * GRIDF),
+                     pz = (double)(int64_t)(c.z * GRIDF);
         auto best_of = [&](int lo, int hi, bool alive_only) {
             int bf = -1;
             double bd = 0;
@@ -632,27 +645,237 @@ __global__ __launch_bounds__(256) void k3_assign(const float *__restrict__ x, co
             }
             return bf;
         };
-        if (first) {
-            f = best_of(0, nfaces, true);
-        } else {
-            int g = fin[t];
-            int steps = 0;
-            while (g >= 0 && !faces[g].alive && steps < CHAIN_MAX) {
-                const int2 r = repl[g];
-                g = best_of(r.x, r.x + r.y, false);
-                steps++;
+        int f = -1;
+        if (live) {
+            if (first) {
+                f = best_of(0, nfaces, true);
+            } else {
+                int g = fin[t];
+                int steps = 0;
+                while (g >= 0 && !faces[g].alive && steps < CHAIN_MAX) {
+                    const int2 r = repl[g];
+                    g = best_of(r.x, r.x + r.y, false);
+                    steps++;
+                }
+                if (g >= 0 && !faces[g].alive) g = best_of(0, nfaces, true);   // chain too long
+                f = g;
             }
-            if (g >= 0 && !faces[g].alive) g = best_of(0, nfaces, true);   // chain too long
-            f = g;
         }
-        if (f < 0) continue;
-        d = plane_dist(planes[f], px, py, pz);
-        const int o = atomicAdd(&C->nout, 1);
-        cout[o] = i;
-        fout[o] = f;
-        const unsigned long long k = key_of(d, i);
-        if (far[f] < k) atomicMax(&far[f], k);
+        const bool keep = f >= 0;
+        const uint64_t m = __ballot(keep);
+        if (m == 0) continue;
+        const int lead = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane_id() == lead) base = atomicAdd(&C->nout, __popcll(m));
+        base = __shfl(base, lead);
+        if (keep) {
+            const int o = base + __popcll(m & lanemask_lt());
+            cout[o] = c;
+            fout[o] = f;
+            const unsigned long long k = key_of(plane_dist(planes[f], px, py, pz), __float_as_uint(c.w));
+            if (far[f] < k) atomicMax(&far[f], k);
+        }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel insertion.  Every face with candidates proposes its farthest one
+// q.  Each proposal finds the faces q sees (breadth-first from its face) and
+// the horizon, and claims those faces and the outside faces across the
+// horizon with its priority (round, coarse distance, ~index; maximum wins).
+// A proposal that holds every claim is inserted.  Two winners touch disjoint
+// faces, so no face one of them creates is seen by the other and the
+// insertions give the hull of inserting them one after another; the
+// proposal of highest priority always wins, so every round inserts.
+struct Pair3 {
+    uint32_t q;
+    int f;
+    unsigned long long prio;
+};
+constexpr int PAIR_CAP = 16384;     // proposals per round at most
+constexpr int PV_CAP = 512;         // faces seen, and horizon edges, per proposal
+
+// Round start: the proposals.  Clears far[] for the next assignment.
+__global__ __launch_bounds__(256) void k3_pick(Hull3Ctl *__restrict__ C, unsigned long long *__restrict__ far,
+                                               Pair3 *__restrict__ pairs, int round) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) C->inserted = 0;
+    const int F = C->nfaces;
+    const int64_t Fw = (F + WAVE - 1) / WAVE * WAVE;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < Fw; t += int64_t(gridDim.x) * blockDim.x) {
+        const unsigned long long k = t < F ? far[t] : 0ull;
+        if (k) far[t] = 0;
+        const uint64_t m = __ballot(k != 0);
+        if (m == 0) continue;
+        const int lead = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane_id() == lead) base = atomicAdd(&C->npair, __popcll(m));
+        base = __shfl(base, lead);
+        const int s = base + __popcll(m & lanemask_lt());
+        if (k && s < PAIR_CAP) {
+            Pair3 P;
+            P.q = ~(uint32_t)k;
+            P.f = (int)t;
+            P.prio = ((unsigned long long)(round + 1) << 44) | ((k >> 52) << 32) | (k & 0xffffffffull);
+            pairs[s] = P;
+        }
+    }
+}
+
+// One wave per proposal: the faces seen and the horizon, then the claims.
+// pn[p] = (faces seen, horizon edges), or (-1, -1) when either list would
+// exceed PV_CAP (the proposal then waits).
+__global__ __launch_bounds__(64) void k3_visible(const float *__restrict__ x, const float *__restrict__ y,
+                                                 const float *__restrict__ z, Hull3Ctl *__restrict__ C,
+                                                 const Face3 *__restrict__ faces, const Plane3 *__restrict__ planes,
+                                                 const Pair3 *__restrict__ pairs, int *__restrict__ pv,
+                                                 int *__restrict__ ph, int2 *__restrict__ pn,
+                                                 unsigned long long *__restrict__ claim) {
+    __shared__ int vl[PV_CAP];
+    __shared__ int hl[PV_CAP];
+    __shared__ int tmp[WAVE];
+    const int lane = threadIdx.x;
+    const int np = min(C->npair, PAIR_CAP);
+    for (int p = blockIdx.x; p < np; p += gridDim.x) {
+        const Pair3 P = pairs[p];
+        const double qx = pdx(x, P.q), qy = pdx(y, P.q), qz = pdx(z, P.q);
+        if (lane == 0) vl[0] = P.f;
+        __syncthreads();
+        int nv = 1, nh = 0, head = 0;
+        bool ok = true;
+        while (head < nv && ok) {
+            const int nb = min(nv - head, WAVE / 3);
+            int g = -1, code = 0;
+            bool seen = false, hz = false;
+            if (lane < 3 * nb) {
+                const int fi = vl[head + lane / 3], e = lane % 3;
+                code = (fi << 2) | e;
+                g = faces[fi].nb[e];
+                if (g < 0) {            // an open mesh: reported, never followed
+                    atomicMax(&C->overflow, 2);
+                } else {
+                    seen = plane_sign(planes[g], qx, qy, qz) > 0;
+                    hz = !seen;
+                }
+                for (int i = 0; i < nv && seen; i++)
+                    if (vl[i] == g) seen = false;       // listed already
+            }
+            tmp[lane] = seen ? g : -1;
+            __syncthreads();
+            for (int j = 0; j < lane && seen; j++)
+                if (tmp[j] == g) seen = false;          // a lower lane lists it
+            const uint64_t mv = __ballot(seen), mh = __ballot(hz);
+            const int cv = __popcll(mv), ch = __popcll(mh);
+            if (nv + cv > PV_CAP || nh + ch > PV_CAP) {
+                ok = false;
+            } else {
+                if (seen) vl[nv + __popcll(mv & lanemask_lt())] = g;
+                if (hz) hl[nh + __popcll(mh & lanemask_lt())] = code;
+            }
+            __syncthreads();
+            nv += cv;
+            nh += ch;
+            head += nb;
+        }
+        if (ok) {
+            for (int i = lane; i < nv; i += WAVE) {
+                pv[(int64_t)p * PV_CAP + i] = vl[i];
+                atomicMax(&claim[vl[i]], P.prio);
+            }
+            for (int h = lane; h < nh; h += WAVE) {
+                ph[(int64_t)p * PV_CAP + h] = hl[h];
+                atomicMax(&claim[faces[hl[h] >> 2].nb[hl[h] & 3]], P.prio);
+            }
+        }
+        if (lane == 0) pn[p] = ok ? make_int2(nv, nh) : make_int2(-1, -1);
+        __syncthreads();
+    }
+}
+
+// One wave per proposal: the winners insert.  New face F + h on horizon edge
+// a -> b is (a, b, q); across a -> b it borders the outside face, across
+// b -> q the new face starting at b, across q -> a the new face ending at a.
+__global__ __launch_bounds__(64) void k3_apply(const float *__restrict__ x, const float *__restrict__ y,
+                                               const float *__restrict__ z, Hull3Ctl *__restrict__ C,
+                                               Face3 *__restrict__ faces, Plane3 *__restrict__ planes,
+                                               unsigned long long *__restrict__ far, int *__restrict__ vis,
+                                               int2 *__restrict__ repl, const Pair3 *__restrict__ pairs,
+                                               const int *__restrict__ pv, const int *__restrict__ ph,
+                                               const int2 *__restrict__ pn,
+                                               const unsigned long long *__restrict__ claim) {
+    __shared__ int ha[PV_CAP], hb[PV_CAP], ho[PV_CAP];
+    __shared__ int base;
+    const int lane = threadIdx.x;
+    const int np = min(C->npair, PAIR_CAP);
+    const int fcap = C->fcap;
+    for (int p = blockIdx.x; p < np; p += gridDim.x) {
+        const int2 cnt = pn[p];
+        if (cnt.x < 0) continue;
+        const Pair3 P = pairs[p];
+        const int *V = pv + (int64_t)p * PV_CAP;
+        const int *Hz = ph + (int64_t)p * PV_CAP;
+        const int NV = cnt.x, NH = cnt.y;
+        bool won = true;
+        for (int i = lane; i < NV; i += WAVE) won = won && claim[V[i]] == P.prio;
+        for (int h = lane; h < NH; h += WAVE) {
+            const int fi = Hz[h] >> 2, e = Hz[h] & 3;
+            const int O = faces[fi].nb[e];
+            won = won && claim[O] == P.prio;
+            ha[h] = faces[fi].v[e];
+            hb[h] = faces[fi].v[e == 2 ? 0 : e + 1];
+            ho[h] = O;
+        }
+        if (__ballot(!won) != 0) {
+            __syncthreads();
+            continue;
+        }
+        if (lane == 0) base = atomicAdd(&C->nfaces, NH);
+        __syncthreads();
+        const int F = base;
+        if (F + NH > fcap) {
+            if (lane == 0) atomicOr(&C->overflow, 1);
+            __syncthreads();
+            continue;
+        }
+        bool bad = false;
+        for (int h = lane; h < NH; h += WAVE) {
+            const int a = ha[h], b = hb[h];
+            Face3 nf;
+            nf.v[0] = a; nf.v[1] = b; nf.v[2] = (int)P.q;
+            nf.nb[0] = ho[h];
+            nf.nb[1] = -1;
+            nf.nb[2] = -1;
+            for (int k = 0; k < NH; k++) {
+                if (ha[k] == b) nf.nb[1] = F + k;
+                if (hb[k] == a) nf.nb[2] = F + k;
+            }
+            bad = bad || nf.nb[1] < 0 || nf.nb[2] < 0;
+            nf.alive = 1;
+            nf.pad = 0;
+            faces[F + h] = nf;
+            face_plane(x, y, z, nf, &planes[F + h]);
+            far[F + h] = 0;
+            vis[F + h] = -1;
+            // the outside face now borders the new one
+            const int O = ho[h];
+            for (int e2 = 0; e2 < 3; e2++)
+                if (faces[O].v[e2] == b && faces[O].v[e2 == 2 ? 0 : e2 + 1] == a) faces[O].nb[e2] = F + h;
+        }
+        for (int i = lane; i < NV; i += WAVE) {
+            faces[V[i]].alive = 0;
+            repl[V[i]] = make_int2(F, NH);
+        }
+        if (__ballot(bad) != 0 && lane == 0) atomicMax(&C->overflow, 2);   // not a closed horizon
+        if (lane == 0) atomicAdd(&C->inserted, 1);
+        __syncthreads();
+    }
+}
+
+// Round end: the assignment's output is the next round's input.
+__global__ void k3_round_end(Hull3Ctl *__restrict__ C) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    C->ncand = C->nout;
+    C->nout = 0;
+    C->npair = 0;
 }
 
 constexpr int INS_THREADS = 1024;

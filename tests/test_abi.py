@@ -17,7 +17,32 @@ HEADER = os.path.join(ROOT, "include", "hull.h")
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int64_t|int|const char \*)\s*(hull_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|const char \*)\s*(hull3?_\w+)\s*\(", txt, re.M)))
+
+
+def _int_of(expr):
+    """Value of a header constant: an integer literal, optionally (1LL << k)
+    or (k u << s)."""
+    e = expr.strip()
+    m = re.fullmatch(r"\(?\s*(\d+)(?:u|U|LL|ll)?\s*<<\s*(\d+)\s*\)?", e)
+    if m:
+        return int(m.group(1)) << int(m.group(2))
+    m = re.fullmatch(r"\(?\s*(-?(?:0x[0-9A-Fa-f]+|\d+))(?:u|U|LL|ll)?\s*\)?", e)
+    return int(m.group(1), 0) if m else None
+
+
+def test_header_constants_match_the_binding():
+    from paper_1405_3454_amd import _lib
+    txt = open(HEADER).read()
+    found = 0
+    for name, expr in re.findall(r"^#define\s+(HULL\w*)\s+([^/\n]+?)\s*(?:/\*.*)?$", txt, re.M):
+        v = _int_of(expr)
+        if v is None or not hasattr(_lib, name):
+            continue
+        assert getattr(_lib, name) == v, (name, expr)
+        found += 1
+    assert found >= 25
+    assert "hull3_compute" in _declared()
 
 
 @pytest.fixture(scope="module")

@@ -38,9 +38,9 @@ def u32(t):
     return as_u32(t)
 
 
-def check3(H, x, y, z, preset=0, what=""):
+def check3(H, x, y, z, preset=0, what="", serial=False):
     H.set_directions(preset)
-    slots, surv, hull = H.compute3(dev(x), dev(y), dev(z))
+    slots, surv, hull = H.compute3(dev(x), dev(y), dev(z), serial=serial)
     o_slots, _ = o3.extremes(x, y, z, preset)
     assert np.array_equal(u32(slots), o_slots), (what, u32(slots), o_slots)
     o_hull, o_surv = o3.compute(x, y, z, preset, want_survivors=True)
@@ -113,3 +113,25 @@ def test_repeated_points_lowest_index(H):
     Y = np.concatenate([y, y])[perm]
     Z = np.concatenate([z, z])[perm]
     check3(H, X, Y, Z, 0, "repeated")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_serial_insertion(H, kind):
+    """The one-block insertion form of the hull stage (also the parallel
+    rounds' fallback) against the oracle."""
+    for n in (5, 4099, 60_000):
+        x, y, z = inputs.DISTRIBUTIONS3[kind](n, 31 + n)
+        check3(H, x, y, z, 0, "serial %s n=%d" % (kind, n), serial=True)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_serial_lattice(H, seed):
+    x, y, z = inputs.lattice3(5000, 4 + seed, 70 + seed, offset=1000 * seed)
+    check3(H, x, y, z, 0, "serial lattice %d" % seed, serial=True)
+
+
+@pytest.mark.parametrize("kind,n", [("ball", 400_000), ("shell", 150_000)])
+def test_large_parallel_rounds(H, kind, n):
+    """Sets whose hull stage runs thousands of proposals per round."""
+    x, y, z = inputs.DISTRIBUTIONS3[kind](n, 123)
+    check3(H, x, y, z, 0, "large %s" % kind)
