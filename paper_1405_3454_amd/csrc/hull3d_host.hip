@@ -160,22 +160,28 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
             LAUNCH(K_MISC, k_fill_i64<<<256, 256, 0, st>>>(reinterpret_cast<int64_t *>(claim), fcap, 0));
             LAUNCH(K_MISC, k3_gather<<<gs, 256, 0, st>>>(x, y, z, cidx, nc, cand[0]));
             const unsigned gp = (unsigned)(ctx->cus * 4), gv = (unsigned)(ctx->cus * 16);
+            const unsigned ga = (unsigned)std::max<int64_t>(
+                1, std::min<int64_t>(ctx->cus * 4, (nc + 256 * AS_ITEMS - 1) / (256 * AS_ITEMS)));
             int cur = 0;
             const bool all_serial = flags & HULL3_SERIAL;
             bool overflow = false, serial = all_serial;
             for (int round = 0;; round++) {
-                LAUNCH(K_REFINE, k3_assign<<<gs, 256, 0, st>>>(cand[cur], cf[cur], cand[1 - cur], cf[1 - cur], C,
+                LAUNCH(K_REFINE, k3_assign<<<ga, 256, 0, st>>>(cand[cur], cf[cur], cand[1 - cur], cf[1 - cur], C,
                                                                faces, planes, repl, far, round == 0));
                 if (serial) {
                     // one block inserts every face's farthest candidate in turn
                     LAUNCH(K_REFINE_SPLIT, k3_insert<<<1, INS_THREADS, 0, st>>>(x, y, z, C, faces, planes, far,
                                                                                  vis, repl));
                 } else {
-                    LAUNCH(K_REFINE_SPLIT, k3_pick<<<gp, 256, 0, st>>>(C, far, pairs, round));
-                    LAUNCH(K_REFINE_SPLIT, k3_visible<<<gv, 64, 0, st>>>(x, y, z, C, faces, planes, pairs, pvis, phz,
-                                                                          pn, claim));
-                    LAUNCH(K_REFINE_SPLIT, k3_apply<<<gv, 64, 0, st>>>(x, y, z, C, faces, planes, far, vis, repl,
-                                                                        pairs, pvis, phz, pn, claim));
+                    LAUNCH(K_REFINE_SPLIT, k3_pick<<<gp, 256, 0, st>>>(C, far, pairs));
+                    for (int sub = 0; sub < INS_PASSES; sub++) {
+                        const int stamp = round * INS_PASSES + sub + 1;
+                        LAUNCH(K_REFINE_SPLIT, k3_visible<<<gv, 64, 0, st>>>(x, y, z, C, faces, planes, pairs, pvis,
+                                                                              phz, pn, claim, stamp));
+                        LAUNCH(K_REFINE_SPLIT, k3_apply<<<gv, 64, 0, st>>>(x, y, z, C, faces, planes, far, vis,
+                                                                            repl, pairs, pvis, phz, pn, claim,
+                                                                            stamp));
+                    }
                     LAUNCH(K_MISC, k3_round_end<<<1, 64, 0, st>>>(C));
                 }
                 HIPCHECK(hipMemcpyAsync(&hc, C, sizeof(hc), hipMemcpyDeviceToHost, st));
@@ -184,7 +190,7 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
                 if (hc.overflow == 2) return HULL_EHIP;      // internal: the mesh lost its shape
                 if (hc.overflow) { overflow = true; break; }
                 if (hc.ncand == 0) break;
-                if (round >= (1 << 20) - 2) return HULL_EHIP;
+                if ((round + 2) * INS_PASSES >= (1 << 20)) return HULL_EHIP;
                 // a round whose proposals all exceeded the per-proposal room
                 // is followed by one serial round
                 serial = all_serial || (!serial && hc.inserted == 0);

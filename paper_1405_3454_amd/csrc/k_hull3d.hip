@@ -228,29 +228,42 @@ struct Poly3 {
     Plane3 f[F3_CAP];
 };
 
+// Triple number t -> (i < j < k) over S3 points.
+__device__ __forceinline__ void triple_of(int t, int &i, int &j, int &k) {
+    int rem = t, cnt;
+    i = 0;
+    while (rem >= (cnt = (S3 - 1 - i) * (S3 - 2 - i) / 2)) { rem -= cnt; i++; }
+    j = i + 1;
+    while (rem >= (cnt = S3 - 1 - j)) { rem -= cnt; j++; }
+    k = j + 1 + rem;
+}
+
+__device__ __forceinline__ bool i3_zero(I3 a) { return a.x == 0 && a.y == 0 && a.z == 0; }
+
+constexpr int TWORDS3 = (TRIPLES3 + 63) / 64;
+
 __global__ __launch_bounds__(1024) void k3_poly(const float *__restrict__ x, const float *__restrict__ y,
                                                 const float *__restrict__ z, int64_t W,
                                                 const double *__restrict__ pval,
                                                 const uint32_t *__restrict__ pidx,
                                                 uint32_t *__restrict__ slots_out, Poly3 *__restrict__ out) {
-    __shared__ double bv[S3];
     __shared__ uint32_t bi[S3];
-    __shared__ double rv[1024 / WAVE];
-    __shared__ uint32_t ri[1024 / WAVE];
+    __shared__ I3 qs[S3];
     __shared__ I3 q[S3];
     __shared__ uint32_t qi[S3];
-    __shared__ int m;
-    __shared__ unsigned long long flags[(TRIPLES3 + 63) / 64];
-    __shared__ int nf;
+    __shared__ int m, nf;
+    __shared__ unsigned long long keep[TWORDS3], flipb[TWORDS3];
+    __shared__ int wpre[TWORDS3];
     __shared__ I3 fn[F3_CAP];
     __shared__ I3 fa[F3_CAP];
-    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    // 1. slots
-    for (int k = 0; k < S3; k++) {
+    __shared__ double rmin[1024 / WAVE];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6, NW = blockDim.x >> 6;
+    // 1. slots: wave w reduces slots w, w + NW, ... over the partials
+    for (int k = w; k < S3; k += NW) {
         const bool mx = k & 1;
         double v = mx ? -INFINITY : INFINITY;
         uint32_t i = NONE;
-        for (int64_t r = tid; r < W; r += blockDim.x) {
+        for (int64_t r = lane; r < W; r += WAVE) {
             const uint32_t ii = pidx[r * S3 + k];
             const double vv = pval[r * S3 + k];
             if (ii == NONE) continue;
@@ -262,110 +275,107 @@ __global__ __launch_bounds__(1024) void k3_poly(const float *__restrict__ x, con
             const uint32_t oi = (uint32_t)__shfl_xor((int)i, o);
             if (oi != NONE && (i == NONE || (mx ? ov > v : ov < v) || (ov == v && oi < i))) { v = ov; i = oi; }
         }
-        if (lane == 0) { rv[w] = v; ri[w] = i; }
-        __syncthreads();
-        if (tid == 0) {
-            for (int ww = 1; ww < (int)(blockDim.x >> 6); ww++) {
-                const double ov = rv[ww];
-                const uint32_t oi = ri[ww];
-                if (oi != NONE && (i == NONE || (mx ? ov > v : ov < v) || (ov == v && oi < i))) { v = ov; i = oi; }
-            }
-            bv[k] = v;
-            bi[k] = i;
-        }
-        __syncthreads();
+        if (lane == 0) bi[k] = i;
     }
-    if (tid < S3 && slots_out) slots_out[tid] = bi[tid];
-    // 2. distinct points (first slot of each coordinate triple)
-    if (tid == 0) {
-        int mm = 0;
-        for (int k = 0; k < S3; k++) {
-            if (bi[k] == NONE) continue;
-            const I3 p = grid3(x, y, z, bi[k]);
-            bool dup = false;
-            for (int j = 0; j < mm; j++) dup = dup || (q[j].x == p.x && q[j].y == p.y && q[j].z == p.z);
-            if (!dup) { q[mm] = p; qi[mm] = bi[k]; mm++; }
-        }
-        m = mm;
-        nf = 0;
-    }
-    for (int i = tid; i < (TRIPLES3 + 63) / 64; i += blockDim.x) flags[i] = 0;
+    for (int i = tid; i < TWORDS3; i += blockDim.x) { keep[i] = 0; flipb[i] = 0; }
     __syncthreads();
-    // 3. supporting planes through three distinct points
+    if (tid < S3 && slots_out) slots_out[tid] = bi[tid];
+    // 2. distinct points: the first slot of each coordinate triple, in slot order
+    if (w == 0) {
+        const bool valid = lane < S3 && bi[lane] != NONE;
+        I3 p{0, 0, 0};
+        if (valid) p = grid3(x, y, z, bi[lane]);
+        if (lane < S3) qs[lane] = p;
+        wave_sync();
+        bool first = valid;
+        for (int j = 0; j < lane && first; j++)
+            if (bi[j] != NONE && qs[j].x == p.x && qs[j].y == p.y && qs[j].z == p.z) first = false;
+        const uint64_t bm = __ballot(first);
+        if (first) {
+            const int pos = __popcll(bm & lanemask_lt());
+            q[pos] = p;
+            qi[pos] = bi[lane];
+        }
+        if (lane == 0) m = __popcll(bm);
+    }
+    __syncthreads();
+    // 3. supporting planes through three distinct points; of the triples on
+    // one plane only the canonical one is kept: the plane's two lowest
+    // points and the lowest point after them off their line
     const int mm = m;
     for (int t = tid; t < TRIPLES3; t += blockDim.x) {
-        // triple number t -> (i < j < k) over S3 points; skip those past m
-        int i = 0, rem = t, cnt;
-        while (rem >= (cnt = (S3 - 1 - i) * (S3 - 2 - i) / 2)) { rem -= cnt; i++; }
-        int j = i + 1;
-        while (rem >= (cnt = S3 - 1 - j)) { rem -= cnt; j++; }
-        const int k = j + 1 + rem;
+        int i, j, k;
+        triple_of(t, i, j, k);
         if (k >= mm) continue;
         const I3 nrm = i3_cross(i3_sub(q[j], q[i]), i3_sub(q[k], q[i]));
-        if (nrm.x == 0 && nrm.y == 0 && nrm.z == 0) continue;
+        if (i3_zero(nrm)) continue;
+        const Plane3 P = make_plane(nrm, q[i]);
         int pos = 0, neg = 0;
+        unsigned long long on = 0;
         for (int r = 0; r < mm; r++) {
-            const __int128 d = i3_dot(nrm, i3_sub(q[r], q[i]));
-            pos += d > 0;
-            neg += d < 0;
+            const int sg = plane_sign(P, (double)q[r].x, (double)q[r].y, (double)q[r].z);
+            pos += sg > 0;
+            neg += sg < 0;
+            on |= (unsigned long long)(sg == 0) << r;
         }
         if ((pos && neg) || (!pos && !neg)) continue;
-        atomicOr(&flags[t >> 6], 1ull << (t & 63));
-    }
-    __syncthreads();
-    // 4. unique planes, oriented inwards (one thread: a few hundred flags)
-    if (tid == 0) {
-        int cntf = 0;
-        for (int t = 0; t < TRIPLES3 && cntf < F3_CAP; t++) {
-            if (!((flags[t >> 6] >> (t & 63)) & 1)) continue;
-            int i = 0, rem = t, c;
-            while (rem >= (c = (S3 - 1 - i) * (S3 - 2 - i) / 2)) { rem -= c; i++; }
-            int j = i + 1;
-            while (rem >= (c = S3 - 1 - j)) { rem -= c; j++; }
-            const int k = j + 1 + rem;
-            I3 nrm = i3_cross(i3_sub(q[j], q[i]), i3_sub(q[k], q[i]));
-            // inwards: towards the points off the plane
-            bool flip = false;
-            for (int r = 0; r < mm; r++) {
-                const __int128 d = i3_dot(nrm, i3_sub(q[r], q[i]));
-                if (d != 0) { flip = d < 0; break; }
-            }
-            if (flip) nrm = I3{-nrm.x, -nrm.y, -nrm.z};
-            // the same plane as one kept (parallel normals, same direction)?
-            bool same = false;
-            for (int g = 0; g < cntf && !same; g++) {
-                const I3 o = fn[g];
-                const __int128 cx = (__int128)o.y * nrm.z - (__int128)o.z * nrm.y;
-                const __int128 cy = (__int128)o.z * nrm.x - (__int128)o.x * nrm.z;
-                const __int128 cz = (__int128)o.x * nrm.y - (__int128)o.y * nrm.x;
-                const __int128 dt = (__int128)o.x * nrm.x + (__int128)o.y * nrm.y + (__int128)o.z * nrm.z;
-                same = cx == 0 && cy == 0 && cz == 0 && dt > 0;
-            }
-            if (same) continue;
-            fn[cntf] = nrm;
-            fa[cntf] = q[i];
-            cntf++;
+        const int i0 = __ffsll(on) - 1;
+        const unsigned long long on1 = on & (on - 1);
+        const int j0 = __ffsll(on1) - 1;
+        if (i != i0 || j != j0) continue;
+        int k0 = -1;
+        for (unsigned long long rest = on1 & (on1 - 1); rest; rest &= rest - 1) {
+            const int r = __ffsll(rest) - 1;
+            if (!i3_zero(i3_cross(i3_sub(q[j0], q[i0]), i3_sub(q[r], q[i0])))) { k0 = r; break; }
         }
-        nf = cntf;
+        if (k != k0) continue;
+        atomicOr(&keep[t >> 6], 1ull << (t & 63));
+        if (neg) atomicOr(&flipb[t >> 6], 1ull << (t & 63));   // inwards: towards the points off it
     }
     __syncthreads();
+    // 4. the kept planes in triple order
+    if (tid == 0) {
+        int sum = 0;
+        for (int wd = 0; wd < TWORDS3; wd++) { wpre[wd] = sum; sum += __popcll(keep[wd]); }
+        nf = min(sum, F3_CAP);      // at most 2 * 42 - 4 faces
+    }
+    __syncthreads();
+    for (int t = tid; t < TRIPLES3; t += blockDim.x) {
+        const unsigned long long kw = keep[t >> 6], bit = 1ull << (t & 63);
+        if (!(kw & bit)) continue;
+        const int pos = wpre[t >> 6] + __popcll(kw & (bit - 1));
+        if (pos >= F3_CAP) continue;
+        int i, j, k;
+        triple_of(t, i, j, k);
+        I3 nrm = i3_cross(i3_sub(q[j], q[i]), i3_sub(q[k], q[i]));
+        if (flipb[t >> 6] & bit) nrm = I3{-nrm.x, -nrm.y, -nrm.z};
+        fn[pos] = nrm;
+        fa[pos] = q[i];
+    }
+    __syncthreads();
+    // 5. output and the quick-accept ball
     const int nff = nf;
     for (int g = tid; g < nff; g += blockDim.x) out->f[g] = make_plane(fn[g], fa[g]);
     if (tid < mm) out->pts[tid] = qi[tid];
+    double cx = 0, cy = 0, cz = 0;
+    for (int r = 0; r < mm; r++) { cx += (double)q[r].x; cy += (double)q[r].y; cz += (double)q[r].z; }
+    cx /= mm > 0 ? mm : 1; cy /= mm > 0 ? mm : 1; cz /= mm > 0 ? mm : 1;
+    double r = INFINITY;
+    for (int g = tid; g < nff; g += blockDim.x) {
+        const I3 nn = fn[g], a = fa[g];
+        const double e = (double)nn.x * (cx - (double)a.x) + (double)nn.y * (cy - (double)a.y) +
+                         (double)nn.z * (cz - (double)a.z);
+        const double len = sqrt((double)nn.x * nn.x + (double)nn.y * nn.y + (double)nn.z * nn.z);
+        r = fmin(r, e / len);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) r = fmin(r, __shfl_xor(r, o));
+    if (lane == 0) rmin[w] = r;
+    __syncthreads();
     if (tid == 0) {
+        for (int ww = 1; ww < NW; ww++) r = fmin(r, rmin[ww]);
         out->nf = nff;
         out->m = mm;
-        double cx = 0, cy = 0, cz = 0;
-        for (int r = 0; r < mm; r++) { cx += (double)q[r].x; cy += (double)q[r].y; cz += (double)q[r].z; }
-        cx /= mm > 0 ? mm : 1; cy /= mm > 0 ? mm : 1; cz /= mm > 0 ? mm : 1;
-        double r = INFINITY;
-        for (int g = 0; g < nff; g++) {
-            const I3 nn = fn[g], a = fa[g];
-            const double e = (double)nn.x * (cx - (double)a.x) + (double)nn.y * (cy - (double)a.y) +
-                             (double)nn.z * (cz - (double)a.z);
-            const double len = sqrt((double)nn.x * nn.x + (double)nn.y * nn.y + (double)nn.z * nn.z);
-            r = fmin(r, e / len);
-        }
         // relative and absolute margins far above the rounding of these sums
         const double rs = nff > 0 ? r * (1.0 - 0x1p-20) - 4.0 : -1.0;
         out->cx = cx; out->cy = cy; out->cz = cz;
@@ -376,11 +386,21 @@ __global__ __launch_bounds__(1024) void k3_poly(const float *__restrict__ x, con
 // ---------------------------------------------------------------------------
 // Step 3: strict-inside test, survivor masks and counts per tile in the
 // layout of the 2D passes (bit l of word 4 c + j: point c*256 + 4 l + j).
+// Each lane takes its four points of a chunk together through the planes.
+// A plane is evaluated as n.p - n.a with n.a rounded once per block: both
+// dot products stay below |n|_1 2^24, so the three roundings of each, and
+// the final subtraction, err by less than |n|_1 2^-26, inside the plane's
+// bound |n|_1 2^-24; within the bound the sign is taken exactly.
+struct PlaneK {
+    double nx, ny, nz, na, bound;
+};
+
 __global__ __launch_bounds__(256) void k3_discard(const float *__restrict__ x, const float *__restrict__ y,
                                                   const float *__restrict__ z, int64_t n,
                                                   const Poly3 *__restrict__ P, uint64_t *__restrict__ masks,
                                                   uint32_t *__restrict__ tile_cnt) {
     __shared__ Plane3 fl[F3_CAP];
+    __shared__ PlaneK fk[F3_CAP];
     __shared__ int nfs;
     __shared__ double ball[4];
     const int tid = threadIdx.x, lane = lane_id();
@@ -390,7 +410,15 @@ __global__ __launch_bounds__(256) void k3_discard(const float *__restrict__ x, c
     }
     __syncthreads();
     const int nf = nfs;
-    for (int g = tid; g < nf; g += blockDim.x) fl[g] = P->f[g];
+    for (int g = tid; g < nf; g += blockDim.x) {
+        const Plane3 Q = P->f[g];
+        fl[g] = Q;
+        PlaneK K;
+        K.nx = Q.nx; K.ny = Q.ny; K.nz = Q.nz;
+        K.na = fma(Q.nz, Q.az, fma(Q.ny, Q.ay, Q.nx * Q.ax));
+        K.bound = Q.bound;
+        fk[g] = K;
+    }
     __syncthreads();
     const double cx = ball[0], cy = ball[1], cz = ball[2], r2 = ball[3];
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + tid) >> 6;
@@ -398,28 +426,65 @@ __global__ __launch_bounds__(256) void k3_discard(const float *__restrict__ x, c
     const int64_t T = (n + TILE - 1) / TILE;
     for (int64_t t = wave; t < T; t += W) {
         const int64_t tb = t * TILE;
+        const bool full = tb + TILE <= n;
         uint32_t cnt = 0;
+#pragma unroll 1
+        for (int c = 0; c < TILE_CHUNKS; c++) {
+            const int64_t p0 = tb + c * CHUNK + 4 * lane;
+            float xs[4], ys[4], zs[4];
+            bool valid[4];
+            if (full) {
+                const float4 X = *reinterpret_cast<const float4 *>(x + p0);
+                const float4 Y = *reinterpret_cast<const float4 *>(y + p0);
+                const float4 Z = *reinterpret_cast<const float4 *>(z + p0);
+                xs[0] = X.x; xs[1] = X.y; xs[2] = X.z; xs[3] = X.w;
+                ys[0] = Y.x; ys[1] = Y.y; ys[2] = Y.z; ys[3] = Y.w;
+                zs[0] = Z.x; zs[1] = Z.y; zs[2] = Z.z; zs[3] = Z.w;
 #pragma unroll
-        for (int c = 0; c < TILE_CHUNKS; c++)
+                for (int j = 0; j < 4; j++) valid[j] = true;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    valid[j] = p0 + j < n;
+                    xs[j] = valid[j] ? x[p0 + j] : 0.f;
+                    ys[j] = valid[j] ? y[p0 + j] : 0.f;
+                    zs[j] = valid[j] ? z[p0 + j] : 0.f;
+                }
+            }
+            double px[4], py[4], pz[4];
+            bool live[4], out[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                const int64_t p = tb + c * CHUNK + 4 * lane + j;
-                bool surv = false;
-                if (p < n) {
-                    const double px = (double)(int64_t)(x[p] * GRIDF), py = (double)(int64_t)(y[p] * GRIDF),
-                                 pz = (double)(int64_t)(z[p] * GRIDF);
-                    const double dx = px - cx, dy = py - cy, dz = pz - cz;
-                    bool inside = nf > 0 && dx * dx + dy * dy + dz * dz < r2;
-                    if (!inside && nf > 0) {
-                        inside = true;
-                        for (int g = 0; g < nf && inside; g++) inside = plane_sign(fl[g], px, py, pz) > 0;
-                    }
-                    surv = !inside;
-                }
-                const uint64_t b = __ballot(surv);
-                cnt += (uint32_t)__popcll(b);
-                if (lane == 0) masks[t * TILE_WORDS + c * 4 + j] = b;
+                px[j] = (double)(int64_t)(xs[j] * GRIDF);
+                py[j] = (double)(int64_t)(ys[j] * GRIDF);
+                pz[j] = (double)(int64_t)(zs[j] * GRIDF);
+                const double dx = px[j] - cx, dy = py[j] - cy, dz = pz[j] - cz;
+                const bool in_ball = dx * dx + dy * dy + dz * dz < r2;
+                live[j] = valid[j] && nf > 0 && !in_ball;     // still to be tested
+                out[j] = false;
             }
+            for (int g = 0; g < nf; g++) {
+                if (!__ballot(live[0] || live[1] || live[2] || live[3])) break;
+                const PlaneK K = fk[g];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (!live[j]) continue;
+                    const double e = fma(K.nz, pz[j], fma(K.ny, py[j], K.nx * px[j])) - K.na;
+                    if (e > K.bound) continue;
+                    if (e < -K.bound || plane_sign(fl[g], px[j], py[j], pz[j]) <= 0) {
+                        live[j] = false;
+                        out[j] = true;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const bool surv = valid[j] && (nf == 0 || out[j]);
+                const uint64_t bm = __ballot(surv);
+                cnt += (uint32_t)__popcll(bm);
+                if (lane == 0) masks[t * TILE_WORDS + c * 4 + j] = bm;
+            }
+        }
         if (lane == 0) tile_cnt[t] = cnt;
     }
 }
@@ -615,42 +680,69 @@ __global__ __launch_bounds__(256) void k3_gather(const float *__restrict__ x, co
 // insertion that removed a face created faces repl[f] = (first, count); the
 // candidate is beyond one of them (then it moves there, and on if that one
 // was removed too) or inside the hull that insertion made (then it drops).
-// The kept candidates are appended per wave, in their order.
+// A block takes AS_ITEMS * 256 candidates per step and appends the kept ones
+// with one counter update; each wave merges the farthest keys of lanes that
+// share a face before updating far[].
 constexpr int CHAIN_MAX = 256;      // chain steps before a full scan
+constexpr int AS_ITEMS = 4;
+constexpr int AS_MERGE = 4;         // faces merged per wave and item; the rest update directly
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void far_raise(unsigned long long *slot, unsigned long long k) {
+    if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) atomicMax(slot, k);
+}
 
 __global__ __launch_bounds__(256) void k3_assign(const float4 *__restrict__ cin, const int *__restrict__ fin,
                                                  float4 *__restrict__ cout, int *__restrict__ fout,
                                                  Hull3Ctl *__restrict__ C, const Face3 *__restrict__ faces,
                                                  const Plane3 *__restrict__ planes, const int2 *__restrict__ repl,
                                                  unsigned long long *__restrict__ far, int first) {
+    __shared__ int bcnt, bbase;
     const int64_t nc = C->ncand;
     const int nfaces = C->nfaces;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    // whole waves run the loop together (the appends are per wave)
-    const int64_t ncw = (nc + WAVE - 1) / WAVE * WAVE;
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < ncw; t += stride) {
-        const bool live = t < nc;
-        float4 c = live ? cin[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const double px = (double)(int64_t)(c.x * GRIDF), py = (double)(int64_t)(c.y * GRIDF),
-                     pz = (double)(int64_t)(c.z * GRIDF);
-        auto best_of = [&](int lo, int hi, bool alive_only) {
-            int bf = -1;
-            double bd = 0;
-            for (int g = lo; g < hi; g++) {
-                if (alive_only && !faces[g].alive) continue;
-                if (plane_sign(planes[g], px, py, pz) > 0) {
-                    const double dg = plane_dist(planes[g], px, py, pz);
-                    if (bf < 0 || dg > bd) { bf = g; bd = dg; }
+    const int lane = lane_id();
+    constexpr int STEP = 256 * AS_ITEMS;
+    if (threadIdx.x == 0) bcnt = 0;
+    __syncthreads();
+    for (int64_t c0 = int64_t(blockIdx.x) * STEP; c0 < nc; c0 += int64_t(gridDim.x) * STEP) {
+        float4 c[AS_ITEMS];
+        int f[AS_ITEMS];
+        unsigned long long key[AS_ITEMS];
+#pragma unroll
+        for (int it = 0; it < AS_ITEMS; it++) {
+            const int64_t t = c0 + it * 256 + threadIdx.x;
+            f[it] = -1;
+            key[it] = 0;
+            c[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (t >= nc) continue;
+            c[it] = cin[t];
+            const double px = (double)(int64_t)(c[it].x * GRIDF), py = (double)(int64_t)(c[it].y * GRIDF),
+                         pz = (double)(int64_t)(c[it].z * GRIDF);
+            auto best_of = [&](int lo, int hi, bool alive_only) {
+                int bf = -1;
+                double bd = 0;
+                for (int g = lo; g < hi; g++) {
+                    if (alive_only && !faces[g].alive) continue;
+                    if (plane_sign(planes[g], px, py, pz) > 0) {
+                        const double dg = plane_dist(planes[g], px, py, pz);
+                        if (bf < 0 || dg > bd) { bf = g; bd = dg; }
+                    }
                 }
-            }
-            return bf;
-        };
-        int f = -1;
-        if (live) {
+                return bf;
+            };
+            int g;
             if (first) {
-                f = best_of(0, nfaces, true);
+                g = best_of(0, nfaces, true);
             } else {
-                int g = fin[t];
+                g = fin[t];
                 int steps = 0;
                 while (g >= 0 && !faces[g].alive && steps < CHAIN_MAX) {
                     const int2 r = repl[g];
@@ -658,22 +750,52 @@ __global__ __launch_bounds__(256) void k3_assign(const float4 *__restrict__ cin,
                     steps++;
                 }
                 if (g >= 0 && !faces[g].alive) g = best_of(0, nfaces, true);   // chain too long
-                f = g;
             }
+            f[it] = g;
+            if (g >= 0) key[it] = key_of(plane_dist(planes[g], px, py, pz), __float_as_uint(c[it].w));
         }
-        const bool keep = f >= 0;
-        const uint64_t m = __ballot(keep);
-        if (m == 0) continue;
-        const int lead = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane_id() == lead) base = atomicAdd(&C->nout, __popcll(m));
-        base = __shfl(base, lead);
-        if (keep) {
-            const int o = base + __popcll(m & lanemask_lt());
-            cout[o] = c;
-            fout[o] = f;
-            const unsigned long long k = key_of(plane_dist(planes[f], px, py, pz), __float_as_uint(c.w));
-            if (far[f] < k) atomicMax(&far[f], k);
+        // appends: wave counts, a block offset, the wave's place in it
+        uint64_t bal[AS_ITEMS];
+        int wc = 0;
+#pragma unroll
+        for (int it = 0; it < AS_ITEMS; it++) {
+            bal[it] = __ballot(f[it] >= 0);
+            wc += __popcll(bal[it]);
+        }
+        int wo = 0;
+        if (lane == 0 && wc) wo = atomicAdd(&bcnt, wc);
+        wo = __shfl(wo, 0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            bbase = bcnt ? atomicAdd(&C->nout, bcnt) : 0;
+            bcnt = 0;
+        }
+        __syncthreads();
+        int o = bbase + wo;
+#pragma unroll
+        for (int it = 0; it < AS_ITEMS; it++) {
+            if (f[it] >= 0) {
+                const int at = o + __popcll(bal[it] & lanemask_lt());
+                cout[at] = c[it];
+                fout[at] = f[it];
+            }
+            o += __popcll(bal[it]);
+        }
+        // farthest keys: lanes on the same face merged first
+#pragma unroll
+        for (int it = 0; it < AS_ITEMS; it++) {
+            bool pend = f[it] >= 0;
+            uint64_t pm = bal[it];
+            for (int r = 0; r < AS_MERGE && pm; r++) {
+                const int lead = __ffsll((unsigned long long)pm) - 1;
+                const int f0 = __shfl(f[it], lead);
+                const bool mine = pend && f[it] == f0;
+                const unsigned long long v = wave_max_u64(mine ? key[it] : 0ull);
+                if (lane == lead) far_raise(&far[f0], v);
+                pend = pend && !mine;
+                pm = __ballot(pend);
+            }
+            if (pend) far_raise(&far[f[it]], key[it]);
         }
     }
 }
@@ -690,14 +812,15 @@ __global__ __launch_bounds__(256) void k3_assign(const float4 *__restrict__ cin,
 struct Pair3 {
     uint32_t q;
     int f;
-    unsigned long long prio;
+    unsigned long long key;     // the far key of q on f
 };
 constexpr int PAIR_CAP = 16384;     // proposals per round at most
 constexpr int PV_CAP = 512;         // faces seen, and horizon edges, per proposal
+constexpr int INS_PASSES = 4;       // claim-and-insert passes per assignment
 
 // Round start: the proposals.  Clears far[] for the next assignment.
 __global__ __launch_bounds__(256) void k3_pick(Hull3Ctl *__restrict__ C, unsigned long long *__restrict__ far,
-                                               Pair3 *__restrict__ pairs, int round) {
+                                               Pair3 *__restrict__ pairs) {
     if (blockIdx.x == 0 && threadIdx.x == 0) C->inserted = 0;
     const int F = C->nfaces;
     const int64_t Fw = (F + WAVE - 1) / WAVE * WAVE;
@@ -715,21 +838,30 @@ __global__ __launch_bounds__(256) void k3_pick(Hull3Ctl *__restrict__ C, unsigne
             Pair3 P;
             P.q = ~(uint32_t)k;
             P.f = (int)t;
-            P.prio = ((unsigned long long)(round + 1) << 44) | ((k >> 52) << 32) | (k & 0xffffffffull);
+            P.key = k;
             pairs[s] = P;
         }
     }
 }
 
+// Priority of a proposal in claim pass `stamp` (increasing over the whole
+// hull stage, so claims left from earlier passes always lose).
+__device__ __forceinline__ unsigned long long claim_prio(unsigned long long key, int stamp) {
+    return ((unsigned long long)stamp << 44) | ((key >> 52) << 32) | (key & 0xffffffffull);
+}
+
 // One wave per proposal: the faces seen and the horizon, then the claims.
 // pn[p] = (faces seen, horizon edges), or (-1, -1) when either list would
-// exceed PV_CAP (the proposal then waits).
+// exceed PV_CAP or the proposal's face is gone (inserted, or removed by
+// another insertion: the proposal waits for the next round).  A proposal
+// that lost a pass and whose face lives is still valid (its point is still
+// strictly beyond a face of the hull) and tries again in the next pass.
 __global__ __launch_bounds__(64) void k3_visible(const float *__restrict__ x, const float *__restrict__ y,
                                                  const float *__restrict__ z, Hull3Ctl *__restrict__ C,
                                                  const Face3 *__restrict__ faces, const Plane3 *__restrict__ planes,
                                                  const Pair3 *__restrict__ pairs, int *__restrict__ pv,
                                                  int *__restrict__ ph, int2 *__restrict__ pn,
-                                                 unsigned long long *__restrict__ claim) {
+                                                 unsigned long long *__restrict__ claim, int stamp) {
     __shared__ int vl[PV_CAP];
     __shared__ int hl[PV_CAP];
     __shared__ int tmp[WAVE];
@@ -737,6 +869,11 @@ __global__ __launch_bounds__(64) void k3_visible(const float *__restrict__ x, co
     const int np = min(C->npair, PAIR_CAP);
     for (int p = blockIdx.x; p < np; p += gridDim.x) {
         const Pair3 P = pairs[p];
+        if (!faces[P.f].alive) {
+            if (lane == 0) pn[p] = make_int2(-1, -1);
+            continue;
+        }
+        const unsigned long long prio = claim_prio(P.key, stamp);
         const double qx = pdx(x, P.q), qy = pdx(y, P.q), qz = pdx(z, P.q);
         if (lane == 0) vl[0] = P.f;
         __syncthreads();
@@ -779,11 +916,11 @@ __global__ __launch_bounds__(64) void k3_visible(const float *__restrict__ x, co
         if (ok) {
             for (int i = lane; i < nv; i += WAVE) {
                 pv[(int64_t)p * PV_CAP + i] = vl[i];
-                atomicMax(&claim[vl[i]], P.prio);
+                atomicMax(&claim[vl[i]], prio);
             }
             for (int h = lane; h < nh; h += WAVE) {
                 ph[(int64_t)p * PV_CAP + h] = hl[h];
-                atomicMax(&claim[faces[hl[h] >> 2].nb[hl[h] & 3]], P.prio);
+                atomicMax(&claim[faces[hl[h] >> 2].nb[hl[h] & 3]], prio);
             }
         }
         if (lane == 0) pn[p] = ok ? make_int2(nv, nh) : make_int2(-1, -1);
@@ -801,7 +938,7 @@ __global__ __launch_bounds__(64) void k3_apply(const float *__restrict__ x, cons
                                                int2 *__restrict__ repl, const Pair3 *__restrict__ pairs,
                                                const int *__restrict__ pv, const int *__restrict__ ph,
                                                const int2 *__restrict__ pn,
-                                               const unsigned long long *__restrict__ claim) {
+                                               const unsigned long long *__restrict__ claim, int stamp) {
     __shared__ int ha[PV_CAP], hb[PV_CAP], ho[PV_CAP];
     __shared__ int base;
     const int lane = threadIdx.x;
@@ -811,15 +948,16 @@ __global__ __launch_bounds__(64) void k3_apply(const float *__restrict__ x, cons
         const int2 cnt = pn[p];
         if (cnt.x < 0) continue;
         const Pair3 P = pairs[p];
+        const unsigned long long prio = claim_prio(P.key, stamp);
         const int *V = pv + (int64_t)p * PV_CAP;
         const int *Hz = ph + (int64_t)p * PV_CAP;
         const int NV = cnt.x, NH = cnt.y;
         bool won = true;
-        for (int i = lane; i < NV; i += WAVE) won = won && claim[V[i]] == P.prio;
+        for (int i = lane; i < NV; i += WAVE) won = won && claim[V[i]] == prio;
         for (int h = lane; h < NH; h += WAVE) {
             const int fi = Hz[h] >> 2, e = Hz[h] & 3;
             const int O = faces[fi].nb[e];
-            won = won && claim[O] == P.prio;
+            won = won && claim[O] == prio;
             ha[h] = faces[fi].v[e];
             hb[h] = faces[fi].v[e == 2 ? 0 : e + 1];
             ho[h] = O;
