@@ -725,9 +725,9 @@ static int64_t *seg_stage(const Plan &p, int64_t *segcnt, int r) {
 }
 
 // Region size of list stage r in discard regions (q * TILE entries).
-static int64_t region_mult(int r) {
+static int64_t region_mult(int r, bool batched) {
     int64_t m = 1;
-    for (int i = 0; i < r; i++) m *= ref_group(i);
+    for (int i = 0; i < r; i++) m *= ref_group(i, batched);
     return m;
 }
 
@@ -751,13 +751,14 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
         const int a = r & 1, b = 1 - a;
         const int er = MAX_SLOTS << r;
         int64_t *cin = seg_stage(p, segcnt, r), *cout = seg_stage(p, segcnt, r + 1);
-        const int64_t nin = stage_regions(p.nwave, r), nout = stage_regions(p.nwave, r + 1);
-        const int kg = ref_group(r);
+        const bool batched = S > 1;
+        const int64_t nin = stage_regions(p.nwave, r, batched), nout = stage_regions(p.nwave, r + 1, batched);
+        const int kg = ref_group(r, batched);
         if (S == 1) {    // later rounds (fewer blocks) in blocks of REF_THREADS_LATE
             auto pass = r == 0 ? k_ref_pass<REF_THREADS> : k_ref_pass<REF_THREADS_LATE>;
             const unsigned rt = r == 0 ? REF_THREADS : REF_THREADS_LATE;
             LAUNCH(K_REFINE, pass<<<(unsigned)nout, rt, 0, st>>>(
-                idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r), tab[b], 2 * er,
+                idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r, batched), tab[b], 2 * er,
                 F[(r + 1) % 3], idxs[b], keys[b], eds[b], cout, 1, x, y, tab[a], F[r % 3], tab[b],
                 F[(r + 2) % 3]));
             continue;
@@ -765,7 +766,7 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
             x, y, S, er, tab[a], far[a], tab[b], far[b]));
         LAUNCH(K_REFINE, k_ref_pass<REF_THREADS><<<(unsigned)nout, REF_THREADS, 0, st>>>(
-            idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r), tab[b], 2 * er,
+            idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r, batched), tab[b], 2 * er,
             far[b], idxs[b], keys[b], eds[b], cout, 0, x, y, nullptr, nullptr, nullptr, nullptr));
     }
     return HULL_OK;
@@ -773,11 +774,11 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
 
 // Region list (surv, keys0) of list stage `stage` -> contiguous (cidx,
 // ckeys); ctx->counts[r] gets the total of stage r <= stage.
-static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, int stage) {
+static int run_gather(hull_ctx *ctx, const Plan &p, hipStream_t st, int stage, int64_t S) {
     const int64_t gb = std::max<int64_t>(stage + 1, std::min<int64_t>(256, p.nwave));
     LAUNCH(K_SCATTER, k_seg_gather<<<(unsigned)gb, 256, 0, st>>>(
         W<uint32_t>(p, p.surv), W<uint64_t>(p, p.keys0), W<int64_t>(p, p.segcnt),
-        (int)p.nwave, stage + 1, W<int64_t>(p, p.segmeta), region_mult(stage),
+        (int)p.nwave, stage + 1, (int)(S > 1), W<int64_t>(p, p.segmeta), region_mult(stage, S > 1),
         W<uint32_t>(p, p.cidx), W<uint64_t>(p, p.ckeys), ctx->counts));
     return HULL_OK;
 }
@@ -849,7 +850,7 @@ static int run_compute(hull_ctx *ctx, hipStream_t st, const float *x, const floa
             return rc;
         const int stage = refine ? REF_ROUNDS : 0;
         if (refine && (rc = run_refine(ctx, p, st, x, y, S))) return rc;
-        if ((rc = run_gather(ctx, p, st, stage))) return rc;
+        if ((rc = run_gather(ctx, p, st, stage, S))) return rc;
         surv = W<uint32_t>(p, p.cidx);
         keys = W<uint64_t>(p, p.ckeys);
         cnt = ctx->counts + stage;

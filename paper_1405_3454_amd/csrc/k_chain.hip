@@ -431,6 +431,98 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
     if (lane == 0) cout[v] = (uint32_t)len;
 }
 
+// Copy n keys src -> dst (disjoint) with the whole block, four loads in
+// flight per thread.
+__device__ __forceinline__ void block_copy(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+                                           int64_t n) {
+    constexpr int K = 4;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)nt * K) {
+        uint64_t v[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int64_t i = i0 + (int64_t)k * nt + tid;
+            v[k] = i < n ? src[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int64_t i = i0 + (int64_t)k * nt + tid;
+            if (i < n) dst[i] = v[k];
+        }
+    }
+}
+
+// A group too large for one wave's LDS stage (or a single long chain), by
+// the whole block: thread 0 walks each junction to its bridge in global
+// memory, then every thread copies the next chain's remainder.
+// sh: 3 + 2 * CHAIN_G int64 of LDS.
+template <bool UPPER>
+__device__ void merge_group_block(const uint64_t *__restrict__ in, const uint32_t *__restrict__ cin,
+                                  int64_t U, int64_t R, int64_t v, uint64_t *__restrict__ out,
+                                  uint32_t *__restrict__ cout, int64_t *sh) {
+    const int64_t base = v * R * CHAIN_G;
+    uint64_t *o = out + base;
+    const int64_t u0 = v * CHAIN_G;
+    int64_t *gm = sh + 3, *gls = sh + 3 + CHAIN_G;
+    // each chain's length and the start of its last set segment, in parallel
+    // (the start within [b, m) is max(b, that)); the barrier keeps these
+    // from being overwritten while the previous group still reads them
+    __syncthreads();
+    if (threadIdx.x < CHAIN_G) {
+        const int g = threadIdx.x;
+        const int64_t m = u0 + g < U ? (int64_t)cin[u0 + g] : 0;
+        gm[g] = m;
+        gls[g] = m > 0 ? last_seg_start(in + (u0 + g) * R, 0, m) : 0;
+    }
+    __syncthreads();
+    int64_t len = 0, tailseg = 0;
+    for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
+        const int64_t m = gm[g];
+        if (m == 0) continue;
+        const uint64_t *src = in + (u0 + g) * R;
+        if (threadIdx.x == 0) {
+            int64_t b;
+            const int64_t nl = bridge<UPPER>(o, len, tailseg, src, m, &b);
+            int64_t nt = tailseg;
+            if (b < m) {
+                const int64_t ls = max(b, gls[g]);
+                if (ls > b) nt = nl + (ls - b);
+                else nt = (nl > 0 && key_set(o[nl - 1]) == key_set(src[b])) ? tailseg : nl;
+            }
+            sh[0] = nl;
+            sh[1] = b;
+            sh[2] = nt;
+        }
+        __syncthreads();
+        const int64_t nl = sh[0], b = sh[1], nt = sh[2];
+        if (b < m) {
+            block_copy(src + b, o + nl, m - b);
+            len = nl + (m - b);
+            tailseg = nt;
+        } else {
+            len = nl;
+        }
+        __threadfence_block();
+        __syncthreads();     // sh and the copied keys are read by the next junction
+    }
+    if (threadIdx.x == 0) cout[v] = (uint32_t)len;
+}
+
+// Groups that go to the block form: more keys than a wave stages, or one
+// long chain to move.
+constexpr int64_t BLOCK_COPY_MIN = 2048;
+
+__device__ __forceinline__ bool block_group(const uint32_t *__restrict__ cin, int64_t U, int64_t v) {
+    const int lane = lane_id();
+    const int64_t u0 = v * CHAIN_G;
+    const int64_t mine = (lane < CHAIN_G && u0 + lane < U) ? (int64_t)cin[u0 + lane] : 0;
+    int64_t tot = mine;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
+    const int nonempty = __popcll(__ballot(mine > 0));
+    return tot > MERGE_CAP || (nonempty <= 1 && tot > BLOCK_COPY_MIN);
+}
+
 __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict__ lo_in,
                                                      const uint64_t *__restrict__ up_in,
                                                      const uint32_t *__restrict__ lo_cin,
@@ -463,10 +555,19 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     if (V == 0 && wave == 0 && threadIdx.x == 0)   // no candidates: empty top chain
         (blockIdx.y == 0 ? lo_cout : up_cout)[0] = 0;
     uint64_t *buf = mbuf[threadIdx.x >> 6];
+    const uint32_t *cin = blockIdx.y == 0 ? lo_cin : up_cin;
     for (int64_t v = wave; v < V; v += nw) {        // groups the count actually has
+        if (block_group(cin, U, v)) continue;
         if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lev, lo_out, lo_cout, buf);
         else merge_group<true>(up_in, up_cin, U, R, v, lev, up_out, up_cout, buf);
         wave_sync();
+    }
+    __shared__ int64_t sh[3 + 2 * CHAIN_G];
+    __syncthreads();
+    for (int64_t v = blockIdx.x; v < V; v += gridDim.x) {
+        if (!block_group(cin, U, v)) continue;     // uniform over the block
+        if (blockIdx.y == 0) merge_group_block<false>(lo_in, lo_cin, U, R, v, lo_out, lo_cout, sh);
+        else merge_group_block<true>(up_in, up_cin, U, R, v, up_out, up_cout, sh);
     }
 }
 

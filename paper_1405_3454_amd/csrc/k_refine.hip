@@ -96,8 +96,11 @@ __device__ __forceinline__ void far_put(bool local, RefFar &L, unsigned long lon
 }
 
 constexpr int REF_GROUP = 4;                      // most input regions one block reads
-// input regions per block in round r: fuller chunks early, enough blocks late
-__host__ __device__ inline int ref_group(int r) { return r == 0 ? 4 : 2; }
+// input regions per block in round r.  One set: fuller chunks early, enough
+// blocks late.  Several sets: one region per block (their survivor counts
+// differ with the sets' shapes, and a block walks its chunks in turn, so
+// the fullest block sets the pass's time).
+__host__ __device__ inline int ref_group(int r, bool batched) { return batched ? 1 : r == 0 ? 4 : 2; }
 
 // One round over the survivors.  A list is a row of regions (region r at
 // r * segcap, cnt[r] entries; round 0 reads the discard pass's, one per
@@ -287,9 +290,9 @@ __global__ __launch_bounds__(RT) void k_ref_pass(
 
 // Regions of list stage r (0: the discard pass's, one per wave; round r
 // reads them and writes stage r + 1, one region per group of ref_group(r)).
-__host__ __device__ inline int64_t stage_regions(int64_t nwave, int r) {
+__host__ __device__ inline int64_t stage_regions(int64_t nwave, int r, bool batched) {
     int64_t n = nwave;
-    for (int i = 0; i < r; i++) n = (n + ref_group(i) - 1) / ref_group(i);
+    for (int i = 0; i < r; i++) n = (n + ref_group(i, batched) - 1) / ref_group(i, batched);
     return n;
 }
 
@@ -301,7 +304,7 @@ __host__ __device__ inline int64_t stage_regions(int64_t nwave, int r) {
 __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__ idx,
                                                     const uint64_t *__restrict__ keys,
                                                     const int64_t *__restrict__ cnt_all, int nwave,
-                                                    int nstage,
+                                                    int nstage, int batched,
                                                     const int64_t *__restrict__ region_size,
                                                     int64_t mult,
                                                     uint32_t *__restrict__ idx_out,
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < nstage) {
         const int64_t *c = cnt_all + (int64_t)blockIdx.x * nwave;
-        const int64_t nr = stage_regions(nwave, (int)blockIdx.x);
+        const int64_t nr = stage_regions(nwave, (int)blockIdx.x, batched);
         int64_t a = 0;
         for (int64_t j = tid; j < nr; j += blockDim.x) a += c[j];
         int64_t t;
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__
     }
     // stage nstage - 1: its regions, of size region_size * mult
     const int64_t *cnt = cnt_all + (int64_t)(nstage - 1) * nwave;
-    const int64_t nseg = stage_regions(nwave, nstage - 1);
+    const int64_t nseg = stage_regions(nwave, nstage - 1, batched);
     const int64_t per = (nseg + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = min((int64_t)nseg, (int64_t)blockIdx.x * per);
     const int64_t g1 = min((int64_t)nseg, g0 + per);

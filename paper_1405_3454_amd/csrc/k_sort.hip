@@ -21,9 +21,16 @@ constexpr int RADIX = 256;
 constexpr int SORT_SMALL = 4096;      // up to this many keys one block sorts them (k_sort_small)
 constexpr int SMALL_THREADS = 1024;
 
+// Tiles per block: enough for SORT_BLOCKS blocks, and up to 8 when that
+// keeps the busy blocks at 64 or fewer (the last block's digit scan then
+// holds every block's count in registers in one batch of loads).
+__device__ __forceinline__ int64_t sort_qq(int64_t count) {
+    const int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
+    return max((tiles + SORT_BLOCKS - 1) / SORT_BLOCKS, min((int64_t)8, (tiles + 63) / 64));
+}
+
 __device__ __forceinline__ void sort_range(int64_t count, int64_t b, int64_t *lo, int64_t *hi) {
-    int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
-    int64_t qq = (tiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
+    const int64_t qq = sort_qq(count);
     *lo = min(count, b * qq * SORT_TILE);
     *hi = min(count, (b + 1) * qq * SORT_TILE);
 }
@@ -31,7 +38,7 @@ __device__ __forceinline__ void sort_range(int64_t count, int64_t b, int64_t *lo
 // Blocks of sort_range that hold keys: 0 .. sort_busy(count) - 1.
 __device__ __forceinline__ int64_t sort_busy(int64_t count) {
     const int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
-    const int64_t qq = (tiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
+    const int64_t qq = sort_qq(count);
     return qq ? (tiles + qq - 1) / qq : 0;
 }
 
