@@ -238,6 +238,7 @@ int hull3_compute(hull_ctx *ctx, const float *x, const float *y, const float *z,
                   int flags, void *stream);
 
 /* ---- batched forms (many sets, CSR offsets) ----------------------------
+ * S: 1 .. 65535 sets.
  * offsets: device int64[S+1], non-decreasing, offsets[0] = 0,
  * offsets[S] = n_total (checked with HULL_VALIDATE).  Set s is points
  * [offsets[s], offsets[s+1]).  Indices stay global. */

@@ -674,8 +674,15 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     const int64_t gmax = (int64_t)ctx->cus * 4;       // blocks of 4 waves; kernels loop
     LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::min(gmax, std::max<int64_t>(1, (u0 + 3) / 4)), 256, 0, st>>>(
         sorted, cnt, lo[0], up[0], locnt[0], upcnt[0]));
-    const int L = chain_levels(ncap);
     int cur = 0;
+    if (S > 1) {
+        // several sets: each set's chain from its own chunk pieces
+        const int64_t gs = std::min<int64_t>(gmax, (S + 3) / 4);
+        LAUNCH(K_CHAIN_COMPACT, k_chain_sets<<<dim3((unsigned)gs, 2), 256, 0, st>>>(
+            sorted, cnt, S, lo[0], up[0], locnt[0], upcnt[0], lo[1], up[1], locnt[1], upcnt[1]));
+        cur = 1;
+    }
+    const int L = S > 1 ? 0 : chain_levels(ncap);
     int64_t R = CHAIN_C;
     for (int lev = 0; lev < L; lev++) {
         int64_t ucap = (ncap + R - 1) / R;
@@ -1076,7 +1083,8 @@ int hull_compute(hull_ctx *ctx, const float *x, const float *y, int64_t n, uint3
 
 static int check_batch(const float *x, const float *y, const int64_t *off, int64_t S,
                        int64_t n_total) {
-    if (!off || S <= 0 || S > 65536) return HULL_EINVAL;
+    // set ids fill a key's 16-bit set field; 0xFFFF marks gaps in the hull stage
+    if (!off || S <= 0 || S > 65535) return HULL_EINVAL;
     return check_points(x, y, n_total);
 }
 

@@ -571,6 +571,94 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     }
 }
 
+// Several sets: after the chunk chains, each set's keys are one range
+// [start, end) of the sorted keys and its chain is merged from the pieces
+// the chunks covering that range hold, by one wave, independently of the
+// other sets.  The set's chain goes to out[start, start + len) and the rest
+// of its range is filled with SET_GAP keys (set field beyond every set), so
+// that out[0, cnt) lists every set's chain in set order.  Pieces are joined
+// left to right at their bridges (staged in LDS when the range fits).
+constexpr uint64_t SET_GAP = ~0ull;
+
+// First index i in sorted[0, n) with set(sorted[i]) >= s.
+__device__ __forceinline__ int64_t set_lower_bound(const uint64_t *__restrict__ sorted, int64_t n, uint32_t s) {
+    int64_t a = 0, b = n;
+    while (a < b) {
+        const int64_t m = (a + b) >> 1;
+        if (key_set(sorted[m]) < s) a = m + 1; else b = m;
+    }
+    return a;
+}
+
+// [p0, p1) of set s in a chunk list (sorted by key, so by set).
+__device__ __forceinline__ void piece_of(const uint64_t *list, int64_t m, uint32_t s, int64_t *p0, int64_t *p1) {
+    int64_t a = 0, b = m;
+    while (a < b) {
+        const int64_t h = (a + b) >> 1;
+        if (key_set(list[h]) < s) a = h + 1; else b = h;
+    }
+    int64_t c = a, d = m;
+    while (c < d) {
+        const int64_t h = (c + d) >> 1;
+        if (key_set(list[h]) <= s) c = h + 1; else d = h;
+    }
+    *p0 = a;
+    *p1 = c;
+}
+
+template <bool UPPER>
+__device__ void set_chain(const uint64_t *__restrict__ sorted, int64_t n, uint32_t s,
+                          const uint64_t *__restrict__ lists, const uint32_t *__restrict__ lcnt,
+                          uint64_t *__restrict__ out, uint64_t *__restrict__ buf) {
+    const int lane = lane_id();
+    const int64_t start = set_lower_bound(sorted, n, s), end = set_lower_bound(sorted, n, s + 1);
+    if (start >= end) return;
+    const int64_t c0 = start / CHAIN_C, c1 = (end - 1) / CHAIN_C;
+    const bool staged = end - start <= MERGE_CAP;
+    uint64_t *o = staged ? buf : out + start;
+    int64_t len = 0;
+    for (int64_t c = c0; c <= c1; c++) {
+        const uint64_t *list = lists + c * CHAIN_C;
+        int64_t p0, p1;
+        piece_of(list, (int64_t)lcnt[c], s, &p0, &p1);
+        const int64_t m = p1 - p0;
+        if (m <= 0) continue;
+        const uint64_t *src = list + p0;
+        int64_t b;
+        len = bridge<UPPER>(o, len, 0, src, m, &b);
+        wave_sync();
+        for (int64_t i = b + lane; i < m; i += WAVE) o[len + (i - b)] = src[i];
+        __threadfence_block();
+        wave_sync();
+        len += m - b;
+    }
+    uint64_t *dst = out + start;
+    if (staged)
+        for (int64_t i = lane; i < len; i += WAVE) dst[i] = buf[i];
+    for (int64_t i = len + lane; i < end - start; i += WAVE) dst[i] = SET_GAP;
+    wave_sync();
+}
+
+__global__ __launch_bounds__(256) void k_chain_sets(const uint64_t *__restrict__ sorted,
+                                                    const int64_t *__restrict__ cnt_ptr, int64_t S,
+                                                    const uint64_t *__restrict__ lo_in,
+                                                    const uint64_t *__restrict__ up_in,
+                                                    const uint32_t *__restrict__ lo_cin,
+                                                    const uint32_t *__restrict__ up_cin,
+                                                    uint64_t *__restrict__ lo_out, uint64_t *__restrict__ up_out,
+                                                    uint32_t *__restrict__ lo_len, uint32_t *__restrict__ up_len) {
+    __shared__ uint64_t mbuf[4][MERGE_CAP];
+    const int64_t n = *cnt_ptr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) (blockIdx.y == 0 ? lo_len : up_len)[0] = (uint32_t)n;
+    uint64_t *buf = mbuf[threadIdx.x >> 6];
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t s = wave; s < S; s += nw) {
+        if (blockIdx.y == 0) set_chain<false>(sorted, n, (uint32_t)s, lo_in, lo_cin, lo_out, buf);
+        else set_chain<true>(sorted, n, (uint32_t)s, up_in, up_cin, up_out, buf);
+    }
+}
+
 // Fill helpers (kernels, so that graph capture records no memset node).
 __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
