@@ -672,17 +672,21 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     uint32_t *upcnt[2] = {cc + 2 * p.u0cap, cc + 3 * p.u0cap};
     const int64_t u0 = (ncap + CHAIN_C - 1) / CHAIN_C;
     const int64_t gmax = (int64_t)ctx->cus * 4;       // blocks of 4 waves; kernels loop
+    int *big = S > 1 ? reinterpret_cast<int *>(W<int64_t>(p, p.consts) + 2) : nullptr;
     LAUNCH(K_CHAIN, k_chain_chunks<<<(unsigned)std::min(gmax, std::max<int64_t>(1, (u0 + 3) / 4)), 256, 0, st>>>(
-        sorted, cnt, lo[0], up[0], locnt[0], upcnt[0]));
-    int cur = 0;
+        sorted, cnt, lo[0], up[0], locnt[0], upcnt[0], big));
+    int L = chain_levels(ncap);
     if (S > 1) {
-        // several sets: each set's chain from its own chunk pieces
+        // several sets: each set's chain from its own chunk pieces into
+        // buffer 1; a set of too many pieces raises *big, and the levels
+        // below (which return at once otherwise) merge every chain into
+        // buffer 1 instead (an odd number of levels ends there)
         const int64_t gs = std::min<int64_t>(gmax, (S + 3) / 4);
         LAUNCH(K_CHAIN_COMPACT, k_chain_sets<<<dim3((unsigned)gs, 2), 256, 0, st>>>(
-            sorted, cnt, S, lo[0], up[0], locnt[0], upcnt[0], lo[1], up[1], locnt[1], upcnt[1]));
-        cur = 1;
+            sorted, cnt, S, lo[0], up[0], locnt[0], upcnt[0], lo[1], up[1], locnt[1], upcnt[1], big));
+        if (L % 2 == 0) L++;
     }
-    const int L = S > 1 ? 0 : chain_levels(ncap);
+    int cur = 0;
     int64_t R = CHAIN_C;
     for (int lev = 0; lev < L; lev++) {
         int64_t ucap = (ncap + R - 1) / R;
@@ -690,7 +694,7 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
         dim3 grid((unsigned)std::min(gmax, std::max<int64_t>(1, (vcap + 3) / 4)), 2);
         LAUNCH(K_CHAIN_COMPACT, k_chain_merge<<<grid, 256, 0, st>>>(
             lo[cur], up[cur], locnt[cur], upcnt[cur], cnt, lev, L, lo[1 - cur], up[1 - cur],
-            locnt[1 - cur], upcnt[1 - cur]));
+            locnt[1 - cur], upcnt[1 - cur], big));
         cur = 1 - cur;
         R *= CHAIN_G;
     }

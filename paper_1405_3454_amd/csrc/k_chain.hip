@@ -159,12 +159,14 @@ __global__ __launch_bounds__(256) void k_chain_chunks(const uint64_t *__restrict
                                                       uint64_t *__restrict__ lo,
                                                       uint64_t *__restrict__ up,
                                                       uint32_t *__restrict__ lo_cnt,
-                                                      uint32_t *__restrict__ up_cnt) {
+                                                      uint32_t *__restrict__ up_cnt,
+                                                      int *__restrict__ big) {
     __shared__ Chain0Lds lds[4];
     Chain0Lds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
     const int64_t cnt = *cnt_ptr;
+    if (big && blockIdx.x == 0 && threadIdx.x == 0) *big = 0;   // raised by k_chain_sets
     const int64_t U = (cnt + CHAIN_C - 1) / CHAIN_C;
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
@@ -532,8 +534,10 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
                                                      uint64_t *__restrict__ lo_out,
                                                      uint64_t *__restrict__ up_out,
                                                      uint32_t *__restrict__ lo_cout,
-                                                     uint32_t *__restrict__ up_cout) {
+                                                     uint32_t *__restrict__ up_cout,
+                                                     const int *__restrict__ big) {
     __shared__ uint64_t mbuf[4][MERGE_CAP];
+    if (big && *big == 0) return;      // several sets, all merged per set already
     const int64_t cnt = *cnt_ptr;
     int64_t R = CHAIN_C;
     int first1 = -1;                                      // first level with at most one chain
@@ -606,14 +610,23 @@ __device__ __forceinline__ void piece_of(const uint64_t *list, int64_t m, uint32
     *p1 = c;
 }
 
+// A set spanning more chunks is not merged here: it raises *big, and the
+// hierarchical merge of all chains (k_chain_merge) then runs and replaces
+// this output.
+constexpr int64_t SET_CHUNKS_MAX = 32;
+
 template <bool UPPER>
 __device__ void set_chain(const uint64_t *__restrict__ sorted, int64_t n, uint32_t s,
                           const uint64_t *__restrict__ lists, const uint32_t *__restrict__ lcnt,
-                          uint64_t *__restrict__ out, uint64_t *__restrict__ buf) {
+                          uint64_t *__restrict__ out, uint64_t *__restrict__ buf, int *__restrict__ big) {
     const int lane = lane_id();
     const int64_t start = set_lower_bound(sorted, n, s), end = set_lower_bound(sorted, n, s + 1);
     if (start >= end) return;
     const int64_t c0 = start / CHAIN_C, c1 = (end - 1) / CHAIN_C;
+    if (c1 - c0 + 1 > SET_CHUNKS_MAX) {     // too many pieces for one wave
+        if (lane == 0) atomicOr(big, 1);
+        return;
+    }
     const bool staged = end - start <= MERGE_CAP;
     uint64_t *o = staged ? buf : out + start;
     int64_t len = 0;
@@ -646,7 +659,8 @@ __global__ __launch_bounds__(256) void k_chain_sets(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ lo_cin,
                                                     const uint32_t *__restrict__ up_cin,
                                                     uint64_t *__restrict__ lo_out, uint64_t *__restrict__ up_out,
-                                                    uint32_t *__restrict__ lo_len, uint32_t *__restrict__ up_len) {
+                                                    uint32_t *__restrict__ lo_len, uint32_t *__restrict__ up_len,
+                                                    int *__restrict__ big) {
     __shared__ uint64_t mbuf[4][MERGE_CAP];
     const int64_t n = *cnt_ptr;
     if (blockIdx.x == 0 && threadIdx.x == 0) (blockIdx.y == 0 ? lo_len : up_len)[0] = (uint32_t)n;
@@ -654,8 +668,8 @@ __global__ __launch_bounds__(256) void k_chain_sets(const uint64_t *__restrict__
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
     for (int64_t s = wave; s < S; s += nw) {
-        if (blockIdx.y == 0) set_chain<false>(sorted, n, (uint32_t)s, lo_in, lo_cin, lo_out, buf);
-        else set_chain<true>(sorted, n, (uint32_t)s, up_in, up_cin, up_out, buf);
+        if (blockIdx.y == 0) set_chain<false>(sorted, n, (uint32_t)s, lo_in, lo_cin, lo_out, buf, big);
+        else set_chain<true>(sorted, n, (uint32_t)s, up_in, up_cin, up_out, buf, big);
     }
 }
 
