@@ -336,7 +336,8 @@ def bench_batched(args, dev):
     def batched():
         H.compute_batched_into(x, y, off, hull, ho)
 
-    t_set = _time(per_set, 2, 1)
+    # profiling runs (--only) leave out the 4096 per-set calls
+    t_set = None if getattr(args, "only", None) else _time(per_set, 2, 1)
     t_bat = _time(batched, args.steps, 1)
     H.graph_capture(x, y, off, hull, ho)
     t_graph = _time(H.graph_launch, args.steps, 1)
@@ -350,12 +351,12 @@ def bench_batched(args, dev):
                                    min(16, host_cpu()["usable_threads"]))
     res = {"workload": "%d sets, sizes log-uniform [1e3, 1e6], square/disk/gaussian/annulus" % S,
            "points": int(n),
-           "per_set_gpts": round(n / t_set / 1e9, 3),
+           "per_set_gpts": round(n / t_set / 1e9, 3) if t_set else None,
            "batched_gpts": round(n / t_bat / 1e9, 3),
            "graph_gpts": round(n / t_graph / 1e9, 3),
-           "ms": {"per_set": round(t_set * 1e3, 3), "batched": round(t_bat * 1e3, 3),
+           "ms": {"per_set": round(t_set * 1e3, 3) if t_set else None, "batched": round(t_bat * 1e3, 3),
                   "graph": round(t_graph * 1e3, 3)},
-           "speedup_graph_vs_per_set": round(t_set / t_graph, 2),
+           "speedup_graph_vs_per_set": round(t_set / t_graph, 2) if t_set else None,
            "discard_fraction": round(disc, 6),
            "tuning": tuning}
     if cpu is not None:
@@ -445,11 +446,20 @@ def main():
                     help="only the four 2^27 sets (no unfiltered, batched or learned lines)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", choices=("batched", "3d", "learned"),
+                    help="run only this extra line and print its JSON (for profiling; "
+                         "not the benchmark's result line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method runs each point set on a single "
               "device, and this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        import torch
+        dev = torch.device("cuda:0")
+        fn = {"batched": bench_batched, "3d": bench_3d, "learned": bench_learned}[args.only]
+        print(json.dumps({args.only: fn(args, dev)}), flush=True)
+        return
 
     import torch
     from paper_1405_3454_amd.api import Hull
