@@ -446,6 +446,8 @@ def main():
                     help="only the four 2^27 sets (no unfiltered, batched or learned lines)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--jsonl", metavar="PATH",
+                    help="also append the result line, with its time and arguments, to PATH")
     ap.add_argument("--only", choices=("batched", "3d", "learned"),
                     help="run only this extra line and print its JSON (for profiling; "
                          "not the benchmark's result line)")
@@ -596,6 +598,10 @@ def main():
         "hbm_gbs": {k: round(v, 1) for k, v in hbm.items()},
         "discard_fraction": {k: round(v, 6) for k, v in disc.items()},
         "hull_vertices": hs,
+        # generator seeds of every line (inputs.py draws every point from them)
+        "seeds": {"sets": dict(SEEDS), "batched": {"sizes": 2024, "points": 2025},
+                  "three_d": {k: 900 + len(k) for k in ("cube", "ball", "shell", "gaussian")},
+                  "learned": {"training": 7, "points": 4242}},
         "per_kernel": per_kernel,
         "hull_stage_passes": passes,
         "tuning": tuning,
@@ -626,6 +632,11 @@ def main():
         out["cpu_baseline"] = cpu_baseline(data, min(n, args.cpu_sample))
         out["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(out), flush=True)
+    if args.jsonl:     # the same record, appended with the time it was taken
+        rec = dict(out, recorded_utc=time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()),
+                   argv=sys.argv[1:])
+        with open(args.jsonl, "a") as f:
+            f.write(json.dumps(rec) + "\n")
     if args.skip_extra:
         H.close()
 

@@ -308,6 +308,16 @@ int hull_tuning_table(hull_ctx *ctx, int32_t *rows, int cap);
 int64_t hull_mlp_param_count(void);
 int hull_mlp_set_params(hull_ctx *ctx, const float *params_host, int64_t count);
 int hull_mlp_get_params(hull_ctx *ctx, float *params_host, int64_t count);
+/* Training state, for checkpoint and resume: count = 3 * hull_mlp_param_count()
+ * float32 values in host memory -- the parameters, then Adam's first moments,
+ * then its second moments, each in the parameter order above -- and the step
+ * count (the bias corrections of the next step use step + 1).  After
+ * hull_mlp_set_state the next hull_mlp_train_step continues exactly where the
+ * saved run stopped (hull_mlp_set_params instead starts a new run: moments
+ * zero, step 0).  Synchronous.  Errors: HULL_EINVAL (count, null pointers,
+ * step < 0; get before any parameters were set). */
+int hull_mlp_get_state(hull_ctx *ctx, float *state_host, int64_t count, int64_t *step);
+int hull_mlp_set_state(hull_ctx *ctx, const float *state_host, int64_t count, int64_t step);
 /* hist: device bf16 bits [S][1024]; hist_f32: device float [S][1024] or NULL.
  * offsets NULL means one set of n_total points (S must be 1).  The sample
  * is every ceil(n/16384)-th point; the bins cover a square window centred

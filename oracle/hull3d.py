@@ -35,9 +35,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        # HULL_ORACLE3D_LIB: another build of the same source (the sanitizer test)
+        path = os.environ.get("HULL_ORACLE3D_LIB", _LIB)
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.oracle3_slot_count.argtypes = [I]
         L.oracle3_slot_count.restype = I

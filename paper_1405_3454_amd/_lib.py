@@ -78,6 +78,8 @@ SIGNATURES = {
     "hull_mlp_param_count": (I64, []),
     "hull_mlp_set_params": (I, [P, P, I64]),
     "hull_mlp_get_params": (I, [P, P, I64]),
+    "hull_mlp_get_state": (I, [P, P, I64, P]),
+    "hull_mlp_set_state": (I, [P, P, I64, I64]),
     "hull_histogram_batched": (I, [P, P, P, P, I64, I64, P, P, P]),
     "hull_mlp_forward": (I, [P, P, I64, P, P]),
     "hull_mlp_backward": (I, [P, P, P, I64, P, P]),

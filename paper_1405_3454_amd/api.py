@@ -306,6 +306,20 @@ class Hull:
               "hull_mlp_get_params")
         return p
 
+    def mlp_get_state(self):
+        """(parameters, Adam first moments, Adam second moments) as one float32
+        array of 3 * param_count values, and the step count."""
+        st = np.zeros(3 * self.mlp_param_count(), np.float32)
+        step = ctypes.c_int64(0)
+        check(lib().hull_mlp_get_state(self._h, st.ctypes.data_as(ctypes.c_void_p), st.size,
+                                       ctypes.byref(step)), "hull_mlp_get_state")
+        return st, int(step.value)
+
+    def mlp_set_state(self, state, step):
+        st = np.ascontiguousarray(state, dtype=np.float32)
+        check(lib().hull_mlp_set_state(self._h, st.ctypes.data_as(ctypes.c_void_p), st.size,
+                                       int(step)), "hull_mlp_set_state")
+
     def histogram_batched(self, x, y, offsets=None, stream=None):
         """(bf16 bits as int16 [S][1024], float32 [S][1024])"""
         n = _pts(x, y)

@@ -1573,6 +1573,28 @@ int hull_mlp_get_params(hull_ctx *ctx, float *params, int64_t count) {
     return HULL_OK;
 }
 
+int hull_mlp_get_state(hull_ctx *ctx, float *state, int64_t count, int64_t *step) {
+    if (!ctx || !state || !step || count != 3 * P_TOTAL || !ctx->learned.loaded) return HULL_EINVAL;
+    HIPCHECK(hipSetDevice(ctx->device));
+    HIPCHECK(hipDeviceSynchronize());
+    const LearnedState &L = ctx->learned;
+    HIPCHECK(hipMemcpy(state, L.params, P_TOTAL * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(state + P_TOTAL, L.m1, P_TOTAL * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(state + 2 * P_TOTAL, L.m2, P_TOTAL * sizeof(float), hipMemcpyDeviceToHost));
+    *step = L.step;
+    return HULL_OK;
+}
+
+int hull_mlp_set_state(hull_ctx *ctx, const float *state, int64_t count, int64_t step) {
+    if (!ctx || !state || count != 3 * P_TOTAL || step < 0) return HULL_EINVAL;
+    RC(hull_mlp_set_params(ctx, state, P_TOTAL));      // parameters and their bf16 copies
+    LearnedState &L = ctx->learned;
+    HIPCHECK(hipMemcpy(L.m1, state + P_TOTAL, P_TOTAL * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.m2, state + 2 * P_TOTAL, P_TOTAL * sizeof(float), hipMemcpyHostToDevice));
+    L.step = step;
+    return HULL_OK;
+}
+
 int hull_histogram_batched(hull_ctx *ctx, const float *x, const float *y, const int64_t *offsets,
                            int64_t S, int64_t n_total, uint16_t *hist, float *hist_f32,
                            void *stream) {

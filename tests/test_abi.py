@@ -82,6 +82,10 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.hull_destroy(None) == _lib.HULL_EINVAL
     assert lib.hull_compute(None, None, None, 0, None, None, 0, None) == _lib.HULL_EINVAL
     assert lib.hull_candidate_counts(None, None, 4) == _lib.HULL_EINVAL
+    assert lib.hull_mlp_get_state(None, None, 0, None) == _lib.HULL_EINVAL
+    assert lib.hull_mlp_set_state(None, None, 0, 0) == _lib.HULL_EINVAL
+    assert lib.hull3_compute(None, None, None, None, 0, None, None, None, None, None, 0,
+                             None) == _lib.HULL_EINVAL
 
 
 def test_candidate_direction_table_correctly_rounded(lib):

@@ -211,6 +211,48 @@ def test_train_step_matches_binary64_adam(H):
     assert checked > 0.05 * len(p)
 
 
+def test_checkpoint_resume(H):
+    """Training state saved after one step and restored gives the same next
+    steps bit for bit (parameters, both Adam moments, step count); setting
+    only the parameters starts a new run (zero moments, step 0)."""
+    import torch
+    p = mlp.he_init(77)
+    hb, _ = _hist_batch(H, 64, 21)
+    gains = [torch.from_numpy(np.abs(np.random.default_rng(10 + i).standard_normal((64, 64)))
+                              .astype(np.float32) * 0.01).to("cuda:0") for i in range(3)]
+    H.mlp_set_params(p)
+    H.mlp_train_step(hb, gains[0], 1e-3)
+    ckpt, step = H.mlp_get_state()
+    assert step == 1
+    n = H.mlp_param_count()
+    assert np.any(ckpt[n:2 * n] != 0) and np.any(ckpt[2 * n:] != 0)
+    for g in gains[1:]:
+        H.mlp_train_step(hb, g, 1e-3)
+    run_a, step_a = H.mlp_get_state()
+    H.mlp_set_params(mlp.he_init(78))                  # something else in between
+    H.mlp_train_step(hb, gains[0], 1e-3)
+    H.mlp_set_state(ckpt, step)
+    again, step_again = H.mlp_get_state()
+    assert step_again == 1 and np.array_equal(again, ckpt)
+    for g in gains[1:]:
+        H.mlp_train_step(hb, g, 1e-3)
+    run_b, step_b = H.mlp_get_state()
+    assert step_a == step_b == 3
+    assert np.array_equal(run_a, run_b)
+    # set_params: a fresh run, the same as restoring zero moments at step 0
+    H.mlp_set_params(p)
+    H.mlp_train_step(hb, gains[0], 1e-3)
+    fresh, _ = H.mlp_get_state()
+    z = np.concatenate([p.astype(np.float32), np.zeros(2 * n, np.float32)])
+    H.mlp_set_state(z, 0)
+    H.mlp_train_step(hb, gains[0], 1e-3)
+    fresh2, _ = H.mlp_get_state()
+    assert np.array_equal(fresh, fresh2)
+    from paper_1405_3454_amd._lib import HullError
+    with pytest.raises(HullError):
+        H.mlp_set_state(z[:-1], 0)
+
+
 def test_training_gains_over_plain(H):
     """A short training run on the GPU: the trained proposal discards more
     than the plain 16-extreme filter and more than the untrained network."""
