@@ -1266,23 +1266,20 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                 uint64_t push[4];
 #pragma unroll
                 for (int j = 0; j < 4; j++) push[j] = MODE == DISCARD_MASKS ? slow[j] : (slow[j] | sw[j]);
-                // Each lane writes an entry for every point of a non-empty
-                // ballot: the queued ones packed at qn, the others after them
-                // (overwritten later, or beyond the queue's end), so the
-                // writes need no branch; the queue holds qn + 64 entries.
+                // The queued lanes append in lane order at qn; a lane's own
+                // bit of a wave mask is read back with inverse ballot (the
+                // mask itself as the lane condition).
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     if (push[j]) {
                         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(push[j] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)push[j], 0u));
-                        const int cnt = __popcll(push[j]);
-                        const bool mine = (push[j] >> lane) & 1;
-                        const int p = qn + (mine ? (int)below : cnt + lane - (int)below);
-                        L.q[p] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
-                                 ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
-                                 ((uint64_t)(tpos + c * CHUNK + 4 * lane + j) << 48) |
-                                 (((sw[j] >> lane) & 1) ? Q_OUTSIDE : 0);
-                        qn += cnt;
+                        if (__builtin_amdgcn_inverse_ballot_w64(push[j]))
+                            L.q[qn + (int)below] = (uint64_t)((uint32_t)kx[j] & 0xFFFFFFu) |
+                                                   ((uint64_t)((uint32_t)ky[j] & 0xFFFFFFu) << 24) |
+                                                   ((uint64_t)(tpos + c * CHUNK + 4 * lane + j) << 48) |
+                                                   (__builtin_amdgcn_inverse_ballot_w64(sw[j]) ? Q_OUTSIDE : 0);
+                        qn += __popcll(push[j]);
                     }
                 }
                 if (MODE == DISCARD_MASKS && lane < 4)
