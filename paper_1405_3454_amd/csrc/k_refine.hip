@@ -176,6 +176,8 @@ __global__ __launch_bounds__(RT) void k_ref_pass(
         return (r0 + j) * segcap + (v - pre[j]);
     };
     int64_t outn = 0;                       // entries packed into the region so far
+    int64_t held = -1;                      // several sets: the set held in LDS (ltab, L.v)
+    __shared__ int64_t sfirst;
     if (one_set) {
         for (int e = tid; e < RE_CAP; e += RT) L.v[e] = 0;
         if (tab_par)
@@ -198,19 +200,35 @@ __global__ __launch_bounds__(RT) void k_ref_pass(
             st[i] = in ? edge[a] : RE_DROP;
             ix[i] = in ? idx[a] : 0;
         }
-        // one set in the whole chunk?  (a region can span sets)
+        // one set in the whole chunk?  (a region can span sets)  The set
+        // whose child edges and farthest keys the block holds in LDS stays
+        // there over consecutive chunks of that set; its keys are raised in
+        // global memory when another set's chunk comes, and at the end.
         int64_t s0 = 0;
         bool local = true;
         if (!one_set) {
-            s0 = (int64_t)(keys[addr(jb)] >> 48);
+            if (tid == 0) sfirst = (int64_t)(k[0] >> 48);   // entry jb is thread 0's first
+            __syncthreads();
+            s0 = sfirst;
             bool same = true;
 #pragma unroll
             for (int i = 0; i < REF_PER_THREAD; i++)
                 same = same && (j0 + (int64_t)i * RT >= je || (int64_t)(k[i] >> 48) == s0);
             local = __syncthreads_and(same) != 0;
-            if (local) {
-                for (int e = tid; e < RE_CAP; e += RT) L.v[e] = 0;
-                for (int e = tid; e < er2; e += RT) ltab[e] = tab_nxt[s0 * RE_CAP + e];
+            if (held >= 0 && (!local || s0 != held)) {   // the held set's keys go out
+                for (int e = tid; e < er2; e += RT) {
+                    const unsigned long long v = L.v[e];
+                    if (v) far_update(&far[held * RE_CAP + e], v);
+                }
+                held = -1;
+                __syncthreads();
+            }
+            if (local && held < 0) {
+                for (int e = tid; e < er2; e += RT) {
+                    L.v[e] = 0;
+                    ltab[e] = tab_nxt[s0 * RE_CAP + e];
+                }
+                held = s0;
             }
         }
         __syncthreads();
@@ -268,21 +286,14 @@ __global__ __launch_bounds__(RT) void k_ref_pass(
             edge_out[pos] = st[i];
         }
         outn += ktot;
-        if (!one_set) {
-            __syncthreads();
-            if (local)
-                for (int e = tid; e < RE_CAP; e += RT) {
-                    const unsigned long long v = L.v[e];
-                    if (v) far_update(&far[s0 * RE_CAP + e], v);
-                }
-        }
         __syncthreads();
     }
-    if (one_set) {
+    if (one_set || held >= 0) {
         __syncthreads();
+        const int64_t fs = one_set ? 0 : held;
         for (int e = tid; e < er2; e += RT) {
             const unsigned long long v = L.v[e];
-            if (v) far_update(&far[e], v);
+            if (v) far_update(&far[fs * RE_CAP + e], v);
         }
     }
     if (tid == 0) cnt_out[g] = outn;
