@@ -320,7 +320,8 @@ int hull_mlp_get_state(hull_ctx *ctx, float *state_host, int64_t count, int64_t 
 int hull_mlp_set_state(hull_ctx *ctx, const float *state_host, int64_t count, int64_t step);
 /* hist: device bf16 bits [S][1024]; hist_f32: device float [S][1024] or NULL.
  * offsets NULL means one set of n_total points (S must be 1).  The sample
- * is every ceil(n/16384)-th point; the bins cover a square window centred
+ * is every point when n <= 16384, else 256 runs of 64 consecutive points,
+ * run r starting at floor(r (n - 64) / 255); the bins cover a square window centred
  * on the sample's bounding box, its side the box's longer side (so the
  * set's aspect ratio is kept); value = count * 1024 / sample size. */
 int hull_histogram_batched(hull_ctx *ctx, const float *x, const float *y,

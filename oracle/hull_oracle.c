@@ -346,18 +346,29 @@ int oracle_compute(const float *x, const float *y, int64_t n,
  * min ky - (w - wy) / 2) and bx = (kx - start x) * 32 / w in integer
  * arithmetic, likewise by.  hist[by * 32 + bx] = count * 1024 / ns (binary64
  * product and quotient, rounded to float), ns the sample size. */
+/* Index of sample j (j < oracle_hist_samples(n)) of a set of n points: all
+ * points when n <= 16384, else 256 runs of 64 consecutive points, run r
+ * starting at floor(r (n - 64) / 255) (the first at 0, the last ending at
+ * n - 1; the runs are disjoint since (n - 64) / 255 >= 64). */
+static int64_t oracle_hist_samples(int64_t n) { return n <= 16384 ? n : 16384; }
+static int64_t oracle_hist_index(int64_t n, int64_t j)
+{
+    if (n <= 16384) return j;
+    return (j / 64) * (n - 64) / 255 + j % 64;
+}
+
 void oracle_histogram(const float *x, const float *y, int64_t n, float *hist)
 {
     int64_t cnt[1024];
     memset(cnt, 0, sizeof(cnt));
     for (int b = 0; b < 1024; b++) hist[b] = 0.0f;
     if (n <= 0) return;
-    int64_t stride = (n + 16383) / 16384;
-    int64_t ns = (n + stride - 1) / stride;
+    const int64_t ns = oracle_hist_samples(n);
     int64_t x0 = INT64_MAX, x1 = INT64_MIN, y0 = INT64_MAX, y1 = INT64_MIN;
     for (int64_t j = 0; j < ns; j++) {
-        int64_t kx = (int64_t)((double)x[j * stride] * 16777216.0);
-        int64_t ky = (int64_t)((double)y[j * stride] * 16777216.0);
+        const int64_t i = oracle_hist_index(n, j);
+        int64_t kx = (int64_t)((double)x[i] * 16777216.0);
+        int64_t ky = (int64_t)((double)y[i] * 16777216.0);
         if (kx < x0) x0 = kx;
         if (kx > x1) x1 = kx;
         if (ky < y0) y0 = ky;
@@ -366,8 +377,9 @@ void oracle_histogram(const float *x, const float *y, int64_t n, float *hist)
     int64_t wx = x1 - x0 + 1, wy = y1 - y0 + 1, w = wx > wy ? wx : wy;
     int64_t sx = x0 - (w - wx) / 2, sy = y0 - (w - wy) / 2;
     for (int64_t j = 0; j < ns; j++) {
-        int64_t kx = (int64_t)((double)x[j * stride] * 16777216.0);
-        int64_t ky = (int64_t)((double)y[j * stride] * 16777216.0);
+        const int64_t i = oracle_hist_index(n, j);
+        int64_t kx = (int64_t)((double)x[i] * 16777216.0);
+        int64_t ky = (int64_t)((double)y[i] * 16777216.0);
         int64_t bx = (kx - sx) * 32 / w;
         int64_t by = (ky - sy) * 32 / w;
         cnt[by * 32 + bx]++;

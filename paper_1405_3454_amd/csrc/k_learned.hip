@@ -53,6 +53,7 @@ __constant__ double dCandSin[NCAND];
 
 constexpr int HBINS = 1024;                   // 32 x 32 histogram
 constexpr int HSAMPLE = 16384;                // at most this many sampled points
+constexpr int HRUNS = HSAMPLE / WAVE;          // in runs of WAVE consecutive points
 constexpr int L1 = 512, L2 = 512, NOUT = NCAND;
 // parameter layout (float32): W1[512][1024] b1[512] W2[512][512] b2[512] W3[64][512] b3[64]
 constexpr int64_t P_W1 = 0, P_B1 = P_W1 + (int64_t)L1 * HBINS, P_W2 = P_B1 + L1,
@@ -106,16 +107,18 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist32(const float *__restrict
         }
         return;
     }
-    // every sample point j * stride (j < ns <= HSAMPLE) loaded once, all of a
-    // thread's loads issued together
-    const int64_t stride = (n + HSAMPLE - 1) / HSAMPLE;
-    const int64_t ns = (n + stride - 1) / stride;
+    // the sample: every point when n <= HSAMPLE, else HRUNS runs of WAVE
+    // consecutive points, run r from floor(r (n - WAVE) / (HRUNS - 1)); each
+    // sample loaded once, all of a thread's loads issued together (a wave
+    // reads one run: whole cache lines)
+    const int64_t ns = n <= HSAMPLE ? n : HSAMPLE;
     int32_t kx[HPER], ky[HPER];
 #pragma unroll
     for (int i = 0; i < HPER; i++) {
         const int64_t j = tid + (int64_t)i * HIST_THREADS;
-        kx[i] = j < ns ? (int32_t)(x[a + j * stride] * GRIDF) : 0;
-        ky[i] = j < ns ? (int32_t)(y[a + j * stride] * GRIDF) : 0;
+        const int64_t p = n <= HSAMPLE ? j : (j / WAVE) * (n - WAVE) / (HRUNS - 1) + j % WAVE;
+        kx[i] = j < ns ? (int32_t)(x[a + p] * GRIDF) : 0;
+        ky[i] = j < ns ? (int32_t)(y[a + p] * GRIDF) : 0;
     }
     int32_t x0 = 0x7fffffff, x1 = -1, y0 = 0x7fffffff, y1 = -1;
 #pragma unroll

@@ -317,12 +317,25 @@ def test_histogram_hand_cases():
     assert (h == want).all()
     h = oracle.histogram(to_float([7] * 10), to_float([9] * 10))
     assert h[0] == 1024.0 and h[1:].sum() == 0
-    # stride: n = 16385 -> every 2nd point, 8193 samples, all at kx = 0 and
-    # ky = 0; the 1 x 1 box becomes a 1 x 1 window
-    kx = np.arange(16385) % 2 * 1000
-    h = oracle.histogram(to_float(kx), to_float(np.zeros(16385, np.int64)))
-    assert h.sum() == pytest.approx(1024.0, rel=1e-6)
-    assert h[0] == np.float32(8193 * 1024.0 / 8193) and h[31] == 0.0
+    # runs: n = 64 + 255 * 128 = 32704 -> 256 runs of 64 points starting at
+    # multiples of 128, i.e. the points i with i % 128 < 64; every sampled
+    # point sits at (0, 0) and every other one at (1000, 1000), so the
+    # sampled points alone give a 1 x 1 window and all the mass in bin 0
+    i = np.arange(32704)
+    kx = np.where(i % 128 < 64, 0, 1000)
+    h = oracle.histogram(to_float(kx), to_float(kx))
+    assert h[0] == 1024.0 and h[1:].sum() == 0
+    # one more point: run r starts at floor(r * 32641 / 255) = 128 r + floor(r / 255),
+    # so only the last run moves (to 32641 .. 32704) and point 32704 is sampled
+    kx2 = np.concatenate([kx, [1000]])
+    kx2[32640] = 1000        # the last run's old first point, now unsampled
+    kx2[32641:] = 0
+    h = oracle.histogram(to_float(kx2), to_float(kx2))
+    assert h[0] == 1024.0 and h[1:].sum() == 0
+    # 16384 points or fewer: every point (a 2 x 1 box in a 2 x 2 window: bins 0 and 16)
+    kx3 = np.arange(16384) % 2
+    h = oracle.histogram(to_float(kx3), to_float(np.zeros(16384, np.int64)))
+    assert h.sum() == pytest.approx(1024.0, rel=1e-6) and np.count_nonzero(h) == 2
     # aspect ratio kept: a 3200 x 100 box sits in the middle rows of a
     # 3200 x 3200 window (origin y = -1550): rows 15 and 16 only
     kx = np.array([0, 3199, 1600, 0, 3199], np.int64)
