@@ -26,11 +26,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch at 2^27 points, from two rocprofv3 counter runs
-# (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0: the factors a 1 GiB device
-# copy gives), averaged over the four sets; reported only while the filter
-# kernels' sources hash to the value they had when the counters were taken.
-TRAFFIC = {"discard": 1.1869e+09, "extremes": 1.0971e+09}
+# HBM bytes per launch of the step (one launch over the four 2^27-point
+# sets), from two rocprofv3 counter runs (FETCH_SIZE scaled by 2.0,
+# WRITE_SIZE by 1.0: the factors a 1 GiB device copy gives); reported only
+# while the filter kernels' sources hash to the value they had when the
+# counters were taken.
+TRAFFIC = {}
 TRAFFIC_SOURCES = ("paper_1405_3454_amd/csrc/k_filter.hip", "paper_1405_3454_amd/csrc/hg_common.h",
                    "paper_1405_3454_amd/csrc/hg_device.h")
 TRAFFIC_SHA = "cec7bc2283e404d2"
@@ -472,18 +473,29 @@ def main():
     print("[bench] generated %d x %d points in %.1fs" % (len(KINDS), n, time.time() - t0),
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
-    X = {k: torch.from_numpy(v[0]).to(dev) for k, v in data.items()}
-    Y = {k: torch.from_numpy(v[1]).to(dev) for k, v in data.items()}
+    # the four sets side by side in HBM (CSR offsets); X[k], Y[k] are views
+    xb = torch.from_numpy(np.concatenate([data[k][0] for k in KINDS])).to(dev)
+    yb = torch.from_numpy(np.concatenate([data[k][1] for k in KINDS])).to(dev)
+    offb = torch.tensor([i * n for i in range(len(KINDS) + 1)], dtype=torch.int64, device=dev)
+    X = {k: xb[i * n:(i + 1) * n] for i, k in enumerate(KINDS)}
+    Y = {k: yb[i * n:(i + 1) * n] for i, k in enumerate(KINDS)}
     if args.no_cpu:
         del data
     H = Hull(0, preset=args.preset)
-    tuning = [] if args.no_autotune else H.autotune(X["disk"], Y["disk"])
+    # launch shapes tuned for the step (the batch) and for the one-set calls
+    # of the diagnostics and the direction-family lines
+    tuning = [] if args.no_autotune else H.autotune(xb, yb, offb)
+    if not args.no_autotune:
+        H.autotune(X["disk"], Y["disk"])
+        tuning = H.tuning_table()
     hull = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in KINDS}
     hcnt = {k: torch.zeros(1, dtype=torch.int64, device=dev) for k in KINDS}
+    hb = torch.empty(len(KINDS) * n, dtype=torch.int32, device=dev)
+    hob = torch.zeros(len(KINDS) + 1, dtype=torch.int64, device=dev)
 
     def step():
-        for k in KINDS:
-            H.compute_into(X[k], Y[k], hull[k], hcnt[k])
+        # the whole method on each of the four sets, in one batched call
+        H.compute_batched_into(xb, yb, offb, hb, hob)
 
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -541,26 +553,27 @@ def main():
                          "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
         passes[k] = row
 
+    total_pts = len(KINDS) * n
     # survivors per set (discard fraction) from one extra discard call each
     disc = {}
-    hs = {}
+    hob_c = hob.cpu().tolist()
+    hs = {k: int(hob_c[i + 1] - hob_c[i]) for i, k in enumerate(KINDS)}
     for k in KINDS:
         slots, _ = H.extremes(X[k], Y[k])
         surv = torch.empty(n, dtype=torch.int32, device=dev)
         cnt = torch.zeros(1, dtype=torch.int64, device=dev)
         H.discard_into(X[k], Y[k], slots, surv, cnt)
         disc[k] = 1.0 - cnt.item() / n
-        hs[k] = int(hcnt[k].item())
+        assert hs[k] == int(hcnt[k].item()), "batched and one-set hulls differ"
 
-    total_pts = len(KINDS) * n
     per_kernel = {name: {"ms_total": round(ms / args.steps, 4), "launches_per_step": c / args.steps,
                          "ms_mean": round(ms / c, 4)} for name, (ms, c) in kt.items()}
     # roofline of the dominant kernel by time per step; algorithmic bytes per
-    # launch, averaged over the four sets: the extremes pass reads x and y
-    # (8 B per point); the full method's discard pass reads them and writes
+    # launch (one launch covers the four sets): the extremes pass reads x and
+    # y (8 B per point); the full method's discard pass reads them and writes
     # each survivor's index, key and round-0 edge (4 + 8 + 2 B)
-    surv_mean = sum((1.0 - disc[k]) * n for k in KINDS) / len(KINDS)
-    alg_bytes = {"extremes": 8.0 * n, "discard": 8.0 * n + 14.0 * surv_mean}
+    surv_all = sum((1.0 - disc[k]) * n for k in KINDS)
+    alg_bytes = {"extremes": 8.0 * total_pts, "discard": 8.0 * total_pts + 14.0 * surv_all}
     # categories that time one kernel each (scan and misc group small helpers)
     dom = max(((k, v) for k, v in kt.items() if k not in ("scan", "misc")),
               key=lambda kv: kv[1][0])[0]
@@ -575,6 +588,7 @@ def main():
     roof = {"kernel": rname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": _traffic(rname, args.log2n),
+            "launch": "one launch over the four sets",
             "dominant_by_time": dom}
 
     out = {
@@ -593,6 +607,7 @@ def main():
         "config": {"workload": "4 sets x 2^%d points (square, disk r=0.5, gaussian s=0.15, "
                                "annulus 0.45..0.5), float32 k*2^-24" % args.log2n,
                    "points_per_step": total_pts,
+                   "calls": "one batched call per step (CSR offsets over the four sets)",
                    "directions": PRESET_NAMES[args.preset]},
         "roofline": roof,
         "hbm_gbs": {k: round(v, 1) for k, v in hbm.items()},
@@ -608,22 +623,21 @@ def main():
     }
     out["latency_100k"] = bench_latency(dev)
     if not args.skip_extra:
-        # unfiltered arm: the same hull without the filter (sort + chain of all points)
-        hull_u = torch.empty(n, dtype=torch.int32, device=dev)
-        hu = torch.zeros(1, dtype=torch.int64, device=dev)
+        # unfiltered arm: the same hull without the filter (sort + chain of
+        # all points), the same one batched call per step
+        hob_u = torch.zeros(len(KINDS) + 1, dtype=torch.int64, device=dev)
 
         def step_u():
-            for k in KINDS:
-                H.compute_into(X[k], Y[k], hull_u, hu, nofilter=True)
+            H.compute_batched_into(xb, yb, offb, hb, hob_u, nofilter=True)
         t_u = _time(step_u, max(2, args.steps // 2), 1)
+        assert hob_u.cpu().tolist() == hob_c, "unfiltered and filtered hulls differ"
         out["unfiltered"] = {"gpts": round(total_pts / t_u / 1e9, 3),
                              "ms_per_step": round(t_u * 1e3, 3),
                              "speedup_of_filter": round(t_u / dt, 3)}
-        del hull_u
         out["direction_families"] = bench_directions(args, X, Y, n)
         out["host_resident"] = bench_host(args, X, Y, n)
         H.close()
-        del X, Y, hull
+        del X, Y, hull, xb, yb, hb
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(args, dev)
         out["three_d"] = bench_3d(args, dev)

@@ -423,6 +423,14 @@ static Launch k3_launch(const hull_ctx *ctx, int64_t n, int64_t S) {
     const Shape sh = shape_of(ctx, 1, n, S);
     return make_launch(ctx, sh, k3_kernel(sh.bs), n, S);
 }
+// Regions of the full method's survivor lists: one per discard wave for one
+// set; for several sets DYN_REGIONS per wave, which the waves take in turn
+// (the sets' tiles differ in cost, so equal shares would leave waves idle).
+constexpr int DYN_REGIONS = 4;
+static int64_t regions_for(int64_t waves, int64_t S) { return waves * (S > 1 ? DYN_REGIONS : 1); }
+static int64_t region_count(const hull_ctx *ctx, int64_t n, int64_t S) {
+    return regions_for(k3_launch(ctx, n, S).waves, S);
+}
 
 // ---------------------------------------------------------------------------
 // Launch sequences
@@ -569,11 +577,11 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     if (nedge <= FIXED_SLOTS)
         LAUNCH(K_DISCARD, (launch_k3<FIXED_SLOTS, DISCARD_MASKS>(
             L, st, x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges,
-            masks, tcnt, nu, nk, ne, nc, nm, nf)));
+            masks, tcnt, nu, nk, ne, nc, nm, nf, L.waves, nullptr)));
     else
         LAUNCH(K_DISCARD, (launch_k3<MAX_SLOTS, DISCARD_MASKS>(
             L, st, x, y, n_total, phase_of(x), off, n1, S, tile_off, tile_set, polys, spans, redges,
-            masks, tcnt, nu, nk, ne, nc, nm, nf)));
+            masks, tcnt, nu, nk, ne, nc, nm, nf, L.waves, nullptr)));
     int rc = run_scan(ctx, p, st, tcnt, tile_off + S, tpos);
     if (rc) return rc;
     LAUNCH(K_SCATTER, k_set_offsets<<<(unsigned)((S + 256) / 256), 256, 0, st>>>(tile_off, tpos, S,
@@ -583,10 +591,11 @@ static int run_discard(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     return HULL_OK;
 }
 
-// Step 3 for the full method: survivors written to one region per discard
-// wave of (surv, keys[, edges]), region counts to seg_cnt[p.nwave] and the
-// region size to segmeta[0]; with gfar, also the refinement's round-0 edge
-// states and farthest points.
+// Step 3 for the full method: survivors written to the regions of
+// (surv, keys[, edges]) -- one per discard wave for one set, DYN_REGIONS per
+// wave for several sets, taken by the waves in turn from a counter --,
+// region counts to seg_cnt[p.nwave] and the region size to segmeta[0]; with
+// gfar, also the refinement's round-0 edge states and farthest points.
 static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, const float *x,
                               const float *y, int64_t n_total, const int64_t *off, int64_t n1,
                               int64_t S, int nedge, uint32_t *surv, uint64_t *keys,
@@ -598,14 +607,19 @@ static int run_discard_append(hull_ctx *ctx, const Plan &p, hipStream_t st, cons
     const uint32_t *redges = W<uint32_t>(p, p.redges);
     int64_t *meta = W<int64_t>(p, p.segmeta);
     const Launch L = k3_launch(ctx, n_total, S);
-    if (L.waves != p.nwave) return HULL_EINVAL;   // the plan's regions assume this grid
+    if (region_count(ctx, n_total, S) != p.nwave) return HULL_EINVAL;   // the plan's regions
     const int ph = phase_of(x);
     uint64_t *nmask = nullptr;
     uint32_t *ncnt = nullptr;
+    int *ctr = nullptr;
+    if (S > 1) {       // regions handed out by a counter, cleared by a kernel (graph-safe)
+        ctr = reinterpret_cast<int *>(W<int64_t>(p, p.consts) + 3);
+        LAUNCH(K_MISC, k_fill_i64<<<1, 64, 0, st>>>(W<int64_t>(p, p.consts) + 3, 1, 0));
+    }
 #define K3A(NE, MODE)                                                                             \
     LAUNCH(K_DISCARD, (launch_k3<NE, MODE>(L, st, x, y, n_total, ph, off, n1, S, tile_off,       \
                                            tile_set, polys, spans, redges, nmask, ncnt, surv,    \
-                                           keys, edges, seg_cnt, meta, gfar)))
+                                           keys, edges, seg_cnt, meta, gfar, p.nwave, ctr)))
     if (gfar) {
         if (nedge <= FIXED_SLOTS) K3A(FIXED_SLOTS, DISCARD_ASSIGN);
         else K3A(MAX_SLOTS, DISCARD_ASSIGN);
@@ -804,7 +818,7 @@ static int init_cand_table();
 
 static int prepare(hull_ctx *ctx, int64_t n, int64_t S, hipStream_t st, Plan *p) {
     HIPCHECK(hipSetDevice(ctx->device));
-    *p = make_plan(n, S, k3_launch(ctx, n, S).waves);
+    *p = make_plan(n, S, region_count(ctx, n, S));
     int rc = ensure_ws(ctx, p->total, st);
     p->base = ctx->ws;
     return rc;
@@ -1146,7 +1160,7 @@ int hull_graph_capture(hull_ctx *ctx, const float *x, const float *y, const int6
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     HIPCHECK(hipSetDevice(ctx->device));
-    Plan p = make_plan(n_total, S, k3_launch(ctx, n_total, S).waves);
+    Plan p = make_plan(n_total, S, region_count(ctx, n_total, S));
     if ((rc = ensure_ws(ctx, p.total, st))) return rc;
     p.base = ctx->ws;
     if ((flags & HULL_LEARNED) && !(flags & HULL_NOFILTER)) {
@@ -1296,7 +1310,8 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     // one workspace for every candidate: only the region counts at the
     // plan's end depend on the discard pass's waves
     int64_t wmax = 1;
-    for (const Shape &sh : c3) wmax = std::max(wmax, make_launch(ctx, sh, k3_kernel(sh.bs), n_total, S).waves);
+    for (const Shape &sh : c3)
+        wmax = std::max(wmax, regions_for(make_launch(ctx, sh, k3_kernel(sh.bs), n_total, S).waves, S));
     Plan big = make_plan(n_total, S, wmax);
     int rc = ensure_ws(ctx, big.total, st);
     if (rc) return rc;
@@ -1342,7 +1357,7 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     for (size_t i = 0; !rc && i < c3.size(); i++) {
         ctx->tuned[1][b] = c3[i];
         ctx->has_tuned[1][b] = true;
-        Plan pc = make_plan(n_total, S, k3_launch(ctx, n_total, S).waves);
+        Plan pc = make_plan(n_total, S, region_count(ctx, n_total, S));
         pc.base = ctx->ws;
         float ms = 0;
         rc = timed([&]() {

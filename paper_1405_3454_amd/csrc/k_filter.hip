@@ -1123,22 +1123,29 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const Span *__restrict__ spans, const uint32_t *__restrict__ redges,
     uint64_t *__restrict__ masks, uint32_t *__restrict__ tile_cnt, uint32_t *__restrict__ surv,
     uint64_t *__restrict__ keys, uint16_t *__restrict__ edges, int64_t *__restrict__ seg_cnt,
-    int64_t *__restrict__ seg_meta, unsigned long long *__restrict__ gfar) {
+    int64_t *__restrict__ seg_meta, unsigned long long *__restrict__ gfar, int64_t nreg,
+    int *__restrict__ regctr) {
     __shared__ DiscardLds lds[BS / WAVE];
     DiscardLds &L = lds[threadIdx.x >> 6];
     const int lane = lane_id();
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t W = (int64_t(gridDim.x) * blockDim.x) >> 6;
     const int64_t T = tile_off[S];
-    const int64_t q = (T + W - 1) / W;
-    const int64_t t0 = wave * q, t1 = min(t0 + q, T);
-    if (MODE != DISCARD_MASKS) {
-        if (wave == 0 && lane == 0) seg_meta[0] = q * TILE;
-        if (t0 >= t1 && lane == 0) seg_cnt[wave] = 0;
-    }
-    if (t0 >= t1) return;
-    // DISCARD_APPEND/ASSIGN: this wave's output region starts at t0 * TILE
-    AppendOut ao{surv, keys, edges, t0 * TILE, 0, 0, 0};
+    // Regions: q consecutive tiles each.  Without regctr region w is wave
+    // w's; with it (appending modes, several sets) there are nreg regions and
+    // each wave takes the next one from *regctr until none is left, so the
+    // waves that meet cheap tiles take more (sets differ in cost per tile).
+    // A region's survivors go to its own part of the list, [r q TILE, ...).
+    const int64_t R = regctr ? nreg : W;
+    const int64_t q = (T + R - 1) / R;
+    if (MODE != DISCARD_MASKS && wave == 0 && lane == 0) seg_meta[0] = q * TILE;
+    auto next_region = [&](int64_t cur) -> int64_t {
+        if (!regctr) return cur < 0 ? wave : R;
+        int v = 0;
+        if (lane == 0) v = atomicAdd(regctr, 1);
+        return (int64_t)__shfl(v, 0);
+    };
+    AppendOut ao{surv, keys, edges, 0, 0, 0, 0};
 
     int64_t o0 = 0, o1 = 0, tile0 = 0, abase = 0, cur_end = -1, cur_s = -1;
     int qn = 0;                 // queued points (wave-uniform)
@@ -1148,6 +1155,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     uint32_t yext = 0;          // in the polygon's y-range: (ky - ymin) <= yext
     bool has_rows = false;
 
+    for (int64_t r = next_region(-1); r < R; r = next_region(r)) {
+    const int64_t t0 = r * q, t1 = min(t0 + q, T);
+    if (t0 >= t1) {
+        if (MODE != DISCARD_MASKS && lane == 0) seg_cnt[r] = 0;
+        continue;
+    }
+    ao.at = t0 * TILE;
     for (int64_t t = t0; t < t1; ++t) {
         if (t >= cur_end) {     // a new set starts (looked up once per set)
             // the queue holds the previous set's points: test them against
@@ -1309,12 +1323,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         }
         wave_sync();
     }
+    // the region's queued points, then its count
     if (MODE != DISCARD_MASKS && qn > 0) {
         wave_sync();
         drain<NEDGE, MODE>(L, 0, qn, ky_lo, shift, ylim, ao);
+        qn = 0;
+        wave_sync();
     }
-    if (MODE == DISCARD_ASSIGN) far_flush(L, gfar, cur_s);
-    if (MODE != DISCARD_MASKS && lane == 0) seg_cnt[wave] = ao.at - t0 * TILE;
+    if (MODE != DISCARD_MASKS && lane == 0) seg_cnt[r] = ao.at - t0 * TILE;
+    }
+    if (MODE == DISCARD_ASSIGN && cur_s >= 0) far_flush(L, gfar, cur_s);
 }
 
 // ---------------------------------------------------------------------------

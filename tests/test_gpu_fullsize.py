@@ -62,3 +62,40 @@ def test_full_size(H, kind, preset):
     assert np.array_equal(g_surv, o_surv)
     o_hull = oracle.hull_subset(x, y, o_surv)
     assert np.array_equal(g_hull, o_hull)
+    if preset == 0:
+        _OHULL[kind] = o_hull
+
+
+_OHULL = {}
+KINDS = ("square", "disk", "gaussian", "annulus")
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_full_size_one_batched_call(H, tuned):
+    """The four sets in one batched call of the whole method, the way
+    bench.py's main line runs them (tuned: after the autotuner has picked
+    the launch shapes on this batch; else the default shapes): each set's
+    hull equals the oracle's."""
+    import torch
+    from paper_1405_3454_amd.api import as_u32
+    xs = [_points(k) for k in KINDS]
+    xb = torch.from_numpy(np.concatenate([p[0] for p in xs])).to("cuda:0")
+    yb = torch.from_numpy(np.concatenate([p[1] for p in xs])).to("cuda:0")
+    off = torch.tensor([i * N for i in range(5)], dtype=torch.int64, device="cuda:0")
+    hb = torch.empty(4 * N, dtype=torch.int32, device="cuda:0")
+    ho = torch.zeros(5, dtype=torch.int64, device="cuda:0")
+    H.set_directions(0)
+    if tuned:       # the untuned case runs first (parameter order): default shapes
+        H.autotune(xb, yb, off)
+    H.compute_batched_into(xb, yb, off, hb, ho)
+    hoc = ho.cpu().numpy()
+    got = as_u32(hb[: int(hoc[-1])]).astype(np.int64)
+    del xb, yb, hb
+    for i, k in enumerate(KINDS):
+        want = _OHULL.get(k)
+        if want is None:
+            x, y = xs[i]
+            want = oracle.compute(x, y, 0)
+            _OHULL[k] = want
+        g = got[hoc[i]:hoc[i + 1]] - i * N
+        assert np.array_equal(g, want.astype(np.int64)), k
