@@ -1321,9 +1321,10 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     hipEvent_t ea, eb;
     HIPCHECK(hipEventCreate(&ea));
     HIPCHECK(hipEventCreate(&eb));
+    // a candidate's time: the best of four runs after a warm-up one
     auto timed = [&](auto &&fn, float *best_ms) -> int {
-        float tot = 0;
-        for (int rep = 0; rep < 3; rep++) {
+        float best = 1e30f;
+        for (int rep = 0; rep < 5; rep++) {
             HIPCHECK(hipEventRecord(ea, st));
             int r = fn();
             if (r) return r;
@@ -1331,9 +1332,9 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
             HIPCHECK(hipEventSynchronize(eb));
             float ms = 0;
             HIPCHECK(hipEventElapsedTime(&ms, ea, eb));
-            if (rep) tot += ms;
+            if (rep) best = std::min(best, ms);
         }
-        *best_ms = tot;
+        *best_ms = best;
         return HULL_OK;
     };
     const bool had1 = ctx->has_tuned[0][b], had3 = ctx->has_tuned[1][b];
