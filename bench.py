@@ -184,25 +184,28 @@ PRESET_NAMES = {0: "0/30/45/60 (paper)", 1: "0/30/75/120 (cumulative)", 2: "4 ev
                 3: "8 even", 4: "12 even", 5: "16 even", 6: "20 even", 7: "24 even"}
 
 
-def bench_directions(args, X, Y, n):
+def bench_directions(args, xb, yb, offb, X, Y, n):
     """Discard-vs-cost curve of the direction families: the whole method on
-    the same four sets under every preset (extremes pass cost grows with the
-    direction count, the discard fraction with it)."""
+    the same four sets under every preset, as the main line runs it (one
+    batched call per step, shapes tuned for the batch); the extremes pass
+    cost grows with the direction count, the discard fraction with it."""
     import torch
     from paper_1405_3454_amd.api import Hull
-    dev = X[KINDS[0]].device
-    hull = torch.empty(n, dtype=torch.int32, device=dev)
-    hcnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    dev = xb.device
+    S = offb.numel() - 1
+    hb = torch.empty(S * n, dtype=torch.int32, device=dev)
+    hob = torch.zeros(S + 1, dtype=torch.int64, device=dev)
     surv = torch.empty(n, dtype=torch.int32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     steps = max(2, args.steps // 2)
     curve = []
     for preset in range(8):
         H = Hull(0, preset=preset)
+        if not args.no_autotune:
+            H.autotune(xb, yb, offb)
 
         def step():
-            for k in KINDS:
-                H.compute_into(X[k], Y[k], hull, hcnt)
+            H.compute_batched_into(xb, yb, offb, hb, hob)
         t = _time(step, steps, 1)
         H.timing(True)
         H.timing_reset()
@@ -220,9 +223,9 @@ def bench_directions(args, X, Y, n):
         us = {name: round(ms / c * 1e3, 1) for name, (ms, c) in kt.items()
               if name in ("extremes", "discard", "refine_pass", "polygon")}
         curve.append({"preset": preset, "directions": PRESET_NAMES[preset],
-                      "gpts": round(len(KINDS) * n / t / 1e9, 3), "ms_per_step": round(t * 1e3, 3),
+                      "gpts": round(S * n / t / 1e9, 3), "ms_per_step": round(t * 1e3, 3),
                       "us_mean_per_launch": us, "discard_fraction": disc})
-    del hull, surv
+    del hb, surv
     return curve
 
 
@@ -634,7 +637,7 @@ def main():
         out["unfiltered"] = {"gpts": round(total_pts / t_u / 1e9, 3),
                              "ms_per_step": round(t_u * 1e3, 3),
                              "speedup_of_filter": round(t_u / dt, 3)}
-        out["direction_families"] = bench_directions(args, X, Y, n)
+        out["direction_families"] = bench_directions(args, xb, yb, offb, X, Y, n)
         out["host_resident"] = bench_host(args, X, Y, n)
         H.close()
         del X, Y, hull, xb, yb, hb
