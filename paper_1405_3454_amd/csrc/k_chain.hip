@@ -326,10 +326,48 @@ __device__ __forceinline__ int64_t bridge(PO o, int64_t len, int64_t tailseg, PC
 // serial bridge walks; larger groups walk the bridges in global memory.
 constexpr int MERGE_CAP = 4096;           // keys staged per wave (32 KB)
 
+// The group's ng chains side by side in buf (chain g of length m_g from
+// in + (u0 + g) R to buf[off_g, off_g + m_g), off_g the sum of the lengths
+// before it; lane g < ng holds incl = off_g + m_g, M the total).  Every lane
+// loads entries of any chain (its chain by binary search over the offsets in
+// goff), eight in flight, so the loads of all the chains overlap.
+__device__ __forceinline__ void stage_group(const uint64_t *__restrict__ in, int64_t R, int64_t u0,
+                                            int ng, int64_t incl, int64_t M, int64_t *goff,
+                                            uint64_t *buf) {
+    constexpr int K = 8;
+    const int lane = lane_id();
+    if (lane < ng) goff[lane + 1] = incl;
+    if (lane == 0) goff[0] = 0;
+    wave_sync();
+    for (int64_t i0 = 0; i0 < M; i0 += (int64_t)K * WAVE) {
+        uint64_t v[K];
+#pragma unroll
+        for (int u = 0; u < K; u++) {
+            const int64_t i = i0 + (int64_t)u * WAVE + lane;
+            v[u] = 0;
+            if (i < M) {
+                int lo = 0, hi = ng - 1;       // the last chain starting at or before i
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (goff[mid] <= i) lo = mid; else hi = mid - 1;
+                }
+                v[u] = in[(u0 + lo) * R + (i - goff[lo])];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < K; u++) {
+            const int64_t i = i0 + (int64_t)u * WAVE + lane;
+            if (i < M) buf[i] = v[u];
+        }
+    }
+    wave_sync();
+}
+
 template <bool UPPER>
 __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__restrict__ cin,
                             int64_t U, int64_t R, int64_t v, int lev, uint64_t *__restrict__ out,
-                            uint32_t *__restrict__ cout, uint64_t *__restrict__ buf) {
+                            uint32_t *__restrict__ cout, uint64_t *__restrict__ buf,
+                            int64_t *__restrict__ goff) {
     const int lane = lane_id();
     const int64_t base = v * R * CHAIN_G;
     uint64_t *o = out + base;
@@ -350,12 +388,7 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
     } else if (M <= MERGE_CAP && lev > 0) {
         // a few long chains (the upper levels): joined left to right in LDS,
         // walking each junction to its bridge
-        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
-            const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
-            const uint64_t *src = in + (u0 + g) * R;
-            for (int64_t i = lane; i < m; i += WAVE) buf[og + i] = src[i];
-        }
-        wave_sync();
+        stage_group(in, R, u0, (int)min((int64_t)CHAIN_G, U - u0), incl, M, goff, buf);
         {
             for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
                 const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
@@ -386,12 +419,7 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
         // level 0: many short chains side by side form one x-sorted list
         // holding every vertex of the merged chain: prune it in place like a
         // level-0 chunk
-        for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
-            const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
-            const uint64_t *src = in + (u0 + g) * R;
-            for (int64_t i = lane; i < m; i += WAVE) buf[og + i] = src[i];
-        }
-        wave_sync();
+        stage_group(in, R, u0, (int)min((int64_t)CHAIN_G, U - u0), incl, M, goff, buf);
         const uint64_t lt = lanemask_lt();
         int n = (int)M;
         bool moved = true;
@@ -558,12 +586,14 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
     if (V == 0 && wave == 0 && threadIdx.x == 0)   // no candidates: empty top chain
         (blockIdx.y == 0 ? lo_cout : up_cout)[0] = 0;
+    __shared__ int64_t moff[4][CHAIN_G + 1];
     uint64_t *buf = mbuf[threadIdx.x >> 6];
+    int64_t *goff = moff[threadIdx.x >> 6];
     const uint32_t *cin = blockIdx.y == 0 ? lo_cin : up_cin;
     for (int64_t v = wave; v < V; v += nw) {        // groups the count actually has
         if (block_group(cin, U, v)) continue;
-        if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lev, lo_out, lo_cout, buf);
-        else merge_group<true>(up_in, up_cin, U, R, v, lev, up_out, up_cout, buf);
+        if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lev, lo_out, lo_cout, buf, goff);
+        else merge_group<true>(up_in, up_cin, U, R, v, lev, up_out, up_cout, buf, goff);
         wave_sync();
     }
     __shared__ int64_t sh[3 + 2 * CHAIN_G];
@@ -618,7 +648,8 @@ constexpr int64_t SET_CHUNKS_MAX = 32;
 template <bool UPPER>
 __device__ void set_chain(const uint64_t *__restrict__ sorted, int64_t n, uint32_t s,
                           const uint64_t *__restrict__ lists, const uint32_t *__restrict__ lcnt,
-                          uint64_t *__restrict__ out, uint64_t *__restrict__ buf, int *__restrict__ big) {
+                          uint64_t *__restrict__ out, uint64_t *__restrict__ buf,
+                          int64_t *__restrict__ goff, int64_t *__restrict__ gsrc, int *__restrict__ big) {
     const int lane = lane_id();
     const int64_t start = set_lower_bound(sorted, n, s), end = set_lower_bound(sorted, n, s + 1);
     if (start >= end) return;
@@ -627,27 +658,65 @@ __device__ void set_chain(const uint64_t *__restrict__ sorted, int64_t n, uint32
         if (lane == 0) atomicOr(big, 1);
         return;
     }
-    const bool staged = end - start <= MERGE_CAP;
-    uint64_t *o = staged ? buf : out + start;
-    int64_t len = 0;
-    for (int64_t c = c0; c <= c1; c++) {
-        const uint64_t *list = lists + c * CHAIN_C;
-        int64_t p0, p1;
-        piece_of(list, (int64_t)lcnt[c], s, &p0, &p1);
-        const int64_t m = p1 - p0;
-        if (m <= 0) continue;
-        const uint64_t *src = list + p0;
-        int64_t b;
-        len = bridge<UPPER>(o, len, 0, src, m, &b);
-        wave_sync();
-        for (int64_t i = b + lane; i < m; i += WAVE) o[len + (i - b)] = src[i];
-        __threadfence_block();
-        wave_sync();
-        len += m - b;
-    }
     uint64_t *dst = out + start;
-    if (staged)
+    int64_t len = 0;
+    if (end - start <= MERGE_CAP) {
+        // staged: lane j finds the set's piece of chunk c0 + j, the pieces
+        // are loaded side by side into LDS together, then joined left to
+        // right at their bridges in place
+        const int nc = (int)(c1 - c0 + 1);
+        int64_t p0 = 0, p1 = 0;
+        if (lane < nc) piece_of(lists + (c0 + lane) * CHAIN_C, (int64_t)lcnt[c0 + lane], s, &p0, &p1);
+        const int64_t m = p1 - p0;
+        const int64_t incl = wave_incl_scan_i64(m);
+        const int64_t M = __shfl(incl, WAVE - 1);
+        if (lane < nc) gsrc[lane] = (c0 + lane) * CHAIN_C + p0 - (incl - m);   // list address - buffer offset
+        if (lane < nc) goff[lane + 1] = incl;
+        if (lane == 0) goff[0] = 0;
+        wave_sync();
+        for (int64_t i = lane; i < M; i += WAVE) {
+            int lo = 0, hi = nc - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (goff[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            buf[i] = lists[gsrc[lo] + i];
+        }
+        wave_sync();
+        for (int j = 0; j < nc; j++) {
+            const int64_t mj = __shfl(m, j), oj = __shfl(incl, j) - mj;
+            if (mj <= 0) continue;
+            const uint64_t *c = buf + oj;
+            int64_t b;
+            len = bridge<UPPER>(buf, len, 0, c, mj, &b);
+            // move c[b..mj) down to buf[len..): len <= oj + b, copy forward
+            for (int64_t i0 = 0; i0 < mj - b; i0 += WAVE) {
+                const int64_t i = i0 + lane;
+                const uint64_t val = i < mj - b ? c[b + i] : 0;
+                wave_sync();
+                if (i < mj - b) buf[len + i] = val;
+                wave_sync();
+            }
+            len += mj - b;
+        }
         for (int64_t i = lane; i < len; i += WAVE) dst[i] = buf[i];
+    } else {
+        for (int64_t c = c0; c <= c1; c++) {
+            const uint64_t *list = lists + c * CHAIN_C;
+            int64_t p0, p1;
+            piece_of(list, (int64_t)lcnt[c], s, &p0, &p1);
+            const int64_t m = p1 - p0;
+            if (m <= 0) continue;
+            const uint64_t *src = list + p0;
+            int64_t b;
+            len = bridge<UPPER>(dst, len, 0, src, m, &b);
+            wave_sync();
+            for (int64_t i = b + lane; i < m; i += WAVE) dst[len + (i - b)] = src[i];
+            __threadfence_block();
+            wave_sync();
+            len += m - b;
+        }
+    }
     for (int64_t i = len + lane; i < end - start; i += WAVE) dst[i] = SET_GAP;
     wave_sync();
 }
@@ -662,14 +731,16 @@ __global__ __launch_bounds__(256) void k_chain_sets(const uint64_t *__restrict__
                                                     uint32_t *__restrict__ lo_len, uint32_t *__restrict__ up_len,
                                                     int *__restrict__ big) {
     __shared__ uint64_t mbuf[4][MERGE_CAP];
+    __shared__ int64_t moff[4][SET_CHUNKS_MAX + 1], msrc[4][SET_CHUNKS_MAX];
     const int64_t n = *cnt_ptr;
     if (blockIdx.x == 0 && threadIdx.x == 0) (blockIdx.y == 0 ? lo_len : up_len)[0] = (uint32_t)n;
     uint64_t *buf = mbuf[threadIdx.x >> 6];
+    int64_t *goff = moff[threadIdx.x >> 6], *gsrc = msrc[threadIdx.x >> 6];
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
     for (int64_t s = wave; s < S; s += nw) {
-        if (blockIdx.y == 0) set_chain<false>(sorted, n, (uint32_t)s, lo_in, lo_cin, lo_out, buf, big);
-        else set_chain<true>(sorted, n, (uint32_t)s, up_in, up_cin, up_out, buf, big);
+        if (blockIdx.y == 0) set_chain<false>(sorted, n, (uint32_t)s, lo_in, lo_cin, lo_out, buf, goff, gsrc, big);
+        else set_chain<true>(sorted, n, (uint32_t)s, up_in, up_cin, up_out, buf, goff, gsrc, big);
     }
 }
 

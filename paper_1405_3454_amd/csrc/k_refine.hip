@@ -23,18 +23,6 @@
 
 namespace hg {
 
-constexpr int REF_PER_THREAD = 8;                 // survivors per thread and block step
-constexpr int REF_THREADS = 256;                  // pass block size
-constexpr int REF_THREADS_LATE = 512;             // one set, rounds after 0 (fewer blocks)
-
-
-// Exact edge function of a->b at p: > 0 strictly left (inside), < 0 outside.
-__device__ __forceinline__ double redge_eval(const REdge &e, double px, double py) {
-    const double ax = (double)e.ax, ay = (double)e.ay;
-    const double ex = (double)e.bx - ax, ey = (double)e.by - ay;
-    const double c = fma(ey, ax, -(ex * ay));
-    return fma(ex, py, fma(-ey, px, c));
-}
 
 __device__ __forceinline__ void key_point(uint64_t k, int64_t *s, double *px, double *py) {
     *s = (int64_t)(k >> 48);
@@ -59,6 +47,32 @@ __device__ __forceinline__ void split_pair(const float *__restrict__ x, const fl
     *c1 = REdge{fx, fy, cur.bx, cur.by};
 }
 
+// A child edge a->b as the coefficients of its edge function at p,
+// E(p) = ex py - ey px + c with (ex, ey) = b - a and c = ey ax - ex ay:
+// > 0 strictly left of a->b (inside), < 0 outside.  On the grid (integers
+// below 2^24) every product and fused sum here is exact in binary64 (|E| <
+// 2^52), so a survivor's test costs two fused multiply-adds per edge.  An
+// empty slot has c = NaN: E is NaN, and no comparison with it holds.
+struct EdgeF {
+    double ex, ey, c;
+};
+__device__ __forceinline__ EdgeF edge_f(const REdge &e) {
+    if (e.ax == INT32_MIN) return EdgeF{0.0, 0.0, __longlong_as_double(0x7ff8000000000000ll)};
+    const double ax = (double)e.ax, ay = (double)e.ay;
+    const double ex = (double)e.bx - ax, ey = (double)e.by - ay;
+    return EdgeF{ex, ey, fma(ey, ax, -(ex * ay))};
+}
+__device__ __forceinline__ double edge_eval(const EdgeF &f, double px, double py) {
+    return fma(f.ex, py, fma(-f.ey, px, f.c));
+}
+
+// A wave-uniform int64 moved into scalar registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Split every edge of round r (er per set) at its farthest outside point and
 // clear the children's farthest-point keys.
 __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
@@ -79,42 +93,39 @@ __global__ __launch_bounds__(256) void k_ref_split(const float *__restrict__ x,
     far_nxt[s * RE_CAP + 2 * e + 1] = 0;
 }
 
-// Farthest-point keys of a chunk: when the whole chunk belongs to one set,
-// the block keeps them in LDS (ds_max_u64) and raises the global slots once
-// per edge at the end; otherwise every point goes to the global slot.
-struct RefFar {
-    unsigned long long v[RE_CAP];
-};
+constexpr int REF_GROUP = 4;                      // most input regions one wave reads
+// input regions per wave in round r.  One region per wave in round 0 (the
+// discard pass's regions hold the most survivors, and a wave walks its
+// chunks in turn); later rounds hold about four times fewer per round, and
+// several sets leave many regions nearly empty, so their waves read two.
+__host__ __device__ inline int ref_group(int r, bool batched) { return r == 0 ? 1 : 2; }
 
-__device__ __forceinline__ void far_put(bool local, RefFar &L, unsigned long long *far, int64_t s,
-                                        int e, uint64_t key) {
-    if (local) {
-        if (L.v[e] < key) atomicMax(&L.v[e], (unsigned long long)key);
-    } else {
-        far_update(&far[s * RE_CAP + e], key);
-    }
+// LDS of a pass: the farthest keys, then the child edges (as EdgeF), of the
+// set a wave holds (er2 of each).
+__host__ __device__ inline size_t ref_lds_bytes(int er2) {
+    return (size_t)er2 * (sizeof(unsigned long long) + 3 * sizeof(double));
 }
 
-constexpr int REF_GROUP = 4;                      // most input regions one block reads
-// input regions per block in round r.  One set: fuller chunks early, enough
-// blocks late.  Several sets: one region per block (their survivor counts
-// differ with the sets' shapes, and a block walks its chunks in turn, so
-// the fullest block sets the pass's time).
-__host__ __device__ inline int ref_group(int r, bool batched) { return batched ? 1 : r == 0 ? 4 : 2; }
-
-// One round over the survivors.  A list is a row of regions (region r at
-// r * segcap, cnt[r] entries; round 0 reads the discard pass's, one per
-// wave).  Block g reads regions [g * kg, (g + 1) * kg) as one list, in
-// chunks of RT * REF_PER_THREAD (thread t holds list entries t, t + RT, ...).
-// Each survivor is classified against the two children of its edge
+// One round over the survivors, one wave per block (no block barriers).  A
+// list is a row of regions (region r at r * segcap, cnt[r] entries; round 0
+// reads the discard pass's).  Wave g reads regions [g * kg, (g + 1) * kg) as
+// one list, in chunks of REF_CHUNK (lane l holds chunk entries l, l + 64,
+// ...).  Each survivor is classified against the two children of its edge
 // (RE_DROP, RE_NONE or the new edge id); the kept ones are packed into region
-// g (size kg * segcap) of the next list, whose count the block writes at the
-// end: no atomics.  The farthest-point key of each new edge is raised.  (Round 0's
-// input is the discard pass's regions, with their edge states.)  With one set
-// (one_set), the set's child edges are staged once per block, before the
-// first chunk's loads return, and the farthest keys are raised once per block.
-template <int RT>
-__global__ __launch_bounds__(RT) void k_ref_pass(
+// g (size kg * segcap) of the next list in (chunk, row, lane) order, and the
+// wave writes their count at the end: no atomics.  The farthest-point key of
+// each new edge is raised.  One set (one_set): the set's child edges and
+// farthest keys live in LDS for the whole wave, and with tab_par the wave
+// splits the parent edges itself (wave 0 also publishes the children for the
+// next round and clears the farthest keys the round after this one raises).
+// Several sets: the set of a chunk that lies in one set is held in LDS over
+// consecutive chunks of that set and its keys are raised in global memory
+// when another set comes and at the end; a chunk that spans sets reads the
+// tables and raises the keys in global memory.
+constexpr int REF_PER_LANE = 8;
+constexpr int REF_CHUNK = WAVE * REF_PER_LANE;    // 512 entries
+
+__global__ __launch_bounds__(WAVE) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
     const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int nreg_in, int kg,
     const int64_t *__restrict__ region_size, int64_t mult, const REdge *__restrict__ tab_nxt, int er2,
@@ -124,36 +135,36 @@ __global__ __launch_bounds__(RT) void k_ref_pass(
     const float *__restrict__ y, const REdge *__restrict__ tab_par,
     const unsigned long long *__restrict__ far_par, REdge *__restrict__ tab_out,
     unsigned long long *__restrict__ far_clr) {
-    constexpr int NW = RT / WAVE;
-    __shared__ RefFar L;
-    __shared__ REdge ltab[RE_CAP];          // the chunk's set's child edges (er2 of them)
-    __shared__ uint32_t kc[REF_PER_THREAD][NW];   // kept per (element row, wave) -> offsets
-    __shared__ uint32_t ktot;
-    __shared__ int64_t pre[REF_GROUP + 1];  // list offsets of the group's regions
-    const int tid = threadIdx.x, w = tid / WAVE;
+    extern __shared__ unsigned long long ref_lds[];
+    unsigned long long *Lv = ref_lds;                       // er2 farthest keys
+    EdgeF *ltab = reinterpret_cast<EdgeF *>(ref_lds + er2);  // er2 child edges
+    const int lane = threadIdx.x;
     const int64_t g = blockIdx.x;
     const int64_t segcap = *region_size * mult;      // input region size
-    const int64_t r0 = g * kg, nr = max((int64_t)0, min((int64_t)kg, (int64_t)nreg_in - r0));
-    if (tid == 0) {
-        int64_t run = 0;
-        for (int j = 0; j < nr; j++) {
-            pre[j] = run;
-            run += cnt_in[r0 + j];
-        }
-        pre[nr] = run;
-    }
-    __syncthreads();
-    const int64_t n_sg = pre[nr];
-    // One set with tab_par: the block splits the er2 / 2 parent edges itself
-    // (children into LDS); block 0 also publishes them for the next round and
-    // clears the farthest keys the round after this one raises.
+    const int64_t r0 = g * kg;
+    const int nr = (int)max((int64_t)0, min((int64_t)kg, (int64_t)nreg_in - r0));
+    // list offsets of the group's regions (pre[j]: entries before region j)
+    const int64_t c = lane < nr ? cnt_in[r0 + lane] : 0;
+    const int64_t incl = wave_incl_scan_i64(c);
+    const int64_t n_sg = uniform_i64(__shfl(incl, WAVE - 1));
+    int64_t pre[REF_GROUP];
+    pre[0] = 0;
+#pragma unroll
+    for (int j = 1; j < REF_GROUP; j++) pre[j] = uniform_i64(__shfl(incl, j - 1));
+    auto addr = [&](int64_t v) {     // list entry v -> its address
+        int64_t a = r0 * segcap + v;
+#pragma unroll
+        for (int j = 1; j < REF_GROUP; j++)
+            if (j < nr && pre[j] <= v) a += segcap - (pre[j] - pre[j - 1]);
+        return a;
+    };
     auto split_here = [&](bool to_lds) {
-        for (int e = tid; e < er2 / 2; e += RT) {
+        for (int e = lane; e < er2 / 2; e += WAVE) {
             REdge c0, c1;
             split_pair(x, y, tab_par[e], far_par[e], &c0, &c1);
             if (to_lds) {
-                ltab[2 * e] = c0;
-                ltab[2 * e + 1] = c1;
+                ltab[2 * e] = edge_f(c0);
+                ltab[2 * e + 1] = edge_f(c1);
             }
             if (g == 0) {
                 tab_out[2 * e] = c0;
@@ -161,142 +172,166 @@ __global__ __launch_bounds__(RT) void k_ref_pass(
             }
         }
         if (g == 0)
-            for (int e = tid; e < RE_CAP; e += RT) far_clr[e] = 0;
+            for (int e = lane; e < RE_CAP; e += WAVE) far_clr[e] = 0;
     };
-    if (n_sg == 0) {                        // nothing to read: an empty region, no far keys
-        if (tid == 0) cnt_out[g] = 0;
+    if (n_sg == 0) {                        // nothing to read: an empty group, no far keys
+        if (lane == 0) cnt_out[g] = 0;
         if (tab_par && g == 0) split_here(false);
         return;
     }
     const int64_t region = r0 * segcap;     // output region g: [region, region + kg * segcap)
-    // list entry v -> its address (regions of the group in order)
-    auto addr = [&](int64_t v) {
-        int j = 0;
-        while (j + 1 < nr && pre[j + 1] <= v) j++;
-        return (r0 + j) * segcap + (v - pre[j]);
-    };
+    const uint64_t lt = lanemask_lt();
     int64_t outn = 0;                       // entries packed into the region so far
-    int64_t held = -1;                      // several sets: the set held in LDS (ltab, L.v)
-    __shared__ int64_t sfirst;
-    if (one_set) {
-        for (int e = tid; e < RE_CAP; e += RT) L.v[e] = 0;
-        if (tab_par)
-            split_here(true);
-        else
-            for (int e = tid; e < er2; e += RT) ltab[e] = tab_nxt[e];
-    }
-    for (int64_t jb = 0; jb < n_sg; jb += (RT * REF_PER_THREAD)) {
-        const int64_t je = min(n_sg, jb + (RT * REF_PER_THREAD));
-        const int64_t j0 = jb + tid;        // element i: j0 + i * RT (coalesced)
-        uint64_t k[REF_PER_THREAD];
-        uint16_t st[REF_PER_THREAD];
-        uint32_t ix[REF_PER_THREAD];
-#pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++) {
-            const int64_t j = j0 + (int64_t)i * RT;
-            const bool in = j < je;
-            const int64_t a = in ? addr(j) : 0;
-            k[i] = in ? keys[a] : 0;
-            st[i] = in ? edge[a] : RE_DROP;
-            ix[i] = in ? idx[a] : 0;
-        }
-        // one set in the whole chunk?  (a region can span sets)  The set
-        // whose child edges and farthest keys the block holds in LDS stays
-        // there over consecutive chunks of that set; its keys are raised in
-        // global memory when another set's chunk comes, and at the end.
-        int64_t s0 = 0;
-        bool local = true;
-        if (!one_set) {
-            if (tid == 0) sfirst = (int64_t)(k[0] >> 48);   // entry jb is thread 0's first
-            __syncthreads();
-            s0 = sfirst;
-            bool same = true;
-#pragma unroll
-            for (int i = 0; i < REF_PER_THREAD; i++)
-                same = same && (j0 + (int64_t)i * RT >= je || (int64_t)(k[i] >> 48) == s0);
-            local = __syncthreads_and(same) != 0;
-            if (held >= 0 && (!local || s0 != held)) {   // the held set's keys go out
-                for (int e = tid; e < er2; e += RT) {
-                    const unsigned long long v = L.v[e];
-                    if (v) far_update(&far[held * RE_CAP + e], v);
-                }
-                held = -1;
-                __syncthreads();
-            }
-            if (local && held < 0) {
-                for (int e = tid; e < er2; e += RT) {
-                    L.v[e] = 0;
-                    ltab[e] = tab_nxt[s0 * RE_CAP + e];
-                }
-                held = s0;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++) {
-            if (st[i] == RE_DROP) continue;
-            int64_t s;
-            double px, py;
-            key_point(k[i], &s, &px, &py);
-            uint16_t out = RE_NONE;
-            double dist = 0.0;
-            if (st[i] != RE_NONE) {
-                const int e0 = 2 * st[i];
-                const REdge c0 = local ? ltab[e0] : tab_nxt[s * RE_CAP + e0];
-                const REdge c1 = local ? ltab[e0 + 1] : tab_nxt[s * RE_CAP + e0 + 1];
-                if (c1.ax == INT32_MIN) {            // edge without a split point
-                    const double E0 = redge_eval(c0, px, py);
-                    if (E0 < 0) { out = (uint16_t)e0; dist = -E0; }
-                } else {
-                    const double E1 = redge_eval(c0, px, py), E2 = redge_eval(c1, px, py);
-                    if (E1 > 0 && E2 > 0) out = RE_DROP;
-                    else if (E1 < 0) { out = (uint16_t)e0; dist = -E1; }
-                    else if (E2 < 0) { out = (uint16_t)(e0 + 1); dist = -E2; }
-                }
-            }
-            if (out != RE_NONE && out != RE_DROP) far_put(local, L, far, s, out, far_key(dist, ix[i]));
-            st[i] = out;
-        }
-        // kept entries packed in (element row, wave, lane) order: every row's
-        // stores from a wave go to consecutive slots
-        uint64_t bm[REF_PER_THREAD];
-#pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++) {
-            bm[i] = __ballot(st[i] != RE_DROP);
-            if (lane_id() == 0) kc[i][w] = (uint32_t)__popcll(bm[i]);
-        }
-        __syncthreads();
-        if (tid < WAVE) {     // exclusive prefix over (row, wave) in one wave
-            static_assert(REF_PER_THREAD * NW <= WAVE, "one lane per (row, wave)");
-            uint32_t *flat = &kc[0][0];
-            const uint32_t c = tid < REF_PER_THREAD * NW ? flat[tid] : 0;
-            const uint32_t inc = (uint32_t)wave_incl_scan_i64(c);
-            if (tid < REF_PER_THREAD * NW) flat[tid] = inc - c;
-            if (tid == WAVE - 1) ktot = inc;
-        }
-        __syncthreads();
-        const uint64_t lt = lanemask_lt();
-        const int64_t base = region + outn;
-#pragma unroll
-        for (int i = 0; i < REF_PER_THREAD; i++) {
-            if (st[i] == RE_DROP) continue;
-            const int64_t pos = base + kc[i][w] + __popcll(bm[i] & lt);
-            idx_out[pos] = ix[i];
-            keys_out[pos] = k[i];
-            edge_out[pos] = st[i];
-        }
-        outn += ktot;
-        __syncthreads();
-    }
-    if (one_set || held >= 0) {
-        __syncthreads();
-        const int64_t fs = one_set ? 0 : held;
-        for (int e = tid; e < er2; e += RT) {
-            const unsigned long long v = L.v[e];
+    int64_t held = -1;                      // several sets: the set held in LDS
+    auto flush = [&](int64_t fs) {          // the held keys -> global slots
+        for (int e = lane; e < er2; e += WAVE) {
+            const unsigned long long v = Lv[e];
             if (v) far_update(&far[fs * RE_CAP + e], v);
         }
+    };
+    for (int64_t jb = 0; jb < n_sg; jb += REF_CHUNK) {
+        uint64_t k[REF_PER_LANE];
+        uint16_t st[REF_PER_LANE];
+        uint32_t ix[REF_PER_LANE];
+        // the region of entry jb; a chunk with no other region start in it
+        // is read from one base address (scalar) plus the lane's offset
+        int jr = 0;
+#pragma unroll
+        for (int t = 1; t < REF_GROUP; t++) jr += (t < nr && pre[t] <= jb);
+        int64_t pre_jr = 0, pre_nx = n_sg;
+#pragma unroll
+        for (int t = 0; t < REF_GROUP; t++) {
+            if (t == jr) pre_jr = pre[t];
+            if (t == jr + 1 && t < nr) pre_nx = pre[t];
+        }
+        if (pre_nx >= min(n_sg, jb + REF_CHUNK)) {
+            const int64_t base = (r0 + jr) * segcap + (jb - pre_jr);
+            const int lim = (int)min((int64_t)REF_CHUNK, n_sg - jb);
+            const uint64_t *kp = keys + base;
+            const uint16_t *ep = edge + base;
+            const uint32_t *ip = idx + base;
+            if (lim == REF_CHUNK) {
+#pragma unroll
+                for (int i = 0; i < REF_PER_LANE; i++) {
+                    const int j = lane + i * WAVE;
+                    k[i] = kp[j];
+                    st[i] = ep[j];
+                    ix[i] = ip[j];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < REF_PER_LANE; i++) {
+                    const int j = lane + i * WAVE;
+                    const bool in = j < lim;
+                    k[i] = in ? kp[j] : 0;
+                    st[i] = in ? ep[j] : RE_DROP;
+                    ix[i] = in ? ip[j] : 0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < REF_PER_LANE; i++) {
+                const int64_t j = jb + lane + (int64_t)i * WAVE;
+                const bool in = j < n_sg;
+                const int64_t a = in ? addr(j) : 0;
+                k[i] = in ? keys[a] : 0;
+                st[i] = in ? edge[a] : RE_DROP;
+                ix[i] = in ? idx[a] : 0;
+            }
+        }
+        bool local = true;
+        if (one_set) {
+            if (jb == 0) {      // the set's tables, while the first chunk's loads fly
+                for (int e = lane; e < er2; e += WAVE) Lv[e] = 0;
+                if (tab_par)
+                    split_here(true);
+                else
+                    for (int e = lane; e < er2; e += WAVE) ltab[e] = edge_f(tab_nxt[e]);
+                wave_sync();
+            }
+        } else {
+            // one set in the whole chunk?  (a region can span sets)  Entry jb
+            // is lane 0's first.
+            const int64_t s0 = (int64_t)(__shfl(k[0], 0) >> 48);
+            bool same = true;
+#pragma unroll
+            for (int i = 0; i < REF_PER_LANE; i++)
+                same = same && (jb + lane + (int64_t)i * WAVE >= n_sg || (int64_t)(k[i] >> 48) == s0);
+            local = __ballot(!same) == 0;
+            if (held >= 0 && (!local || s0 != held)) {
+                flush(held);
+                held = -1;
+                wave_sync();
+            }
+            if (local && held < 0) {
+                for (int e = lane; e < er2; e += WAVE) {
+                    Lv[e] = 0;
+                    ltab[e] = edge_f(tab_nxt[s0 * RE_CAP + e]);
+                }
+                held = s0;
+                wave_sync();
+            }
+        }
+        // each entry against the two children of its edge, without branches
+        // but the farthest-key update: E1 < 0 -> child 2e, else E2 < 0 ->
+        // child 2e + 1, else both > 0 -> dropped, else kept unassigned
+        auto classify = [&](int i, const EdgeF &f0, const EdgeF &f1, int e0, uint16_t *out_, double *dist_) {
+            const double px = (double)(uint32_t)((k[i] >> 24) & 0xFFFFFF);
+            const double py = (double)(uint32_t)(k[i] & 0xFFFFFF);
+            const double E1 = edge_eval(f0, px, py), E2 = edge_eval(f1, px, py);
+            uint16_t out = (E1 > 0 && E2 > 0) ? RE_DROP : RE_NONE;
+            double dist = 0.0;
+            if (E2 < 0) { out = (uint16_t)(e0 + 1); dist = -E2; }
+            if (E1 < 0) { out = (uint16_t)e0; dist = -E1; }
+            *out_ = out;
+            *dist_ = dist;
+        };
+        if (__builtin_amdgcn_readfirstlane((int)local)) {
+#pragma unroll
+            for (int i = 0; i < REF_PER_LANE; i++) {
+                const uint16_t s_in = st[i];
+                const bool act = s_in < RE_DROP;           // assigned to an edge
+                const int e0 = act ? 2 * (int)s_in : 0;
+                uint16_t out;
+                double dist;
+                classify(i, ltab[e0], ltab[e0 + 1], e0, &out, &dist);
+                st[i] = act ? out : s_in;
+                if (act && out < RE_DROP) atomicMax(&Lv[out], (unsigned long long)far_key(dist, ix[i]));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < REF_PER_LANE; i++) {
+                const uint16_t s_in = st[i];
+                const bool act = s_in < RE_DROP;
+                const int e0 = act ? 2 * (int)s_in : 0;
+                const int64_t s = (int64_t)(k[i] >> 48);
+                uint16_t out;
+                double dist;
+                classify(i, edge_f(tab_nxt[s * RE_CAP + e0]), edge_f(tab_nxt[s * RE_CAP + e0 + 1]), e0,
+                         &out, &dist);
+                st[i] = act ? out : s_in;
+                if (act && out < RE_DROP) far_update(&far[s * RE_CAP + out], far_key(dist, ix[i]));
+            }
+        }
+        // kept entries packed row by row: every row's stores go to
+        // consecutive slots
+#pragma unroll
+        for (int i = 0; i < REF_PER_LANE; i++) {
+            const uint64_t bm = __ballot(st[i] != RE_DROP);
+            if (st[i] != RE_DROP) {
+                const int pos = __popcll(bm & lt);
+                idx_out[region + outn + pos] = ix[i];
+                keys_out[region + outn + pos] = k[i];
+                edge_out[region + outn + pos] = st[i];
+            }
+            outn += __popcll(bm);
+        }
     }
-    if (tid == 0) cnt_out[g] = outn;
+    if (one_set || held >= 0) {
+        wave_sync();
+        flush(one_set ? 0 : held);
+    }
+    if (lane == 0) cnt_out[g] = outn;
 }
 
 // Regions of list stage r (0: the discard pass's, one per wave; round r
@@ -307,11 +342,31 @@ __host__ __device__ inline int64_t stage_regions(int64_t nwave, int r, bool batc
     return n;
 }
 
+// This thread's share of c[0, n) (thread t: entries t, t + 256, ...), eight
+// loads in flight.
+__device__ __forceinline__ int64_t sum_counts(const int64_t *__restrict__ c, int64_t n) {
+    constexpr int GT = 256, K = 8;
+    int64_t a = 0;
+    for (int64_t j0 = threadIdx.x; j0 < n; j0 += (int64_t)GT * K) {
+        int64_t v[K];
+#pragma unroll
+        for (int u = 0; u < K; u++) {
+            const int64_t j = j0 + (int64_t)u * GT;
+            v[u] = j < n ? c[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < K; u++) a += v[u];
+    }
+    return a;
+}
+
 // Region list (idx, keys) of list stage nstage - 1 (region counts of stage r
 // at cnt_all + r * nwave) -> contiguous arrays in region order.  Block b
 // copies the consecutive regions [b * per, (b + 1) * per), starting at the
-// sum of the counts before them; totals[r] gets the entries of stage r for
-// every r < nstage.
+// sum of the counts before them, up to 256 regions at a time: their counts
+// are scanned into LDS and every thread copies entries of any of them (its
+// region by binary search), four in flight.  totals[r] gets the entries of
+// stage r for every r < nstage.
 __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__ idx,
                                                     const uint64_t *__restrict__ keys,
                                                     const int64_t *__restrict__ cnt_all, int nwave,
@@ -321,13 +376,14 @@ __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__
                                                     uint32_t *__restrict__ idx_out,
                                                     uint64_t *__restrict__ keys_out,
                                                     int64_t *__restrict__ totals) {
+    constexpr int GT = 256, GK = 4;
     __shared__ int64_t sh[17];
+    __shared__ int64_t roff[GT];
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < nstage) {
         const int64_t *c = cnt_all + (int64_t)blockIdx.x * nwave;
         const int64_t nr = stage_regions(nwave, (int)blockIdx.x, batched);
-        int64_t a = 0;
-        for (int64_t j = tid; j < nr; j += blockDim.x) a += c[j];
+        const int64_t a = sum_counts(c, nr);
         int64_t t;
         block_excl_scan_i64(a, sh, &t);
         if (tid == 0) totals[blockIdx.x] = t;
@@ -338,18 +394,46 @@ __global__ __launch_bounds__(256) void k_seg_gather(const uint32_t *__restrict__
     const int64_t per = (nseg + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = min((int64_t)nseg, (int64_t)blockIdx.x * per);
     const int64_t g1 = min((int64_t)nseg, g0 + per);
-    int64_t acc = 0;
-    for (int64_t j = tid; j < g0; j += blockDim.x) acc += cnt[j];
+    const int64_t acc = sum_counts(cnt, g0);
     int64_t dst;
     block_excl_scan_i64(acc, sh, &dst);
     const int64_t segcap = *region_size * mult;
-    for (int64_t sg = g0; sg < g1; sg++) {
-        const int64_t n = cnt[sg], src = sg * segcap;
-        for (int64_t i = tid; i < n; i += blockDim.x) {
-            idx_out[dst + i] = idx[src + i];
-            keys_out[dst + i] = keys[src + i];
+    for (int64_t b0 = g0; b0 < g1; b0 += GT) {
+        const int nb = (int)min((int64_t)GT, g1 - b0);
+        const int64_t n = tid < nb ? cnt[b0 + tid] : 0;
+        int64_t tot;
+        roff[tid] = block_excl_scan_i64(n, sh, &tot);   // ends with a barrier
+        __syncthreads();
+        for (int64_t i0 = 0; i0 < tot; i0 += (int64_t)GT * GK) {
+            uint32_t vi[GK];
+            uint64_t vk[GK];
+#pragma unroll
+            for (int u = 0; u < GK; u++) {
+                const int64_t i = i0 + (int64_t)u * GT + tid;
+                vi[u] = 0;
+                vk[u] = 0;
+                if (i < tot) {
+                    int lo = 0, hi = nb - 1;       // the last region starting at or before i
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (roff[mid] <= i) lo = mid; else hi = mid - 1;
+                    }
+                    const int64_t src = (b0 + lo) * segcap + (i - roff[lo]);
+                    vi[u] = idx[src];
+                    vk[u] = keys[src];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < GK; u++) {
+                const int64_t i = i0 + (int64_t)u * GT + tid;
+                if (i < tot) {
+                    idx_out[dst + i] = vi[u];
+                    keys_out[dst + i] = vk[u];
+                }
+            }
         }
-        dst += n;
+        dst += tot;
+        __syncthreads();      // roff is rewritten by the next batch
     }
 }
 
