@@ -164,7 +164,7 @@ struct Plan {
     char *base = nullptr;   // device workspace the offsets below point into
     size_t tile_off, tile_set, pval, pidx, slots, vals, polys, spans, redges, masks, tile_cnt, tile_pos,
         scan_bs, surv_off, surv, keys0, keysA, keysB, lo0, up0, lo1, up1, ccnt, bounds, hcnt,
-        hoff, hkeys, hpos, hist, hoffs, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
+        hoff, hkeys, hpos, sstat, sgst, consts, err, setdirs, learn, cand, rtab0, rtab1, rfar0,
         rfar1, rfar2, segcnt, segmeta, cidx, ckeys, bpart, pticket, total;
     int64_t tcap, u0cap;
     int64_t nwave;      // discard waves = regions of the full method's survivor lists
@@ -214,8 +214,8 @@ static Plan make_plan(int64_t n, int64_t S, int64_t W) {
     p.hoff = take((S + 1) * 8);
     p.hkeys = take(n * 8 + 16);
     p.hpos = take(n * 4 + 16);
-    p.hist = take(RADIX * SORT_BLOCKS * 4);
-    p.hoffs = take((RADIX * SORT_BLOCKS + 1) * 8);
+    p.sstat = take(SORT_BLOCKS * RADIX * 8);                    // look-back entries of the ranges
+    p.sgst = take(SORT_MAX_PASSES * (RADIX + 1) * 4);          // digit totals, range counters
     p.consts = take(8 * 8);
     p.err = take(8);
     p.setdirs = take(S * MAX_DIRS * 2 * 8);
@@ -640,18 +640,20 @@ static int sort_passes(int64_t S) {
 // Sort keys (count at *cnt) ascending; returns the buffer holding the result.
 static int run_sort(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint64_t *keys,
                     const int64_t *cnt, int passes, const uint64_t **sorted) {
+    if (passes > SORT_MAX_PASSES) return HULL_EINVAL;
     uint64_t *A = W<uint64_t>(p, p.keysA), *B = W<uint64_t>(p, p.keysB);
-    uint32_t *hist = W<uint32_t>(p, p.hist);
-    int64_t *hoffs = W<int64_t>(p, p.hoffs);
+    unsigned long long *status = W<unsigned long long>(p, p.sstat);
+    uint32_t *gst = W<uint32_t>(p, p.sgst);
     const uint64_t *in = keys;
     uint64_t *out = A;
-    // small counts: sorted at once into the buffer the last pass would fill
-    LAUNCH(K_SORT_HIST, k_sort_small<<<1, SMALL_THREADS, 0, st>>>(keys, cnt, passes % 2 ? A : B));
+    // small counts: sorted at once into the buffer the last pass would fill;
+    // otherwise the passes' state is cleared
+    LAUNCH(K_SORT_HIST, k_sort_small<<<1 + SMALL_CLEAR_BLOCKS, SMALL_THREADS, 0, st>>>(
+        keys, cnt, passes % 2 ? A : B, status, gst));
+    LAUNCH(K_SORT_HIST, k_sort_prep<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(keys, cnt, passes, gst));
     for (int ps = 0; ps < passes; ps++) {
-        LAUNCH(K_SORT_HIST, k_sort_hist<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
-            in, cnt, 8 * ps, hist, hoffs, ctx->tickets + 1));
-        LAUNCH(K_SORT_SCATTER, k_sort_scatter<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
-            in, cnt, 8 * ps, hoffs, out));
+        LAUNCH(K_SORT_SCATTER, k_sort_pass<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
+            in, cnt, ps, gst, status, gst + SORT_MAX_PASSES * RADIX + ps, out));
         in = out;
         out = (out == A) ? B : A;
     }

@@ -2,13 +2,16 @@
 // pass).  The key count is read from device memory so the whole sort can run
 // behind earlier kernels without a host round trip.
 //
-// Decomposition: SORT_BLOCKS persistent blocks; block b owns the contiguous
-// key tiles [b qq, (b+1) qq) of SORT_TILE keys.  Per pass: (1) per-block digit
-// histograms, after which the last block to finish scans the table
-// hist[b][d] digit-major (only the blocks that hold keys), (2) scatter: each block
-// walks its tiles in order and ranks keys stably with wave ballots (peers =
+// Decomposition: the keys are cut into at most SORT_BLOCKS contiguous ranges
+// of qq tiles of SORT_TILE keys.  One kernel counts every pass's digits over
+// all keys (global digit totals, hence each digit's start in the output).
+// Then one kernel per pass: a block claims the next range (a counter, so
+// ranges are taken in order), counts its digits, publishes the counts and
+// sums those of the ranges before it by decoupled look-back (a range's entry
+// holds its own counts or, once known, the counts of all ranges up to it),
+// and scatters its keys: each tile ranked stably with wave ballots (peers =
 // lanes with the same digit) plus per-wave digit counts in LDS, so equal
-// digits keep their input order across lanes, waves, rounds and blocks.
+// digits keep their input order across lanes, waves, tiles and ranges.
 #include "hg_device.h"
 
 namespace hg {
@@ -20,10 +23,10 @@ constexpr int SORT_BLOCKS = 512;
 constexpr int RADIX = 256;
 constexpr int SORT_SMALL = 4096;      // up to this many keys one block sorts them (k_sort_small)
 constexpr int SMALL_THREADS = 1024;
+constexpr int SMALL_CLEAR_BLOCKS = 32;  // k_sort_small's blocks after the first: clear the passes' state
 
-// Tiles per block: enough for SORT_BLOCKS blocks, and up to 8 when that
-// keeps the busy blocks at 64 or fewer (the last block's digit scan then
-// holds every block's count in registers in one batch of loads).
+// Tiles per range: enough for SORT_BLOCKS ranges, and up to 8 when that
+// keeps the ranges at 64 or fewer (a shorter look-back per pass).
 __device__ __forceinline__ int64_t sort_qq(int64_t count) {
     const int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
     return max((tiles + SORT_BLOCKS - 1) / SORT_BLOCKS, min((int64_t)8, (tiles + 63) / 64));
@@ -35,25 +38,45 @@ __device__ __forceinline__ void sort_range(int64_t count, int64_t b, int64_t *lo
     *hi = min(count, (b + 1) * qq * SORT_TILE);
 }
 
-// Blocks of sort_range that hold keys: 0 .. sort_busy(count) - 1.
+// Ranges of sort_range that hold keys: 0 .. sort_busy(count) - 1.
 __device__ __forceinline__ int64_t sort_busy(int64_t count) {
     const int64_t tiles = (count + SORT_TILE - 1) / SORT_TILE;
     const int64_t qq = sort_qq(count);
     return qq ? (tiles + qq - 1) / qq : 0;
 }
 
-// At most SORT_SMALL keys: one block sorts them in LDS (bitonic network over
+// Range look-back entries: pass tag (pass + 1) << 56 | state << 54 | value,
+// 0 = not yet written this call.
+constexpr uint64_t LB_AGG = 1ull << 54, LB_INC = 2ull << 54;
+constexpr uint64_t LB_VAL = (1ull << 54) - 1, LB_TAG = ~((1ull << 56) - 1);
+constexpr int SORT_MAX_PASSES = 8;
+
+// At most SORT_SMALL keys: block 0 sorts them in LDS (bitonic network over
 // the next power of two, padded with the largest key) and writes them where
 // the radix passes would have left them; the passes then return at once.
-// Above SORT_SMALL it returns at once.  The sort is by key only, so equal
-// keys are interchangeable and the result is the radix sort's.
+// Above SORT_SMALL the other blocks clear the passes' state (the digit
+// totals, the range counters and the look-back entries of the busy ranges).
+// The sort is by key only, so equal keys are interchangeable and the result
+// is the radix sort's.
 __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small(const uint64_t *__restrict__ keys,
                                                               const int64_t *__restrict__ cnt_ptr,
-                                                              uint64_t *__restrict__ out) {
+                                                              uint64_t *__restrict__ out,
+                                                              unsigned long long *__restrict__ status,
+                                                              uint32_t *__restrict__ gstate) {
     __shared__ uint64_t b[SORT_SMALL];
     const int64_t count = *cnt_ptr;
-    if (count > SORT_SMALL || count <= 0) return;
-    const int n = (int)count, tid = threadIdx.x;
+    const int tid = threadIdx.x;
+    if (count > SORT_SMALL) {
+        if (blockIdx.x == 0) return;
+        const int64_t nst = sort_busy(count) * RADIX;
+        const int64_t nt = (int64_t)(gridDim.x - 1) * SMALL_THREADS;
+        for (int64_t i = (int64_t)(blockIdx.x - 1) * SMALL_THREADS + tid; i < nst; i += nt) status[i] = 0;
+        if (blockIdx.x == 1)
+            for (int i = tid; i < SORT_MAX_PASSES * (RADIX + 1); i += SMALL_THREADS) gstate[i] = 0;
+        return;
+    }
+    if (blockIdx.x != 0 || count <= 0) return;
+    const int n = (int)count;
     int m = 2;
     while (m < n) m <<= 1;
     for (int i = tid; i < m; i += SMALL_THREADS) b[i] = i < n ? keys[i] : ~0ull;
@@ -75,111 +98,136 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small(const uint64_t *__
     for (int i = tid; i < n; i += SMALL_THREADS) out[i] = b[i];
 }
 
-// Per-block digit histograms of the blocks that hold keys; the last of them
-// to finish (ticket, self-resetting) turns them into the exclusive offsets
-// hoff[b][d] of the stable scatter.  Both tables are block-major, so a block
-// writes its column, and the last block reads each block's, with consecutive
-// lanes on consecutive words.  Blocks without keys leave at once (the scatter
-// does not read their offsets).
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__restrict__ keys,
+// Digit totals of every pass over all keys: block b counts the digits of
+// range b in LDS and adds them to gcount[pass][digit] (cleared by
+// k_sort_small).
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_prep(const uint64_t *__restrict__ keys,
                                                             const int64_t *__restrict__ cnt_ptr,
-                                                            int shift, uint32_t *__restrict__ hist,
-                                                            int64_t *__restrict__ hoff,
-                                                            uint32_t *__restrict__ ticket) {
-    __shared__ uint32_t h[RADIX];
-    __shared__ int64_t scan_sh[17];
-    __shared__ bool last;
+                                                            int passes, uint32_t *__restrict__ gcount) {
+    __shared__ uint32_t h[SORT_MAX_PASSES][RADIX];
     const int tid = threadIdx.x;
     const int64_t count = *cnt_ptr;
-    if (count <= SORT_SMALL) return;     // k_sort_small has sorted them
-    const int nb = (int)sort_busy(count);
-    if ((int)blockIdx.x >= nb) return;   // no keys: nothing to count or scan
-    h[tid] = 0;
+    if (count <= SORT_SMALL) return;
+    if ((int64_t)blockIdx.x >= sort_busy(count)) return;
+    for (int ps = 0; ps < SORT_MAX_PASSES; ps++) h[ps][tid] = 0;
     __syncthreads();
     int64_t lo, hi;
     sort_range(count, blockIdx.x, &lo, &hi);
-    for (int64_t base = lo; base < hi; base += SORT_TILE) {     // a tile's loads, then its counts
-        uint32_t d[SORT_ROUNDS];
+    for (int64_t base = lo; base < hi; base += SORT_TILE) {
+        uint64_t k[SORT_ROUNDS];
 #pragma unroll
         for (int r = 0; r < SORT_ROUNDS; r++) {
             const int64_t i = base + r * SORT_THREADS + tid;
-            d[r] = i < hi ? (uint32_t)(keys[i] >> shift) & (RADIX - 1) : (uint32_t)RADIX;
+            k[r] = i < hi ? keys[i] : 0;
         }
 #pragma unroll
-        for (int r = 0; r < SORT_ROUNDS; r++)
-            if (d[r] < RADIX) atomicAdd(&h[d[r]], 1u);
-    }
-    __syncthreads();
-    hist[(int64_t)blockIdx.x * RADIX + tid] = h[tid];
-    __threadfence();   // every wave publishes its part of the block's column
-    __syncthreads();
-    if (tid == 0) {
-        last = atomicAdd(ticket, 1u) == (uint32_t)nb - 1;
-        if (last) __threadfence();
-    }
-    __syncthreads();
-    if (!last) return;
-    // thread d: digit d over the busy blocks, up to HB independent loads per
-    // step (in groups of HG, skipped past the last busy block); with at most
-    // HB busy blocks the values stay in registers for the second walk
-    constexpr int HB = 64, HG = 8;
-    uint32_t v[HB];
-    auto load = [&](int b0) {
-#pragma unroll
-        for (int gi = 0; gi < HB / HG; gi++) {
-            const bool any = b0 + gi * HG < nb;
-#pragma unroll
-            for (int i = 0; i < HG; i++) {
-                const int bb = b0 + gi * HG + i;
-                v[gi * HG + i] = any && bb < nb ? hist[(int64_t)bb * RADIX + tid] : 0u;
-            }
-        }
-    };
-    uint32_t tot = 0;
-    for (int b0 = 0; b0 < nb; b0 += HB) {
-        load(b0);
-#pragma unroll
-        for (int i = 0; i < HB; i++) tot += v[i];
-    }
-    int64_t all;
-    int64_t run = block_excl_scan_i64(tot, scan_sh, &all);
-    for (int b0 = 0; b0 < nb; b0 += HB) {
-        if (nb > HB) load(b0);
-#pragma unroll
-        for (int gi = 0; gi < HB / HG; gi++) {
-            if (b0 + gi * HG < nb) {
-#pragma unroll
-                for (int i = 0; i < HG; i++) {
-                    const int bb = b0 + gi * HG + i;
-                    if (bb < nb) hoff[(int64_t)bb * RADIX + tid] = run;
-                    run += v[gi * HG + i];
-                }
-            }
+        for (int r = 0; r < SORT_ROUNDS; r++) {
+            if (base + r * SORT_THREADS + tid >= hi) continue;
+            for (int ps = 0; ps < passes; ps++) atomicAdd(&h[ps][(uint32_t)(k[r] >> (8 * ps)) & (RADIX - 1)], 1u);
         }
     }
-    if (tid == 0) *ticket = 0;
+    __syncthreads();
+    for (int ps = 0; ps < passes; ps++)
+        if (h[ps][tid]) atomicAdd(&gcount[ps * RADIX + tid], h[ps][tid]);
 }
 
-// Scatter of one pass.  Per tile of SORT_TILE keys (round r, wave w, lane l
-// holds key r*256 + w*64 + l): stable ranks from wave ballots and per
-// (round, wave, digit) counts; the tile is reordered by digit in LDS and then
+// Sum of the digit-d counts of the ranges before range r (thread d), from
+// their look-back entries: an entry with the range's own counts (LB_AGG) is
+// added and the walk goes on, one with the counts up to and including that
+// range (LB_INC) ends it; an entry not yet written this pass is read again.
+// Ranges are claimed in order by running blocks, and each publishes its own
+// counts before it looks back, so every wait ends.
+__device__ __forceinline__ int64_t look_back(const unsigned long long *__restrict__ status, int64_t r,
+                                             int d, uint64_t tag) {
+    constexpr int LB = 16;
+    int64_t excl = 0;
+    int64_t k = r - 1;
+    while (k >= 0) {
+        uint64_t v[LB];
+#pragma unroll
+        for (int i = 0; i < LB; i++)
+            v[i] = k - i >= 0 ? __hip_atomic_load(&status[(k - i) * RADIX + d], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : 0;
+        int used = 0;
+        bool done = false;
+#pragma unroll
+        for (int i = 0; i < LB; i++) {
+            if (done || used < i || k - i < 0) continue;
+            if ((v[i] & LB_TAG) != tag) continue;     // not written yet: read it again
+            excl += (int64_t)(v[i] & LB_VAL);
+            used = i + 1;
+            if (v[i] & LB_INC) done = true;
+        }
+        if (done) break;
+        k -= used;
+        if (used == 0) __builtin_amdgcn_s_sleep(1);
+    }
+    return excl;
+}
+
+// One pass: claim a range, count its digits, publish them, look back, and
+// scatter the range tile by tile.  Per tile (round r, wave w, lane l holds
+// key r*256 + w*64 + l): stable ranks from wave ballots and per (round,
+// wave, digit) counts; the tile is reordered by digit in LDS and then
 // written out run by run, so consecutive lanes write consecutive addresses.
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint64_t *__restrict__ in,
-                                                               const int64_t *__restrict__ cnt_ptr,
-                                                               int shift,
-                                                               const int64_t *__restrict__ hoff,
-                                                               uint64_t *__restrict__ out) {
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(const uint64_t *__restrict__ in,
+                                                            const int64_t *__restrict__ cnt_ptr,
+                                                            int pass, const uint32_t *__restrict__ gcount,
+                                                            unsigned long long *__restrict__ status,
+                                                            uint32_t *__restrict__ claim,
+                                                            uint64_t *__restrict__ out) {
     constexpr int NW = SORT_THREADS / WAVE;
     __shared__ int64_t run[RADIX];                       // next output position per digit
     __shared__ __attribute__((aligned(16))) uint16_t wcnt[SORT_ROUNDS][NW][RADIX];
-    __shared__ uint32_t dstart[RADIX + 1], dtot[RADIX];
+    __shared__ uint32_t dstart[RADIX + 1], dtot[RADIX], rh[RADIX];
     __shared__ int64_t scan_sh[17];
     __shared__ uint64_t buf[SORT_TILE];
+    __shared__ int64_t rsh;
     const int tid = threadIdx.x, w = tid >> 6;
-    if (*cnt_ptr <= SORT_SMALL) return;  // k_sort_small has sorted them
-    run[tid] = hoff[(int64_t)blockIdx.x * RADIX + tid];
+    const int shift = 8 * pass;
+    const int64_t count = *cnt_ptr;
+    if (count <= SORT_SMALL) return;     // k_sort_small has sorted them
+    if (tid == 0) rsh = (int64_t)atomicAdd(claim, 1u);
+    const uint32_t gd = gcount[pass * RADIX + tid];      // this digit's total (in flight with the claim)
+    rh[tid] = 0;
+    __syncthreads();
+    const int64_t rr = rsh;
+    if (rr >= sort_busy(count)) return;
     int64_t lo, hi;
-    sort_range(*cnt_ptr, blockIdx.x, &lo, &hi);
+    sort_range(count, rr, &lo, &hi);
+    // the range's digit counts (a single tile keeps its keys in registers)
+    const bool one_tile = hi - lo <= SORT_TILE;
+    uint64_t k[SORT_ROUNDS];
+    for (int64_t base = lo; base < hi; base += SORT_TILE) {
+#pragma unroll
+        for (int r = 0; r < SORT_ROUNDS; r++) {
+            const int64_t i = base + r * SORT_THREADS + tid;
+            k[r] = i < hi ? in[i] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < SORT_ROUNDS; r++)
+            if (base + r * SORT_THREADS + tid < hi) atomicAdd(&rh[(uint32_t)(k[r] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    {   // publish, look back, and the digit's first output position
+        const uint64_t tag = (uint64_t)(pass + 1) << 56;
+        const uint32_t mine = rh[tid];
+        int64_t tot;
+        const int64_t gs = block_excl_scan_i64((int64_t)gd, scan_sh, &tot);
+        unsigned long long *e = &status[rr * RADIX + tid];
+        int64_t excl = 0;
+        if (rr == 0) {
+            __hip_atomic_store(e, tag | LB_INC | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(e, tag | LB_AGG | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            excl = look_back(status, rr, tid, tag);
+            __hip_atomic_store(e, tag | LB_INC | (uint64_t)(excl + mine), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        run[tid] = gs + excl;
+    }
+    __syncthreads();
     const uint64_t lt = lanemask_lt();
     for (int64_t base = lo; base < hi; base += SORT_TILE) {
         const int ntile = (int)min((int64_t)SORT_TILE, hi - base);
@@ -188,14 +236,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const uint64_t *_
             for (int i = tid; i < (int)(sizeof(wcnt) / sizeof(uint4)); i += SORT_THREADS)
                 z[i] = make_uint4(0, 0, 0, 0);
         }
-        uint64_t k[SORT_ROUNDS];
         uint32_t d[SORT_ROUNDS];
         int rank[SORT_ROUNDS], cnt[SORT_ROUNDS];
 #pragma unroll
         for (int r = 0; r < SORT_ROUNDS; r++) {
             const int i = r * SORT_THREADS + tid;
             const bool valid = i < ntile;
-            k[r] = valid ? in[base + i] : 0;
+            if (!one_tile) k[r] = valid ? in[base + i] : 0;
             d[r] = (uint32_t)(k[r] >> shift) & (RADIX - 1);
             uint64_t peers = __ballot(valid);
 #pragma unroll
