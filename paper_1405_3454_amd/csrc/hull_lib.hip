@@ -707,7 +707,10 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
     for (int lev = 0; lev < L; lev++) {
         int64_t ucap = (ncap + R - 1) / R;
         int64_t vcap = (ucap + CHAIN_G - 1) / CHAIN_G;
-        dim3 grid((unsigned)std::min(gmax, std::max<int64_t>(1, (vcap + 3) / 4)), 2);
+        // one block per CU at most (each stages 4 x 32 KB in LDS, so no
+        // second one fits); the waves loop over the groups the count has
+        const int64_t mcap = std::max<int64_t>(1, (int64_t)ctx->cus / 2);
+        dim3 grid((unsigned)std::min(mcap, std::max<int64_t>(1, (vcap + 3) / 4)), 2);
         LAUNCH(K_CHAIN_COMPACT, k_chain_merge<<<grid, 256, 0, st>>>(
             lo[cur], up[cur], locnt[cur], upcnt[cur], cnt, lev, L, lo[1 - cur], up[1 - cur],
             locnt[1 - cur], upcnt[1 - cur], big));

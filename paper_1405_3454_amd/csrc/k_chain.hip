@@ -363,11 +363,91 @@ __device__ __forceinline__ void stage_group(const uint64_t *__restrict__ in, int
     wave_sync();
 }
 
+// The junctions of the staged chains walked at once, one lane per junction
+// (chain A, then the next non-empty chain B): the same retreat along A's
+// tail and advance along B's head as the left-to-right join, except that
+// the retreat stops at the start of A's last set segment within A.  Chain i
+// keeps [lo_i, hi_i] (lo from its left junction, hi from its right one).
+// When every walk stays inside its own two chains, which holds when no chain
+// whose both junctions were walked is left with fewer than two points and
+// none is consumed, the joined chain is these pieces in order, the same as
+// the left-to-right join's, and it is written to o; otherwise returns false
+// (nothing written) and the caller joins left to right.
+template <bool UPPER>
+__device__ bool parallel_join(const uint64_t *__restrict__ buf, const int64_t *__restrict__ goff,
+                              int ng, int64_t mine, uint64_t *__restrict__ o, int64_t *len_out,
+                              int *__restrict__ ne, int64_t *__restrict__ pref,
+                              int64_t *__restrict__ src) {
+    const int lane = lane_id();
+    wave_sync();
+    const uint64_t nz = __ballot(lane < ng && mine > 0);
+    const int nn = __popcll(nz);
+    if (lane < ng && mine > 0) ne[__popcll(nz & lanemask_lt())] = lane;
+    wave_sync();
+    int64_t aj = 0, bj = 0;
+    int walked = 0;
+    if (lane < nn - 1) {
+        const int ga = ne[lane], gb = ne[lane + 1];
+        const uint64_t *A = buf + goff[ga], *B = buf + goff[gb];
+        const int64_t ma = goff[ga + 1] - goff[ga], mb = goff[gb + 1] - goff[gb];
+        const uint64_t last = A[ma - 1];
+        int64_t a = ma - 1, b = B[0] == last ? 1 : 0;
+        if (b < mb && key_set(last) == key_set(B[b])) {
+            const int64_t ls = last_seg_start(A, 0, ma);
+            bool changed = true;
+            while (changed) {
+                changed = false;
+                while (a > ls && drop_mid<UPPER>(A[a - 1], A[a], B[b])) {
+                    a--;
+                    changed = true;
+                }
+                while (b + 1 < mb && key_set(B[b + 1]) == key_set(B[b]) &&
+                       drop_mid<UPPER>(A[a], B[b], B[b + 1])) {
+                    b++;
+                    changed = true;
+                }
+            }
+            walked = 1;
+        }
+        aj = a;
+        bj = b;
+    }
+    const int64_t bl = __shfl_up(bj, 1);
+    const int wl_ = __shfl_up(walked, 1);
+    const bool wl = lane >= 1 && wl_;
+    const int gi = lane < nn ? ne[lane] : 0;
+    const int64_t mi = lane < nn ? goff[gi + 1] - goff[gi] : 0;
+    const int64_t lo = lane >= 1 && lane < nn ? bl : 0;
+    const int64_t hi = lane < nn - 1 ? aj : mi - 1;
+    const bool wr = lane < nn - 1 && walked;
+    const bool bad = lane < nn && (lo > hi || (wl && wr && lo == hi));
+    if (__ballot(bad)) return false;
+    const int64_t cnt = lane < nn ? hi - lo + 1 : 0;
+    const int64_t inc = wave_incl_scan_i64(cnt);
+    const int64_t total = __shfl(inc, WAVE - 1);
+    if (lane < nn) {
+        pref[lane] = inc - cnt;
+        src[lane] = goff[gi] + lo - (inc - cnt);
+    }
+    wave_sync();
+    for (int64_t i = lane; i < total; i += WAVE) {
+        int l = 0, h = nn - 1;          // the last piece starting at or before i
+        while (l < h) {
+            const int mid = (l + h + 1) >> 1;
+            if (pref[mid] <= i) l = mid; else h = mid - 1;
+        }
+        o[i] = buf[src[l] + i];
+    }
+    *len_out = total;
+    return true;
+}
+
 template <bool UPPER>
 __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__restrict__ cin,
                             int64_t U, int64_t R, int64_t v, int lev, uint64_t *__restrict__ out,
                             uint32_t *__restrict__ cout, uint64_t *__restrict__ buf,
-                            int64_t *__restrict__ goff) {
+                            int64_t *__restrict__ goff, int *__restrict__ ne,
+                            int64_t *__restrict__ pref, int64_t *__restrict__ psrc) {
     const int lane = lane_id();
     const int64_t base = v * R * CHAIN_G;
     uint64_t *o = out + base;
@@ -389,7 +469,8 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
         // a few long chains (the upper levels): joined left to right in LDS,
         // walking each junction to its bridge
         stage_group(in, R, u0, (int)min((int64_t)CHAIN_G, U - u0), incl, M, goff, buf);
-        {
+        if (!parallel_join<UPPER>(buf, goff, (int)min((int64_t)CHAIN_G, U - u0), mine, o, &len, ne, pref,
+                                  psrc)) {
             for (int g = 0; g < CHAIN_G && u0 + g < U; g++) {
                 const int64_t m = __shfl(mine, g), og = __shfl(incl, g) - m;
                 if (m == 0) continue;
@@ -413,8 +494,8 @@ __device__ void merge_group(const uint64_t *__restrict__ in, const uint32_t *__r
                     tailseg = newtail;
                 }
             }
+            for (int64_t i = lane; i < len; i += WAVE) o[i] = buf[i];
         }
-        for (int64_t i = lane; i < len; i += WAVE) o[i] = buf[i];
     } else if (M <= MERGE_CAP) {
         // level 0: many short chains side by side form one x-sorted list
         // holding every vertex of the merged chain: prune it in place like a
@@ -586,14 +667,18 @@ __global__ __launch_bounds__(256) void k_chain_merge(const uint64_t *__restrict_
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
     if (V == 0 && wave == 0 && threadIdx.x == 0)   // no candidates: empty top chain
         (blockIdx.y == 0 ? lo_cout : up_cout)[0] = 0;
-    __shared__ int64_t moff[4][CHAIN_G + 1];
+    __shared__ int64_t moff[4][CHAIN_G + 1], mpre[4][CHAIN_G], msrc[4][CHAIN_G];
+    __shared__ int mne[4][CHAIN_G];
     uint64_t *buf = mbuf[threadIdx.x >> 6];
     int64_t *goff = moff[threadIdx.x >> 6];
     const uint32_t *cin = blockIdx.y == 0 ? lo_cin : up_cin;
     for (int64_t v = wave; v < V; v += nw) {        // groups the count actually has
         if (block_group(cin, U, v)) continue;
-        if (blockIdx.y == 0) merge_group<false>(lo_in, lo_cin, U, R, v, lev, lo_out, lo_cout, buf, goff);
-        else merge_group<true>(up_in, up_cin, U, R, v, lev, up_out, up_cout, buf, goff);
+        const int wv = threadIdx.x >> 6;
+        if (blockIdx.y == 0)
+            merge_group<false>(lo_in, lo_cin, U, R, v, lev, lo_out, lo_cout, buf, goff, mne[wv], mpre[wv], msrc[wv]);
+        else
+            merge_group<true>(up_in, up_cin, U, R, v, lev, up_out, up_cout, buf, goff, mne[wv], mpre[wv], msrc[wv]);
         wave_sync();
     }
     __shared__ int64_t sh[3 + 2 * CHAIN_G];
