@@ -784,9 +784,10 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
         const bool batched = S > 1;
         const int64_t nin = stage_regions(p.nwave, r, batched), nout = stage_regions(p.nwave, r + 1, batched);
         const int kg = ref_group(r, batched);
-        const size_t lds = ref_lds_bytes(2 * er);
+        const size_t lds = ref_lds_bytes(2 * er, S == 1);
+        const unsigned nb = (unsigned)((nout + REF_WAVES - 1) / REF_WAVES);
         if (S == 1) {
-            LAUNCH(K_REFINE, k_ref_pass<<<(unsigned)nout, WAVE, lds, st>>>(
+            LAUNCH(K_REFINE, k_ref_pass<<<nb, REF_WAVES * WAVE, lds, st>>>(
                 idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r, batched), tab[b], 2 * er,
                 F[(r + 1) % 3], idxs[b], keys[b], eds[b], cout, 1, x, y, tab[a], F[r % 3], tab[b],
                 F[(r + 2) % 3]));
@@ -794,7 +795,7 @@ static int run_refine(hull_ctx *ctx, const Plan &p, hipStream_t st, const float 
         }
         LAUNCH(K_REFINE_SPLIT, k_ref_split<<<(unsigned)((S * er + 255) / 256), 256, 0, st>>>(
             x, y, S, er, tab[a], far[a], tab[b], far[b]));
-        LAUNCH(K_REFINE, k_ref_pass<<<(unsigned)nout, WAVE, lds, st>>>(
+        LAUNCH(K_REFINE, k_ref_pass<<<nb, REF_WAVES * WAVE, lds, st>>>(
             idxs[a], keys[a], eds[a], cin, (int)nin, kg, meta, region_mult(r, batched), tab[b], 2 * er,
             far[b], idxs[b], keys[b], eds[b], cout, 0, x, y, nullptr, nullptr, nullptr, nullptr));
     }

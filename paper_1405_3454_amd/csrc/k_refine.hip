@@ -100,32 +100,41 @@ constexpr int REF_GROUP = 4;                      // most input regions one wave
 // several sets leave many regions nearly empty, so their waves read two.
 __host__ __device__ inline int ref_group(int r, bool batched) { return r == 0 ? 1 : 2; }
 
-// LDS of a pass: the farthest keys, then the child edges (as EdgeF), of the
-// set a wave holds (er2 of each).
-__host__ __device__ inline size_t ref_lds_bytes(int er2) {
-    return (size_t)er2 * (sizeof(unsigned long long) + 3 * sizeof(double));
+// Waves per block of a pass.  Each wave works alone; the block shares the
+// farthest keys (one table with one set, and waves holding the same set
+// merge theirs at the end), so each block raises the global slots once
+// instead of each wave: thousands of waves raising the same few dozen slots
+// serialise on them.
+constexpr int REF_WAVES = 4;
+
+// LDS of a pass: the farthest keys, then the child edges (as EdgeF), er2 of
+// each: one table per block with one set, one per wave with several.
+__host__ __device__ inline size_t ref_lds_bytes(int er2, bool one_set) {
+    return (size_t)(one_set ? 1 : REF_WAVES) * er2 * (sizeof(unsigned long long) + 3 * sizeof(double));
 }
 
-// One round over the survivors, one wave per block (no block barriers).  A
-// list is a row of regions (region r at r * segcap, cnt[r] entries; round 0
-// reads the discard pass's).  Wave g reads regions [g * kg, (g + 1) * kg) as
-// one list, in chunks of REF_CHUNK (lane l holds chunk entries l, l + 64,
-// ...).  Each survivor is classified against the two children of its edge
-// (RE_DROP, RE_NONE or the new edge id); the kept ones are packed into region
-// g (size kg * segcap) of the next list in (chunk, row, lane) order, and the
-// wave writes their count at the end: no atomics.  The farthest-point key of
-// each new edge is raised.  One set (one_set): the set's child edges and
-// farthest keys live in LDS for the whole wave, and with tab_par the wave
-// splits the parent edges itself (wave 0 also publishes the children for the
-// next round and clears the farthest keys the round after this one raises).
-// Several sets: the set of a chunk that lies in one set is held in LDS over
-// consecutive chunks of that set and its keys are raised in global memory
-// when another set comes and at the end; a chunk that spans sets reads the
-// tables and raises the keys in global memory.
+// One round over the survivors.  A list is a row of regions (region r at
+// r * segcap, cnt[r] entries; round 0 reads the discard pass's).  Wave g of
+// the grid reads regions [g * kg, (g + 1) * kg) as one list, in chunks of
+// REF_CHUNK (lane l holds chunk entries l, l + 64, ...), with no block
+// barriers in its walk.  Each survivor is classified against the two
+// children of its edge (RE_DROP, RE_NONE or the new edge id); the kept ones
+// are packed into region g (size kg * segcap) of the next list in (chunk,
+// row, lane) order, and the wave writes their count at the end: no atomics.
+// The farthest-point key of each new edge is raised in LDS and, at the end,
+// in the global slots.  One set (one_set): the block stages the set's child
+// edges once (with tab_par it splits the parent edges itself, and block 0
+// also publishes the children for the next round and clears the farthest
+// keys the round after this one raises) and shares one key table.  Several
+// sets: each wave holds the set of a chunk that lies in one set, in its own
+// tables, over consecutive chunks of that set, and raises its keys in global
+// memory when another set comes; a chunk that spans sets reads the tables
+// and raises the keys in global memory.  At the end the waves of a block that
+// hold the same set merge their keys and raise them once.
 constexpr int REF_PER_LANE = 8;
 constexpr int REF_CHUNK = WAVE * REF_PER_LANE;    // 512 entries
 
-__global__ __launch_bounds__(WAVE) void k_ref_pass(
+__global__ __launch_bounds__(REF_WAVES * WAVE) void k_ref_pass(
     const uint32_t *__restrict__ idx, const uint64_t *__restrict__ keys,
     const uint16_t *__restrict__ edge, const int64_t *__restrict__ cnt_in, int nreg_in, int kg,
     const int64_t *__restrict__ region_size, int64_t mult, const REdge *__restrict__ tab_nxt, int er2,
@@ -136,10 +145,13 @@ __global__ __launch_bounds__(WAVE) void k_ref_pass(
     const unsigned long long *__restrict__ far_par, REdge *__restrict__ tab_out,
     unsigned long long *__restrict__ far_clr) {
     extern __shared__ unsigned long long ref_lds[];
-    unsigned long long *Lv = ref_lds;                       // er2 farthest keys
-    EdgeF *ltab = reinterpret_cast<EdgeF *>(ref_lds + er2);  // er2 child edges
-    const int lane = threadIdx.x;
-    const int64_t g = blockIdx.x;
+    __shared__ int64_t hsh[REF_WAVES];            // several sets: the set each wave holds at the end
+    const int lane = lane_id(), w = threadIdx.x >> 6, tid = threadIdx.x;
+    const int tw = one_set ? 0 : w;               // this wave's tables
+    unsigned long long *Lv = ref_lds + (size_t)tw * er2 * 4;               // er2 farthest keys
+    EdgeF *ltab = reinterpret_cast<EdgeF *>(ref_lds + (size_t)tw * er2 * 4 + er2);  // er2 child edges
+    const int64_t g = (int64_t)blockIdx.x * REF_WAVES + w;
+    const int64_t ngroups = ((int64_t)nreg_in + kg - 1) / kg;
     const int64_t segcap = *region_size * mult;      // input region size
     const int64_t r0 = g * kg;
     const int nr = (int)max((int64_t)0, min((int64_t)kg, (int64_t)nreg_in - r0));
@@ -158,43 +170,12 @@ __global__ __launch_bounds__(WAVE) void k_ref_pass(
             if (j < nr && pre[j] <= v) a += segcap - (pre[j] - pre[j - 1]);
         return a;
     };
-    auto split_here = [&](bool to_lds) {
-        for (int e = lane; e < er2 / 2; e += WAVE) {
-            REdge c0, c1;
-            split_pair(x, y, tab_par[e], far_par[e], &c0, &c1);
-            if (to_lds) {
-                ltab[2 * e] = edge_f(c0);
-                ltab[2 * e + 1] = edge_f(c1);
-            }
-            if (g == 0) {
-                tab_out[2 * e] = c0;
-                tab_out[2 * e + 1] = c1;
-            }
-        }
-        if (g == 0)
-            for (int e = lane; e < RE_CAP; e += WAVE) far_clr[e] = 0;
-    };
-    if (n_sg == 0) {                        // nothing to read: an empty group, no far keys
-        if (lane == 0) cnt_out[g] = 0;
-        if (tab_par && g == 0) split_here(false);
-        return;
-    }
-    const int64_t region = r0 * segcap;     // output region g: [region, region + kg * segcap)
-    const uint64_t lt = lanemask_lt();
-    int64_t outn = 0;                       // entries packed into the region so far
-    int64_t held = -1;                      // several sets: the set held in LDS
-    auto flush = [&](int64_t fs) {          // the held keys -> global slots
-        for (int e = lane; e < er2; e += WAVE) {
-            const unsigned long long v = Lv[e];
-            if (v) far_update(&far[fs * RE_CAP + e], v);
-        }
-    };
-    for (int64_t jb = 0; jb < n_sg; jb += REF_CHUNK) {
-        uint64_t k[REF_PER_LANE];
-        uint16_t st[REF_PER_LANE];
-        uint32_t ix[REF_PER_LANE];
-        // the region of entry jb; a chunk with no other region start in it
-        // is read from one base address (scalar) plus the lane's offset
+    uint64_t k[REF_PER_LANE];
+    uint16_t st[REF_PER_LANE];
+    uint32_t ix[REF_PER_LANE];
+    // the chunk at jb: a chunk with no other region start in it is read from
+    // one base address (scalar) plus the lane's offset
+    auto load_chunk = [&](int64_t jb) {
         int jr = 0;
 #pragma unroll
         for (int t = 1; t < REF_GROUP; t++) jr += (t < nr && pre[t] <= jb);
@@ -239,17 +220,46 @@ __global__ __launch_bounds__(WAVE) void k_ref_pass(
                 ix[i] = in ? idx[a] : 0;
             }
         }
-        bool local = true;
-        if (one_set) {
-            if (jb == 0) {      // the set's tables, while the first chunk's loads fly
-                for (int e = lane; e < er2; e += WAVE) Lv[e] = 0;
-                if (tab_par)
-                    split_here(true);
-                else
-                    for (int e = lane; e < er2; e += WAVE) ltab[e] = edge_f(tab_nxt[e]);
-                wave_sync();
+    };
+    if (n_sg > 0) load_chunk(0);              // in flight while the tables are staged
+    if (!__syncthreads_or(n_sg > 0 ? 1 : 0)) {  // the whole block is empty
+        if (lane == 0 && g < ngroups) cnt_out[g] = 0;
+        if (!(one_set && tab_par && blockIdx.x == 0)) return;
+    }
+    if (one_set) {
+        for (int e = tid; e < er2; e += REF_WAVES * WAVE) Lv[e] = 0;
+        if (tab_par) {
+            for (int e = tid; e < er2 / 2; e += REF_WAVES * WAVE) {
+                REdge c0, c1;
+                split_pair(x, y, tab_par[e], far_par[e], &c0, &c1);
+                ltab[2 * e] = edge_f(c0);
+                ltab[2 * e + 1] = edge_f(c1);
+                if (blockIdx.x == 0) {
+                    tab_out[2 * e] = c0;
+                    tab_out[2 * e + 1] = c1;
+                }
             }
+            if (blockIdx.x == 0)
+                for (int e = tid; e < RE_CAP; e += REF_WAVES * WAVE) far_clr[e] = 0;
         } else {
+            for (int e = tid; e < er2; e += REF_WAVES * WAVE) ltab[e] = edge_f(tab_nxt[e]);
+        }
+        __syncthreads();
+    }
+    const int64_t region = r0 * segcap;     // output region g: [region, region + kg * segcap)
+    const uint64_t lt = lanemask_lt();
+    int64_t outn = 0;                       // entries packed into the region so far
+    int64_t held = -1;                      // several sets: the set held in LDS
+    auto flush_wave = [&](int64_t fs) {     // the wave's held keys -> global slots
+        for (int e = lane; e < er2; e += WAVE) {
+            const unsigned long long v = Lv[e];
+            if (v) far_update(&far[fs * RE_CAP + e], v);
+        }
+    };
+    for (int64_t jb = 0; jb < n_sg; jb += REF_CHUNK) {
+        if (jb > 0) load_chunk(jb);
+        bool local = true;
+        if (!one_set) {
             // one set in the whole chunk?  (a region can span sets)  Entry jb
             // is lane 0's first.
             const int64_t s0 = (int64_t)(__shfl(k[0], 0) >> 48);
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(WAVE) void k_ref_pass(
                 same = same && (jb + lane + (int64_t)i * WAVE >= n_sg || (int64_t)(k[i] >> 48) == s0);
             local = __ballot(!same) == 0;
             if (held >= 0 && (!local || s0 != held)) {
-                flush(held);
+                flush_wave(held);
                 held = -1;
                 wave_sync();
             }
@@ -327,11 +337,29 @@ __global__ __launch_bounds__(WAVE) void k_ref_pass(
             outn += __popcll(bm);
         }
     }
-    if (one_set || held >= 0) {
-        wave_sync();
-        flush(one_set ? 0 : held);
+    if (lane == 0 && g < ngroups) cnt_out[g] = outn;
+    // the block's farthest keys -> global slots, once per set
+    if (!one_set && lane == 0) hsh[w] = held;
+    __syncthreads();
+    if (one_set) {
+        for (int e = tid; e < er2; e += REF_WAVES * WAVE) {
+            const unsigned long long v = Lv[e];
+            if (v) far_update(&far[e], v);
+        }
+        return;
     }
-    if (lane == 0) cnt_out[g] = outn;
+    int first = w;                          // the first wave holding the same set
+    if (held >= 0) {
+        for (int v = w - 1; v >= 0; v--)
+            if (hsh[v] == held) first = v;
+        if (first != w) {
+            unsigned long long *dst = ref_lds + (size_t)first * er2 * 4;
+            for (int e = lane; e < er2; e += WAVE)
+                if (Lv[e]) atomicMax(&dst[e], Lv[e]);
+        }
+    }
+    __syncthreads();
+    if (held >= 0 && first == w) flush_wave(held);
 }
 
 // Regions of list stage r (0: the discard pass's, one per wave; round r
