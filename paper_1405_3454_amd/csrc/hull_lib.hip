@@ -546,8 +546,10 @@ static int run_polygon(hull_ctx *ctx, const Plan &p, hipStream_t st, const float
     default: return HULL_EINVAL;
     }
 #undef K2
-    LAUNCH(K_POLYGON, k_rows<<<dim3((unsigned)S, SPAN_ROWS / ROWS_PER_BLOCK), 256, 0, st>>>(
-        polys, spans, W<uint32_t>(p, p.redges)));
+    // row-group blocks per set: all 16 for a few sets, one for thousands
+    const unsigned ny = (unsigned)std::max<int64_t>(1, std::min<int64_t>(SPAN_ROWS / ROWS_PER_BLOCK,
+                                                                         (2 * ctx->cus + S - 1) / S));
+    LAUNCH(K_POLYGON, k_rows<<<dim3((unsigned)S, ny), 256, 0, st>>>(polys, spans, W<uint32_t>(p, p.redges)));
     return HULL_OK;
 }
 
@@ -1057,6 +1059,7 @@ int hull_polygon(hull_ctx *ctx, const float *x, const float *y, int64_t n, const
     hipStream_t st = (hipStream_t)stream;
     Plan p;
     if ((rc = prepare(ctx, n, 1, st, &p))) return rc;
+    if ((rc = run_tilemap(ctx, p, st, x, nullptr, n, 1))) return rc;    // the set's size sets its rows
     if ((rc = run_polygon(ctx, p, st, x, y, n, 1, false, slots, n_slots, nullptr, nullptr))) return rc;
     LAUNCH(K_MISC, k_poly_out<<<1, 64, 0, st>>>(W<Poly>(p, p.polys), n_slots, verts, m));
     return HULL_OK;
@@ -1326,10 +1329,12 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     hipEvent_t ea, eb;
     HIPCHECK(hipEventCreate(&ea));
     HIPCHECK(hipEventCreate(&eb));
-    // a candidate's time: the best of four runs after a warm-up one
-    auto timed = [&](auto &&fn, float *best_ms) -> int {
-        float best = 1e30f;
-        for (int rep = 0; rep < 5; rep++) {
+    // a candidate's time: the best of its timed runs, taken in three rounds
+    // over all the candidates (two runs each, after a warm-up one in the
+    // first), so that a drift of the clocks during the sweep does not favour
+    // the candidates timed at one end of it
+    auto timed = [&](auto &&fn, bool warm, float *best_ms) -> int {
+        for (int rep = warm ? 0 : 1; rep < 3; rep++) {
             HIPCHECK(hipEventRecord(ea, st));
             int r = fn();
             if (r) return r;
@@ -1337,22 +1342,28 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
             HIPCHECK(hipEventSynchronize(eb));
             float ms = 0;
             HIPCHECK(hipEventElapsedTime(&ms, ea, eb));
-            if (rep) best = std::min(best, ms);
+            if (rep) *best_ms = std::min(*best_ms, ms);
         }
-        *best_ms = best;
         return HULL_OK;
     };
+    constexpr int ROUNDS = 3;
     const bool had1 = ctx->has_tuned[0][b], had3 = ctx->has_tuned[1][b];
     const Shape old1 = ctx->tuned[0][b], old3 = ctx->tuned[1][b];
     Shape best1 = shape_of(ctx, 0, n_total, S), best3 = shape_of(ctx, 1, n_total, S);
-    float t1 = 1e30f, t3 = 1e30f;
+    std::vector<float> t1(c1.size(), 1e30f), t3(c3.size(), 1e30f);
     rc = run_tilemap(ctx, big, st, x, offsets, n1, S);
-    for (size_t i = 0; !rc && i < c1.size(); i++) {
-        ctx->tuned[0][b] = c1[i];
-        ctx->has_tuned[0][b] = true;
-        float ms = 0;
-        rc = timed([&]() { return run_extremes(ctx, big, st, x, y, n_total, offsets, n1, S, false); }, &ms);
-        if (!rc && ms < t1) { t1 = ms; best1 = c1[i]; }
+    for (int round = 0; !rc && round < ROUNDS; round++)
+        for (size_t i = 0; !rc && i < c1.size(); i++) {
+            ctx->tuned[0][b] = c1[i];
+            ctx->has_tuned[0][b] = true;
+            rc = timed([&]() { return run_extremes(ctx, big, st, x, y, n_total, offsets, n1, S, false); },
+                       round == 0, &t1[i]);
+        }
+    {
+        size_t k = 0;
+        for (size_t i = 1; i < c1.size(); i++)
+            if (t1[i] < t1[k]) k = i;
+        if (!c1.empty()) best1 = c1[k];
     }
     ctx->tuned[0][b] = best1;
     ctx->has_tuned[0][b] = true;
@@ -1360,19 +1371,24 @@ int hull_autotune(hull_ctx *ctx, const float *x, const float *y, const int64_t *
     // polygon of the best extremes shape
     if (!rc) rc = run_extremes(ctx, big, st, x, y, n_total, offsets, n1, S, false);
     if (!rc) rc = run_polygon(ctx, big, st, x, y, n_total, S, false, nullptr, 0, nullptr, nullptr, true);
-    for (size_t i = 0; !rc && i < c3.size(); i++) {
-        ctx->tuned[1][b] = c3[i];
-        ctx->has_tuned[1][b] = true;
-        Plan pc = make_plan(n_total, S, region_count(ctx, n_total, S));
-        pc.base = ctx->ws;
-        float ms = 0;
-        rc = timed([&]() {
-            return run_discard_append(ctx, pc, st, x, y, n_total, offsets, n1, S, slot_count(ctx, false),
-                                      W<uint32_t>(pc, pc.surv), W<uint64_t>(pc, pc.keys0),
-                                      W<uint16_t>(pc, pc.up0), W<int64_t>(pc, pc.segcnt),
-                                      W<unsigned long long>(pc, pc.rfar0));
-        }, &ms);
-        if (!rc && ms < t3) { t3 = ms; best3 = c3[i]; }
+    for (int round = 0; !rc && round < ROUNDS; round++)
+        for (size_t i = 0; !rc && i < c3.size(); i++) {
+            ctx->tuned[1][b] = c3[i];
+            ctx->has_tuned[1][b] = true;
+            Plan pc = make_plan(n_total, S, region_count(ctx, n_total, S));
+            pc.base = ctx->ws;
+            rc = timed([&]() {
+                return run_discard_append(ctx, pc, st, x, y, n_total, offsets, n1, S, slot_count(ctx, false),
+                                          W<uint32_t>(pc, pc.surv), W<uint64_t>(pc, pc.keys0),
+                                          W<uint16_t>(pc, pc.up0), W<int64_t>(pc, pc.segcnt),
+                                          W<unsigned long long>(pc, pc.rfar0));
+            }, round == 0, &t3[i]);
+        }
+    {
+        size_t k = 0;
+        for (size_t i = 1; i < c3.size(); i++)
+            if (t3[i] < t3[k]) k = i;
+        if (!c3.empty()) best3 = c3[k];
     }
     ctx->tuned[1][b] = best3;
     ctx->has_tuned[1][b] = true;
