@@ -205,7 +205,7 @@ extern "C" int hull3_compute(hull_ctx *ctx, const float *x, const float *y, cons
             LAUNCH(K_MISC, k3_count_i64<<<1, 64, 0, st>>>(ncorner, hcount));
         }
         // ascending indices
-        if ((rc = run_sort(ctx, ph, st, corner, hcount, 4, &sorted))) return rc;
+        if ((rc = run_sort(ctx, ph, st, corner, hcount, 4, 1, &sorted))) return rc;
         LAUNCH(K_MISC, k3_copy_sorted<<<256, 256, 0, st>>>(sorted, hcount, hull, h));
         return HULL_OK;
     }

@@ -640,22 +640,33 @@ static int sort_passes(int64_t S) {
 }
 
 // Sort keys (count at *cnt) ascending; returns the buffer holding the result.
+// Several sets (S > 1): the keys arrive grouped by set in set order, and each
+// set is sorted alone in LDS; the radix passes run only when that is not so
+// or a set is too large for it.
 static int run_sort(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint64_t *keys,
-                    const int64_t *cnt, int passes, const uint64_t **sorted) {
+                    const int64_t *cnt, int passes, int64_t S, const uint64_t **sorted) {
     if (passes > SORT_MAX_PASSES) return HULL_EINVAL;
     uint64_t *A = W<uint64_t>(p, p.keysA), *B = W<uint64_t>(p, p.keysB);
     unsigned long long *status = W<unsigned long long>(p, p.sstat);
     uint32_t *gst = W<uint32_t>(p, p.sgst);
+    int *seg = S > 1 ? reinterpret_cast<int *>(W<int64_t>(p, p.consts) + 4) : nullptr;
     const uint64_t *in = keys;
     uint64_t *out = A;
-    // small counts: sorted at once into the buffer the last pass would fill;
-    // otherwise the passes' state is cleared
+    uint64_t *fin = passes % 2 ? A : B;        // where the last pass leaves the keys
+    // small counts: sorted at once into that buffer; otherwise the passes'
+    // state is cleared (and the sets' fallback flag)
     LAUNCH(K_SORT_HIST, k_sort_small<<<1 + SMALL_CLEAR_BLOCKS, SMALL_THREADS, 0, st>>>(
-        keys, cnt, passes % 2 ? A : B, status, gst));
-    LAUNCH(K_SORT_HIST, k_sort_prep<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(keys, cnt, passes, gst));
+        keys, cnt, fin, status, gst, seg));
+    if (seg) {
+        int64_t *starts = W<int64_t>(p, p.bounds);    // S + 1 entries (the final stage rewrites it)
+        LAUNCH(K_SORT_HIST, k_set_starts<<<(unsigned)ctx->cus * 4, 256, 0, st>>>(keys, cnt, S, starts, seg));
+        LAUNCH(K_SORT_HIST, k_sort_sets<<<(unsigned)std::min<int64_t>(S, (int64_t)ctx->cus * 2), SEG_THREADS, 0,
+                                          st>>>(keys, cnt, S, starts, fin, seg));
+    }
+    LAUNCH(K_SORT_HIST, k_sort_prep<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(keys, cnt, passes, gst, seg));
     for (int ps = 0; ps < passes; ps++) {
         LAUNCH(K_SORT_SCATTER, k_sort_pass<<<SORT_BLOCKS, SORT_THREADS, 0, st>>>(
-            in, cnt, ps, gst, status, gst + SORT_MAX_PASSES * RADIX + ps, out));
+            in, cnt, ps, gst, status, gst + SORT_MAX_PASSES * RADIX + ps, out, seg));
         in = out;
         out = (out == A) ? B : A;
     }
@@ -681,7 +692,7 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
                     const uint64_t *keys, const int64_t *cnt, int64_t ncap, int64_t S,
                     int64_t *hoff, uint32_t *hull, int64_t *h_out = nullptr) {
     const uint64_t *sorted = nullptr;
-    int rc = run_sort(ctx, p, st, keys, cnt, sort_passes(S), &sorted);
+    int rc = run_sort(ctx, p, st, keys, cnt, sort_passes(S), S, &sorted);
     if (rc) return rc;
     uint64_t *lo[2] = {W<uint64_t>(p, p.lo0), W<uint64_t>(p, p.lo1)};
     uint64_t *up[2] = {W<uint64_t>(p, p.up0), W<uint64_t>(p, p.up1)};

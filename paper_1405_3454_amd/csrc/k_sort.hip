@@ -62,10 +62,12 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small(const uint64_t *__
                                                               const int64_t *__restrict__ cnt_ptr,
                                                               uint64_t *__restrict__ out,
                                                               unsigned long long *__restrict__ status,
-                                                              uint32_t *__restrict__ gstate) {
+                                                              uint32_t *__restrict__ gstate,
+                                                              int *__restrict__ seg_fallback) {
     __shared__ uint64_t b[SORT_SMALL];
     const int64_t count = *cnt_ptr;
     const int tid = threadIdx.x;
+    if (seg_fallback && blockIdx.x == 0 && tid == 0) *seg_fallback = 0;
     if (count > SORT_SMALL) {
         if (blockIdx.x == 0) return;
         const int64_t nst = sort_busy(count) * RADIX;
@@ -98,16 +100,98 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small(const uint64_t *__
     for (int i = tid; i < n; i += SMALL_THREADS) out[i] = b[i];
 }
 
+// Several sets.  The candidates of the hull stage arrive grouped by set in
+// ascending set order (the filter's regions follow the tiles, and the tiles
+// follow the sets), so each set can be sorted alone: start[s] = the first
+// candidate of set s for s = 0..S (start[S] = n), from the keys' set field;
+// a key whose set is below its predecessor's raises *fallback, and the radix
+// passes then sort everything.
+__global__ __launch_bounds__(256) void k_set_starts(const uint64_t *__restrict__ keys,
+                                                    const int64_t *__restrict__ cnt_ptr, int64_t S,
+                                                    int64_t *__restrict__ start, int *__restrict__ fallback) {
+    const int64_t n = *cnt_ptr;
+    if (n <= SORT_SMALL) return;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i <= n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> 48);
+        const int64_t cur = i == n ? S : (int64_t)(keys[i] >> 48);
+        if (cur < prev) atomicOr(fallback, 1);
+        for (int64_t t = prev + 1; t <= cur && t <= S; t++) start[t] = i;
+    }
+}
+
+constexpr int SEG_THREADS = 1024;
+constexpr int SEG_MAX = 8192;         // keys of one set a block sorts in LDS (64 KB)
+
+// Each set's range [start[s], start[s + 1]) sorted in LDS by one block
+// (bitonic network over the next power of two, padded with the largest key)
+// into out, where the radix passes would have left it; block b takes the
+// sets b, b + gridDim.x, ...  A set of more than SEG_MAX keys, or a key in a
+// range that is not its set's, raises *fallback.
+__global__ __launch_bounds__(SEG_THREADS) void k_sort_sets(const uint64_t *__restrict__ keys,
+                                                           const int64_t *__restrict__ cnt_ptr, int64_t S,
+                                                           const int64_t *__restrict__ start,
+                                                           uint64_t *__restrict__ out,
+                                                           int *__restrict__ fallback) {
+    __shared__ uint64_t b[SEG_MAX];
+    __shared__ int bad;
+    const int64_t n = *cnt_ptr;
+    if (n <= SORT_SMALL) return;
+    const int tid = threadIdx.x;
+    for (int64_t s = blockIdx.x; s < S; s += gridDim.x) {
+        const int64_t a = start[s], e = start[s + 1];
+        if (e <= a) continue;
+        if (e - a > SEG_MAX) {
+            if (tid == 0) atomicOr(fallback, 1);
+            continue;
+        }
+        const int m = (int)(e - a);
+        int P = 1;
+        while (P < m) P <<= 1;
+        if (tid == 0) bad = 0;
+        __syncthreads();
+        for (int i = tid; i < P; i += SEG_THREADS) {
+            const uint64_t k = i < m ? keys[a + i] : ~0ull;
+            if (i < m && (int64_t)(k >> 48) != s) bad = 1;
+            b[i] = k;
+        }
+        __syncthreads();
+        if (bad) {
+            if (tid == 0) atomicOr(fallback, 1);
+            __syncthreads();
+            continue;
+        }
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = tid; t < (P >> 1); t += SEG_THREADS) {
+                    const int i = 2 * j * (t / j) + (t % j), l = i + j;    // pair (i, l), i < l
+                    const bool up = (i & k) == 0;                         // ascending run
+                    const uint64_t x = b[i], y = b[l];
+                    if ((x > y) == up) {
+                        b[i] = y;
+                        b[l] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < m; i += SEG_THREADS) out[a + i] = b[i];
+        __syncthreads();      // b is refilled for the next set
+    }
+}
+
 // Digit totals of every pass over all keys: block b counts the digits of
 // range b in LDS and adds them to gcount[pass][digit] (cleared by
 // k_sort_small).
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_prep(const uint64_t *__restrict__ keys,
                                                             const int64_t *__restrict__ cnt_ptr,
-                                                            int passes, uint32_t *__restrict__ gcount) {
+                                                            int passes, uint32_t *__restrict__ gcount,
+                                                            const int *__restrict__ seg_fallback) {
     __shared__ uint32_t h[SORT_MAX_PASSES][RADIX];
     const int tid = threadIdx.x;
     const int64_t count = *cnt_ptr;
     if (count <= SORT_SMALL) return;
+    if (seg_fallback && *seg_fallback == 0) return;    // k_sort_sets has sorted every set
     if ((int64_t)blockIdx.x >= sort_busy(count)) return;
     for (int ps = 0; ps < SORT_MAX_PASSES; ps++) h[ps][tid] = 0;
     __syncthreads();
@@ -176,7 +260,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(const uint64_t *__re
                                                             int pass, const uint32_t *__restrict__ gcount,
                                                             unsigned long long *__restrict__ status,
                                                             uint32_t *__restrict__ claim,
-                                                            uint64_t *__restrict__ out) {
+                                                            uint64_t *__restrict__ out,
+                                                            const int *__restrict__ seg_fallback) {
     constexpr int NW = SORT_THREADS / WAVE;
     __shared__ int64_t run[RADIX];                       // next output position per digit
     __shared__ __attribute__((aligned(16))) uint16_t wcnt[SORT_ROUNDS][NW][RADIX];
@@ -188,6 +273,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(const uint64_t *__re
     const int shift = 8 * pass;
     const int64_t count = *cnt_ptr;
     if (count <= SORT_SMALL) return;     // k_sort_small has sorted them
+    if (seg_fallback && *seg_fallback == 0) return;    // k_sort_sets has sorted every set
     if (tid == 0) rsh = (int64_t)atomicAdd(claim, 1u);
     const uint32_t gd = gcount[pass * RADIX + tid];      // this digit's total (in flight with the claim)
     rh[tid] = 0;
