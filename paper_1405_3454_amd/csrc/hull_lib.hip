@@ -712,7 +712,8 @@ static int run_hull(hull_ctx *ctx, const Plan &p, hipStream_t st, const uint32_t
         // buffer 1 instead (an odd number of levels ends there)
         const int64_t gs = std::min<int64_t>(gmax, (S + 3) / 4);
         LAUNCH(K_CHAIN_COMPACT, k_chain_sets<<<dim3((unsigned)gs, 2), 256, 0, st>>>(
-            sorted, cnt, S, lo[0], up[0], locnt[0], upcnt[0], lo[1], up[1], locnt[1], upcnt[1], big));
+            sorted, cnt, S, lo[0], up[0], locnt[0], upcnt[0], lo[1], up[1], locnt[1], upcnt[1], big,
+            W<int64_t>(p, p.bounds), reinterpret_cast<const int *>(W<int64_t>(p, p.consts) + 4)));
         if (L % 2 == 0) L++;
     }
     int cur = 0;

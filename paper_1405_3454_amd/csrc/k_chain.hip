@@ -732,11 +732,13 @@ constexpr int64_t SET_CHUNKS_MAX = 32;
 
 template <bool UPPER>
 __device__ void set_chain(const uint64_t *__restrict__ sorted, int64_t n, uint32_t s,
+                          const int64_t *__restrict__ starts,
                           const uint64_t *__restrict__ lists, const uint32_t *__restrict__ lcnt,
                           uint64_t *__restrict__ out, uint64_t *__restrict__ buf,
                           int64_t *__restrict__ goff, int64_t *__restrict__ gsrc, int *__restrict__ big) {
     const int lane = lane_id();
-    const int64_t start = set_lower_bound(sorted, n, s), end = set_lower_bound(sorted, n, s + 1);
+    const int64_t start = starts ? starts[s] : set_lower_bound(sorted, n, s);
+    const int64_t end = starts ? starts[s + 1] : set_lower_bound(sorted, n, s + 1);
     if (start >= end) return;
     const int64_t c0 = start / CHAIN_C, c1 = (end - 1) / CHAIN_C;
     if (c1 - c0 + 1 > SET_CHUNKS_MAX) {     // too many pieces for one wave
@@ -814,7 +816,9 @@ __global__ __launch_bounds__(256) void k_chain_sets(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ up_cin,
                                                     uint64_t *__restrict__ lo_out, uint64_t *__restrict__ up_out,
                                                     uint32_t *__restrict__ lo_len, uint32_t *__restrict__ up_len,
-                                                    int *__restrict__ big) {
+                                                    int *__restrict__ big,
+                                                    const int64_t *__restrict__ set_starts,
+                                                    const int *__restrict__ seg_flag) {
     __shared__ uint64_t mbuf[4][MERGE_CAP];
     __shared__ int64_t moff[4][SET_CHUNKS_MAX + 1], msrc[4][SET_CHUNKS_MAX];
     const int64_t n = *cnt_ptr;
@@ -823,9 +827,14 @@ __global__ __launch_bounds__(256) void k_chain_sets(const uint64_t *__restrict__
     int64_t *goff = moff[threadIdx.x >> 6], *gsrc = msrc[threadIdx.x >> 6];
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    // the sets' ranges from the sort's set starts when the keys came in set
+    // order, else by binary search in the sorted keys
+    const int64_t *starts = set_starts && (*seg_flag & SEG_UNORDERED) == 0 ? set_starts : nullptr;
     for (int64_t s = wave; s < S; s += nw) {
-        if (blockIdx.y == 0) set_chain<false>(sorted, n, (uint32_t)s, lo_in, lo_cin, lo_out, buf, goff, gsrc, big);
-        else set_chain<true>(sorted, n, (uint32_t)s, up_in, up_cin, up_out, buf, goff, gsrc, big);
+        if (blockIdx.y == 0)
+            set_chain<false>(sorted, n, (uint32_t)s, starts, lo_in, lo_cin, lo_out, buf, goff, gsrc, big);
+        else
+            set_chain<true>(sorted, n, (uint32_t)s, starts, up_in, up_cin, up_out, buf, goff, gsrc, big);
     }
 }
 

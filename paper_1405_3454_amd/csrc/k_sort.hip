@@ -104,18 +104,21 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_sort_small(const uint64_t *__
 // ascending set order (the filter's regions follow the tiles, and the tiles
 // follow the sets), so each set can be sorted alone: start[s] = the first
 // candidate of set s for s = 0..S (start[S] = n), from the keys' set field;
-// a key whose set is below its predecessor's raises *fallback, and the radix
-// passes then sort everything.
+// a key whose set is below its predecessor's raises SEG_UNORDERED in
+// *fallback, and the radix passes then sort everything.  Without it the
+// starts are also the sets' ranges in the sorted keys (the sort keeps each
+// set's range), which the chain stage reads.
+constexpr int SEG_TOO_BIG = 1, SEG_UNORDERED = 2;
+
 __global__ __launch_bounds__(256) void k_set_starts(const uint64_t *__restrict__ keys,
                                                     const int64_t *__restrict__ cnt_ptr, int64_t S,
                                                     int64_t *__restrict__ start, int *__restrict__ fallback) {
     const int64_t n = *cnt_ptr;
-    if (n <= SORT_SMALL) return;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i <= n;
          i += int64_t(gridDim.x) * blockDim.x) {
         const int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] >> 48);
         const int64_t cur = i == n ? S : (int64_t)(keys[i] >> 48);
-        if (cur < prev) atomicOr(fallback, 1);
+        if (cur < prev) atomicOr(fallback, SEG_UNORDERED);
         for (int64_t t = prev + 1; t <= cur && t <= S; t++) start[t] = i;
     }
 }
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(SEG_THREADS) void k_sort_sets(const uint64_t *__res
         const int64_t a = start[s], e = start[s + 1];
         if (e <= a) continue;
         if (e - a > SEG_MAX) {
-            if (tid == 0) atomicOr(fallback, 1);
+            if (tid == 0) atomicOr(fallback, SEG_TOO_BIG);
             continue;
         }
         const int m = (int)(e - a);
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(SEG_THREADS) void k_sort_sets(const uint64_t *__res
         }
         __syncthreads();
         if (bad) {
-            if (tid == 0) atomicOr(fallback, 1);
+            if (tid == 0) atomicOr(fallback, SEG_UNORDERED);
             __syncthreads();
             continue;
         }
