@@ -1290,15 +1290,32 @@ int hull_tuning_table(hull_ctx *ctx, int32_t *rows, int cap) {
 // Candidate shapes of the tuner: each block size at 1..8 blocks per CU (the
 // same waves per CU counted once per block size) and 1, 4 or 16 tiles per
 // wave, the latter only where they shrink the grid.
+// Candidate shapes of a kernel for n points: every (block size, blocks per
+// CU, tiles per wave) that launches a distinct number of waves.  On large
+// inputs (2^26 points and more) only the shapes that keep the kernel's most
+// waves resident per CU: timed alone, a shape of lower occupancy has come out
+// ahead several times and then run 8-17 % slower in the step, where each
+// pass follows the other kernels instead of itself.
 static std::vector<Shape> shape_candidates(const hull_ctx *ctx, int kind, int64_t n, int64_t S,
                                            bool learned) {
     std::vector<Shape> out;
     std::vector<std::pair<int, int64_t>> seen;     // (block size, waves)
+    auto per_cu = [&](const Shape &sh, const void *fn) {
+        return (int64_t)std::min(sh.bpc, resident_blocks(fn, sh.bs)) * (sh.bs / WAVE);
+    };
+    int64_t full = 0;
+    for (int bs : SHAPE_BS)
+        for (int bpc : {1, 2, 3, 4, 6, 8}) {
+            const void *fn = kind == 0 ? k1_kernel(ctx->preset, learned, bs) : k3_kernel(bs);
+            full = std::max(full, per_cu(Shape{bs, bpc, 1}, fn));
+        }
+    const bool full_only = n >= (int64_t(1) << 26);
     for (int bs : SHAPE_BS)
         for (int bpc : {1, 2, 3, 4, 6, 8})
             for (int tpw : {1, 4, 16}) {
                 const Shape sh{bs, bpc, tpw};
                 const void *fn = kind == 0 ? k1_kernel(ctx->preset, learned, bs) : k3_kernel(bs);
+                if (full_only && per_cu(sh, fn) < full) continue;
                 const Launch L = make_launch(ctx, sh, fn, n, S);
                 bool dup = false;
                 for (auto &q : seen) dup = dup || (q.first == bs && q.second == L.waves);
