@@ -167,3 +167,26 @@ def test_refinement_batched_matches_plain_chain(H):
         p, q = off[s], off[s + 1]
         want = oracle.hull_subset(x[p:q], y[p:q]).astype(np.int64) + p
         assert np.array_equal(a[ao[s]:ao[s + 1]].astype(np.int64), want), s
+
+
+def test_small_sets_with_one_beyond_the_per_set_sort(H):
+    """Many small sets (each sorted alone in LDS in the hull stage) and one
+    annulus of 2^24 points whose candidates after the refinement rounds are
+    more than one block sorts: the radix passes then sort the whole batch.
+    Every set against the oracle."""
+    big = 1 << 24
+    xb, yb = inputs.annulus(big, 77)
+    H.set_directions(0)
+    H.compute(dev(xb), dev(yb))
+    assert H.candidate_counts()[-1] > 8192      # the big set alone: beyond the per-set sort
+    sizes = (list(inputs.batch_sizes(120, 43, lo=1_000, hi=30_000)) + [big]
+             + list(inputs.batch_sizes(40, 44, lo=1_000, hi=30_000)))
+    x, y, off, _ = make_batch(sizes, 12)
+    a = int(off[120])
+    x[a:a + big], y[a:a + big] = xb, yb
+    want = oracle_sets(x, y, off, 0)
+    hull, ho = H.compute_batched(dev(x), dev(y), dev(off.astype(np.int64)))
+    ho = ho.cpu().numpy()
+    hv = u32(hull)
+    for s in range(len(sizes)):
+        assert np.array_equal(hv[ho[s]:ho[s + 1]], want[s][2]), ("mixed", s)
